@@ -1,0 +1,185 @@
+/*
+ * epic.h -- C ABI of the MI355X (gfx950) sparse-to-dense, edge-preserving
+ * interpolation library (EpicFlow, Revaud et al. 2015, Sec. 3).
+ *
+ * Given an edge cost map C and a sparse set of matches M = {(p_m, p'_m)},
+ * the library computes a dense displacement field:
+ *   1. geodesic distance D(p) from every pixel to its nearest match and the
+ *      geodesic Voronoi label L(p) (Eq. 3; Sec. 3.4, "Geodesic Voronoi
+ *      diagram");
+ *   2. the match graph: cells adjacent in L are joined, weighted by the
+ *      geodesic distance restricted to the two cells (Sec. 3.4,
+ *      "Approximated geodesic distance", Eq. 4);
+ *   3. the K nearest matches of every match by Dijkstra on that graph
+ *      (Algorithm 1, steps 4-5);
+ *   4. one Nadaraya-Watson (Eq. 1) or locally-weighted affine (Eq. 2) model
+ *      per match with weights exp(-a d) (Algorithm 1, step 6);
+ *   5. every pixel takes the model of its cell (Algorithm 1, steps 7-8;
+ *      Sec. 3.4, "Piecewise field").
+ *
+ * Conventions (all entry points):
+ *   - C linkage; no exception crosses the ABI; every entry point returns an
+ *     epic_status (0 = success) unless stated otherwise.
+ *   - Device pointers are plain HIP device addresses (e.g. torch tensors'
+ *     data pointers) on the context's device; host pointers are marked.
+ *   - The caller owns every input and output buffer and keeps it alive until
+ *     the work queued on `stream` has completed.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Calls are asynchronous: they enqueue kernels and return without
+ *     synchronising, except where stated.
+ *   - A context is used by one host thread at a time.  Its workspace is
+ *     allocated once, in epic_create; no call allocates device memory.
+ *   - Coordinates: pixel (x = column, y = row), integer pixel centres,
+ *     origin at the top-left pixel.  Row-major images.
+ *   - cost: H*W float32, every value finite and > 0 (not checked on the
+ *     device; other values give undefined results).
+ *   - matches: N*4 float32 rows (x, y, x', y').  A match is placed on the
+ *     pixel floor(x+0.5), floor(y+0.5) (matches are pixels, Sec. 3.1);
+ *     matches outside the image are dropped, and when several matches fall
+ *     on one pixel the lowest index keeps it.  Dropped matches are counted.
+ *   - flow: H*W*2 float32, interleaved displacement (u, v) = F(p) - p.
+ */
+#ifndef EPIC_H_
+#define EPIC_H_
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    EPIC_NW = 0,   /* Nadaraya-Watson: kernel-weighted mean displacement, Eq. (1) */
+    EPIC_LA = 1    /* locally-weighted affine least squares, Eq. (2)              */
+} epic_mode;
+
+typedef enum {
+    EPIC_OK = 0,
+    EPIC_ERR_ARG = -1,         /* invalid argument (checked on the host)            */
+    EPIC_ERR_WORKSPACE = -2,   /* workspace of the context too small for the call   */
+    EPIC_ERR_NO_MATCHES = -3,  /* no match lies in the image (flow is filled with NaN) */
+    EPIC_ERR_HIP = -4,         /* a HIP runtime call failed                          */
+    EPIC_ERR_BUDGET = -5,      /* request exceeds the memory budget it was given     */
+    EPIC_ERR_CAPACITY = -6,    /* a fixed-capacity device structure overflowed       */
+    EPIC_ERR_CONVERGENCE = -7  /* the geodesic transform hit its iteration bound     */
+} epic_status;
+
+/* Options; NULL selects the defaults shown. */
+typedef struct epic_options {
+    int   connectivity;     /* 8 (default) or 4: pixel neighbourhood of the
+                               discretised geodesic (Eq. 3)                    */
+    int   la_weight_power;  /* 2 (default): each equation of Eq. (2) scaled by
+                               k, i.e. weights k^2 in the normal equations;
+                               1: weights k                                    */
+    int   precision;        /* 0 (default): FP32 distances and fits, FP64 only
+                               for ill-conditioned affine fits;
+                               1: FP64 graph distances and fits everywhere     */
+    float fp64_route;       /* FP32 conditioning (eigenvalue ratio of the
+                               weighted neighbour covariance) below which an
+                               affine fit is redone in FP64; default 1e-3      */
+    double degenerate_tau;  /* eigenvalue ratio at or below which the
+                               neighbourhood is near-collinear and LA falls
+                               back to NW (decided in FP64); default 1e-9      */
+    int   tile_w, tile_h;   /* geodesic-transform tile (0 = default 32 x 32;
+                               supported: 32x32, 64x16, 64x32)                 */
+} epic_options;
+
+typedef struct epic_ctx epic_ctx;
+
+/* Creates a context on HIP device `device` that owns `workspace_bytes` of
+ * device memory (allocated here, once).  Returns NULL on failure (bad
+ * device, allocation failure); epic_last_error() then tells why. */
+epic_ctx* epic_create(int device, size_t workspace_bytes, const epic_options* opts);
+
+/* Frees the context and its workspace.  The caller must have synchronised
+ * every stream used with it.  NULL is ignored. */
+void epic_destroy(epic_ctx* ctx);
+
+/* Workspace bytes one call with these sizes needs (host only; no device
+ * access).  Returns 0 for invalid sizes. */
+size_t epic_workspace_bytes(int H, int W, int N, int K, int mode, int precision);
+
+/* Dense interpolation of one image pair (Algorithm 1).
+ *   cost    device, H*W float32 (edge cost map C)
+ *   matches device, N*4 float32 (x, y, x', y')
+ *   K       neighbours per match (>= 1; clamped to the number of usable
+ *           matches); supported up to 256
+ *   a       kernel parameter of exp(-a d) (finite, >= 0)
+ *   mode    EPIC_NW or EPIC_LA
+ *   flow    device, H*W*2 float32 output (u, v)
+ * Host-side validation returns EPIC_ERR_ARG (null pointers, H, W, N or K
+ * < 1, H*W >= 2^31, K > 256, non-finite or negative a, bad mode) and
+ * EPIC_ERR_WORKSPACE, before anything is enqueued.  Conditions found on the
+ * device (no usable match, capacity overflow) are reported by
+ * epic_get_stats after the stream has been synchronised. */
+int epic_interp(epic_ctx* ctx, const float* cost, int H, int W,
+                const float* matches, int N, int K, float a, int mode,
+                float* flow, void* stream);
+
+/* One request of a batch: same meaning as the arguments of epic_interp. */
+typedef struct epic_request {
+    const float* cost;
+    int H, W;
+    const float* matches;
+    int N, K;
+    float a;
+    int mode;
+    float* flow;
+} epic_request;
+
+/* Interpolates n independent pairs in one fused sequence of launches: each
+ * stage runs once for all pairs (tiles, pixels and matches of every pair
+ * are the work items of one launch).  Each pair's result equals what
+ * epic_interp gives for it alone.  `reqs` is a host array.  The sum of the
+ * pairs' workspace needs must fit the context workspace. */
+int epic_interp_batch(epic_ctx* ctx, const epic_request* reqs, int n, void* stream);
+
+/* Per-call device-side counters, valid once the stream of the last call
+ * has been synchronised (this call synchronises that stream itself). */
+typedef struct epic_stats {
+    int status;            /* EPIC_OK or a device-detected epic_status     */
+    int n_used;            /* matches placed on a pixel                     */
+    int n_outside;         /* matches dropped: outside the image            */
+    int n_duplicate;       /* matches dropped: pixel held by a lower index  */
+    int n_edges;           /* edges of the match graph                      */
+    int n_degenerate;      /* LA fits that fell back to NW                  */
+    int n_fp64_fits;       /* affine fits solved in FP64                    */
+    int tile_visits;       /* tiles processed by the geodesic transform     */
+} epic_stats;
+int epic_get_stats(epic_ctx* ctx, int pair, epic_stats* out);
+
+/* Stage outputs of one epic_interp call for testing; every output pointer
+ * is a device pointer and may be NULL.
+ *   D        H*W float32 geodesic distance to the nearest match
+ *   L        H*W int32 nearest-match label
+ *   edge_m, edge_n, edge_w   graph edges (m < n), up to max_edges of them,
+ *            in no particular order; n_edges (device int) receives the
+ *            number of edges
+ *   knn_idx, knn_d  N*K neighbour ids (-1 = none) and graph distances, in
+ *            (distance, index) order
+ *   params   N*6 float32 model b00 b01 b10 b11 c0 c1 of
+ *            flow(p) = B (p - p_m) + c
+ *   flow     as in epic_interp (may be NULL here) */
+int epic_debug_stages(epic_ctx* ctx, const float* cost, int H, int W,
+                      const float* matches, int N, int K, float a, int mode,
+                      float* D, int* L, int* edge_m, int* edge_n,
+                      float* edge_w, int max_edges, int* n_edges,
+                      int* knn_idx, float* knn_d, float* params, float* flow,
+                      void* stream);
+
+/* Human-readable text of an epic_status. */
+const char* epic_strerror(int status);
+
+/* Text of the last error of epic_create on this thread ("" if none). */
+const char* epic_last_error(void);
+
+/* Host-only validation of one request's arguments (what epic_interp checks
+ * before enqueueing).  Returns EPIC_OK or EPIC_ERR_ARG. */
+int epic_validate(const float* cost, int H, int W, const float* matches,
+                  int N, int K, float a, int mode, const float* flow);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EPIC_H_ */

@@ -1,0 +1,179 @@
+"""MI355X-native sparse-to-dense, edge-preserving interpolation (EpicFlow,
+Revaud et al. 2015, Sec. 3), as a HIP library with a thin Python binding.
+
+All computation runs in the HIP kernels of ``libepic.so``; this module only
+marshals torch tensors (device memory) and streams into the C ABI of
+``include/epic.h``.
+
+    import torch, paper_1501_02565_amd as epic
+    ctx = epic.Context()
+    flow = ctx.interp(cost, matches, K=100, a=1.0, mode=epic.LA)   # (H, W, 2)
+"""
+from __future__ import annotations
+
+import ctypes
+
+from . import _lib
+from ._lib import (LA, NW, OK, EpicError, ERR_ARG, ERR_BUDGET, ERR_CAPACITY,  # noqa: F401
+                   ERR_CONVERGENCE, ERR_HIP, ERR_NO_MATCHES, ERR_WORKSPACE)
+
+__all__ = ["Context", "workspace_bytes", "LA", "NW", "EpicError"]
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def workspace_bytes(H: int, W: int, N: int, K: int, mode: int = LA,
+                    precision: int = 0) -> int:
+    """Device workspace one call of this size needs (host-only query)."""
+    return int(_lib.load().epic_workspace_bytes(H, W, N, K, mode, precision))
+
+
+def _stream_handle(stream):
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _check_tensor(t, name, dtype, shape_tail=None):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape_tail is not None and tuple(t.shape[-len(shape_tail):]) != shape_tail:
+        raise ValueError(f"{name} must end in shape {shape_tail}")
+
+
+class Context:
+    """Owns one epic_ctx: a device workspace allocated once (``workspace``
+    bytes, default enough for a 2048 x 1080 image with 40000 matches)."""
+
+    def __init__(self, device: int = 0, workspace: int | None = None, *,
+                 connectivity: int = 8, la_weight_power: int = 2,
+                 precision: int = 0, fp64_route: float = 1e-3,
+                 degenerate_tau: float = 1e-9, tile: tuple[int, int] = (32, 32)):
+        torch = _torch()
+        L = _lib.load()
+        self.device = int(device)
+        if workspace is None:
+            workspace = workspace_bytes(1080, 2048, 40000, 256)
+        self.workspace = int(workspace)
+        self.options = _lib.Options(connectivity, la_weight_power, precision,
+                                    fp64_route, degenerate_tau, tile[0], tile[1])
+        torch.cuda.init()
+        with torch.cuda.device(self.device):
+            self._ctx = L.epic_create(self.device, self.workspace,
+                                      ctypes.byref(self.options))
+        if not self._ctx:
+            raise RuntimeError("epic_create failed: " + L.epic_last_error().decode())
+
+    def close(self):
+        if getattr(self, "_ctx", None):
+            _lib.load().epic_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # ------------------------------------------------------------------
+    def interp(self, cost, matches, K: int, a: float, mode: int = LA, out=None,
+               stream=None):
+        """Dense flow (H, W, 2) float32 for one pair.  cost (H, W) and
+        matches (N, 4) are float32 CUDA tensors.  Asynchronous on `stream`
+        (default: torch's current stream)."""
+        torch = _torch()
+        _check_tensor(cost, "cost", torch.float32)
+        _check_tensor(matches, "matches", torch.float32, (4,))
+        H, W = cost.shape
+        N = matches.shape[0]
+        if out is None:
+            out = torch.empty((H, W, 2), dtype=torch.float32, device=cost.device)
+        _check_tensor(out, "out", torch.float32, (H, W, 2))
+        rc = _lib.load().epic_interp(self._ctx, cost.data_ptr(), H, W,
+                                     matches.data_ptr(), N, int(K), float(a),
+                                     int(mode), out.data_ptr(),
+                                     _stream_handle(stream))
+        if rc != OK:
+            raise EpicError(rc, "epic_interp")
+        return out
+
+    def interp_batch(self, problems, outs=None, stream=None):
+        """problems: list of (cost, matches, K, a, mode).  One fused launch
+        sequence for all of them; returns the list of flows."""
+        torch = _torch()
+        n = len(problems)
+        reqs = (_lib.Request * n)()
+        flows = []
+        for i, (cost, matches, K, a, mode) in enumerate(problems):
+            _check_tensor(cost, "cost", torch.float32)
+            _check_tensor(matches, "matches", torch.float32, (4,))
+            H, W = cost.shape
+            f = outs[i] if outs is not None else torch.empty(
+                (H, W, 2), dtype=torch.float32, device=cost.device)
+            _check_tensor(f, "out", torch.float32, (H, W, 2))
+            flows.append(f)
+            reqs[i] = _lib.Request(cost.data_ptr(), H, W, matches.data_ptr(),
+                                   matches.shape[0], int(K), float(a), int(mode),
+                                   f.data_ptr())
+        rc = _lib.load().epic_interp_batch(self._ctx, reqs, n, _stream_handle(stream))
+        if rc != OK:
+            raise EpicError(rc, "epic_interp_batch")
+        return flows
+
+    def debug_stages(self, cost, matches, K: int, a: float, mode: int = LA,
+                     max_edges: int | None = None, stream=None):
+        """Every stage output of one call (synchronises): D, L, edges, K-NN
+        lists, per-match parameters, flow, stats."""
+        torch = _torch()
+        _check_tensor(cost, "cost", torch.float32)
+        _check_tensor(matches, "matches", torch.float32, (4,))
+        H, W = cost.shape
+        N = matches.shape[0]
+        dev = cost.device
+        if max_edges is None:
+            max_edges = 16 * N + 1024
+        D = torch.empty((H, W), dtype=torch.float32, device=dev)
+        L = torch.empty((H, W), dtype=torch.int32, device=dev)
+        em = torch.empty(max_edges, dtype=torch.int32, device=dev)
+        en = torch.empty(max_edges, dtype=torch.int32, device=dev)
+        ew = torch.empty(max_edges, dtype=torch.float32, device=dev)
+        ne = torch.zeros(1, dtype=torch.int32, device=dev)
+        ki = torch.empty((N, K), dtype=torch.int32, device=dev)
+        kd = torch.empty((N, K), dtype=torch.float32, device=dev)
+        P = torch.empty((N, 6), dtype=torch.float32, device=dev)
+        flow = torch.empty((H, W, 2), dtype=torch.float32, device=dev)
+        rc = _lib.load().epic_debug_stages(
+            self._ctx, cost.data_ptr(), H, W, matches.data_ptr(), N, int(K),
+            float(a), int(mode), D.data_ptr(), L.data_ptr(), em.data_ptr(),
+            en.data_ptr(), ew.data_ptr(), max_edges, ne.data_ptr(),
+            ki.data_ptr(), kd.data_ptr(), P.data_ptr(), flow.data_ptr(),
+            _stream_handle(stream))
+        if rc != OK:
+            raise EpicError(rc, "epic_debug_stages")
+        st = self.stats(0)
+        E = min(int(ne.item()), max_edges)
+        return dict(D=D, L=L, em=em[:E], en=en[:E], ew=ew[:E], knn_idx=ki,
+                    knn_d=kd, params=P, flow=flow, stats=st)
+
+    def stats(self, pair: int = 0) -> dict:
+        """Device counters of the last call (synchronises its stream)."""
+        s = _lib.Stats()
+        rc = _lib.load().epic_get_stats(self._ctx, int(pair), ctypes.byref(s))
+        if rc != OK:
+            raise EpicError(rc, "epic_get_stats")
+        return {k: getattr(s, k) for k, _ in _lib.Stats._fields_}

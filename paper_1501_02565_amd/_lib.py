@@ -1,0 +1,97 @@
+"""ctypes declarations of the C ABI in ``include/epic.h``.
+
+Loading fails loudly when ``libepic.so`` has not been built: there is no
+fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libepic.so")
+
+# epic_status
+OK, ERR_ARG, ERR_WORKSPACE, ERR_NO_MATCHES, ERR_HIP, ERR_BUDGET, ERR_CAPACITY, \
+    ERR_CONVERGENCE = 0, -1, -2, -3, -4, -5, -6, -7
+NW, LA = 0, 1
+
+SYMBOLS = ["epic_create", "epic_destroy", "epic_workspace_bytes", "epic_interp",
+           "epic_interp_batch", "epic_get_stats", "epic_debug_stages",
+           "epic_strerror", "epic_last_error", "epic_validate"]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("connectivity", ctypes.c_int),
+                ("la_weight_power", ctypes.c_int),
+                ("precision", ctypes.c_int),
+                ("fp64_route", ctypes.c_float),
+                ("degenerate_tau", ctypes.c_double),
+                ("tile_w", ctypes.c_int),
+                ("tile_h", ctypes.c_int)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("cost", ctypes.c_void_p),
+                ("H", ctypes.c_int), ("W", ctypes.c_int),
+                ("matches", ctypes.c_void_p),
+                ("N", ctypes.c_int), ("K", ctypes.c_int),
+                ("a", ctypes.c_float), ("mode", ctypes.c_int),
+                ("flow", ctypes.c_void_p)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("n_used", ctypes.c_int),
+                ("n_outside", ctypes.c_int), ("n_duplicate", ctypes.c_int),
+                ("n_edges", ctypes.c_int), ("n_degenerate", ctypes.c_int),
+                ("n_fp64_fits", ctypes.c_int), ("tile_visits", ctypes.c_int)]
+
+
+_lib = None
+
+
+def load():
+    """Loads libepic.so (raises if it is missing: build it first)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(
+            f"{LIB_PATH} is missing: build the HIP library first "
+            "(python -c 'import __graft_entry__ as g; g.build()')")
+    L = ctypes.CDLL(LIB_PATH)
+    P, i32, f32, f64, sz = (ctypes.c_void_p, ctypes.c_int, ctypes.c_float,
+                            ctypes.c_double, ctypes.c_size_t)
+    L.epic_create.argtypes = [i32, sz, ctypes.POINTER(Options)]
+    L.epic_create.restype = P
+    L.epic_destroy.argtypes = [P]
+    L.epic_destroy.restype = None
+    L.epic_workspace_bytes.argtypes = [i32, i32, i32, i32, i32, i32]
+    L.epic_workspace_bytes.restype = sz
+    L.epic_interp.argtypes = [P, P, i32, i32, P, i32, i32, f32, i32, P, P]
+    L.epic_interp.restype = i32
+    L.epic_interp_batch.argtypes = [P, ctypes.POINTER(Request), i32, P]
+    L.epic_interp_batch.restype = i32
+    L.epic_get_stats.argtypes = [P, i32, ctypes.POINTER(Stats)]
+    L.epic_get_stats.restype = i32
+    L.epic_debug_stages.argtypes = [P, P, i32, i32, P, i32, i32, f32, i32,
+                                    P, P, P, P, P, i32, P, P, P, P, P, P]
+    L.epic_debug_stages.restype = i32
+    L.epic_strerror.argtypes = [i32]
+    L.epic_strerror.restype = ctypes.c_char_p
+    L.epic_last_error.argtypes = []
+    L.epic_last_error.restype = ctypes.c_char_p
+    L.epic_validate.argtypes = [P, i32, i32, P, i32, i32, f32, i32, P]
+    L.epic_validate.restype = i32
+    _lib = L
+    return L
+
+
+def strerror(status: int) -> str:
+    return load().epic_strerror(int(status)).decode()
+
+
+class EpicError(RuntimeError):
+    def __init__(self, status: int, where: str = ""):
+        self.status = status
+        super().__init__(f"{where}: {strerror(status)} ({status})")

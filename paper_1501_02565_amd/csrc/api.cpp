@@ -1,0 +1,406 @@
+// api.cpp -- host side of the C ABI declared in include/epic.h: context and
+// workspace management, host-side validation, per-pair descriptors, and the
+// launch sequence of the interpolation (Algorithm 1 of the paper):
+//   clear -> seed -> geodesic transform -> graph emit -> CSR scan ->
+//   CSR scatter -> K-NN + fit -> assignment
+// Every stage is one launch for all pairs of a call.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "epic.h"
+#include "epic_dev.h"
+
+using namespace epic;
+
+namespace {
+
+constexpr int kMaxPairs = 1024;      // pairs per call
+constexpr int kRing = 4;             // descriptor upload slots
+constexpr size_t kAlign = 256;
+constexpr int kMaxK = 256;
+
+thread_local std::string g_last_error;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
+
+int next_pow2(long long v) {
+    int p = 1;
+    while (p < v) p <<= 1;
+    return p;
+}
+
+int hash_cap_for(int N) { return next_pow2(std::max(1024LL, 16LL * N)); }
+
+struct Tiling {
+    int tw, th;
+};
+
+Tiling tiling_from(const epic_options& o) {
+    if (o.tile_w == 64 && o.tile_h == 16) return {64, 16};
+    if (o.tile_w == 64 && o.tile_h == 32) return {64, 32};
+    return {32, 32};
+}
+
+size_t pair_bytes(int H, int W, int N) {
+    const size_t HW = (size_t)H * W;
+    const size_t cap = (size_t)hash_cap_for(N);
+    size_t b = 0;
+    b += align_up(8 * HW);            // keys
+    b += align_up(4 * (size_t)N);     // seed_pix
+    b += align_up(8 * cap);           // hkey
+    b += align_up(4 * cap);           // hval
+    b += 3 * align_up(4 * (size_t)N); // deg, fill, minin
+    b += align_up(4 * ((size_t)N + 1));
+    b += 2 * align_up(4 * cap);       // col, cw
+    b += align_up(24 * (size_t)N);    // params
+    b += align_up(4 * C_NCOUNTERS);
+    return b;
+}
+
+size_t tiles_of(int H, int W, Tiling t) {
+    return (size_t)((W + t.tw - 1) / t.tw) * ((H + t.th - 1) / t.th);
+}
+
+constexpr size_t kFixed = 4096 + (size_t)kRing * kMaxPairs * sizeof(PairDev);
+
+}  // namespace
+
+struct epic_ctx {
+    int device = 0;
+    epic_options opt{};
+    char* ws = nullptr;
+    size_t ws_bytes = 0;
+    PairDev* h_desc = nullptr;          // pinned, kRing * kMaxPairs
+    hipEvent_t ring_ev[kRing]{};
+    bool ring_used[kRing]{};
+    int ring_next = 0;
+    long long wall_rate = 100000000;    // wall_clock64 ticks per second
+    int geo_workers = 0;
+    // last call
+    hipStream_t last_stream = nullptr;
+    int last_npairs = 0;
+    std::vector<int*> last_counters;
+    int* g_pending = nullptr;
+    int* g_error = nullptr;
+};
+
+extern "C" {
+
+const char* epic_strerror(int s) {
+    switch (s) {
+        case EPIC_OK: return "ok";
+        case EPIC_ERR_ARG: return "invalid argument";
+        case EPIC_ERR_WORKSPACE: return "workspace too small for this call";
+        case EPIC_ERR_NO_MATCHES: return "no match lies in the image";
+        case EPIC_ERR_HIP: return "HIP runtime error";
+        case EPIC_ERR_BUDGET: return "request exceeds its memory budget";
+        case EPIC_ERR_CAPACITY: return "fixed-capacity device structure overflowed";
+        case EPIC_ERR_CONVERGENCE: return "geodesic transform did not converge within its bound";
+        default: return "unknown status";
+    }
+}
+
+const char* epic_last_error(void) { return g_last_error.c_str(); }
+
+int epic_validate(const float* cost, int H, int W, const float* matches, int N, int K, float a, int mode,
+                  const float* flow) {
+    if (!cost || !matches || !flow) return EPIC_ERR_ARG;
+    if (H < 1 || W < 1 || N < 1 || K < 1 || K > kMaxK) return EPIC_ERR_ARG;
+    if ((long long)H * W >= (1LL << 31) || N >= (1 << 30)) return EPIC_ERR_ARG;
+    if (!std::isfinite(a) || a < 0.0f) return EPIC_ERR_ARG;
+    if (mode != EPIC_NW && mode != EPIC_LA) return EPIC_ERR_ARG;
+    return EPIC_OK;
+}
+
+size_t epic_workspace_bytes(int H, int W, int N, int K, int mode, int precision) {
+    if (H < 1 || W < 1 || N < 1 || K < 1 || K > kMaxK || (mode != 0 && mode != 1) ||
+        (precision != 0 && precision != 1) || (long long)H * W >= (1LL << 31))
+        return 0;
+    // the smallest tiling gives the largest tile-state array
+    return kFixed + align_up(4 * tiles_of(H, W, Tiling{32, 16})) + pair_bytes(H, W, N);
+}
+
+epic_ctx* epic_create(int device, size_t workspace_bytes, const epic_options* opts) {
+    g_last_error.clear();
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) {
+        g_last_error = "no such HIP device";
+        return nullptr;
+    }
+    epic_ctx* c = new epic_ctx();
+    c->device = device;
+    epic_options o{};
+    o.connectivity = 8;
+    o.la_weight_power = 2;
+    o.precision = 0;
+    o.fp64_route = 1e-3f;
+    o.degenerate_tau = 1e-9;
+    o.tile_w = 32;
+    o.tile_h = 32;
+    if (opts) {
+        o = *opts;
+        if (o.connectivity != 4) o.connectivity = 8;
+        if (o.la_weight_power != 1) o.la_weight_power = 2;
+        if (o.precision != 1) o.precision = 0;
+        if (!(o.fp64_route > 0.0f)) o.fp64_route = 1e-3f;
+        if (!(o.degenerate_tau > 0.0)) o.degenerate_tau = 1e-9;
+        const Tiling t = tiling_from(o);
+        o.tile_w = t.tw;
+        o.tile_h = t.th;
+    }
+    c->opt = o;
+    auto fail = [&](const char* what) {
+        g_last_error = what;
+        epic_destroy(c);
+        return (epic_ctx*)nullptr;
+    };
+    if (hipSetDevice(device) != hipSuccess) return fail("hipSetDevice failed");
+    c->ws_bytes = std::max(workspace_bytes, kFixed + 4096);
+    if (hipMalloc((void**)&c->ws, c->ws_bytes) != hipSuccess) return fail("workspace allocation failed");
+    if (hipHostMalloc((void**)&c->h_desc, sizeof(PairDev) * kRing * kMaxPairs, hipHostMallocDefault) !=
+        hipSuccess)
+        return fail("pinned descriptor allocation failed");
+    for (int i = 0; i < kRing; ++i)
+        if (hipEventCreateWithFlags(&c->ring_ev[i], hipEventDisableTiming) != hipSuccess)
+            return fail("event creation failed");
+    int rate_khz = 0;
+    if (hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, device) == hipSuccess && rate_khz > 0)
+        c->wall_rate = (long long)rate_khz * 1000;
+    c->geo_workers = geodesic_max_workers(o.tile_w, o.tile_h);
+    if (c->geo_workers <= 0) return fail("occupancy query failed");
+    c->g_pending = reinterpret_cast<int*>(c->ws);
+    c->g_error = reinterpret_cast<int*>(c->ws) + 64;
+    return c;
+}
+
+void epic_destroy(epic_ctx* c) {
+    if (!c) return;
+    hipSetDevice(c->device);
+    for (int i = 0; i < kRing; ++i)
+        if (c->ring_ev[i]) {
+            if (c->ring_used[i]) hipEventSynchronize(c->ring_ev[i]);
+            hipEventDestroy(c->ring_ev[i]);
+        }
+    if (c->h_desc) hipHostFree(c->h_desc);
+    if (c->ws) hipFree(c->ws);
+    delete c;
+}
+
+}  // extern "C"
+
+namespace {
+
+struct DebugOut {
+    float* D = nullptr;
+    int* L = nullptr;
+    int* em = nullptr;
+    int* en = nullptr;
+    float* ew = nullptr;
+    int max_edges = 0;
+    int* n_edges = nullptr;
+    int* knn_idx = nullptr;
+    float* knn_d = nullptr;
+    float* params = nullptr;
+};
+
+int run_pairs(epic_ctx* c, const epic_request* reqs, int n, hipStream_t stream, const DebugOut* dbg) {
+    if (!c || !reqs || n < 1 || n > kMaxPairs) return EPIC_ERR_ARG;
+    for (int i = 0; i < n; ++i) {
+        const epic_request& r = reqs[i];
+        const float* flow_chk = (dbg && !r.flow) ? r.cost : r.flow;   // debug may omit the flow
+        const int v = epic_validate(r.cost, r.H, r.W, r.matches, r.N, r.K, r.a, r.mode, flow_chk);
+        if (v != EPIC_OK) return v;
+    }
+    const Tiling tl{c->opt.tile_w, c->opt.tile_h};
+    // ---- carve the workspace
+    size_t total_tiles = 0, need = kFixed;
+    for (int i = 0; i < n; ++i) total_tiles += tiles_of(reqs[i].H, reqs[i].W, tl);
+    need += align_up(4 * total_tiles);
+    for (int i = 0; i < n; ++i) need += pair_bytes(reqs[i].H, reqs[i].W, reqs[i].N);
+    if (need > c->ws_bytes) return EPIC_ERR_WORKSPACE;
+    if (hipSetDevice(c->device) != hipSuccess) return EPIC_ERR_HIP;
+
+    const int slot = c->ring_next;
+    c->ring_next = (c->ring_next + 1) % kRing;
+    if (c->ring_used[slot] && hipEventSynchronize(c->ring_ev[slot]) != hipSuccess) return EPIC_ERR_HIP;
+    PairDev* hd = c->h_desc + (size_t)slot * kMaxPairs;
+    PairDev* dd = reinterpret_cast<PairDev*>(c->ws + 4096) + (size_t)slot * kMaxPairs;
+
+    char* cur = c->ws + kFixed;
+    auto take = [&](size_t bytes) {
+        char* p = cur;
+        cur += align_up(bytes);
+        return p;
+    };
+    u32* tile_state = reinterpret_cast<u32*>(take(4 * total_tiles));
+    int tile_base = 0, pix_blocks = 0, seed_blocks = 0, src_blocks = 0, slot_blocks = 0, init_blocks = 0;
+    int kmax = 1;
+    c->last_counters.assign(n, nullptr);
+    for (int i = 0; i < n; ++i) {
+        const epic_request& r = reqs[i];
+        PairDev& P = hd[i];
+        std::memset(&P, 0, sizeof(P));
+        P.cost = r.cost;
+        P.matches = r.matches;
+        P.flow = r.flow;
+        P.H = r.H;
+        P.W = r.W;
+        P.N = r.N;
+        P.K = r.K;
+        P.a = r.a;
+        P.mode = r.mode;
+        kmax = std::max(kmax, r.K);
+        P.tiles_x = (r.W + tl.tw - 1) / tl.tw;
+        P.tiles_y = (r.H + tl.th - 1) / tl.th;
+        P.tile_base = tile_base;
+        tile_base += P.tiles_x * P.tiles_y;
+        const long long HW = (long long)r.H * r.W;
+        P.pix_block_base = pix_blocks;
+        pix_blocks += (int)((HW + PIX_BLOCK - 1) / PIX_BLOCK);
+        P.seed_block_base = seed_blocks;
+        seed_blocks += (r.N + PIX_BLOCK - 1) / PIX_BLOCK;
+        P.src_block_base = src_blocks;
+        src_blocks += r.N;
+        P.hash_cap = hash_cap_for(r.N);
+        int lg = 0;
+        while ((1 << lg) < P.hash_cap) ++lg;
+        P.hash_shift = 64 - lg;
+        P.slot_block_base = slot_blocks;
+        slot_blocks += P.hash_cap / SLOT_BLOCK;
+        P.init_block_base = init_blocks;
+        P.init_blocks = (int)std::min<long long>(1024, std::max<long long>(1, (std::max<long long>(HW, P.hash_cap) + 1023) / 1024));
+        init_blocks += P.init_blocks;
+        const size_t cap = (size_t)P.hash_cap;
+        P.keys = reinterpret_cast<u64*>(take(8 * (size_t)HW));
+        P.seed_pix = reinterpret_cast<int*>(take(4 * (size_t)r.N));
+        P.hkey = reinterpret_cast<u64*>(take(8 * cap));
+        P.hval = reinterpret_cast<u32*>(take(4 * cap));
+        P.deg = reinterpret_cast<u32*>(take(4 * (size_t)r.N));
+        P.fill = reinterpret_cast<u32*>(take(4 * (size_t)r.N));
+        P.minin = reinterpret_cast<u32*>(take(4 * (size_t)r.N));
+        P.row_ptr = reinterpret_cast<u32*>(take(4 * ((size_t)r.N + 1)));
+        P.col = reinterpret_cast<int*>(take(4 * cap));
+        P.cw = reinterpret_cast<float*>(take(4 * cap));
+        P.params = reinterpret_cast<float*>(take(24 * (size_t)r.N));
+        P.counters = reinterpret_cast<int*>(take(4 * C_NCOUNTERS));
+        c->last_counters[i] = P.counters;
+        if (dbg && i == 0) {
+            P.dbg_knn_idx = dbg->knn_idx;
+            P.dbg_knn_d = dbg->knn_d;
+            if (dbg->knn_idx && !dbg->knn_d) P.dbg_knn_d = nullptr;
+            P.dbg_em = (dbg->em && dbg->en && dbg->ew && dbg->n_edges) ? dbg->em : nullptr;
+            P.dbg_en = dbg->en;
+            P.dbg_ew = dbg->ew;
+            P.dbg_max_edges = dbg->max_edges;
+            P.dbg_n_edges = dbg->n_edges;
+        }
+    }
+    if ((size_t)(cur - c->ws) > c->ws_bytes) return EPIC_ERR_WORKSPACE;
+    if (dbg && dbg->knn_idx && !dbg->knn_d) return EPIC_ERR_ARG;
+
+    RunDev run{};
+    run.tile_state = tile_state;
+    run.pending = c->g_pending;
+    run.error = c->g_error;
+    run.total_tiles = tile_base;
+    run.npairs = n;
+    run.conn = c->opt.connectivity;
+    run.tile_w = tl.tw;
+    run.tile_h = tl.th;
+    run.la_wpow = c->opt.la_weight_power;
+    run.precision = c->opt.precision;
+    run.fp64_route = c->opt.fp64_route;
+    run.deg_tau = c->opt.degenerate_tau;
+    run.spin_ticks = 2 * c->wall_rate;   // two seconds without progress
+
+    hipError_t e = hipMemcpyAsync(dd, hd, sizeof(PairDev) * n, hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipEventRecord(c->ring_ev[slot], stream);
+    if (e != hipSuccess) return EPIC_ERR_HIP;
+    c->ring_used[slot] = true;
+
+    const int workers = std::max(1, std::min(c->geo_workers, tile_base));
+    if (e == hipSuccess) e = launch_clear(dd, run, init_blocks, stream);
+    if (e == hipSuccess) e = launch_seed(dd, run, seed_blocks, stream);
+    if (e == hipSuccess) e = launch_geodesic(dd, run, tl.tw, tl.th, workers, stream);
+    if (e == hipSuccess) e = launch_graph_emit(dd, run, pix_blocks, stream);
+    if (e == hipSuccess) e = launch_csr_scan(dd, run, stream);
+    if (e == hipSuccess) e = launch_csr_scatter(dd, run, slot_blocks, stream);
+    if (e == hipSuccess) e = launch_knn_fit(dd, run, src_blocks, kmax, stream);
+    bool any_flow = false;
+    for (int i = 0; i < n; ++i) any_flow |= reqs[i].flow != nullptr;
+    if (e == hipSuccess && any_flow) e = launch_assign(dd, run, pix_blocks, stream);
+    if (e == hipSuccess && dbg && (dbg->D || dbg->L)) e = launch_unpack(dd, run, pix_blocks, dbg->D, dbg->L, stream);
+    if (e == hipSuccess && dbg && dbg->params)
+        e = hipMemcpyAsync(dbg->params, hd[0].params, 24 * (size_t)reqs[0].N, hipMemcpyDeviceToDevice, stream);
+    if (e != hipSuccess) return EPIC_ERR_HIP;
+    c->last_stream = stream;
+    c->last_npairs = n;
+    return EPIC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int epic_interp(epic_ctx* ctx, const float* cost, int H, int W, const float* matches, int N, int K, float a,
+                int mode, float* flow, void* stream) {
+    const int v = epic_validate(cost, H, W, matches, N, K, a, mode, flow);
+    if (v != EPIC_OK) return v;
+    if (!ctx) return EPIC_ERR_ARG;
+    epic_request r{cost, H, W, matches, N, K, a, mode, flow};
+    return run_pairs(ctx, &r, 1, (hipStream_t)stream, nullptr);
+}
+
+int epic_interp_batch(epic_ctx* ctx, const epic_request* reqs, int n, void* stream) {
+    if (!ctx || !reqs || n < 1) return EPIC_ERR_ARG;
+    return run_pairs(ctx, reqs, n, (hipStream_t)stream, nullptr);
+}
+
+int epic_debug_stages(epic_ctx* ctx, const float* cost, int H, int W, const float* matches, int N, int K,
+                      float a, int mode, float* D, int* L, int* edge_m, int* edge_n, float* edge_w,
+                      int max_edges, int* n_edges, int* knn_idx, float* knn_d, float* params, float* flow,
+                      void* stream) {
+    if (!ctx) return EPIC_ERR_ARG;
+    DebugOut d;
+    d.D = D;
+    d.L = L;
+    d.em = edge_m;
+    d.en = edge_n;
+    d.ew = edge_w;
+    d.max_edges = max_edges;
+    d.n_edges = n_edges;
+    d.knn_idx = knn_idx;
+    d.knn_d = knn_d;
+    d.params = params;
+    epic_request r{cost, H, W, matches, N, K, a, mode, flow};
+    return run_pairs(ctx, &r, 1, (hipStream_t)stream, &d);
+}
+
+int epic_get_stats(epic_ctx* ctx, int pair, epic_stats* out) {
+    if (!ctx || !out || pair < 0 || pair >= ctx->last_npairs) return EPIC_ERR_ARG;
+    if (hipSetDevice(ctx->device) != hipSuccess) return EPIC_ERR_HIP;
+    if (hipStreamSynchronize(ctx->last_stream) != hipSuccess) return EPIC_ERR_HIP;
+    int cnt[C_NCOUNTERS];
+    int gerr = 0;
+    if (hipMemcpy(cnt, ctx->last_counters[pair], sizeof(cnt), hipMemcpyDeviceToHost) != hipSuccess)
+        return EPIC_ERR_HIP;
+    if (hipMemcpy(&gerr, ctx->g_error, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) return EPIC_ERR_HIP;
+    out->status = cnt[C_STATUS];
+    if (gerr && out->status == 0) out->status = EPIC_ERR_CONVERGENCE;
+    out->n_used = cnt[C_USED];
+    out->n_outside = cnt[C_OUTSIDE];
+    out->n_duplicate = cnt[C_DUPLICATE];
+    out->n_edges = cnt[C_EDGES];
+    out->n_degenerate = cnt[C_DEGENERATE];
+    out->n_fp64_fits = cnt[C_FP64];
+    out->tile_visits = cnt[C_TILE_VISITS];
+    return EPIC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,136 @@
+// epic_dev.h -- shared device-side definitions of the interpolation library:
+// the per-pair descriptor that every kernel reads, key packing, and the
+// host-side launcher declarations.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace epic {
+
+typedef unsigned long long u64;
+typedef unsigned int u32;
+
+// A pixel's transform state is one 64-bit key: the float bits of the geodesic
+// distance D in the high word and the match label in the low word.  D >= 0,
+// so the float bits order like the values, and the unsigned order of keys is
+// the lexicographic order on (D, label): a lexicographic min is one integer
+// min, and ties in D go to the lowest label.
+constexpr u64 KEY_INF = 0x7f800000ffffffffull;   // (+inf, no label)
+constexpr u32 NO_LABEL = 0xffffffffu;
+constexpr u64 HASH_EMPTY = ~0ull;
+constexpr u32 FLOAT_INF_BITS = 0x7f800000u;
+
+__device__ __forceinline__ float key_dist(u64 k) { return __uint_as_float((u32)(k >> 32)); }
+__device__ __forceinline__ u32 key_label(u64 k) { return (u32)k; }
+__device__ __forceinline__ u64 make_key(float d, u32 label) {
+    return ((u64)__float_as_uint(d) << 32) | (u64)label;
+}
+
+// Per-pair counters (int32 each).
+enum Counter {
+    C_STATUS = 0,      // epic_status found on the device
+    C_USED = 1,
+    C_OUTSIDE = 2,
+    C_DUPLICATE = 3,
+    C_EDGES = 4,
+    C_DEGENERATE = 5,
+    C_FP64 = 6,
+    C_KEFF = 7,        // K clamped to the usable matches
+    C_OVERFLOW = 8,    // bit 0 graph hash, bit 1 Dijkstra visited table
+    C_TILE_VISITS = 9,
+    C_NCOUNTERS = 16
+};
+
+// Everything a kernel needs about one image pair.  Kernels of a batch launch
+// receive an array of these and find their pair from their work-item index.
+struct PairDev {
+    // inputs / output (caller-owned)
+    const float* cost;      // H*W
+    const float* matches;   // N*4
+    float* flow;            // H*W*2
+    int H, W, N, K;
+    float a;
+    int mode;
+    // work decomposition (global index bases across the batch)
+    int tiles_x, tiles_y;
+    int tile_base;          // first global tile id of this pair
+    int pix_block_base;     // first block of pixel-parallel grids
+    int src_block_base;     // first block of the per-match grid (one match per block)
+    int seed_block_base;    // first block of the seeding grid (PIX_BLOCK matches per block)
+    int slot_block_base;    // first block of the hash-slot grid
+    int init_block_base;    // first block of the clearing grid
+    int init_blocks;        // blocks of the clearing grid for this pair
+    int hash_cap;           // power of two
+    int hash_shift;         // 64 - log2(hash_cap)
+    // workspace (context-owned)
+    u64* keys;              // H*W transform state
+    int* seed_pix;          // N: seed pixel of a match, -1 when outside
+    u64* hkey;              // hash_cap: (m << 32 | n), m < n
+    u32* hval;              // hash_cap: float bits of the edge weight
+    u32* deg;               // N
+    u32* fill;              // N
+    u32* row_ptr;           // N + 1
+    u32* minin;             // N: float bits of the lightest incident edge
+    int* col;               // hash_cap: CSR neighbour ids
+    float* cw;              // hash_cap: CSR edge weights
+    float* params;          // N*6
+    int* counters;          // C_NCOUNTERS
+    // optional stage dumps (NULL = off)
+    int* dbg_knn_idx;       // N*K
+    float* dbg_knn_d;       // N*K
+    int* dbg_em;            // max_edges
+    int* dbg_en;
+    float* dbg_ew;
+    int dbg_max_edges;
+    int* dbg_n_edges;       // device int
+};
+
+// Globals of one launch sequence (shared by all pairs of a batch).
+struct RunDev {
+    u32* tile_state;        // total tiles
+    int* pending;           // dirty + busy tiles
+    int* error;             // global error word
+    int total_tiles;
+    int npairs;
+    int conn;               // 8 or 4
+    int tile_w, tile_h;     // geodesic-transform tile
+    int la_wpow;            // 1 or 2
+    int precision;          // 0 or 1
+    float fp64_route;
+    double deg_tau;
+    long long spin_ticks;   // wall-clock bound of the transform's idle wait
+};
+
+// Binary search: the pair whose base <= idx (bases ascending).
+template <typename F>
+__device__ __forceinline__ int find_pair(int npairs, int idx, F base_of) {
+    int lo = 0, hi = npairs - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (base_of(mid) <= idx) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// ---------------------------------------------------------------------------
+// host-side launchers (one per stage; defined next to their kernels)
+// ---------------------------------------------------------------------------
+constexpr int PIX_BLOCK = 256;      // pixels per block of pixel-parallel kernels
+constexpr int SLOT_BLOCK = 256;     // hash slots per block
+
+hipError_t launch_clear(const PairDev* d_pairs, const RunDev& run, int total_blocks, hipStream_t s);
+hipError_t launch_seed(const PairDev* d_pairs, const RunDev& run, int total_blocks, hipStream_t s);
+hipError_t launch_geodesic(const PairDev* d_pairs, const RunDev& run, int tile_w, int tile_h,
+                           int workers, hipStream_t s);
+int geodesic_max_workers(int tile_w, int tile_h);
+hipError_t launch_graph_emit(const PairDev* d_pairs, const RunDev& run, int total_blocks, hipStream_t s);
+hipError_t launch_csr_scan(const PairDev* d_pairs, const RunDev& run, hipStream_t s);
+hipError_t launch_csr_scatter(const PairDev* d_pairs, const RunDev& run, int total_blocks, hipStream_t s);
+hipError_t launch_knn_fit(const PairDev* d_pairs, const RunDev& run, int total_blocks, int kmax,
+                          hipStream_t s);
+hipError_t launch_assign(const PairDev* d_pairs, const RunDev& run, int total_blocks, hipStream_t s);
+hipError_t launch_unpack(const PairDev* d_pairs, const RunDev& run, int total_blocks, float* D, int* L,
+                         hipStream_t s);
+
+}  // namespace epic

@@ -1,0 +1,53 @@
+// k_assign.hip -- dense assignment (Algorithm 1, steps 7-8; Sec. 3.4,
+// "Piecewise field"): every pixel takes the model of its geodesic Voronoi
+// cell, flow(p) = B_m (p - p_m) + c_m with m = L(p).  NW models have B = 0,
+// so the field is piecewise constant for NW and piecewise affine for LA.
+// Pixels of an image without any usable match get NaN.
+//
+// Also: k_unpack splits the packed (D, label) keys for the debug entry point.
+#include "epic_dev.h"
+
+namespace epic {
+
+__global__ __launch_bounds__(PIX_BLOCK) void k_assign(const PairDev* __restrict__ pairs, RunDev run) {
+    const int p = find_pair(run.npairs, (int)blockIdx.x, [&](int i) { return pairs[i].pix_block_base; });
+    const PairDev& P = pairs[p];
+    const long long i = (long long)((int)blockIdx.x - P.pix_block_base) * PIX_BLOCK + threadIdx.x;
+    const int W = P.W;
+    if (i >= (long long)W * P.H) return;
+    const u32 m = key_label(P.keys[i]);
+    float2 f;
+    if (m == NO_LABEL) {
+        f.x = f.y = __int_as_float(0x7fc00000);
+    } else {
+        const float* B = P.params + 6LL * m;
+        const float2 pm = *reinterpret_cast<const float2*>(P.matches + 4LL * m);
+        const float dx = (float)(int)(i % W) - pm.x, dy = (float)(int)(i / W) - pm.y;
+        f.x = B[0] * dx + B[1] * dy + B[4];
+        f.y = B[2] * dx + B[3] * dy + B[5];
+    }
+    reinterpret_cast<float2*>(P.flow)[i] = f;
+}
+
+__global__ __launch_bounds__(PIX_BLOCK) void k_unpack(const PairDev* __restrict__ pairs, RunDev run, float* D,
+                                                      int* L) {
+    const PairDev& P = pairs[0];
+    const long long i = (long long)blockIdx.x * PIX_BLOCK + threadIdx.x;
+    if (i >= (long long)P.W * P.H) return;
+    const u64 k = P.keys[i];
+    if (D) D[i] = key_dist(k);
+    if (L) L[i] = key_label(k) == NO_LABEL ? -1 : (int)key_label(k);
+}
+
+hipError_t launch_assign(const PairDev* d_pairs, const RunDev& run, int total_blocks, hipStream_t s) {
+    hipLaunchKernelGGL(k_assign, dim3(total_blocks), dim3(PIX_BLOCK), 0, s, d_pairs, run);
+    return hipGetLastError();
+}
+
+hipError_t launch_unpack(const PairDev* d_pairs, const RunDev& run, int total_blocks, float* D, int* L,
+                         hipStream_t s) {
+    hipLaunchKernelGGL(k_unpack, dim3(total_blocks), dim3(PIX_BLOCK), 0, s, d_pairs, run, D, L);
+    return hipGetLastError();
+}
+
+}  // namespace epic

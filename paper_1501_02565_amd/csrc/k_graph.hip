@@ -1,0 +1,190 @@
+// k_graph.hip -- the match graph of Sec. 3.4 ("Approximated geodesic
+// distance"): matches whose Voronoi cells touch are joined by an edge whose
+// weight is the geodesic distance between the two matches restricted to
+// their two cells.
+//
+// Because every cell is star-shaped around its match for the geodesic
+// (each pixel's shortest path to its match stays in the cell), that
+// restricted distance equals the minimum over adjacent pixel pairs (p in
+// cell m, q in cell n) of D(p) + step(p, q) + D(q): every restricted path
+// crosses from cell m to cell n a last time, and the two in-cell shortest
+// paths joined by that step attain the bound.  So the graph is built by one
+// scan over adjacent pixel pairs with a keyed minimum:
+//   k_graph_emit     each pixel looks at its "forward" neighbours (right,
+//                    down, and the two lower diagonals for 8-connectivity),
+//                    so every unordered pair is seen once; pairs with
+//                    different labels insert (min label, max label) into an
+//                    open-addressing hash with an atomic min on the weight
+//                    (positive floats order like their bits).  The first
+//                    insertion of an edge raises both endpoints' degree.
+//   k_csr_scan       one workgroup per pair: counts usable matches, clamps K,
+//                    and turns degrees into CSR row offsets.
+//   k_csr_scatter    writes both directions of every edge into CSR and the
+//                    lightest incident edge of every match.
+#include "epic_dev.h"
+
+namespace epic {
+
+namespace {
+__device__ __forceinline__ u32 hash_slot(u64 key, int shift) {
+    // 64-bit multiplicative mix (Fibonacci hashing of a murmur-style mix)
+    key ^= key >> 33;
+    key *= 0xff51afd7ed558ccdull;
+    key ^= key >> 33;
+    return (u32)((key * 0x9e3779b97f4a7c15ull) >> shift);
+}
+}  // namespace
+
+template <int CONN>
+__global__ __launch_bounds__(PIX_BLOCK) void k_graph_emit(const PairDev* __restrict__ pairs, RunDev run) {
+    const int p = find_pair(run.npairs, (int)blockIdx.x, [&](int i) { return pairs[i].pix_block_base; });
+    const PairDev& P = pairs[p];
+    const long long i = (long long)((int)blockIdx.x - P.pix_block_base) * PIX_BLOCK + threadIdx.x;
+    const int W = P.W, H = P.H;
+    if (i >= (long long)W * H) return;
+    const int x = (int)(i % W), y = (int)(i / W);
+    const u64 kp = P.keys[i];
+    const u32 lp = key_label(kp);
+    if (lp == NO_LABEL) return;
+    const float dp = key_dist(kp);
+    const float cp = P.cost[i];
+    // forward half-neighbourhood: (1,0), (0,1), (1,1), (-1,1)
+    constexpr int HX[4] = {1, 0, 1, -1};
+    constexpr int HY[4] = {0, 1, 1, 1};
+    const u32 mask = (u32)P.hash_cap - 1u;
+#pragma unroll
+    for (int k = 0; k < (CONN == 8 ? 4 : 2); ++k) {
+        const int qx = x + HX[k], qy = y + HY[k];
+        if (qx < 0 || qx >= W || qy >= H) continue;
+        const long long qi = (long long)qy * W + qx;
+        const u64 kq = P.keys[qi];
+        const u32 lq = key_label(kq);
+        if (lq == lp || lq == NO_LABEL) continue;
+        const float len = (k < 2) ? 1.0f : 1.41421356237309515f;
+        const float w = len * (0.5f * (cp + P.cost[qi]));
+        const float cand = (dp + w) + key_dist(kq);
+        const u32 m = min(lp, lq), n = max(lp, lq);
+        const u64 hk = ((u64)m << 32) | n;
+        const u32 wb = __float_as_uint(cand);
+        u32 h = hash_slot(hk, P.hash_shift);
+        bool done = false;
+        for (int probe = 0; probe < P.hash_cap; ++probe) {
+            u64 cur = P.hkey[h];
+            if (cur == HASH_EMPTY) {
+                const u64 prev = atomicCAS(&P.hkey[h], HASH_EMPTY, hk);
+                if (prev == HASH_EMPTY) {
+                    atomicAdd(&P.deg[m], 1u);
+                    atomicAdd(&P.deg[n], 1u);
+                    atomicAdd(&P.counters[C_EDGES], 1);
+                    atomicMin(&P.hval[h], wb);
+                    done = true;
+                    break;
+                }
+                cur = prev;
+            }
+            if (cur == hk) {
+                atomicMin(&P.hval[h], wb);
+                done = true;
+                break;
+            }
+            h = (h + 1u) & mask;
+        }
+        if (!done) atomicOr(&P.counters[C_OVERFLOW], 1);
+    }
+}
+
+// One workgroup of 1024 threads per pair.
+__global__ __launch_bounds__(1024) void k_csr_scan(const PairDev* __restrict__ pairs, RunDev run) {
+    const PairDev& P = pairs[blockIdx.x];
+    __shared__ int s_used;
+    __shared__ u32 s_part[1024];
+    const int tid = threadIdx.x;
+    const int N = P.N;
+    if (tid == 0) s_used = 0;
+    __syncthreads();
+    int used = 0;
+    for (int m = tid; m < N; m += 1024) {
+        const int sp = P.seed_pix[m];
+        if (sp >= 0 && key_label(P.keys[sp]) == (u32)m) ++used;
+    }
+    if (used) atomicAdd(&s_used, used);
+    // exclusive scan of the degrees: each thread owns a contiguous chunk
+    const int chunk = (N + 1023) / 1024;
+    const int b = tid * chunk, e = min(N, b + chunk);
+    u32 sum = 0;
+    for (int m = b; m < e; ++m) sum += P.deg[m];
+    s_part[tid] = sum;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const u32 v = tid >= off ? s_part[tid - off] : 0u;
+        __syncthreads();
+        s_part[tid] += v;
+        __syncthreads();
+    }
+    u32 run_sum = s_part[tid] - sum;
+    for (int m = b; m < e; ++m) {
+        P.row_ptr[m] = run_sum;
+        run_sum += P.deg[m];
+    }
+    if (tid == 1023) P.row_ptr[N] = s_part[1023];
+    if (tid == 0) {
+        const int u = s_used;
+        P.counters[C_USED] = u;
+        P.counters[C_DUPLICATE] = N - P.counters[C_OUTSIDE] - u;
+        P.counters[C_KEFF] = min(P.K, u);
+        int status = 0;
+        if (u == 0) status = -3;                                       // EPIC_ERR_NO_MATCHES
+        if (2LL * P.counters[C_EDGES] > (long long)P.hash_cap) {
+            P.counters[C_OVERFLOW] |= 1;
+        }
+        if (P.counters[C_OVERFLOW]) status = -6;                       // EPIC_ERR_CAPACITY
+        if (*run.error) status = -7;                                   // EPIC_ERR_CONVERGENCE
+        P.counters[C_STATUS] = status;
+    }
+}
+
+__global__ __launch_bounds__(SLOT_BLOCK) void k_csr_scatter(const PairDev* __restrict__ pairs, RunDev run) {
+    const int p = find_pair(run.npairs, (int)blockIdx.x, [&](int i) { return pairs[i].slot_block_base; });
+    const PairDev& P = pairs[p];
+    const int h = ((int)blockIdx.x - P.slot_block_base) * SLOT_BLOCK + threadIdx.x;
+    if (h >= P.hash_cap) return;
+    const u64 key = P.hkey[h];
+    if (key == HASH_EMPTY) return;
+    const u32 m = (u32)(key >> 32), n = (u32)key;
+    const u32 wb = P.hval[h];
+    const float w = __uint_as_float(wb);
+    const u32 pm = P.row_ptr[m] + atomicAdd(&P.fill[m], 1u);
+    const u32 pn = P.row_ptr[n] + atomicAdd(&P.fill[n], 1u);
+    if (pm < (u32)P.hash_cap) { P.col[pm] = (int)n; P.cw[pm] = w; }
+    if (pn < (u32)P.hash_cap) { P.col[pn] = (int)m; P.cw[pn] = w; }
+    atomicMin(&P.minin[m], wb);
+    atomicMin(&P.minin[n], wb);
+    if (P.dbg_em) {
+        const int e = atomicAdd(P.dbg_n_edges, 1);
+        if (e < P.dbg_max_edges) {
+            P.dbg_em[e] = (int)m;
+            P.dbg_en[e] = (int)n;
+            P.dbg_ew[e] = w;
+        }
+    }
+}
+
+hipError_t launch_graph_emit(const PairDev* d_pairs, const RunDev& run, int total_blocks, hipStream_t s) {
+    if (run.conn == 4)
+        hipLaunchKernelGGL(k_graph_emit<4>, dim3(total_blocks), dim3(PIX_BLOCK), 0, s, d_pairs, run);
+    else
+        hipLaunchKernelGGL(k_graph_emit<8>, dim3(total_blocks), dim3(PIX_BLOCK), 0, s, d_pairs, run);
+    return hipGetLastError();
+}
+
+hipError_t launch_csr_scan(const PairDev* d_pairs, const RunDev& run, hipStream_t s) {
+    hipLaunchKernelGGL(k_csr_scan, dim3(run.npairs), dim3(1024), 0, s, d_pairs, run);
+    return hipGetLastError();
+}
+
+hipError_t launch_csr_scatter(const PairDev* d_pairs, const RunDev& run, int total_blocks, hipStream_t s) {
+    hipLaunchKernelGGL(k_csr_scatter, dim3(total_blocks), dim3(SLOT_BLOCK), 0, s, d_pairs, run);
+    return hipGetLastError();
+}
+
+}  // namespace epic

@@ -1,0 +1,419 @@
+// k_knn_fit.hip -- K nearest matches per match on the match graph and the
+// per-match interpolation model (Algorithm 1, steps 4-6; Sec. 3.2-3.4).
+//
+// One wavefront per match s:
+//  1. Dijkstra from s on the match graph, with the visited set held in LDS
+//     (open-addressing node -> entry table).  Several frontier nodes are
+//     settled per step: a frontier node v with tentative d(v) is final once
+//     d(v) <= dmin + lightest_edge(v), where dmin is the smallest tentative
+//     distance on the frontier (no unsettled node can still lower it).  The
+//     edges of all nodes settled in a step are relaxed in parallel, one lane
+//     per edge.  Float sums are monotone, so the distances equal those of a
+//     sequential Dijkstra in the same precision.
+//  2. The search stops once at least K settled nodes lie strictly below the
+//     frontier minimum: the K smallest (distance, index) pairs are then all
+//     settled.  They are selected by a bitonic sort of packed
+//     (distance bits, index) keys, which also fixes the order of the sums
+//     below (deterministic results).  s itself is first, at distance 0.
+//  3. Weights k = exp(-a d) (Eq. 1).  NW: kernel-weighted mean displacement.
+//     LA: weighted least squares of Eq. (2) with weights k^2 (each equation
+//     scaled by k) or k, solved about the weighted centroid of the
+//     neighbours (a 2x2 system per displacement component).  The fit is
+//     done in FP32; when the neighbourhood is ill-conditioned (eigenvalue
+//     ratio of the weighted position covariance below fp64_route, or fewer
+//     than 3 neighbours) it is re-accumulated and solved in FP64, where a
+//     near-collinear neighbourhood (ratio <= deg_tau) falls back to NW.
+//  Output per match: b00 b01 b10 b11 c0 c1 with flow(p) = B (p - p_s) + c.
+#include "epic_dev.h"
+
+namespace epic {
+
+namespace {
+
+__device__ __forceinline__ float wave_min(float v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o));
+    return v;
+}
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+__device__ __forceinline__ double wave_sum_d(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+__device__ __forceinline__ int wave_sum_i(int v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+__device__ __forceinline__ int wave_incl_scan(int v, int lane) {
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int t = __shfl_up(v, o);
+        if (lane >= o) v += t;
+    }
+    return v;
+}
+__device__ __forceinline__ u32 node_slot(int v, int hbits) {
+    return ((u32)v * 2654435761u) >> (32 - hbits);
+}
+
+}  // namespace
+
+template <int VCAP, int KMAX>
+__global__ __launch_bounds__(64) void k_knn_fit(const PairDev* __restrict__ pairs, RunDev run) {
+    constexpr int HCAP = 2 * VCAP;
+    constexpr int HBITS = (HCAP == 1024) ? 10 : (HCAP == 2048 ? 11 : 9);
+    static_assert((1 << HBITS) == HCAP, "hash size");
+    constexpr int R = KMAX / 64;
+    __shared__ int v_node[VCAP];
+    __shared__ u32 v_dist[VCAP];
+    __shared__ u32 v_minin[VCAP];
+    __shared__ unsigned char v_state[VCAP];     // 0 frontier, 1 settled
+    __shared__ u64 s_buf[VCAP];                 // node table, then sort buffer
+    __shared__ unsigned short hidx[HCAP];
+    __shared__ unsigned short newly[VCAP];
+    __shared__ int f_off[65], f_start[64];
+    __shared__ float f_d[64];
+    __shared__ int s_nvis, s_nnew, s_ncand, s_ovf;
+    int* htab = reinterpret_cast<int*>(s_buf);  // HCAP ints
+
+    const int lane = threadIdx.x;
+    const int p = find_pair(run.npairs, (int)blockIdx.x, [&](int i) { return pairs[i].src_block_base; });
+    const PairDev& P = pairs[p];
+    const int s = (int)blockIdx.x - P.src_block_base;
+    if (s >= P.N) return;
+    const int K = P.K;
+    const int keff = P.counters[C_KEFF];
+    const int sp = P.seed_pix[s];
+    // a pair whose graph overflowed its hash has incomplete adjacency: skip it
+    // (its status already reports EPIC_ERR_CAPACITY)
+    const bool graph_ok = (P.counters[C_OVERFLOW] & 1) == 0;
+    const bool active = graph_ok && sp >= 0 && key_label(P.keys[sp]) == (u32)s && keff > 0;
+    float* prm = P.params + 6LL * s;
+    if (!active) {
+        if (lane < 6) prm[lane] = 0.0f;
+        if (P.dbg_knn_idx)
+            for (int j = lane; j < K; j += 64) {
+                P.dbg_knn_idx[(long long)s * K + j] = -1;
+                P.dbg_knn_d[(long long)s * K + j] = __int_as_float(0x7f800000);
+            }
+        return;
+    }
+
+    // ------------------------------------------------------------ Dijkstra
+    for (int i = lane; i < HCAP; i += 64) htab[i] = -1;
+    __syncthreads();
+    if (lane == 0) {
+        s_nvis = 1;
+        s_ovf = 0;
+        v_node[0] = s;
+        v_dist[0] = 0u;
+        v_state[0] = 0;
+        v_minin[0] = P.minin[s];
+        const u32 h = node_slot(s, HBITS);
+        htab[h] = s;
+        hidx[h] = 0;
+    }
+    __syncthreads();
+
+    float dstop;
+    for (;;) {
+        const int nv = min(s_nvis, VCAP);
+        float dmin = __int_as_float(0x7f800000);
+        for (int e = lane; e < nv; e += 64)
+            if (v_state[e] == 0) dmin = fminf(dmin, __uint_as_float(v_dist[e]));
+        dmin = wave_min(dmin);
+        int below = 0;
+        for (int e = lane; e < nv; e += 64)
+            below += (v_state[e] == 1 && __uint_as_float(v_dist[e]) < dmin) ? 1 : 0;
+        below = wave_sum_i(below);
+        if (below >= keff || dmin == __int_as_float(0x7f800000) || s_ovf) {
+            dstop = dmin;
+            break;
+        }
+        if (lane == 0) s_nnew = 0;
+        __syncthreads();
+        for (int e = lane; e < nv; e += 64) {
+            if (v_state[e] == 0 &&
+                __uint_as_float(v_dist[e]) <= dmin + __uint_as_float(v_minin[e])) {
+                v_state[e] = 1;
+                newly[atomicAdd(&s_nnew, 1)] = (unsigned short)e;
+            }
+        }
+        __syncthreads();
+        const int nn = s_nnew;
+        for (int base = 0; base < nn; base += 64) {
+            const int cnt = min(64, nn - base);
+            int dg = 0;
+            if (lane < cnt) {
+                const int e = newly[base + lane];
+                const int u = v_node[e];
+                const u32 st = P.row_ptr[u];
+                dg = (int)(P.row_ptr[u + 1] - st);
+                f_start[lane] = (int)st;
+                f_d[lane] = __uint_as_float(v_dist[e]);
+            }
+            const int incl = wave_incl_scan(dg, lane);
+            const int total = __shfl(incl, 63);
+            if (lane < cnt) f_off[lane] = incl - dg;
+            if (lane == 0) f_off[cnt] = total;
+            __syncthreads();
+            for (int j0 = 0; j0 < total; j0 += 64) {
+                const int j = j0 + lane;
+                const bool act = j < total;
+                int v = -1;
+                float cand = 0.0f;
+                if (act) {
+                    int lo = 0, hi = cnt - 1;       // last i with f_off[i] <= j
+                    while (lo < hi) {
+                        const int mid = (lo + hi + 1) >> 1;
+                        if (f_off[mid] <= j) lo = mid; else hi = mid - 1;
+                    }
+                    const int ei = f_start[lo] + (j - f_off[lo]);
+                    v = P.col[ei];
+                    cand = f_d[lo] + P.cw[ei];
+                }
+                // phase A: find or claim v's slot
+                int h = -1;
+                bool won = false;
+                if (act) {
+                    u32 hh = node_slot(v, HBITS);
+                    for (int probe = 0; probe < HCAP; ++probe) {
+                        const int cur = htab[hh];
+                        if (cur == v) { h = (int)hh; break; }
+                        if (cur == -1) {
+                            const int prev = atomicCAS(&htab[hh], -1, v);
+                            if (prev == -1) { h = (int)hh; won = true; break; }
+                            if (prev == v) { h = (int)hh; break; }
+                        }
+                        hh = (hh + 1u) & (u32)(HCAP - 1);
+                    }
+                    if (h < 0) s_ovf = 1;
+                }
+                // phase B: new nodes get an entry
+                if (won) {
+                    const int e = atomicAdd(&s_nvis, 1);
+                    if (e < VCAP) {
+                        v_node[e] = v;
+                        v_dist[e] = 0x7f800000u;
+                        v_state[e] = 0;
+                        v_minin[e] = P.minin[v];
+                        hidx[h] = (unsigned short)e;
+                    } else {
+                        hidx[h] = 0xffff;
+                        s_ovf = 1;
+                    }
+                }
+                __syncthreads();
+                // phase C: relax
+                if (act && h >= 0) {
+                    const int e = hidx[h];
+                    if (e != 0xffff && v_state[e] == 0) atomicMin(&v_dist[e], __float_as_uint(cand));
+                }
+                __syncthreads();
+            }
+        }
+    }
+    if (s_ovf && lane == 0) atomicOr(&P.counters[C_OVERFLOW], 2);
+
+    // ---------------------------------------- select the K nearest (sorted)
+    const int nv = min(s_nvis, VCAP);
+    if (lane == 0) s_ncand = 0;
+    __syncthreads();
+    for (int e = lane; e < nv; e += 64) {
+        const float d = __uint_as_float(v_dist[e]);
+        if (v_state[e] == 1 && d < dstop)
+            s_buf[atomicAdd(&s_ncand, 1)] = ((u64)v_dist[e] << 32) | (u32)v_node[e];
+    }
+    __syncthreads();
+    const int nc = s_ncand;
+    int p2 = 1;
+    while (p2 < nc) p2 <<= 1;
+    for (int i = nc + lane; i < p2; i += 64) s_buf[i] = ~0ull;
+    __syncthreads();
+    for (int k = 2; k <= p2; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = lane; i < p2; i += 64) {
+                const int ixj = i ^ j;
+                if (ixj > i) {
+                    const u64 a = s_buf[i], b = s_buf[ixj];
+                    const bool up = (i & k) == 0;
+                    if (up ? (a > b) : (a < b)) {
+                        s_buf[i] = b;
+                        s_buf[ixj] = a;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    const int n = min(keff, nc);
+    if (P.dbg_knn_idx) {
+        for (int j = lane; j < K; j += 64) {
+            const bool ok = j < n;
+            P.dbg_knn_idx[(long long)s * K + j] = ok ? (int)(u32)s_buf[j] : -1;
+            P.dbg_knn_d[(long long)s * K + j] =
+                ok ? __uint_as_float((u32)(s_buf[j] >> 32)) : __int_as_float(0x7f800000);
+        }
+    }
+
+    // ----------------------------------------------------------------- fit
+    const float* M = P.matches;
+    const float xm = M[4LL * s + 0], ym = M[4LL * s + 1];
+    const float um = M[4LL * s + 2] - xm, vm = M[4LL * s + 3] - ym;
+    const float a = P.a;
+    const int wpow = run.la_wpow;
+    float dx[R], dy[R], du[R], dv[R], kk[R], ww[R];
+    float tk = 0.f, tu = 0.f, tv = 0.f, sw = 0.f, sx = 0.f, sy = 0.f;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int j = lane + 64 * r;
+        dx[r] = dy[r] = du[r] = dv[r] = kk[r] = ww[r] = 0.f;
+        if (j < n) {
+            const u64 key = s_buf[j];
+            const int node = (int)(u32)key;
+            const float d = __uint_as_float((u32)(key >> 32));
+            const float x = M[4LL * node + 0], y = M[4LL * node + 1];
+            dx[r] = x - xm;
+            dy[r] = y - ym;
+            du[r] = (M[4LL * node + 2] - x) - um;
+            dv[r] = (M[4LL * node + 3] - y) - vm;
+            kk[r] = expf(-a * d);
+            ww[r] = wpow == 1 ? kk[r] : kk[r] * kk[r];
+            tk += kk[r];
+            tu += kk[r] * du[r];
+            tv += kk[r] * dv[r];
+            sw += ww[r];
+            sx += ww[r] * dx[r];
+            sy += ww[r] * dy[r];
+        }
+    }
+    tk = wave_sum(tk);
+    tu = wave_sum(tu);
+    tv = wave_sum(tv);
+    float out[6] = {0.f, 0.f, 0.f, 0.f, um + tu / tk, vm + tv / tk};
+    bool need64 = false;
+    if (P.mode == 1) {
+        sw = wave_sum(sw);
+        sx = wave_sum(sx);
+        sy = wave_sum(sy);
+        const float mx = sx / sw, my = sy / sw;
+        float sxx = 0.f, sxy = 0.f, syy = 0.f, sxu = 0.f, syu = 0.f, sxv = 0.f, syv = 0.f, su = 0.f, sv = 0.f;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const float ex = dx[r] - mx, ey = dy[r] - my, w = ww[r];
+            sxx += w * ex * ex;
+            sxy += w * ex * ey;
+            syy += w * ey * ey;
+            sxu += w * ex * du[r];
+            syu += w * ey * du[r];
+            sxv += w * ex * dv[r];
+            syv += w * ey * dv[r];
+            su += w * du[r];
+            sv += w * dv[r];
+        }
+        sxx = wave_sum(sxx); sxy = wave_sum(sxy); syy = wave_sum(syy);
+        sxu = wave_sum(sxu); syu = wave_sum(syu); sxv = wave_sum(sxv); syv = wave_sum(syv);
+        su = wave_sum(su); sv = wave_sum(sv);
+        const float det = sxx * syy - sxy * sxy;
+        const float tr = sxx + syy;
+        const float disc = sqrtf((sxx - syy) * (sxx - syy) + 4.0f * sxy * sxy);
+        const float l1 = 0.5f * (tr + disc);
+        const float ratio = l1 > 0.f ? (det / l1) / l1 : 0.f;
+        need64 = run.precision == 1 || n < 3 || !(ratio >= run.fp64_route);
+        if (!need64) {
+            const float b00 = (syy * sxu - sxy * syu) / det, b01 = (sxx * syu - sxy * sxu) / det;
+            const float b10 = (syy * sxv - sxy * syv) / det, b11 = (sxx * syv - sxy * sxv) / det;
+            out[0] = b00; out[1] = b01; out[2] = b10; out[3] = b11;
+            out[4] = um + su / sw - (b00 * mx + b01 * my);
+            out[5] = vm + sv / sw - (b10 * mx + b11 * my);
+        }
+    }
+    if (P.mode == 0 && run.precision == 1) need64 = true;
+    if (need64) {
+        // FP64: re-accumulate from the inputs and solve (or fall back to NW)
+        const double xmd = xm, ymd = ym;
+        const double umd = (double)M[4LL * s + 2] - xmd, vmd = (double)M[4LL * s + 3] - ymd;
+        double Dx[R], Dy[R], Du[R], Dv[R], Dw[R];
+        double Tk = 0, Tu = 0, Tv = 0, Sw = 0, Sx = 0, Sy = 0;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int j = lane + 64 * r;
+            Dx[r] = Dy[r] = Du[r] = Dv[r] = Dw[r] = 0.0;
+            if (j < n) {
+                const u64 key = s_buf[j];
+                const int node = (int)(u32)key;
+                const double d = (double)__uint_as_float((u32)(key >> 32));
+                const double x = M[4LL * node + 0], y = M[4LL * node + 1];
+                Dx[r] = x - xmd;
+                Dy[r] = y - ymd;
+                Du[r] = ((double)M[4LL * node + 2] - x) - umd;
+                Dv[r] = ((double)M[4LL * node + 3] - y) - vmd;
+                const double k = exp(-(double)a * d);
+                Dw[r] = wpow == 1 ? k : k * k;
+                Tk += k; Tu += k * Du[r]; Tv += k * Dv[r];
+                Sw += Dw[r]; Sx += Dw[r] * Dx[r]; Sy += Dw[r] * Dy[r];
+            }
+        }
+        Tk = wave_sum_d(Tk); Tu = wave_sum_d(Tu); Tv = wave_sum_d(Tv);
+        double o[6] = {0, 0, 0, 0, umd + Tu / Tk, vmd + Tv / Tk};
+        bool degenerate = false;
+        if (P.mode == 1) {
+            Sw = wave_sum_d(Sw); Sx = wave_sum_d(Sx); Sy = wave_sum_d(Sy);
+            const double mx = Sx / Sw, my = Sy / Sw;
+            double sxx = 0, sxy = 0, syy = 0, sxu = 0, syu = 0, sxv = 0, syv = 0, su = 0, sv = 0;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const double ex = Dx[r] - mx, ey = Dy[r] - my, w = Dw[r];
+                sxx += w * ex * ex; sxy += w * ex * ey; syy += w * ey * ey;
+                sxu += w * ex * Du[r]; syu += w * ey * Du[r];
+                sxv += w * ex * Dv[r]; syv += w * ey * Dv[r];
+                su += w * Du[r]; sv += w * Dv[r];
+            }
+            sxx = wave_sum_d(sxx); sxy = wave_sum_d(sxy); syy = wave_sum_d(syy);
+            sxu = wave_sum_d(sxu); syu = wave_sum_d(syu); sxv = wave_sum_d(sxv); syv = wave_sum_d(syv);
+            su = wave_sum_d(su); sv = wave_sum_d(sv);
+            // covariance normalised by the weight sum; eigenvalues l1 >= l2
+            const double cxx = sxx / Sw, cxy = sxy / Sw, cyy = syy / Sw;
+            const double tr = cxx + cyy;
+            const double disc = sqrt((cxx - cyy) * (cxx - cyy) + 4.0 * cxy * cxy);
+            const double l1 = 0.5 * (tr + disc), l2 = 0.5 * (tr - disc);
+            degenerate = n < 3 || !(l1 > 0.0) || l2 <= run.deg_tau * l1;
+            if (!degenerate) {
+                const double det = sxx * syy - sxy * sxy;
+                const double b00 = (syy * sxu - sxy * syu) / det, b01 = (sxx * syu - sxy * sxu) / det;
+                const double b10 = (syy * sxv - sxy * syv) / det, b11 = (sxx * syv - sxy * sxv) / det;
+                o[0] = b00; o[1] = b01; o[2] = b10; o[3] = b11;
+                o[4] = umd + su / Sw - (b00 * mx + b01 * my);
+                o[5] = vmd + sv / Sw - (b10 * mx + b11 * my);
+            }
+        }
+        for (int i = 0; i < 6; ++i) out[i] = (float)o[i];
+        if (lane == 0) {
+            if (P.mode == 1) atomicAdd(&P.counters[C_FP64], 1);
+            if (degenerate) atomicAdd(&P.counters[C_DEGENERATE], 1);
+        }
+    }
+    if (lane < 6) {
+        float v = out[0];
+#pragma unroll
+        for (int i = 1; i < 6; ++i) v = lane == i ? out[i] : v;
+        prm[lane] = v;
+    }
+}
+
+hipError_t launch_knn_fit(const PairDev* d_pairs, const RunDev& run, int total_blocks, int kmax,
+                          hipStream_t s) {
+    if (kmax <= 128)
+        hipLaunchKernelGGL((k_knn_fit<512, 128>), dim3(total_blocks), dim3(64), 0, s, d_pairs, run);
+    else
+        hipLaunchKernelGGL((k_knn_fit<1024, 256>), dim3(total_blocks), dim3(64), 0, s, d_pairs, run);
+    return hipGetLastError();
+}
+
+}  // namespace epic

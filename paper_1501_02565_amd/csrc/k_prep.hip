@@ -1,0 +1,76 @@
+// k_prep.hip -- per-call workspace clearing and match seeding.
+//
+// Seeding places every match on the pixel that contains it (matches are
+// pixels, Sec. 3.1 of the paper): pixel (floor(x+0.5), floor(y+0.5)), decided
+// in double precision.  Matches outside the image are dropped; when several
+// matches fall on one pixel, the 64-bit atomic min on the packed key
+// (D = 0, label) keeps the lowest match index.  The tile holding a seed is
+// marked dirty for the geodesic transform.
+#include "epic_dev.h"
+
+namespace epic {
+
+// Clears the per-pair workspace with grid-stride loops; each pair owns
+// init_blocks consecutive blocks of the grid.
+__global__ __launch_bounds__(256) void k_clear(const PairDev* __restrict__ pairs, RunDev run) {
+    const int p = find_pair(run.npairs, (int)blockIdx.x,
+                            [&](int i) { return pairs[i].init_block_base; });
+    const PairDev& P = pairs[p];
+    const int lb = (int)blockIdx.x - P.init_block_base;
+    const long long stride = (long long)P.init_blocks * blockDim.x;
+    const long long i0 = (long long)lb * blockDim.x + threadIdx.x;
+    const long long HW = (long long)P.H * P.W;
+    for (long long i = i0; i < HW; i += stride) P.keys[i] = KEY_INF;
+    for (long long i = i0; i < P.hash_cap; i += stride) {
+        P.hkey[i] = HASH_EMPTY;
+        P.hval[i] = FLOAT_INF_BITS;
+    }
+    for (long long i = i0; i < P.N; i += stride) {
+        P.deg[i] = 0u;
+        P.fill[i] = 0u;
+        P.minin[i] = FLOAT_INF_BITS;
+    }
+    const int ntiles = P.tiles_x * P.tiles_y;
+    for (long long i = i0; i < ntiles; i += stride) run.tile_state[P.tile_base + i] = 0u;
+    if (i0 < C_NCOUNTERS) P.counters[i0] = 0;
+    if (i0 == 0 && P.dbg_n_edges) *P.dbg_n_edges = 0;
+    if (p == 0 && i0 == 0) {
+        *run.pending = 0;
+        *run.error = 0;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_seed(const PairDev* __restrict__ pairs, RunDev run) {
+    const int p = find_pair(run.npairs, (int)blockIdx.x,
+                            [&](int i) { return pairs[i].seed_block_base; });
+    const PairDev& P = pairs[p];
+    const int m = ((int)blockIdx.x - P.seed_block_base) * blockDim.x + threadIdx.x;
+    if (m >= P.N) return;
+    const double x = P.matches[4LL * m + 0];
+    const double y = P.matches[4LL * m + 1];
+    int pix = -1;
+    if (isfinite(x) && isfinite(y)) {
+        const double fx = floor(x + 0.5), fy = floor(y + 0.5);
+        if (fx >= 0.0 && fy >= 0.0 && fx < (double)P.W && fy < (double)P.H) {
+            const int ix = (int)fx, iy = (int)fy;
+            pix = iy * P.W + ix;
+            atomicMin(&P.keys[pix], make_key(0.0f, (u32)m));
+            const int t = P.tile_base + (iy / run.tile_h) * P.tiles_x + ix / run.tile_w;
+            if ((atomicOr(&run.tile_state[t], 1u) & 1u) == 0u) atomicAdd(run.pending, 1);
+        }
+    }
+    if (pix < 0) atomicAdd(&P.counters[C_OUTSIDE], 1);
+    P.seed_pix[m] = pix;
+}
+
+hipError_t launch_clear(const PairDev* d_pairs, const RunDev& run, int total_blocks, hipStream_t s) {
+    hipLaunchKernelGGL(k_clear, dim3(total_blocks), dim3(256), 0, s, d_pairs, run);
+    return hipGetLastError();
+}
+
+hipError_t launch_seed(const PairDev* d_pairs, const RunDev& run, int total_blocks, hipStream_t s) {
+    hipLaunchKernelGGL(k_seed, dim3(total_blocks), dim3(PIX_BLOCK), 0, s, d_pairs, run);
+    return hipGetLastError();
+}
+
+}  // namespace epic

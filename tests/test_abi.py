@@ -1,0 +1,100 @@
+"""CPU-only checks of the C ABI: the HIP library loads, exports every entry
+point that include/epic.h declares, and its host-side logic (validation,
+workspace sizing, error strings) behaves as documented.  No device call."""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "epic.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1501_02565_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.fail("libepic.so is not built (run __graft_entry__.build())")
+    return _lib.load()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(epic_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_declares_the_binding_symbols():
+    from paper_1501_02565_amd import _lib
+    assert set(declared_functions()) == set(_lib.SYMBOLS)
+
+
+def test_every_declared_symbol_is_exported(lib):
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+P = ctypes.c_void_p(0x1000)   # never dereferenced by validation
+
+
+def test_validate(lib):
+    ok = lib.epic_validate(P, 10, 20, P, 5, 3, 1.0, 1, P)
+    assert ok == 0
+    bad = [
+        (None, 10, 20, P, 5, 3, 1.0, 1, P),
+        (P, 10, 20, None, 5, 3, 1.0, 1, P),
+        (P, 10, 20, P, 5, 3, 1.0, 1, None),
+        (P, 0, 20, P, 5, 3, 1.0, 1, P),
+        (P, 10, 0, P, 5, 3, 1.0, 1, P),
+        (P, 10, 20, P, 0, 3, 1.0, 1, P),
+        (P, 10, 20, P, 5, 0, 1.0, 1, P),
+        (P, 10, 20, P, 5, 257, 1.0, 1, P),
+        (P, 10, 20, P, 5, 3, -0.5, 1, P),
+        (P, 10, 20, P, 5, 3, float("nan"), 1, P),
+        (P, 10, 20, P, 5, 3, float("inf"), 1, P),
+        (P, 10, 20, P, 5, 3, 1.0, 2, P),
+        (P, 65536, 32768, P, 5, 3, 1.0, 1, P),
+    ]
+    for args in bad:
+        assert lib.epic_validate(*args) == -1, args
+
+
+def test_interp_rejects_before_touching_the_device(lib):
+    # invalid arguments are rejected on the host, before the context is used
+    assert lib.epic_interp(None, P, 10, 20, P, 5, 3, -1.0, 1, P, None) == -1
+    assert lib.epic_interp(None, P, 10, 20, P, 5, 3, 1.0, 1, P, None) == -1  # no context
+    assert lib.epic_interp_batch(None, None, 1, None) == -1
+    from paper_1501_02565_amd import _lib
+    st = _lib.Stats()
+    assert lib.epic_get_stats(None, 0, ctypes.byref(st)) == -1
+
+
+def test_workspace_bytes(lib):
+    f = lib.epic_workspace_bytes
+    small = f(96, 128, 300, 32, 1, 0)
+    big = f(436, 1024, 8000, 100, 1, 0)
+    assert 0 < small < big
+    assert f(436, 1024, 16000, 100, 1, 0) > big
+    assert f(0, 10, 5, 3, 1, 0) == 0
+    assert f(10, 10, 5, 0, 1, 0) == 0
+    assert f(10, 10, 5, 3, 7, 0) == 0
+    # 8 B/px transform state dominates the image-size term
+    assert f(872, 1024, 8000, 100, 1, 0) - big >= 8 * 436 * 1024
+
+
+def test_strerror(lib):
+    for code in range(-7, 1):
+        s = lib.epic_strerror(code).decode()
+        assert s and s != "unknown status"
+    assert lib.epic_strerror(42).decode() == "unknown status"
+
+
+def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
+    from paper_1501_02565_amd import _lib
+    monkeypatch.setattr(_lib, "LIB_PATH", str(tmp_path / "missing.so"))
+    monkeypatch.setattr(_lib, "_lib", None)
+    with pytest.raises(RuntimeError, match="missing"):
+        _lib.load()

@@ -1,0 +1,163 @@
+"""GPU parity: every stage of the HIP path against the FP64 oracle on the
+same seeded inputs (tolerances in tests/parity.py).  Runs through the C ABI
+(ctypes binding).  Needs an MI355X."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import parity
+from scenes import config_scene, random_case
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_1501_02565_amd as epic
+    c = epic.Context(0)
+    yield c
+    c.close()
+
+
+def _announce(name):
+    print(f"\n[case] {name}", flush=True)
+
+
+@pytest.mark.parametrize("H,W,N,seed", [(45, 70, 40, 0), (130, 100, 200, 1),
+                                        (33, 97, 120, 2), (64, 64, 64, 3),
+                                        (200, 45, 150, 4)])
+def test_random_cases(ctx, H, W, N, seed):
+    """Several tiles with ragged right/bottom tails, sub-pixel matches,
+    matches outside the image and on shared pixels."""
+    sc = random_case(H, W, N, seed=seed, K=12, outside=3, duplicates=4)
+    _announce(sc.name)
+    for mode in (1, 0):
+        res = parity.full_check(ctx, sc, mode=mode)
+        print(res, flush=True)
+
+
+@pytest.mark.parametrize("i,mode", [(1, 1), (2, 1), (3, 1), (3, 0)])
+def test_config_scenes(ctx, i, mode):
+    """The small scene, the 1024x436 large-displacement scene and the
+    1242x375 road scene (NW and LA)."""
+    sc = config_scene(i, mode=mode)
+    _announce(f"{sc.name} mode={mode}")
+    res = parity.full_check(ctx, sc, knn_tol=0.001)
+    print(res, flush=True)
+
+
+@pytest.mark.parametrize("K", [1, 2, 3, 7, 128, 256])
+def test_k_values(ctx, K):
+    sc = random_case(60, 80, 300, seed=11, K=K)
+    _announce(f"{sc.name} K={K}")
+    parity.full_check(ctx, sc, K=K)
+
+
+def test_k_larger_than_matches(ctx):
+    sc = random_case(40, 50, 9, seed=12, K=50)
+    _announce(sc.name)
+    res = parity.full_check(ctx, sc)
+    assert res["stats"]["n_used"] == 9
+
+
+def test_single_and_two_matches(ctx):
+    for N in (1, 2):
+        sc = random_case(37, 41, N, seed=13 + N, K=5)
+        _announce(sc.name)
+        parity.full_check(ctx, sc)
+
+
+def test_no_match_in_image(ctx):
+    sc = random_case(20, 30, 4, seed=15, K=3, outside=4)
+    _announce(sc.name)
+    res = parity.full_check(ctx, sc)
+    assert res["epe"] == 0.0
+
+
+@pytest.mark.parametrize("H,W", [(1, 1), (1, 77), (90, 1), (2, 2)])
+def test_degenerate_shapes(ctx, H, W):
+    rng = np.random.default_rng(H * 100 + W)
+    sc = random_case(max(H, 3), max(W, 3), 3, seed=16, K=3)
+    sc.cost = rng.uniform(0.01, 1, (H, W)).astype(np.float32)
+    N = min(3, H * W)
+    m = np.zeros((N, 4), np.float32)
+    pix = rng.choice(H * W, N, replace=False)
+    m[:, 0], m[:, 1] = pix % W, pix // W
+    m[:, 2:] = m[:, :2] + rng.normal(0, 2, (N, 2))
+    sc.matches = m
+    _announce(f"shape {H}x{W}")
+    parity.full_check(ctx, sc, K=3)
+
+
+def test_a_zero_and_large(ctx):
+    sc = random_case(50, 60, 80, seed=17, K=10)
+    for a in (0.0, 5.0):
+        _announce(f"{sc.name} a={a}")
+        parity.full_check(ctx, sc, a=a)
+
+
+def test_global_affine_recovered(ctx):
+    """A single global affine motion is reproduced at every pixel by LA,
+    for any cost map (exactly in the oracle; to FP32 rounding here)."""
+    import torch
+    H, W, N = 96, 128, 300
+    rng = np.random.default_rng(18)
+    A = np.array([[1.0625, -0.03125], [0.046875, 0.9375]])
+    t = np.array([2.25, -3.5])
+    sc = random_case(H, W, N, seed=18, K=32)
+    pix = rng.choice(H * W, N, replace=False)
+    m = np.zeros((N, 4), np.float32)
+    m[:, 0], m[:, 1] = pix % W, pix // W
+    m[:, 2:] = m[:, :2].astype(np.float64) @ A.T + t
+    t_cost = torch.from_numpy(sc.cost).cuda()
+    flow = ctx.interp(t_cost, torch.from_numpy(m).cuda(), 32, 1.0, 1).cpu().numpy()
+    ys, xs = np.mgrid[0:H, 0:W]
+    np.testing.assert_allclose(flow[..., 0], (A[0, 0] - 1) * xs + A[0, 1] * ys + t[0], atol=2e-3)
+    np.testing.assert_allclose(flow[..., 1], A[1, 0] * xs + (A[1, 1] - 1) * ys + t[1], atol=2e-3)
+
+
+def test_label_invariance_under_cost_scaling(ctx):
+    """C -> 4 C keeps every label and scales D exactly (powers of two)."""
+    sc = random_case(100, 120, 150, seed=19, K=10)
+    g1 = parity.gpu_stages(ctx, sc)
+    sc2 = random_case(100, 120, 150, seed=19, K=10)
+    sc2.cost = sc2.cost * np.float32(4.0)
+    g2 = parity.gpu_stages(ctx, sc2, a=sc.a / 4.0)
+    np.testing.assert_array_equal(g1["L"], g2["L"])
+    np.testing.assert_array_equal(g1["D"] * 4, g2["D"])
+    np.testing.assert_array_equal(g1["flow"], g2["flow"])
+
+
+def test_repeatable(ctx):
+    """Two runs give bitwise identical flows."""
+    import torch
+    sc = config_scene(1)
+    c = torch.from_numpy(sc.cost).cuda()
+    m = torch.from_numpy(sc.matches).cuda()
+    f1 = ctx.interp(c, m, sc.K, sc.a, sc.mode).clone()
+    f2 = ctx.interp(c, m, sc.K, sc.a, sc.mode)
+    torch.cuda.synchronize()
+    assert torch.equal(f1, f2)
+
+
+@pytest.mark.parametrize("opts", [dict(connectivity=4), dict(la_weight_power=1),
+                                  dict(tile=(64, 16)), dict(tile=(64, 32))])
+def test_options(opts):
+    import paper_1501_02565_amd as epic
+    sc = random_case(150, 170, 250, seed=20, K=16)
+    conn = opts.get("connectivity", 8)
+    wpow = opts.get("la_weight_power", 2)
+    _announce(f"{sc.name} {opts}")
+    with epic.Context(0, epic.workspace_bytes(sc.H, sc.W, sc.N, sc.K), **opts) as c:
+        parity.full_check(c, sc, conn=conn, wpow=wpow)
+
+
+def test_workspace_too_small():
+    import torch
+    import paper_1501_02565_amd as epic
+    sc = random_case(64, 64, 50, seed=21, K=8)
+    with epic.Context(0, epic.workspace_bytes(32, 32, 10, 8)) as c:
+        with pytest.raises(epic.EpicError) as ei:
+            c.interp(torch.from_numpy(sc.cost).cuda(), torch.from_numpy(sc.matches).cuda(), 8, 1.0, 1)
+        assert ei.value.status == epic.ERR_WORKSPACE
