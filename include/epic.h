@@ -82,6 +82,11 @@ typedef struct epic_options {
                                back to NW (decided in FP64); default 1e-9      */
     int   tile_w, tile_h;   /* geodesic-transform tile (0 = default 32 x 32;
                                supported: 32x32, 64x16, 64x32)                 */
+    int   geo_passes;       /* bulk-synchronous passes of the geodesic
+                               transform launched per call (0 = default 16,
+                               at most 64); a single-workgroup finisher
+                               completes the transform if they do not reach
+                               the fixpoint, so this only affects speed        */
 } epic_options;
 
 typedef struct epic_ctx epic_ctx;
@@ -134,6 +139,18 @@ typedef struct epic_request {
  * pairs' workspace needs must fit the context workspace. */
 int epic_interp_batch(epic_ctx* ctx, const epic_request* reqs, int n, void* stream);
 
+/* Captured launch sequence of one batch (a HIP graph).  The graph is bound
+ * to the buffers of `reqs` (their contents may change between launches) and
+ * to the context's workspace; replaying it runs exactly the work that
+ * epic_interp_batch(ctx, reqs, n, ...) enqueues, with one graph launch.
+ * Capture happens on a private stream and does not run any work.  The
+ * context must outlive the graph, and launches of graphs and other calls
+ * on one context must be ordered by the caller (same stream, or events). */
+typedef struct epic_graph epic_graph;
+epic_graph* epic_graph_capture(epic_ctx* ctx, const epic_request* reqs, int n);
+int epic_graph_launch(epic_graph* g, void* stream);
+void epic_graph_destroy(epic_graph* g);
+
 /* Per-call device-side counters, valid once the stream of the last call
  * has been synchronised (this call synchronises that stream itself). */
 typedef struct epic_stats {
@@ -166,6 +183,20 @@ int epic_debug_stages(epic_ctx* ctx, const float* cost, int H, int W,
                       float* edge_w, int max_edges, int* n_edges,
                       int* knn_idx, float* knn_d, float* params, float* flow,
                       void* stream);
+
+/* Stage timing (instrumentation).  While enabled, every call records HIP
+ * events between its stages on the call's stream (a ring of the last 64
+ * calls).  epic_stage_times synchronises those calls and writes, for each
+ * stage in launch order, the mean elapsed milliseconds over the last
+ * `calls` profiled calls (at most 64) into ms[0..n_stages): 0 clear,
+ * 1 seed, 2 geodesic transform, 3 graph emit, 4 CSR scan, 5 CSR scatter,
+ * 6 K-NN + fit, 7 assignment.  Returns the number of stages written, or a
+ * negative epic_status. */
+int epic_profile(epic_ctx* ctx, int enable);
+int epic_stage_times(epic_ctx* ctx, float* ms, int n_stages, int calls);
+
+/* Name of stage i of epic_stage_times ("" when out of range). */
+const char* epic_stage_name(int i);
 
 /* Human-readable text of an epic_status. */
 const char* epic_strerror(int status);

@@ -57,7 +57,8 @@ class Context:
     def __init__(self, device: int = 0, workspace: int | None = None, *,
                  connectivity: int = 8, la_weight_power: int = 2,
                  precision: int = 0, fp64_route: float = 1e-3,
-                 degenerate_tau: float = 1e-9, tile: tuple[int, int] = (32, 32)):
+                 degenerate_tau: float = 1e-9, tile: tuple[int, int] = (32, 32),
+                 passes: int = 16):
         torch = _torch()
         L = _lib.load()
         self.device = int(device)
@@ -65,7 +66,8 @@ class Context:
             workspace = workspace_bytes(1080, 2048, 40000, 256)
         self.workspace = int(workspace)
         self.options = _lib.Options(connectivity, la_weight_power, precision,
-                                    fp64_route, degenerate_tau, tile[0], tile[1])
+                                    fp64_route, degenerate_tau, tile[0], tile[1],
+                                    passes)
         torch.cuda.init()
         with torch.cuda.device(self.device):
             self._ctx = L.epic_create(self.device, self.workspace,
@@ -115,6 +117,14 @@ class Context:
     def interp_batch(self, problems, outs=None, stream=None):
         """problems: list of (cost, matches, K, a, mode).  One fused launch
         sequence for all of them; returns the list of flows."""
+        reqs, flows = self._requests(problems, outs)
+        rc = _lib.load().epic_interp_batch(self._ctx, reqs, len(problems),
+                                           _stream_handle(stream))
+        if rc != OK:
+            raise EpicError(rc, "epic_interp_batch")
+        return flows
+
+    def _requests(self, problems, outs):
         torch = _torch()
         n = len(problems)
         reqs = (_lib.Request * n)()
@@ -130,10 +140,17 @@ class Context:
             reqs[i] = _lib.Request(cost.data_ptr(), H, W, matches.data_ptr(),
                                    matches.shape[0], int(K), float(a), int(mode),
                                    f.data_ptr())
-        rc = _lib.load().epic_interp_batch(self._ctx, reqs, n, _stream_handle(stream))
-        if rc != OK:
-            raise EpicError(rc, "epic_interp_batch")
-        return flows
+        return reqs, flows
+
+    def capture(self, problems, outs=None):
+        """Captures the launch sequence of interp_batch(problems) as a HIP
+        graph bound to these tensors; returns a Graph whose launch() replays
+        it (the tensors' contents may change between launches)."""
+        reqs, flows = self._requests(problems, outs)
+        g = _lib.load().epic_graph_capture(self._ctx, reqs, len(problems))
+        if not g:
+            raise RuntimeError("epic_graph_capture failed")
+        return Graph(self, g, flows, problems)
 
     def debug_stages(self, cost, matches, K: int, a: float, mode: int = LA,
                      max_edges: int | None = None, stream=None):
@@ -170,6 +187,22 @@ class Context:
         return dict(D=D, L=L, em=em[:E], en=en[:E], ew=ew[:E], knn_idx=ki,
                     knn_d=kd, params=P, flow=flow, stats=st)
 
+    def profile(self, enable: bool = True) -> None:
+        """Turns per-stage HIP-event timing of every call on or off."""
+        rc = _lib.load().epic_profile(self._ctx, int(bool(enable)))
+        if rc != OK:
+            raise EpicError(rc, "epic_profile")
+
+    def stage_times(self, calls: int = 64) -> dict:
+        """Mean milliseconds per stage over the last `calls` profiled calls
+        (synchronises them)."""
+        L = _lib.load()
+        buf = (ctypes.c_float * 16)()
+        n = L.epic_stage_times(self._ctx, buf, 16, int(calls))
+        if n < 0:
+            raise EpicError(n, "epic_stage_times")
+        return {L.epic_stage_name(i).decode(): float(buf[i]) for i in range(n)}
+
     def stats(self, pair: int = 0) -> dict:
         """Device counters of the last call (synchronises its stream)."""
         s = _lib.Stats()
@@ -177,3 +210,30 @@ class Context:
         if rc != OK:
             raise EpicError(rc, "epic_get_stats")
         return {k: getattr(s, k) for k, _ in _lib.Stats._fields_}
+
+
+class Graph:
+    """A captured batch (see Context.capture)."""
+
+    def __init__(self, ctx: Context, handle, flows, problems):
+        self.ctx = ctx
+        self._g = handle
+        self.flows = flows
+        self.problems = problems      # keeps the bound tensors alive
+
+    def launch(self, stream=None):
+        rc = _lib.load().epic_graph_launch(self._g, _stream_handle(stream))
+        if rc != OK:
+            raise EpicError(rc, "epic_graph_launch")
+        return self.flows
+
+    def close(self):
+        if getattr(self, "_g", None):
+            _lib.load().epic_graph_destroy(self._g)
+            self._g = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

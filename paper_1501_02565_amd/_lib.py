@@ -18,7 +18,9 @@ NW, LA = 0, 1
 
 SYMBOLS = ["epic_create", "epic_destroy", "epic_workspace_bytes", "epic_interp",
            "epic_interp_batch", "epic_get_stats", "epic_debug_stages",
-           "epic_strerror", "epic_last_error", "epic_validate"]
+           "epic_strerror", "epic_last_error", "epic_validate", "epic_profile",
+           "epic_stage_times", "epic_stage_name", "epic_graph_capture",
+           "epic_graph_launch", "epic_graph_destroy"]
 
 
 class Options(ctypes.Structure):
@@ -28,7 +30,8 @@ class Options(ctypes.Structure):
                 ("fp64_route", ctypes.c_float),
                 ("degenerate_tau", ctypes.c_double),
                 ("tile_w", ctypes.c_int),
-                ("tile_h", ctypes.c_int)]
+                ("tile_h", ctypes.c_int),
+                ("geo_passes", ctypes.c_int)]
 
 
 class Request(ctypes.Structure):
@@ -83,6 +86,18 @@ def load():
     L.epic_last_error.restype = ctypes.c_char_p
     L.epic_validate.argtypes = [P, i32, i32, P, i32, i32, f32, i32, P]
     L.epic_validate.restype = i32
+    L.epic_profile.argtypes = [P, i32]
+    L.epic_profile.restype = i32
+    L.epic_stage_times.argtypes = [P, ctypes.POINTER(ctypes.c_float), i32, i32]
+    L.epic_stage_times.restype = i32
+    L.epic_stage_name.argtypes = [i32]
+    L.epic_stage_name.restype = ctypes.c_char_p
+    L.epic_graph_capture.argtypes = [P, ctypes.POINTER(Request), i32]
+    L.epic_graph_capture.restype = P
+    L.epic_graph_launch.argtypes = [P, P]
+    L.epic_graph_launch.restype = i32
+    L.epic_graph_destroy.argtypes = [P]
+    L.epic_graph_destroy.restype = None
     _lib = L
     return L
 

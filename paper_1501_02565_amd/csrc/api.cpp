@@ -24,6 +24,10 @@ constexpr int kMaxPairs = 1024;      // pairs per call
 constexpr int kRing = 4;             // descriptor upload slots
 constexpr size_t kAlign = 256;
 constexpr int kMaxK = 256;
+constexpr int kStages = 8;
+constexpr int kProfRing = 64;
+const char* const kStageNames[kStages] = {"clear", "seed", "geodesic", "graph_emit",
+                                          "csr_scan", "csr_scatter", "knn_fit", "assign"};
 
 thread_local std::string g_last_error;
 
@@ -80,14 +84,19 @@ struct epic_ctx {
     hipEvent_t ring_ev[kRing]{};
     bool ring_used[kRing]{};
     int ring_next = 0;
-    long long wall_rate = 100000000;    // wall_clock64 ticks per second
-    int geo_workers = 0;
     // last call
     hipStream_t last_stream = nullptr;
     int last_npairs = 0;
     std::vector<int*> last_counters;
-    int* g_pending = nullptr;
+    int* g_any = nullptr;
     int* g_error = nullptr;
+    int passes = 16;                    // geodesic passes launched per call
+    // stage timing
+    bool prof = false;
+    hipEvent_t prof_ev[kProfRing][kStages + 1]{};
+    bool prof_ok[kProfRing]{};
+    int prof_next = 0;
+    int prof_count = 0;
 };
 
 extern "C" {
@@ -122,8 +131,9 @@ size_t epic_workspace_bytes(int H, int W, int N, int K, int mode, int precision)
     if (H < 1 || W < 1 || N < 1 || K < 1 || K > kMaxK || (mode != 0 && mode != 1) ||
         (precision != 0 && precision != 1) || (long long)H * W >= (1LL << 31))
         return 0;
-    // the smallest tiling gives the largest tile-state array
-    return kFixed + align_up(4 * tiles_of(H, W, Tiling{32, 16})) + pair_bytes(H, W, N);
+    // the smallest tiling gives the largest tile-state array and queue ring
+    const size_t t = tiles_of(H, W, Tiling{32, 16});
+    return kFixed + 2 * align_up(4 * t) + pair_bytes(H, W, N);
 }
 
 epic_ctx* epic_create(int device, size_t workspace_bytes, const epic_options* opts) {
@@ -143,6 +153,7 @@ epic_ctx* epic_create(int device, size_t workspace_bytes, const epic_options* op
     o.degenerate_tau = 1e-9;
     o.tile_w = 32;
     o.tile_h = 32;
+    o.geo_passes = 16;
     if (opts) {
         o = *opts;
         if (o.connectivity != 4) o.connectivity = 8;
@@ -153,7 +164,10 @@ epic_ctx* epic_create(int device, size_t workspace_bytes, const epic_options* op
         const Tiling t = tiling_from(o);
         o.tile_w = t.tw;
         o.tile_h = t.th;
+        if (o.geo_passes <= 0) o.geo_passes = 16;
+        if (o.geo_passes > kMaxPasses - 1) o.geo_passes = kMaxPasses - 1;
     }
+    c->passes = o.geo_passes;
     c->opt = o;
     auto fail = [&](const char* what) {
         g_last_error = what;
@@ -169,13 +183,8 @@ epic_ctx* epic_create(int device, size_t workspace_bytes, const epic_options* op
     for (int i = 0; i < kRing; ++i)
         if (hipEventCreateWithFlags(&c->ring_ev[i], hipEventDisableTiming) != hipSuccess)
             return fail("event creation failed");
-    int rate_khz = 0;
-    if (hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, device) == hipSuccess && rate_khz > 0)
-        c->wall_rate = (long long)rate_khz * 1000;
-    c->geo_workers = geodesic_max_workers(o.tile_w, o.tile_h);
-    if (c->geo_workers <= 0) return fail("occupancy query failed");
-    c->g_pending = reinterpret_cast<int*>(c->ws);
-    c->g_error = reinterpret_cast<int*>(c->ws) + 64;
+    c->g_error = reinterpret_cast<int*>(c->ws);
+    c->g_any = reinterpret_cast<int*>(c->ws) + 256;         // kMaxPasses ints
     return c;
 }
 
@@ -187,6 +196,9 @@ void epic_destroy(epic_ctx* c) {
             if (c->ring_used[i]) hipEventSynchronize(c->ring_ev[i]);
             hipEventDestroy(c->ring_ev[i]);
         }
+    for (int r = 0; r < kProfRing; ++r)
+        for (int i = 0; i <= kStages; ++i)
+            if (c->prof_ev[r][i]) hipEventDestroy(c->prof_ev[r][i]);
     if (c->h_desc) hipHostFree(c->h_desc);
     if (c->ws) hipFree(c->ws);
     delete c;
@@ -209,7 +221,15 @@ struct DebugOut {
     float* params = nullptr;
 };
 
-int run_pairs(epic_ctx* c, const epic_request* reqs, int n, hipStream_t stream, const DebugOut* dbg) {
+// Where a call's descriptor table lives: the context's upload ring (default)
+// or buffers owned by a captured graph.
+struct DescTarget {
+    PairDev* host;      // pinned
+    PairDev* dev;
+};
+
+int run_pairs(epic_ctx* c, const epic_request* reqs, int n, hipStream_t stream, const DebugOut* dbg,
+              const DescTarget* tgt = nullptr) {
     if (!c || !reqs || n < 1 || n > kMaxPairs) return EPIC_ERR_ARG;
     for (int i = 0; i < n; ++i) {
         const epic_request& r = reqs[i];
@@ -221,16 +241,24 @@ int run_pairs(epic_ctx* c, const epic_request* reqs, int n, hipStream_t stream, 
     // ---- carve the workspace
     size_t total_tiles = 0, need = kFixed;
     for (int i = 0; i < n; ++i) total_tiles += tiles_of(reqs[i].H, reqs[i].W, tl);
-    need += align_up(4 * total_tiles);
+    need += 2 * align_up(4 * total_tiles);
     for (int i = 0; i < n; ++i) need += pair_bytes(reqs[i].H, reqs[i].W, reqs[i].N);
     if (need > c->ws_bytes) return EPIC_ERR_WORKSPACE;
     if (hipSetDevice(c->device) != hipSuccess) return EPIC_ERR_HIP;
 
-    const int slot = c->ring_next;
-    c->ring_next = (c->ring_next + 1) % kRing;
-    if (c->ring_used[slot] && hipEventSynchronize(c->ring_ev[slot]) != hipSuccess) return EPIC_ERR_HIP;
-    PairDev* hd = c->h_desc + (size_t)slot * kMaxPairs;
-    PairDev* dd = reinterpret_cast<PairDev*>(c->ws + 4096) + (size_t)slot * kMaxPairs;
+    int slot = -1;
+    PairDev* hd = nullptr;
+    PairDev* dd = nullptr;
+    if (tgt) {
+        hd = tgt->host;
+        dd = tgt->dev;
+    } else {
+        slot = c->ring_next;
+        c->ring_next = (c->ring_next + 1) % kRing;
+        if (c->ring_used[slot] && hipEventSynchronize(c->ring_ev[slot]) != hipSuccess) return EPIC_ERR_HIP;
+        hd = c->h_desc + (size_t)slot * kMaxPairs;
+        dd = reinterpret_cast<PairDev*>(c->ws + 4096) + (size_t)slot * kMaxPairs;
+    }
 
     char* cur = c->ws + kFixed;
     auto take = [&](size_t bytes) {
@@ -238,7 +266,8 @@ int run_pairs(epic_ctx* c, const epic_request* reqs, int n, hipStream_t stream, 
         cur += align_up(bytes);
         return p;
     };
-    u32* tile_state = reinterpret_cast<u32*>(take(4 * total_tiles));
+    u32* dirty0 = reinterpret_cast<u32*>(take(4 * total_tiles));
+    u32* dirty1 = reinterpret_cast<u32*>(take(4 * total_tiles));
     int tile_base = 0, pix_blocks = 0, seed_blocks = 0, src_blocks = 0, slot_blocks = 0, init_blocks = 0;
     int kmax = 1;
     c->last_counters.assign(n, nullptr);
@@ -305,8 +334,9 @@ int run_pairs(epic_ctx* c, const epic_request* reqs, int n, hipStream_t stream, 
     if (dbg && dbg->knn_idx && !dbg->knn_d) return EPIC_ERR_ARG;
 
     RunDev run{};
-    run.tile_state = tile_state;
-    run.pending = c->g_pending;
+    run.dirty[0] = dirty0;
+    run.dirty[1] = dirty1;
+    run.any = c->g_any;
     run.error = c->g_error;
     run.total_tiles = tile_base;
     run.npairs = n;
@@ -317,24 +347,47 @@ int run_pairs(epic_ctx* c, const epic_request* reqs, int n, hipStream_t stream, 
     run.precision = c->opt.precision;
     run.fp64_route = c->opt.fp64_route;
     run.deg_tau = c->opt.degenerate_tau;
-    run.spin_ticks = 2 * c->wall_rate;   // two seconds without progress
 
     hipError_t e = hipMemcpyAsync(dd, hd, sizeof(PairDev) * n, hipMemcpyHostToDevice, stream);
-    if (e == hipSuccess) e = hipEventRecord(c->ring_ev[slot], stream);
+    if (e == hipSuccess && slot >= 0) e = hipEventRecord(c->ring_ev[slot], stream);
     if (e != hipSuccess) return EPIC_ERR_HIP;
-    c->ring_used[slot] = true;
+    if (slot >= 0) c->ring_used[slot] = true;
 
-    const int workers = std::max(1, std::min(c->geo_workers, tile_base));
+    hipEvent_t* ev = nullptr;
+    if (c->prof && !tgt) {
+        const int r = c->prof_next;
+        c->prof_next = (c->prof_next + 1) % kProfRing;
+        ev = c->prof_ev[r];
+        c->prof_ok[r] = false;
+        for (int i = 0; i <= kStages && e == hipSuccess; ++i)
+            if (!ev[i]) e = hipEventCreate(&ev[i]);
+        if (e == hipSuccess) e = hipEventRecord(ev[0], stream);
+        if (e == hipSuccess) {
+            c->prof_ok[r] = true;
+            c->prof_count = std::min(kProfRing, c->prof_count + 1);
+        }
+    }
+    auto mark = [&](int stage) {
+        if (ev && e == hipSuccess) e = hipEventRecord(ev[stage + 1], stream);
+    };
     if (e == hipSuccess) e = launch_clear(dd, run, init_blocks, stream);
+    mark(0);
     if (e == hipSuccess) e = launch_seed(dd, run, seed_blocks, stream);
-    if (e == hipSuccess) e = launch_geodesic(dd, run, tl.tw, tl.th, workers, stream);
+    mark(1);
+    if (e == hipSuccess) e = launch_geodesic(dd, run, tl.tw, tl.th, c->passes, stream);
+    mark(2);
     if (e == hipSuccess) e = launch_graph_emit(dd, run, pix_blocks, stream);
+    mark(3);
     if (e == hipSuccess) e = launch_csr_scan(dd, run, stream);
+    mark(4);
     if (e == hipSuccess) e = launch_csr_scatter(dd, run, slot_blocks, stream);
+    mark(5);
     if (e == hipSuccess) e = launch_knn_fit(dd, run, src_blocks, kmax, stream);
+    mark(6);
     bool any_flow = false;
     for (int i = 0; i < n; ++i) any_flow |= reqs[i].flow != nullptr;
     if (e == hipSuccess && any_flow) e = launch_assign(dd, run, pix_blocks, stream);
+    mark(7);
     if (e == hipSuccess && dbg && (dbg->D || dbg->L)) e = launch_unpack(dd, run, pix_blocks, dbg->D, dbg->L, stream);
     if (e == hipSuccess && dbg && dbg->params)
         e = hipMemcpyAsync(dbg->params, hd[0].params, 24 * (size_t)reqs[0].N, hipMemcpyDeviceToDevice, stream);
@@ -381,6 +434,100 @@ int epic_debug_stages(epic_ctx* ctx, const float* cost, int H, int W, const floa
     epic_request r{cost, H, W, matches, N, K, a, mode, flow};
     return run_pairs(ctx, &r, 1, (hipStream_t)stream, &d);
 }
+
+struct epic_graph {
+    epic_ctx* ctx = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    PairDev* h_desc = nullptr;
+    PairDev* d_desc = nullptr;
+    int n = 0;
+    std::vector<int*> counters;
+};
+
+void epic_graph_destroy(epic_graph* g) {
+    if (!g) return;
+    if (g->ctx) hipSetDevice(g->ctx->device);
+    if (g->exec) hipGraphExecDestroy(g->exec);
+    if (g->graph) hipGraphDestroy(g->graph);
+    if (g->d_desc) hipFree(g->d_desc);
+    if (g->h_desc) hipHostFree(g->h_desc);
+    delete g;
+}
+
+epic_graph* epic_graph_capture(epic_ctx* ctx, const epic_request* reqs, int n) {
+    if (!ctx || !reqs || n < 1 || n > kMaxPairs) return nullptr;
+    if (hipSetDevice(ctx->device) != hipSuccess) return nullptr;
+    epic_graph* g = new epic_graph();
+    g->ctx = ctx;
+    g->n = n;
+    hipStream_t s = nullptr;
+    bool ok = hipHostMalloc((void**)&g->h_desc, sizeof(PairDev) * n, hipHostMallocDefault) == hipSuccess &&
+              hipMalloc((void**)&g->d_desc, sizeof(PairDev) * n) == hipSuccess &&
+              hipStreamCreateWithFlags(&s, hipStreamNonBlocking) == hipSuccess;
+    if (ok) ok = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) == hipSuccess;
+    if (ok) {
+        DescTarget tgt{g->h_desc, g->d_desc};
+        const int rc = run_pairs(ctx, reqs, n, s, nullptr, &tgt);
+        const hipError_t e = hipStreamEndCapture(s, &g->graph);
+        ok = rc == EPIC_OK && e == hipSuccess && g->graph;
+    }
+    if (ok) ok = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0) == hipSuccess;
+    if (s) hipStreamDestroy(s);
+    if (!ok) {
+        epic_graph_destroy(g);
+        return nullptr;
+    }
+    g->counters = ctx->last_counters;
+    return g;
+}
+
+int epic_graph_launch(epic_graph* g, void* stream) {
+    if (!g || !g->exec) return EPIC_ERR_ARG;
+    epic_ctx* c = g->ctx;
+    if (hipSetDevice(c->device) != hipSuccess) return EPIC_ERR_HIP;
+    if (hipGraphLaunch(g->exec, (hipStream_t)stream) != hipSuccess) return EPIC_ERR_HIP;
+    c->last_counters = g->counters;
+    c->last_npairs = g->n;
+    c->last_stream = (hipStream_t)stream;
+    return EPIC_OK;
+}
+
+int epic_profile(epic_ctx* ctx, int enable) {
+    if (!ctx) return EPIC_ERR_ARG;
+    ctx->prof = enable != 0;
+    if (!ctx->prof) {
+        ctx->prof_count = 0;
+        for (int r = 0; r < kProfRing; ++r) ctx->prof_ok[r] = false;
+    }
+    return EPIC_OK;
+}
+
+int epic_stage_times(epic_ctx* ctx, float* ms, int n_stages, int calls) {
+    if (!ctx || !ms || n_stages < 1 || calls < 1) return EPIC_ERR_ARG;
+    if (hipSetDevice(ctx->device) != hipSuccess) return EPIC_ERR_HIP;
+    const int n = std::min(n_stages, kStages);
+    const int use = std::min(calls, ctx->prof_count);
+    for (int i = 0; i < n; ++i) ms[i] = 0.0f;
+    if (use == 0) return n;
+    int got = 0;
+    for (int k = 1; k <= kProfRing && got < use; ++k) {
+        const int r = (ctx->prof_next - k + kProfRing) % kProfRing;
+        if (!ctx->prof_ok[r]) continue;
+        if (hipEventSynchronize(ctx->prof_ev[r][kStages]) != hipSuccess) return EPIC_ERR_HIP;
+        for (int i = 0; i < n; ++i) {
+            float t = 0.0f;
+            if (hipEventElapsedTime(&t, ctx->prof_ev[r][i], ctx->prof_ev[r][i + 1]) != hipSuccess)
+                return EPIC_ERR_HIP;
+            ms[i] += t;
+        }
+        ++got;
+    }
+    for (int i = 0; i < n; ++i) ms[i] /= (float)got;
+    return n;
+}
+
+const char* epic_stage_name(int i) { return (i >= 0 && i < kStages) ? kStageNames[i] : ""; }
 
 int epic_get_stats(epic_ctx* ctx, int pair, epic_stats* out) {
     if (!ctx || !out || pair < 0 || pair >= ctx->last_npairs) return EPIC_ERR_ARG;

@@ -88,8 +88,8 @@ struct PairDev {
 
 // Globals of one launch sequence (shared by all pairs of a batch).
 struct RunDev {
-    u32* tile_state;        // total tiles
-    int* pending;           // dirty + busy tiles
+    u32* dirty[2];          // per tile, by pass parity: tile needs a visit
+    int* any;               // per pass: some tile border changed (kMaxPasses)
     int* error;             // global error word
     int total_tiles;
     int npairs;
@@ -99,8 +99,9 @@ struct RunDev {
     int precision;          // 0 or 1
     float fp64_route;
     double deg_tau;
-    long long spin_ticks;   // wall-clock bound of the transform's idle wait
 };
+
+constexpr int kMaxPasses = 64;   // passes launched per call, at most
 
 // Binary search: the pair whose base <= idx (bases ascending).
 template <typename F>
@@ -122,8 +123,7 @@ constexpr int SLOT_BLOCK = 256;     // hash slots per block
 hipError_t launch_clear(const PairDev* d_pairs, const RunDev& run, int total_blocks, hipStream_t s);
 hipError_t launch_seed(const PairDev* d_pairs, const RunDev& run, int total_blocks, hipStream_t s);
 hipError_t launch_geodesic(const PairDev* d_pairs, const RunDev& run, int tile_w, int tile_h,
-                           int workers, hipStream_t s);
-int geodesic_max_workers(int tile_w, int tile_h);
+                           int passes, hipStream_t s);
 hipError_t launch_graph_emit(const PairDev* d_pairs, const RunDev& run, int total_blocks, hipStream_t s);
 hipError_t launch_csr_scan(const PairDev* d_pairs, const RunDev& run, hipStream_t s);
 hipError_t launch_csr_scatter(const PairDev* d_pairs, const RunDev& run, int total_blocks, hipStream_t s);

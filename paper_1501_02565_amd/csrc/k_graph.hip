@@ -35,62 +35,93 @@ __device__ __forceinline__ u32 hash_slot(u64 key, int shift) {
 }
 }  // namespace
 
+namespace {
+// Inserts (key, weight) into the pair's global hash with an atomic min on
+// the weight; the first insertion of a key raises both endpoints' degree.
+__device__ __forceinline__ void global_insert(const PairDev& P, u64 hk, u32 wb) {
+    const u32 mask = (u32)P.hash_cap - 1u;
+    u32 h = hash_slot(hk, P.hash_shift);
+    for (int probe = 0; probe < P.hash_cap; ++probe) {
+        u64 cur = P.hkey[h];
+        if (cur == HASH_EMPTY) {
+            const u64 prev = atomicCAS(&P.hkey[h], HASH_EMPTY, hk);
+            if (prev == HASH_EMPTY) {
+                atomicAdd(&P.deg[(u32)(hk >> 32)], 1u);
+                atomicAdd(&P.deg[(u32)hk], 1u);
+                atomicMin(&P.hval[h], wb);
+                return;
+            }
+            cur = prev;
+        }
+        if (cur == hk) {
+            atomicMin(&P.hval[h], wb);
+            return;
+        }
+        h = (h + 1u) & mask;
+    }
+    atomicOr(&P.counters[C_OVERFLOW], 1);
+}
+}  // namespace
+
+// Each block handles PIX_BLOCK consecutive pixels.  Candidates are first
+// reduced in a block-local LDS hash (adjacent pixels mostly share their pair
+// of cells), then each distinct edge goes to the global hash once per block.
 template <int CONN>
 __global__ __launch_bounds__(PIX_BLOCK) void k_graph_emit(const PairDev* __restrict__ pairs, RunDev run) {
+    constexpr int LCAP = 4 * PIX_BLOCK;               // >= candidates per block
+    __shared__ u64 lkey[LCAP];
+    __shared__ u32 lval[LCAP];
     const int p = find_pair(run.npairs, (int)blockIdx.x, [&](int i) { return pairs[i].pix_block_base; });
     const PairDev& P = pairs[p];
+    for (int i = threadIdx.x; i < LCAP; i += PIX_BLOCK) {
+        lkey[i] = HASH_EMPTY;
+        lval[i] = FLOAT_INF_BITS;
+    }
+    __syncthreads();
     const long long i = (long long)((int)blockIdx.x - P.pix_block_base) * PIX_BLOCK + threadIdx.x;
     const int W = P.W, H = P.H;
-    if (i >= (long long)W * H) return;
-    const int x = (int)(i % W), y = (int)(i / W);
-    const u64 kp = P.keys[i];
-    const u32 lp = key_label(kp);
-    if (lp == NO_LABEL) return;
-    const float dp = key_dist(kp);
-    const float cp = P.cost[i];
-    // forward half-neighbourhood: (1,0), (0,1), (1,1), (-1,1)
-    constexpr int HX[4] = {1, 0, 1, -1};
-    constexpr int HY[4] = {0, 1, 1, 1};
-    const u32 mask = (u32)P.hash_cap - 1u;
+    if (i < (long long)W * H) {
+        const int x = (int)(i % W), y = (int)(i / W);
+        const u64 kp = P.keys[i];
+        const u32 lp = key_label(kp);
+        if (lp != NO_LABEL) {
+            const float dp = key_dist(kp);
+            const float cp = P.cost[i];
+            // forward half-neighbourhood: (1,0), (0,1), (1,1), (-1,1)
+            constexpr int HX[4] = {1, 0, 1, -1};
+            constexpr int HY[4] = {0, 1, 1, 1};
 #pragma unroll
-    for (int k = 0; k < (CONN == 8 ? 4 : 2); ++k) {
-        const int qx = x + HX[k], qy = y + HY[k];
-        if (qx < 0 || qx >= W || qy >= H) continue;
-        const long long qi = (long long)qy * W + qx;
-        const u64 kq = P.keys[qi];
-        const u32 lq = key_label(kq);
-        if (lq == lp || lq == NO_LABEL) continue;
-        const float len = (k < 2) ? 1.0f : 1.41421356237309515f;
-        const float w = len * (0.5f * (cp + P.cost[qi]));
-        const float cand = (dp + w) + key_dist(kq);
-        const u32 m = min(lp, lq), n = max(lp, lq);
-        const u64 hk = ((u64)m << 32) | n;
-        const u32 wb = __float_as_uint(cand);
-        u32 h = hash_slot(hk, P.hash_shift);
-        bool done = false;
-        for (int probe = 0; probe < P.hash_cap; ++probe) {
-            u64 cur = P.hkey[h];
-            if (cur == HASH_EMPTY) {
-                const u64 prev = atomicCAS(&P.hkey[h], HASH_EMPTY, hk);
-                if (prev == HASH_EMPTY) {
-                    atomicAdd(&P.deg[m], 1u);
-                    atomicAdd(&P.deg[n], 1u);
-                    atomicAdd(&P.counters[C_EDGES], 1);
-                    atomicMin(&P.hval[h], wb);
-                    done = true;
-                    break;
+            for (int k = 0; k < (CONN == 8 ? 4 : 2); ++k) {
+                const int qx = x + HX[k], qy = y + HY[k];
+                if (qx < 0 || qx >= W || qy >= H) continue;
+                const long long qi = (long long)qy * W + qx;
+                const u64 kq = P.keys[qi];
+                const u32 lq = key_label(kq);
+                if (lq == lp || lq == NO_LABEL) continue;
+                const float len = (k < 2) ? 1.0f : 1.41421356237309515f;
+                const float w = len * (0.5f * (cp + P.cost[qi]));
+                const float cand = (dp + w) + key_dist(kq);
+                const u32 m = min(lp, lq), n = max(lp, lq);
+                const u64 hk = ((u64)m << 32) | n;
+                const u32 wb = __float_as_uint(cand);
+                u32 h = (u32)(((hk ^ (hk >> 29)) * 0x9e3779b97f4a7c15ull) >> 54) & (LCAP - 1);
+                bool done = false;
+                for (int probe = 0; probe < LCAP; ++probe) {
+                    const u64 prev = atomicCAS(&lkey[h], HASH_EMPTY, hk);
+                    if (prev == HASH_EMPTY || prev == hk) {
+                        atomicMin(&lval[h], wb);
+                        done = true;
+                        break;
+                    }
+                    h = (h + 1u) & (LCAP - 1);
                 }
-                cur = prev;
+                if (!done) global_insert(P, hk, wb);
             }
-            if (cur == hk) {
-                atomicMin(&P.hval[h], wb);
-                done = true;
-                break;
-            }
-            h = (h + 1u) & mask;
         }
-        if (!done) atomicOr(&P.counters[C_OVERFLOW], 1);
     }
+    __syncthreads();
+    for (int j = threadIdx.x; j < LCAP; j += PIX_BLOCK)
+        if (lkey[j] != HASH_EMPTY) global_insert(P, lkey[j], lval[j]);
 }
 
 // One workgroup of 1024 threads per pair.
@@ -134,9 +165,9 @@ __global__ __launch_bounds__(1024) void k_csr_scan(const PairDev* __restrict__ p
         P.counters[C_KEFF] = min(P.K, u);
         int status = 0;
         if (u == 0) status = -3;                                       // EPIC_ERR_NO_MATCHES
-        if (2LL * P.counters[C_EDGES] > (long long)P.hash_cap) {
-            P.counters[C_OVERFLOW] |= 1;
-        }
+        const u32 two_e = s_part[1023];       // every edge counted at both ends
+        P.counters[C_EDGES] = (int)(two_e / 2);
+        if ((long long)two_e > (long long)P.hash_cap) P.counters[C_OVERFLOW] |= 1;
         if (P.counters[C_OVERFLOW]) status = -6;                       // EPIC_ERR_CAPACITY
         if (*run.error) status = -7;                                   // EPIC_ERR_CONVERGENCE
         P.counters[C_STATUS] = status;

@@ -31,13 +31,14 @@ __global__ __launch_bounds__(256) void k_clear(const PairDev* __restrict__ pairs
         P.minin[i] = FLOAT_INF_BITS;
     }
     const int ntiles = P.tiles_x * P.tiles_y;
-    for (long long i = i0; i < ntiles; i += stride) run.tile_state[P.tile_base + i] = 0u;
+    for (long long i = i0; i < ntiles; i += stride) {
+        run.dirty[0][P.tile_base + i] = 0u;
+        run.dirty[1][P.tile_base + i] = 0u;
+    }
     if (i0 < C_NCOUNTERS) P.counters[i0] = 0;
     if (i0 == 0 && P.dbg_n_edges) *P.dbg_n_edges = 0;
-    if (p == 0 && i0 == 0) {
-        *run.pending = 0;
-        *run.error = 0;
-    }
+    if (p == 0 && i0 < kMaxPasses) run.any[i0] = 0;
+    if (p == 0 && i0 == 0) *run.error = 0;
 }
 
 __global__ __launch_bounds__(256) void k_seed(const PairDev* __restrict__ pairs, RunDev run) {
@@ -56,7 +57,7 @@ __global__ __launch_bounds__(256) void k_seed(const PairDev* __restrict__ pairs,
             pix = iy * P.W + ix;
             atomicMin(&P.keys[pix], make_key(0.0f, (u32)m));
             const int t = P.tile_base + (iy / run.tile_h) * P.tiles_x + ix / run.tile_w;
-            if ((atomicOr(&run.tile_state[t], 1u) & 1u) == 0u) atomicAdd(run.pending, 1);
+            run.dirty[0][t] = 1u;
         }
     }
     if (pix < 0) atomicAdd(&P.counters[C_OUTSIDE], 1);

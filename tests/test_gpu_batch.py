@@ -1,0 +1,124 @@
+"""GPU: the batched form.  Many pairs in one fused launch sequence (and its
+captured HIP graph) give each pair the result it gets alone, and match the
+oracle on sampled pairs at full size."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import parity
+from oracle import epic_ref
+from scenes import batch_scenes, random_case
+
+pytestmark = pytest.mark.gpu
+
+
+def _dev(sc):
+    import torch
+    return (torch.from_numpy(sc.cost).cuda(), torch.from_numpy(sc.matches).cuda(),
+            sc.K, sc.a, sc.mode)
+
+
+def _mixed(n=8):
+    out = []
+    for i in range(n):
+        sc = random_case(40 + 23 * i, 70 + 31 * (i % 3), 30 + 40 * i, seed=100 + i,
+                         K=[4, 16, 100, 33][i % 4], mode=i % 2, outside=i % 2, duplicates=i % 3)
+        out.append(sc)
+    return out
+
+
+def _epe(a, b):
+    return np.linalg.norm(a.astype(np.float64) - b.astype(np.float64), axis=2)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_1501_02565_amd as epic
+    c = epic.Context(0, 512 << 20)
+    yield c
+    c.close()
+
+
+def test_batch_equals_single(ctx):
+    import torch
+    scs = _mixed()
+    probs = [_dev(sc) for sc in scs]
+    flows = [f.cpu().numpy() for f in ctx.interp_batch(probs)]
+    stats = [ctx.stats(i) for i in range(len(scs))]
+    identical = 0
+    for sc, p, f, st in zip(scs, probs, flows, stats):
+        alone = ctx.interp(*p).cpu().numpy()
+        assert st["status"] == 0
+        identical += int(np.array_equal(alone, f))
+        assert _epe(alone, f).mean() <= parity.EPE_MEAN
+        ref = epic_ref.interp(sc.cost, sc.matches, sc.K, sc.a, sc.mode)[0]
+        assert _epe(f, ref).mean() <= parity.EPE_MEAN
+    print(f"bitwise identical alone vs batched: {identical}/{len(scs)}")
+    assert identical >= len(scs) - 1
+
+
+def test_graph_replay_matches_eager(ctx):
+    """Replays of the captured graph, with eager work and synchronisation in
+    between, reproduce the eager batch every time."""
+    import torch
+    scs = _mixed(5)
+    probs = [_dev(sc) for sc in scs]
+    eager = [f.clone() for f in ctx.interp_batch(probs)]
+    torch.cuda.synchronize()
+    g = ctx.capture(probs)
+    try:
+        for rep in range(3):
+            for f in g.flows:
+                f.fill_(float("nan"))
+            g.launch()
+            torch.cuda.synchronize()
+            for a, b in zip(eager, g.flows):
+                assert _epe(a.cpu().numpy(), b.cpu().numpy()).mean() <= 1e-6
+            # unrelated eager work between replays
+            ctx.interp(*probs[0])
+            torch.cuda.synchronize()
+    finally:
+        g.close()
+
+
+def test_graph_sees_new_inputs(ctx):
+    """The graph is bound to buffers, not to their contents."""
+    import torch
+    sc = random_case(60, 80, 120, seed=7, K=12)
+    c, m, K, a, mode = _dev(sc)
+    g = ctx.capture([(c, m, K, a, mode)])
+    try:
+        g.launch()
+        torch.cuda.synchronize()
+        sc2 = random_case(60, 80, 120, seed=8, K=12)
+        c.copy_(torch.from_numpy(sc2.cost))
+        m.copy_(torch.from_numpy(sc2.matches))
+        g.launch()
+        torch.cuda.synchronize()
+        ref = epic_ref.interp(sc2.cost, sc2.matches, K, a, mode)[0]
+        assert _epe(g.flows[0].cpu().numpy(), ref).mean() <= parity.EPE_MEAN
+    finally:
+        g.close()
+
+
+def test_full_size_batch_sampled_parity():
+    """The 64-pair mixed-size batch at full size (the batched benchmark's
+    launch configuration); every 8th pair is checked against the oracle."""
+    import torch
+    import paper_1501_02565_amd as epic
+    scs = batch_scenes(64)
+    print(f"[case] batch of 64, {sum(s.H * s.W for s in scs) / 1e6:.1f} Mpx, "
+          f"{sum(s.N for s in scs)} matches", flush=True)
+    need = sum(epic.workspace_bytes(s.H, s.W, s.N, s.K) for s in scs)
+    with epic.Context(0, need) as c:
+        probs = [_dev(sc) for sc in scs]
+        flows = c.interp_batch(probs)
+        torch.cuda.synchronize()
+        for i in range(0, 64, 8):
+            st = c.stats(i)
+            assert st["status"] == 0, st
+            ref = epic_ref.interp(scs[i].cost, scs[i].matches, scs[i].K, scs[i].a, scs[i].mode)[0]
+            e = _epe(flows[i].cpu().numpy(), ref).mean()
+            print(f"pair {i} {scs[i].name}: mean EPE {e:.2e}", flush=True)
+            assert e <= parity.EPE_MEAN
