@@ -112,7 +112,8 @@ size_t epic_workspace_bytes(int H, int W, int N, int K, int mode, int precision)
  *   a       kernel parameter of exp(-a d) (finite, >= 0)
  *   mode    EPIC_NW or EPIC_LA
  *   flow    device, H*W*2 float32 output (u, v)
- * Host-side validation returns EPIC_ERR_ARG (null pointers, H, W, N or K
+ * Host-side validation returns EPIC_ERR_ARG (null pointers, cost not
+ * 4-byte, matches not 16-byte or flow not 8-byte aligned, H, W, N or K
  * < 1, H*W >= 2^31, K > 256, non-finite or negative a, bad mode) and
  * EPIC_ERR_WORKSPACE, before anything is enqueued.  Conditions found on the
  * device (no usable match, capacity overflow) are reported by

@@ -61,7 +61,8 @@ size_t pair_bytes(int H, int W, int N) {
     b += align_up(4 * cap);           // hval
     b += 3 * align_up(4 * (size_t)N); // deg, fill, minin
     b += align_up(4 * ((size_t)N + 1));
-    b += 2 * align_up(4 * cap);       // col, cw
+    b += align_up(8 * cap);           // adjacency (neighbour, weight)
+    b += align_up(4 * (size_t)N);     // K-NN overflow list share
     b += align_up(24 * (size_t)N);    // params
     b += align_up(4 * C_NCOUNTERS);
     return b;
@@ -120,6 +121,8 @@ const char* epic_last_error(void) { return g_last_error.c_str(); }
 int epic_validate(const float* cost, int H, int W, const float* matches, int N, int K, float a, int mode,
                   const float* flow) {
     if (!cost || !matches || !flow) return EPIC_ERR_ARG;
+    // vector loads and stores: matches rows are read as float4, flow as float2
+    if (((uintptr_t)cost & 3) || ((uintptr_t)matches & 15) || ((uintptr_t)flow & 7)) return EPIC_ERR_ARG;
     if (H < 1 || W < 1 || N < 1 || K < 1 || K > kMaxK) return EPIC_ERR_ARG;
     if ((long long)H * W >= (1LL << 31) || N >= (1 << 30)) return EPIC_ERR_ARG;
     if (!std::isfinite(a) || a < 0.0f) return EPIC_ERR_ARG;
@@ -268,6 +271,9 @@ int run_pairs(epic_ctx* c, const epic_request* reqs, int n, hipStream_t stream, 
     };
     u32* dirty0 = reinterpret_cast<u32*>(take(4 * total_tiles));
     u32* dirty1 = reinterpret_cast<u32*>(take(4 * total_tiles));
+    long long total_n = 0;
+    for (int i = 0; i < n; ++i) total_n += reqs[i].N;
+    int* ovf_list = reinterpret_cast<int*>(take(4 * (size_t)total_n));
     int tile_base = 0, pix_blocks = 0, seed_blocks = 0, src_blocks = 0, slot_blocks = 0, init_blocks = 0;
     int kmax = 1;
     c->last_counters.assign(n, nullptr);
@@ -314,8 +320,7 @@ int run_pairs(epic_ctx* c, const epic_request* reqs, int n, hipStream_t stream, 
         P.fill = reinterpret_cast<u32*>(take(4 * (size_t)r.N));
         P.minin = reinterpret_cast<u32*>(take(4 * (size_t)r.N));
         P.row_ptr = reinterpret_cast<u32*>(take(4 * ((size_t)r.N + 1)));
-        P.col = reinterpret_cast<int*>(take(4 * cap));
-        P.cw = reinterpret_cast<float*>(take(4 * cap));
+        P.adj = reinterpret_cast<uint2*>(take(8 * cap));
         P.params = reinterpret_cast<float*>(take(24 * (size_t)r.N));
         P.counters = reinterpret_cast<int*>(take(4 * C_NCOUNTERS));
         c->last_counters[i] = P.counters;
@@ -338,6 +343,8 @@ int run_pairs(epic_ctx* c, const epic_request* reqs, int n, hipStream_t stream, 
     run.dirty[1] = dirty1;
     run.any = c->g_any;
     run.error = c->g_error;
+    run.ovf_list = ovf_list;
+    run.ovf_count = c->g_error + 8;
     run.total_tiles = tile_base;
     run.npairs = n;
     run.conn = c->opt.connectivity;

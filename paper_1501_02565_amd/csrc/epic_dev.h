@@ -72,8 +72,7 @@ struct PairDev {
     u32* fill;              // N
     u32* row_ptr;           // N + 1
     u32* minin;             // N: float bits of the lightest incident edge
-    int* col;               // hash_cap: CSR neighbour ids
-    float* cw;              // hash_cap: CSR edge weights
+    uint2* adj;             // hash_cap: CSR edges (neighbour id, weight bits)
     float* params;          // N*6
     int* counters;          // C_NCOUNTERS
     // optional stage dumps (NULL = off)
@@ -91,6 +90,8 @@ struct RunDev {
     u32* dirty[2];          // per tile, by pass parity: tile needs a visit
     int* any;               // per pass: some tile border changed (kMaxPasses)
     int* error;             // global error word
+    int* ovf_list;          // K-NN sources to redo with a larger table
+    int* ovf_count;
     int total_tiles;
     int npairs;
     int conn;               // 8 or 4

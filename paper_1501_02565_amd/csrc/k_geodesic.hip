@@ -17,10 +17,9 @@
 //     plain cached loads and stores are coherent; no workgroup waits for
 //     another.  A pass in which no border changed ends the transform: every
 //     later pass exits at once.
-//   * In-tile relaxation is push-based over a frontier: the first round
-//     pushes from every reached pixel of the tile and halo; later rounds only
-//     from pixels that improved in the previous round.  A push is a 64-bit
-//     LDS atomic min of (D(p) + step, L(p)) into an in-tile neighbour.
+//   * In-tile relaxation is Gauss-Seidel over lines of pixels owned by one
+//     thread, alternating between rows and columns and between sweep
+//     directions, until a round changes nothing.
 //   * Each pixel's state is a packed (D, label) key, so relaxation is an
 //     integer min: any relaxation order reaches the same fixpoint D (the
 //     minimum over paths of the left-fold float sums); labels agree with the
@@ -44,25 +43,30 @@ struct TileLds {
     static constexpr int LW = TW + 2, LH = TH + 2, NL = LW * LH;
     u64 key[NL];
     float cost[NL];
-    unsigned short list[2][NL];
-    u32 flag[2][NL];
-    u64 dummy_key[256];     // per-thread targets of pushes that do not apply
-    u32 dummy_flag[256];
-    int n[2];
     int border;
 };
 
 // Visits one tile: load with halo, relax to a local fixpoint, write back.
 // Returns (to every thread) the mask of borders with a changed pixel.
+//
+// In-tile relaxation is Gauss-Seidel over lines: each thread owns a run of
+// PPT consecutive pixels, along a row in even rounds and along a column in
+// odd rounds, and sweeps it (forwards, then backwards two rounds later),
+// updating every pixel in place from its 8 (or 4) neighbours.  A straight
+// path therefore advances up to PPT pixels per round.  A round in which no
+// pixel changed is a local fixpoint (every pixel was recomputed from all of
+// its neighbours).
 template <int TW, int TH, int CONN>
-__device__ int visit_tile(const PairDev& P, int tx, int ty, bool first, TileLds<TW, TH>& S, int* error) {
-    constexpr int NG = 256 / TW, PPT = TH / NG;
+__device__ __forceinline__ int visit_tile(const PairDev& P, int tx, int ty, TileLds<TW, TH>& S, int* error) {
+    constexpr int PPT = TW * TH / 256;
     constexpr int LW = TileLds<TW, TH>::LW, NL = TileLds<TW, TH>::NL;
+    constexpr int HR = TW / PPT;           // row runs per row
+    constexpr int VG = TH / PPT;           // column runs per column
+    static_assert(PPT * 256 == TW * TH && HR * PPT == TW && VG * PPT == TH && HR * TH == 256 &&
+                      VG * TW == 256, "tile shape");
     constexpr int DX[8] = {1, -1, 0, 0, 1, -1, 1, -1};
     constexpr int DY[8] = {0, 0, 1, -1, 1, 1, -1, -1};
-    static_assert(NG * TW == 256 && PPT * NG == TH, "tile shape");
     const int tid = threadIdx.x;
-    const int lx = tid % TW, grp = tid / TW;
     const int x0 = tx * TW, y0 = ty * TH, W = P.W, H = P.H;
     const int twe = min(TW, W - x0), the = min(TH, H - y0);
 
@@ -78,134 +82,62 @@ __device__ int visit_tile(const PairDev& P, int tx, int ty, bool first, TileLds<
         }
         S.key[i] = k;
         S.cost[i] = c;
-        S.flag[0][i] = 0u;
-        S.flag[1][i] = 0u;
     }
-    if (tid == 0) {
-        S.n[0] = 0;
-        S.n[1] = 0;
-        S.border = 0;
-    }
+    if (tid == 0) S.border = 0;
     __syncthreads();
+    // original values of this thread's row run (also used for write-back)
+    const int hy = tid / HR, hx = (tid % HR) * PPT;       // row run: (hx.., hy)
+    const int vx = tid % TW, vy = (tid / TW) * PPT;       // column run: (vx, vy..)
     u64 orig[PPT];
 #pragma unroll
-    for (int j = 0; j < PPT; ++j) orig[j] = S.key[(grp * PPT + j + 1) * LW + lx + 1];
+    for (int j = 0; j < PPT; ++j) orig[j] = S.key[(hy + 1) * LW + hx + j + 1];
 
-    // Initial frontier: the reached halo pixels, and on the first pass the
-    // reached pixels inside the tile (its seeds).  A tile visited before is
-    // at a fixpoint relative to its previous halo, so only the halo can
-    // bring anything new.
-    for (int i0 = 0; i0 < NL; i0 += 256) {
-        const int i = i0 + tid;
-        const int iy = i / LW, ix = i - iy * LW;
-        const bool halo = iy == 0 || ix == 0 || iy > the || ix > twe;
-        const bool add = i < NL && key_label(S.key[i]) != NO_LABEL && (first || halo);
-        const u64 mask = __ballot(add);
-        if (mask) {
-            const int leader = __ffsll((long long)mask) - 1;
-            int base = 0;
-            if ((tid & 63) == leader) base = atomicAdd(&S.n[0], __popcll(mask));
-            base = __builtin_amdgcn_readlane(base, leader);
-            if (add) {
-                const int pos = base + (int)__builtin_amdgcn_mbcnt_hi((u32)(mask >> 32),
-                                                                  __builtin_amdgcn_mbcnt_lo((u32)mask, 0u));
-                S.list[0][pos] = (unsigned short)i;
-                S.flag[0][i] = 1u;
+    const int round_cap = 4 * NL + 8;
+    for (int round = 0;; ++round) {
+        const bool rows = (round & 1) == 0;
+        const bool fwd = (round & 2) == 0;
+        const int bx = rows ? hx : vx, by = rows ? hy : vy;
+        const int sx = rows ? 1 : 0, sy = rows ? 0 : 1;
+        int changed = 0;
+#pragma unroll
+        for (int jj = 0; jj < PPT; ++jj) {
+            const int j = fwd ? jj : PPT - 1 - jj;
+            const int lx = bx + sx * j, ly = by + sy * j;
+            if (lx >= twe || ly >= the) continue;
+            const int ci = (ly + 1) * LW + lx + 1;
+            const float cp = S.cost[ci];
+            u64 kq[CONN];
+            float cq[CONN];
+#pragma unroll
+            for (int k = 0; k < CONN; ++k) {
+                kq[k] = S.key[ci + DY[k] * LW + DX[k]];
+                cq[k] = S.cost[ci + DY[k] * LW + DX[k]];
+            }
+            const u64 cur = S.key[ci];
+            u64 best = cur;
+#pragma unroll
+            for (int k = 0; k < CONN; ++k) {
+                const float len = (k < 4) ? 1.0f : 1.41421356237309515f;
+                const u64 cand = make_key(key_dist(kq[k]) + len * (0.5f * (cp + cq[k])), key_label(kq[k]));
+                best = cand < best ? cand : best;
+            }
+            if (best < cur) {
+                S.key[ci] = best;
+                changed = 1;
             }
         }
-    }
-    __syncthreads();
-
-    int par = 0;
-    const int round_cap = 4 * NL;
-    for (int round = 0;; ++round) {
-        const int nf = S.n[par];
-        if (nf == 0) break;
+        if (!__syncthreads_or(changed)) break;
         if (round > round_cap) {
             if (tid == 0) atomicOr(error, 2);
             break;
         }
-        const int nxt = par ^ 1;
-        for (int i0 = 0; i0 < nf; i0 += 256) {
-            const int i = i0 + tid;
-            const bool act = i < nf;
-            int pidx = 0;
-            if (act) {
-                pidx = S.list[par][i];
-                S.flag[par][pidx] = 0u;
-            }
-            const u64 kp = act ? S.key[pidx] : KEY_INF;
-            const int py = pidx / LW, px = pidx - py * LW;
-            const float dp = key_dist(kp);
-            const u32 lp = key_label(kp);
-            const float cp = S.cost[pidx];
-            // The pushes are independent and branch-free: a push that does not
-            // apply targets this thread's dummy slot with a key that never
-            // lowers it, so the reads, atomic mins and flag claims issue as
-            // three back-to-back batches of LDS operations.
-            int q[CONN];
-            bool ok[CONN];
-#pragma unroll
-            for (int k = 0; k < CONN; ++k) {
-                const int qy = py + DY[k], qx = px + DX[k];
-                ok[k] = act && qy >= 1 && qy <= the && qx >= 1 && qx <= twe;
-                q[k] = ok[k] ? qy * LW + qx : 0;
-            }
-            float cq[CONN];
-#pragma unroll
-            for (int k = 0; k < CONN; ++k) cq[k] = S.cost[q[k]];
-            u64 old[CONN], cand[CONN];
-#pragma unroll
-            for (int k = 0; k < CONN; ++k) {
-                const float len = (k < 4) ? 1.0f : 1.41421356237309515f;
-                cand[k] = ok[k] ? make_key(dp + len * (0.5f * (cp + cq[k])), lp) : ~0ull;
-                old[k] = atomicMin(ok[k] ? &S.key[q[k]] : &S.dummy_key[tid], cand[k]);
-            }
-            u32 fo[CONN];
-#pragma unroll
-            for (int k = 0; k < CONN; ++k) {
-                ok[k] = ok[k] && cand[k] < old[k];
-                fo[k] = atomicExch(ok[k] ? &S.flag[nxt][q[k]] : &S.dummy_flag[tid], 1u);
-            }
-            u32 bits = 0;
-#pragma unroll
-            for (int k = 0; k < CONN; ++k)
-                if (ok[k] && fo[k] == 0u) bits |= 1u << k;
-            // append: per direction a ballot, one LDS atomic per wavefront
-            u64 masks[CONN];
-            int total = 0;
-#pragma unroll
-            for (int k = 0; k < CONN; ++k) {
-                masks[k] = __ballot((bits >> k) & 1u);
-                total += __popcll(masks[k]);
-            }
-            if (total) {
-                int base = 0;
-                if ((tid & 63) == 0) base = atomicAdd(&S.n[nxt], total);
-                base = __builtin_amdgcn_readfirstlane(base);
-#pragma unroll
-                for (int k = 0; k < CONN; ++k) {
-                    if ((bits >> k) & 1u) {
-                        const int pos = base + (int)__builtin_amdgcn_mbcnt_hi(
-                                                   (u32)(masks[k] >> 32),
-                                                   __builtin_amdgcn_mbcnt_lo((u32)masks[k], 0u));
-                        S.list[nxt][pos] = (unsigned short)q[k];
-                    }
-                    base += __popcll(masks[k]);
-                }
-            }
-        }
-        __syncthreads();
-        if (tid == 0) S.n[par] = 0;
-        par = nxt;
-        __syncthreads();
     }
 
     // write back the improved pixels and note the borders they lie on
     int bm = 0;
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
-        const int ly = grp * PPT + j;
+        const int lx = hx + j, ly = hy;
         const u64 k = S.key[(ly + 1) * LW + lx + 1];
         if (lx < twe && ly < the && k != orig[j]) {
             P.keys[(long long)(y0 + ly) * W + x0 + lx] = k;
@@ -261,7 +193,7 @@ __global__ __launch_bounds__(256) void k_geo_pass(const PairDev* __restrict__ pa
     const int tx = lt % P.tiles_x, ty = lt / P.tiles_x;
     __syncthreads();
     if (threadIdx.x == 0) dirty[tile] = 0u;                  // reused two passes later
-    const int border = visit_tile<TW, TH, CONN>(P, tx, ty, pass == 0, S, run.error);
+    const int border = visit_tile<TW, TH, CONN>(P, tx, ty, S, run.error);
     if (threadIdx.x == 0) {
         atomicAdd(&P.counters[C_TILE_VISITS], 1);
         if (border) {
@@ -290,7 +222,7 @@ __global__ __launch_bounds__(256) void k_geo_finish(const PairDev* __restrict__ 
             const int tx = lt % P.tiles_x, ty = lt / P.tiles_x;
             __syncthreads();
             if (threadIdx.x == 0) dirty[tile] = 0u;
-            const int border = visit_tile<TW, TH, CONN>(P, tx, ty, false, S, run.error);
+            const int border = visit_tile<TW, TH, CONN>(P, tx, ty, S, run.error);
             if (threadIdx.x == 0) {
                 atomicAdd(&P.counters[C_TILE_VISITS], 1);
                 if (border) {

@@ -186,8 +186,8 @@ __global__ __launch_bounds__(SLOT_BLOCK) void k_csr_scatter(const PairDev* __res
     const float w = __uint_as_float(wb);
     const u32 pm = P.row_ptr[m] + atomicAdd(&P.fill[m], 1u);
     const u32 pn = P.row_ptr[n] + atomicAdd(&P.fill[n], 1u);
-    if (pm < (u32)P.hash_cap) { P.col[pm] = (int)n; P.cw[pm] = w; }
-    if (pn < (u32)P.hash_cap) { P.col[pn] = (int)m; P.cw[pn] = w; }
+    if (pm < (u32)P.hash_cap) P.adj[pm] = make_uint2(n, wb);
+    if (pn < (u32)P.hash_cap) P.adj[pn] = make_uint2(m, wb);
     atomicMin(&P.minin[m], wb);
     atomicMin(&P.minin[n], wb);
     if (P.dbg_em) {

@@ -3,8 +3,11 @@
 //
 // One wavefront per match s:
 //  1. Dijkstra from s on the match graph, with the visited set held in LDS
-//     (open-addressing node -> entry table).  Several frontier nodes are
-//     settled per step: a frontier node v with tentative d(v) is final once
+//     (open-addressing node -> entry table).  When a node enters the table
+//     its adjacency range and lightest incident edge are fetched with it, so
+//     each step needs one round of global loads (the settled nodes' packed
+//     (neighbour, weight) edges).  Several frontier nodes are settled per
+//     step: a frontier node v with tentative d(v) is final once
 //     d(v) <= dmin + lightest_edge(v), where dmin is the smallest tentative
 //     distance on the frontier (no unsettled node can still lower it).  The
 //     edges of all nodes settled in a step are relaxed in parallel, one lane
@@ -24,6 +27,10 @@
 //     than 3 neighbours) it is re-accumulated and solved in FP64, where a
 //     near-collinear neighbourhood (ratio <= deg_tau) falls back to NW.
 //  Output per match: b00 b01 b10 b11 c0 c1 with flow(p) = B (p - p_s) + c.
+//
+// A source whose visited set outgrows the small LDS table is put on an
+// overflow list and redone by a second launch with a table four times
+// larger; only if that overflows too is the pair's status set.
 #include "epic_dev.h"
 
 namespace epic {
@@ -62,106 +69,102 @@ __device__ __forceinline__ u32 node_slot(int v, int hbits) {
     return ((u32)v * 2654435761u) >> (32 - hbits);
 }
 
-}  // namespace
+template <int VCAP>
+struct KnnLds {
+    static constexpr int HCAP = 2 * VCAP;
+    int node[VCAP];
+    u32 dist[VCAP];          // float bits
+    u32 minin[VCAP];         // float bits of the lightest incident edge
+    u32 rs[VCAP];            // adjacency start
+    u32 deg[VCAP];
+    unsigned char state[VCAP];   // 0 frontier, 1 settled
+    unsigned short newly[VCAP];
+    u64 buf[VCAP];           // node table (HCAP ints), then sort buffer
+    unsigned short hidx[HCAP];
+    int f_off[65];
+    u32 f_start[64];
+    float f_d[64];
+    int nvis, nnew, ncand, ovf;
+};
 
+// Loads a node's adjacency range and lightest edge into entry e.
+__device__ __forceinline__ void fetch_node(const PairDev& P, int v, u32* rs, u32* deg, u32* minin, int e) {
+    const u32 a = P.row_ptr[v], b = P.row_ptr[v + 1];
+    minin[e] = P.minin[v];
+    rs[e] = a;
+    deg[e] = b - a;
+}
+
+// Processes source `s` of pair P; returns false when the visited set did not
+// fit the table (nothing written then).
 template <int VCAP, int KMAX>
-__global__ __launch_bounds__(64) void k_knn_fit(const PairDev* __restrict__ pairs, RunDev run) {
-    constexpr int HCAP = 2 * VCAP;
-    constexpr int HBITS = (HCAP == 1024) ? 10 : (HCAP == 2048 ? 11 : 9);
+__device__ __forceinline__ bool knn_fit_one(const PairDev& P, const RunDev& run, int s, KnnLds<VCAP>& S) {
+    constexpr int HCAP = KnnLds<VCAP>::HCAP;
+    constexpr int HBITS = (HCAP == 512) ? 9 : (HCAP == 1024) ? 10 : (HCAP == 2048) ? 11 : 12;
     static_assert((1 << HBITS) == HCAP, "hash size");
     constexpr int R = KMAX / 64;
-    __shared__ int v_node[VCAP];
-    __shared__ u32 v_dist[VCAP];
-    __shared__ u32 v_minin[VCAP];
-    __shared__ unsigned char v_state[VCAP];     // 0 frontier, 1 settled
-    __shared__ u64 s_buf[VCAP];                 // node table, then sort buffer
-    __shared__ unsigned short hidx[HCAP];
-    __shared__ unsigned short newly[VCAP];
-    __shared__ int f_off[65], f_start[64];
-    __shared__ float f_d[64];
-    __shared__ int s_nvis, s_nnew, s_ncand, s_ovf;
-    int* htab = reinterpret_cast<int*>(s_buf);  // HCAP ints
-
     const int lane = threadIdx.x;
-    const int p = find_pair(run.npairs, (int)blockIdx.x, [&](int i) { return pairs[i].src_block_base; });
-    const PairDev& P = pairs[p];
-    const int s = (int)blockIdx.x - P.src_block_base;
-    if (s >= P.N) return;
     const int K = P.K;
     const int keff = P.counters[C_KEFF];
-    const int sp = P.seed_pix[s];
-    // a pair whose graph overflowed its hash has incomplete adjacency: skip it
-    // (its status already reports EPIC_ERR_CAPACITY)
-    const bool graph_ok = (P.counters[C_OVERFLOW] & 1) == 0;
-    const bool active = graph_ok && sp >= 0 && key_label(P.keys[sp]) == (u32)s && keff > 0;
+    int* htab = reinterpret_cast<int*>(S.buf);
     float* prm = P.params + 6LL * s;
-    if (!active) {
-        if (lane < 6) prm[lane] = 0.0f;
-        if (P.dbg_knn_idx)
-            for (int j = lane; j < K; j += 64) {
-                P.dbg_knn_idx[(long long)s * K + j] = -1;
-                P.dbg_knn_d[(long long)s * K + j] = __int_as_float(0x7f800000);
-            }
-        return;
-    }
 
     // ------------------------------------------------------------ Dijkstra
     for (int i = lane; i < HCAP; i += 64) htab[i] = -1;
     __syncthreads();
     if (lane == 0) {
-        s_nvis = 1;
-        s_ovf = 0;
-        v_node[0] = s;
-        v_dist[0] = 0u;
-        v_state[0] = 0;
-        v_minin[0] = P.minin[s];
+        S.nvis = 1;
+        S.ovf = 0;
+        S.node[0] = s;
+        S.dist[0] = 0u;
+        S.state[0] = 0;
+        fetch_node(P, s, S.rs, S.deg, S.minin, 0);
         const u32 h = node_slot(s, HBITS);
         htab[h] = s;
-        hidx[h] = 0;
+        S.hidx[h] = 0;
     }
     __syncthreads();
 
     float dstop;
     for (;;) {
-        const int nv = min(s_nvis, VCAP);
+        const int nv = min(S.nvis, VCAP);
         float dmin = __int_as_float(0x7f800000);
         for (int e = lane; e < nv; e += 64)
-            if (v_state[e] == 0) dmin = fminf(dmin, __uint_as_float(v_dist[e]));
+            if (S.state[e] == 0) dmin = fminf(dmin, __uint_as_float(S.dist[e]));
         dmin = wave_min(dmin);
-        int below = 0;
-        for (int e = lane; e < nv; e += 64)
-            below += (v_state[e] == 1 && __uint_as_float(v_dist[e]) < dmin) ? 1 : 0;
-        below = wave_sum_i(below);
-        if (below >= keff || dmin == __int_as_float(0x7f800000) || s_ovf) {
-            dstop = dmin;
-            break;
-        }
-        if (lane == 0) s_nnew = 0;
+        if (lane == 0) S.nnew = 0;
         __syncthreads();
+        // one scan: count settled nodes below dmin, settle the final ones
+        int below = 0;
         for (int e = lane; e < nv; e += 64) {
-            if (v_state[e] == 0 &&
-                __uint_as_float(v_dist[e]) <= dmin + __uint_as_float(v_minin[e])) {
-                v_state[e] = 1;
-                newly[atomicAdd(&s_nnew, 1)] = (unsigned short)e;
+            const float d = __uint_as_float(S.dist[e]);
+            if (S.state[e] == 1) {
+                below += d < dmin ? 1 : 0;
+            } else if (d <= dmin + __uint_as_float(S.minin[e])) {
+                S.state[e] = 1;
+                S.newly[atomicAdd(&S.nnew, 1)] = (unsigned short)e;
             }
         }
+        below = wave_sum_i(below);
         __syncthreads();
-        const int nn = s_nnew;
+        if (below >= keff || dmin == __int_as_float(0x7f800000) || S.ovf) {
+            dstop = dmin;    // nodes settled in this scan lie at or above dmin
+            break;
+        }
+        const int nn = S.nnew;
         for (int base = 0; base < nn; base += 64) {
             const int cnt = min(64, nn - base);
             int dg = 0;
             if (lane < cnt) {
-                const int e = newly[base + lane];
-                const int u = v_node[e];
-                const u32 st = P.row_ptr[u];
-                dg = (int)(P.row_ptr[u + 1] - st);
-                f_start[lane] = (int)st;
-                f_d[lane] = __uint_as_float(v_dist[e]);
+                const int e = S.newly[base + lane];
+                dg = S.deg[e];
+                S.f_start[lane] = S.rs[e];
+                S.f_d[lane] = __uint_as_float(S.dist[e]);
             }
             const int incl = wave_incl_scan(dg, lane);
             const int total = __shfl(incl, 63);
-            if (lane < cnt) f_off[lane] = incl - dg;
-            if (lane == 0) f_off[cnt] = total;
+            if (lane < cnt) S.f_off[lane] = incl - dg;
+            if (lane == 0) S.f_off[cnt] = total;
             __syncthreads();
             for (int j0 = 0; j0 < total; j0 += 64) {
                 const int j = j0 + lane;
@@ -172,11 +175,11 @@ __global__ __launch_bounds__(64) void k_knn_fit(const PairDev* __restrict__ pair
                     int lo = 0, hi = cnt - 1;       // last i with f_off[i] <= j
                     while (lo < hi) {
                         const int mid = (lo + hi + 1) >> 1;
-                        if (f_off[mid] <= j) lo = mid; else hi = mid - 1;
+                        if (S.f_off[mid] <= j) lo = mid; else hi = mid - 1;
                     }
-                    const int ei = f_start[lo] + (j - f_off[lo]);
-                    v = P.col[ei];
-                    cand = f_d[lo] + P.cw[ei];
+                    const uint2 ed = P.adj[S.f_start[lo] + (u32)(j - S.f_off[lo])];
+                    v = (int)ed.x;
+                    cand = S.f_d[lo] + __uint_as_float(ed.y);
                 }
                 // phase A: find or claim v's slot
                 int h = -1;
@@ -193,59 +196,59 @@ __global__ __launch_bounds__(64) void k_knn_fit(const PairDev* __restrict__ pair
                         }
                         hh = (hh + 1u) & (u32)(HCAP - 1);
                     }
-                    if (h < 0) s_ovf = 1;
+                    if (h < 0) S.ovf = 1;
                 }
-                // phase B: new nodes get an entry
+                // phase B: new nodes get an entry (with their adjacency range)
                 if (won) {
-                    const int e = atomicAdd(&s_nvis, 1);
+                    const int e = atomicAdd(&S.nvis, 1);
                     if (e < VCAP) {
-                        v_node[e] = v;
-                        v_dist[e] = 0x7f800000u;
-                        v_state[e] = 0;
-                        v_minin[e] = P.minin[v];
-                        hidx[h] = (unsigned short)e;
+                        S.node[e] = v;
+                        S.dist[e] = 0x7f800000u;
+                        S.state[e] = 0;
+                        fetch_node(P, v, S.rs, S.deg, S.minin, e);
+                        S.hidx[h] = (unsigned short)e;
                     } else {
-                        hidx[h] = 0xffff;
-                        s_ovf = 1;
+                        S.hidx[h] = 0xffff;
+                        S.ovf = 1;
                     }
                 }
                 __syncthreads();
                 // phase C: relax
                 if (act && h >= 0) {
-                    const int e = hidx[h];
-                    if (e != 0xffff && v_state[e] == 0) atomicMin(&v_dist[e], __float_as_uint(cand));
+                    const int e = S.hidx[h];
+                    if (e != 0xffff && S.state[e] == 0) atomicMin(&S.dist[e], __float_as_uint(cand));
                 }
                 __syncthreads();
             }
         }
     }
-    if (s_ovf && lane == 0) atomicOr(&P.counters[C_OVERFLOW], 2);
+    if (S.ovf) return false;
 
     // ---------------------------------------- select the K nearest (sorted)
-    const int nv = min(s_nvis, VCAP);
-    if (lane == 0) s_ncand = 0;
+    const int nv = min(S.nvis, VCAP);
+    if (lane == 0) S.ncand = 0;
     __syncthreads();
     for (int e = lane; e < nv; e += 64) {
-        const float d = __uint_as_float(v_dist[e]);
-        if (v_state[e] == 1 && d < dstop)
-            s_buf[atomicAdd(&s_ncand, 1)] = ((u64)v_dist[e] << 32) | (u32)v_node[e];
+        const float d = __uint_as_float(S.dist[e]);
+        if (S.state[e] == 1 && d < dstop)
+            S.buf[atomicAdd(&S.ncand, 1)] = ((u64)S.dist[e] << 32) | (u32)S.node[e];
     }
     __syncthreads();
-    const int nc = s_ncand;
+    const int nc = S.ncand;
     int p2 = 1;
     while (p2 < nc) p2 <<= 1;
-    for (int i = nc + lane; i < p2; i += 64) s_buf[i] = ~0ull;
+    for (int i = nc + lane; i < p2; i += 64) S.buf[i] = ~0ull;
     __syncthreads();
     for (int k = 2; k <= p2; k <<= 1) {
         for (int j = k >> 1; j > 0; j >>= 1) {
             for (int i = lane; i < p2; i += 64) {
                 const int ixj = i ^ j;
                 if (ixj > i) {
-                    const u64 a = s_buf[i], b = s_buf[ixj];
+                    const u64 a = S.buf[i], b = S.buf[ixj];
                     const bool up = (i & k) == 0;
                     if (up ? (a > b) : (a < b)) {
-                        s_buf[i] = b;
-                        s_buf[ixj] = a;
+                        S.buf[i] = b;
+                        S.buf[ixj] = a;
                     }
                 }
             }
@@ -256,9 +259,9 @@ __global__ __launch_bounds__(64) void k_knn_fit(const PairDev* __restrict__ pair
     if (P.dbg_knn_idx) {
         for (int j = lane; j < K; j += 64) {
             const bool ok = j < n;
-            P.dbg_knn_idx[(long long)s * K + j] = ok ? (int)(u32)s_buf[j] : -1;
+            P.dbg_knn_idx[(long long)s * K + j] = ok ? (int)(u32)S.buf[j] : -1;
             P.dbg_knn_d[(long long)s * K + j] =
-                ok ? __uint_as_float((u32)(s_buf[j] >> 32)) : __int_as_float(0x7f800000);
+                ok ? __uint_as_float((u32)(S.buf[j] >> 32)) : __int_as_float(0x7f800000);
         }
     }
 
@@ -275,14 +278,14 @@ __global__ __launch_bounds__(64) void k_knn_fit(const PairDev* __restrict__ pair
         const int j = lane + 64 * r;
         dx[r] = dy[r] = du[r] = dv[r] = kk[r] = ww[r] = 0.f;
         if (j < n) {
-            const u64 key = s_buf[j];
+            const u64 key = S.buf[j];
             const int node = (int)(u32)key;
             const float d = __uint_as_float((u32)(key >> 32));
-            const float x = M[4LL * node + 0], y = M[4LL * node + 1];
-            dx[r] = x - xm;
-            dy[r] = y - ym;
-            du[r] = (M[4LL * node + 2] - x) - um;
-            dv[r] = (M[4LL * node + 3] - y) - vm;
+            const float4 mn = *reinterpret_cast<const float4*>(M + 4LL * node);
+            dx[r] = mn.x - xm;
+            dy[r] = mn.y - ym;
+            du[r] = (mn.z - mn.x) - um;
+            dv[r] = (mn.w - mn.y) - vm;
             kk[r] = expf(-a * d);
             ww[r] = wpow == 1 ? kk[r] : kk[r] * kk[r];
             tk += kk[r];
@@ -346,7 +349,7 @@ __global__ __launch_bounds__(64) void k_knn_fit(const PairDev* __restrict__ pair
             const int j = lane + 64 * r;
             Dx[r] = Dy[r] = Du[r] = Dv[r] = Dw[r] = 0.0;
             if (j < n) {
-                const u64 key = s_buf[j];
+                const u64 key = S.buf[j];
                 const int node = (int)(u32)key;
                 const double d = (double)__uint_as_float((u32)(key >> 32));
                 const double x = M[4LL * node + 0], y = M[4LL * node + 1];
@@ -405,14 +408,77 @@ __global__ __launch_bounds__(64) void k_knn_fit(const PairDev* __restrict__ pair
         for (int i = 1; i < 6; ++i) v = lane == i ? out[i] : v;
         prm[lane] = v;
     }
+    return true;
+}
+
+// Writes the model and debug rows of a match that is not a graph node.
+__device__ __forceinline__ void knn_fit_inactive(const PairDev& P, int s) {
+    const int lane = threadIdx.x;
+    if (lane < 6) P.params[6LL * s + lane] = 0.0f;
+    if (P.dbg_knn_idx)
+        for (int j = lane; j < P.K; j += 64) {
+            P.dbg_knn_idx[(long long)s * P.K + j] = -1;
+            P.dbg_knn_d[(long long)s * P.K + j] = __int_as_float(0x7f800000);
+        }
+}
+
+__device__ __forceinline__ bool knn_active(const PairDev& P, int s) {
+    // a pair whose graph overflowed its hash has incomplete adjacency: skip
+    // it (its status already reports EPIC_ERR_CAPACITY)
+    const bool graph_ok = (P.counters[C_OVERFLOW] & 1) == 0;
+    const int sp = P.seed_pix[s];
+    return graph_ok && sp >= 0 && key_label(P.keys[sp]) == (u32)s && P.counters[C_KEFF] > 0;
+}
+
+}  // namespace
+
+// First launch: one block (one wavefront) per match of every pair.
+template <int VCAP, int KMAX>
+__global__ __launch_bounds__(64) void k_knn_fit(const PairDev* __restrict__ pairs, RunDev run) {
+    __shared__ KnnLds<VCAP> S;
+    const int p = find_pair(run.npairs, (int)blockIdx.x, [&](int i) { return pairs[i].src_block_base; });
+    const PairDev& P = pairs[p];
+    const int s = (int)blockIdx.x - P.src_block_base;
+    if (!knn_active(P, s)) {
+        knn_fit_inactive(P, s);
+        return;
+    }
+    if (!knn_fit_one<VCAP, KMAX>(P, run, s, S) && threadIdx.x == 0)
+        run.ovf_list[atomicAdd(run.ovf_count, 1)] = (int)blockIdx.x;
+}
+
+// Second launch: the matches whose visited set did not fit, with a larger
+// table.  A fixed grid walks the overflow list.
+template <int VCAP, int KMAX>
+__global__ __launch_bounds__(64) void k_knn_fit_retry(const PairDev* __restrict__ pairs, RunDev run) {
+    __shared__ KnnLds<VCAP> S;
+    const int count = *run.ovf_count;
+    for (int i = (int)blockIdx.x; i < count; i += (int)gridDim.x) {
+        const int gb = run.ovf_list[i];
+        const int p = find_pair(run.npairs, gb, [&](int k) { return pairs[k].src_block_base; });
+        const PairDev& P = pairs[p];
+        const int s = gb - P.src_block_base;
+        if (!knn_fit_one<VCAP, KMAX>(P, run, s, S)) {
+            knn_fit_inactive(P, s);
+            if (threadIdx.x == 0) atomicOr(&P.counters[C_OVERFLOW], 2);
+        }
+        __syncthreads();
+    }
 }
 
 hipError_t launch_knn_fit(const PairDev* d_pairs, const RunDev& run, int total_blocks, int kmax,
                           hipStream_t s) {
-    if (kmax <= 128)
-        hipLaunchKernelGGL((k_knn_fit<512, 128>), dim3(total_blocks), dim3(64), 0, s, d_pairs, run);
-    else
-        hipLaunchKernelGGL((k_knn_fit<1024, 256>), dim3(total_blocks), dim3(64), 0, s, d_pairs, run);
+    const int retry_grid = 512;
+    if (kmax <= 64) {
+        hipLaunchKernelGGL((k_knn_fit<256, 64>), dim3(total_blocks), dim3(64), 0, s, d_pairs, run);
+        hipLaunchKernelGGL((k_knn_fit_retry<1024, 64>), dim3(retry_grid), dim3(64), 0, s, d_pairs, run);
+    } else if (kmax <= 128) {
+        hipLaunchKernelGGL((k_knn_fit<256, 128>), dim3(total_blocks), dim3(64), 0, s, d_pairs, run);
+        hipLaunchKernelGGL((k_knn_fit_retry<2048, 128>), dim3(retry_grid), dim3(64), 0, s, d_pairs, run);
+    } else {
+        hipLaunchKernelGGL((k_knn_fit<512, 256>), dim3(total_blocks), dim3(64), 0, s, d_pairs, run);
+        hipLaunchKernelGGL((k_knn_fit_retry<2048, 256>), dim3(retry_grid), dim3(64), 0, s, d_pairs, run);
+    }
     return hipGetLastError();
 }
 

@@ -38,7 +38,10 @@ __global__ __launch_bounds__(256) void k_clear(const PairDev* __restrict__ pairs
     if (i0 < C_NCOUNTERS) P.counters[i0] = 0;
     if (i0 == 0 && P.dbg_n_edges) *P.dbg_n_edges = 0;
     if (p == 0 && i0 < kMaxPasses) run.any[i0] = 0;
-    if (p == 0 && i0 == 0) *run.error = 0;
+    if (p == 0 && i0 == 0) {
+        *run.error = 0;
+        *run.ovf_count = 0;
+    }
 }
 
 __global__ __launch_bounds__(256) void k_seed(const PairDev* __restrict__ pairs, RunDev run) {
