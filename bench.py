@@ -13,6 +13,7 @@ Prints ONE JSON line on stdout; progress goes to stderr.
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import json
 import os
 import sys
@@ -72,6 +73,109 @@ def cpu_baseline(sc, seconds):
                       f"({sc.N} matches, K={sc.K}) in {el:.1f} s"}
 
 
+def batched_form(args, np, torch, epic):
+    """The 64-pair mixed-size batch: one fused launch sequence per batch,
+    captured as a HIP graph with the autotuned configuration, against the
+    plain single-pair form (one epic_interp call per pair) on the same GPU."""
+    from oracle import epic_ref
+    from paper_1501_02565_amd import tune
+    from scenes import batch_scenes
+    t0 = time.perf_counter()
+    scs = batch_scenes(64)
+    log(f"bench: batch scenes generated in {time.perf_counter() - t0:.1f} s")
+    dev = torch.device("cuda:0")
+    probs = [(torch.from_numpy(sc.cost).to(dev), torch.from_numpy(sc.matches).to(dev), sc.K, sc.a, sc.mode)
+             for sc in scs]
+    px = sum(sc.H * sc.W for sc in scs)
+    need = sum(epic.workspace_bytes(sc.H, sc.W, sc.N, sc.K) for sc in scs)
+    best = tune.tune(probs, need, reps=5, use_cache=False)
+    log(f"bench: tuned {best['tile']} passes {best['passes']} ({best['ms']:.3f} ms); trials "
+        + ", ".join(f"{t['tile']}/{t['passes']}: {t['ms']:.3f}" for t in best["trials"]))
+    with epic.Context(0, need, tile=best["tile"], passes=best["passes"]) as ctx:
+        g = ctx.capture(probs)
+        for _ in range(3):
+            g.launch()
+        torch.cuda.synchronize()
+        reps = max(3, args.batch_reps)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            g.launch()
+        torch.cuda.synchronize()
+        ms_batch = (time.perf_counter() - t0) / reps * 1e3
+        flows = [f.cpu().numpy() for f in g.flows]
+        stats = [ctx.stats(i) for i in range(len(scs))]
+        g.close()
+        # the plain single-pair form on the same pairs and GPU
+        for c, m, K, a, mode in probs[:4]:
+            ctx.interp(c, m, K, a, mode)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for c, m, K, a, mode in probs:
+            ctx.interp(c, m, K, a, mode)
+        torch.cuda.synchronize()
+        ms_plain = (time.perf_counter() - t0) * 1e3
+    assert all(st["status"] == 0 for st in stats), stats
+    epes = []
+    for i in (0, 21, 42, 63):
+        ref = epic_ref.interp(scs[i].cost, scs[i].matches, scs[i].K, scs[i].a, scs[i].mode)[0]
+        epes.append(float(np.linalg.norm(flows[i].astype(np.float64) - ref, axis=2).mean()))
+    out = {"workload": f"batch of 64 mixed pairs, {px / 1e6:.2f} Mpx, {sum(sc.N for sc in scs)} matches",
+           "mpix_s": round(px / ms_batch / 1e3, 2), "ms_per_batch": round(ms_batch, 4),
+           "plain_mpix_s": round(px / ms_plain / 1e3, 2), "plain_ms": round(ms_plain, 4),
+           "speedup_vs_plain": round(ms_plain / ms_batch, 3),
+           "tuned": {"tile": list(best["tile"]), "passes": best["passes"]},
+           "sampled_mean_epe_vs_oracle_px": epes}
+    log(f"bench: batched {out}")
+    return out
+
+
+def served_form(args, np, torch, epic, precision):
+    """Poisson stream (200 req/s) of mixed-size pairs through the continuous
+    batching server; latency = completion - arrival."""
+    from paper_1501_02565_amd.serve import GpuExecutor, Request, Server, percentile_ms
+    from scenes import serve_scene, serve_stream
+    stream = serve_stream(args.served_requests)
+    pool = {}
+    reqs = []
+    for i, r in enumerate(stream):
+        key = (r["H"], r["W"], r["K"])
+        if key not in pool:
+            pool[key] = serve_scene(r)
+        sc = pool[key]
+        reqs.append(Request(i, r["arrival"], sc.H, sc.W, sc.N, sc.K, sc.a, sc.mode, sc.cost, sc.matches))
+    ex = GpuExecutor(slots=2, slot_workspace=args.served_budget // 2, precision=precision)
+    srv = Server(ex, args.served_budget, max_batch=64)
+    # warm up every kernel variant once
+    srv_w = Server(ex, args.served_budget, max_batch=64)
+    srv_w.run([dataclasses.replace(reqs[0], rid=-1, arrival=0.0)])
+    t0 = time.perf_counter()
+    done = srv.run(reqs)
+    wall = time.perf_counter() - t0
+    ok = [r for r in done if r.status == "done"]
+    # each result alone equals its result in the mix
+    ident, max_epe = 0, 0.0
+    sample = ok[:: max(1, len(ok) // 16)][:16]
+    for r in sample:
+        c = torch.from_numpy(r.cost).cuda()
+        m = torch.from_numpy(r.matches).cuda()
+        alone = ex.ctx[0].interp(c, m, r.K, r.a, r.mode).cpu().numpy()
+        mixed = r.flow.cpu().numpy()
+        ident += int(np.array_equal(alone, mixed))
+        max_epe = max(max_epe, float(np.linalg.norm(alone.astype(np.float64) - mixed, axis=2).mean()))
+    ex.close()
+    px = sum(r.pixels for r in ok)
+    out = {"precision": "fp64-everywhere" if precision else "fp32",
+           "requests": len(done), "served": len(ok), "rejected": len(done) - len(ok),
+           "p50_ms": round(percentile_ms([r.latency for r in ok], 50), 3),
+           "p99_ms": round(percentile_ms([r.latency for r in ok], 99), 3),
+           "mpix_s": round(px / wall / 1e6, 2), "wall_s": round(wall, 3), "batches": srv.batches,
+           "overlapped_batches": srv.overlap_events,
+           "alone_vs_mix": {"checked": len(sample), "bitwise_identical": ident,
+                            "max_mean_epe_px": max_epe}}
+    log(f"bench: served {out}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -79,8 +183,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--tile", default="32x32", help="geodesic tile WxH")
+    ap.add_argument("--tile", default="32x16", help="geodesic tile WxH")
     ap.add_argument("--passes", type=int, default=16, help="geodesic passes per call")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--batch-reps", type=int, default=10)
+    ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--served-requests", type=int, default=2000)
+    ap.add_argument("--served-budget", type=int, default=8 << 30)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         log("bench.py: this build runs on one GPU only (--gpus 1); "
@@ -149,6 +258,13 @@ def main():
     epe = np.linalg.norm(flow.cpu().numpy().astype(np.float64) - ref, axis=2)
     log(f"bench: mean EPE vs oracle {epe.mean():.3e} px (max {epe.max():.3e})")
 
+    ctx.close()
+    batched = None if args.no_batched else batched_form(args, np, torch, epic)
+    served = None
+    if not args.no_served:
+        served = {"fp32": served_form(args, np, torch, epic, 0),
+                  "fp64": served_form(args, np, torch, epic, 1)}
+
     cpu = None
     if not args.no_cpu_baseline:
         log("bench: timing the oracle on the host")
@@ -173,8 +289,9 @@ def main():
                    "stage_ms": {k: round(v, 5) for k, v in stages.items()}},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "batched": batched,
+        "served": served,
     }
-    ctx.close()
     print(json.dumps(out), flush=True)
 
 

@@ -80,8 +80,8 @@ typedef struct epic_options {
     double degenerate_tau;  /* eigenvalue ratio at or below which the
                                neighbourhood is near-collinear and LA falls
                                back to NW (decided in FP64); default 1e-9      */
-    int   tile_w, tile_h;   /* geodesic-transform tile (0 = default 32 x 32;
-                               supported: 32x32, 64x16, 64x32)                 */
+    int   tile_w, tile_h;   /* geodesic-transform tile (0 = default 32 x 16;
+                               supported: 32x16, 32x32, 32x64; tile_w is 32)   */
     int   geo_passes;       /* bulk-synchronous passes of the geodesic
                                transform launched per call (0 = default 16,
                                at most 64); a single-workgroup finisher

@@ -57,7 +57,7 @@ class Context:
     def __init__(self, device: int = 0, workspace: int | None = None, *,
                  connectivity: int = 8, la_weight_power: int = 2,
                  precision: int = 0, fp64_route: float = 1e-3,
-                 degenerate_tau: float = 1e-9, tile: tuple[int, int] = (32, 32),
+                 degenerate_tau: float = 1e-9, tile: tuple[int, int] = (32, 16),
                  passes: int = 16):
         torch = _torch()
         L = _lib.load()

@@ -46,9 +46,9 @@ struct Tiling {
 };
 
 Tiling tiling_from(const epic_options& o) {
-    if (o.tile_w == 64 && o.tile_h == 16) return {64, 16};
-    if (o.tile_w == 64 && o.tile_h == 32) return {64, 32};
-    return {32, 32};
+    if (o.tile_h == 32) return {32, 32};
+    if (o.tile_h == 64) return {32, 64};
+    return {32, 16};
 }
 
 size_t pair_bytes(int H, int W, int N) {
@@ -135,7 +135,7 @@ size_t epic_workspace_bytes(int H, int W, int N, int K, int mode, int precision)
         (precision != 0 && precision != 1) || (long long)H * W >= (1LL << 31))
         return 0;
     // the smallest tiling gives the largest tile-state array and queue ring
-    const size_t t = tiles_of(H, W, Tiling{32, 16});
+    const size_t t = tiles_of(H, W, Tiling{32, 16});       // the smallest tile
     return kFixed + 2 * align_up(4 * t) + pair_bytes(H, W, N);
 }
 
@@ -155,7 +155,7 @@ epic_ctx* epic_create(int device, size_t workspace_bytes, const epic_options* op
     o.fp64_route = 1e-3f;
     o.degenerate_tau = 1e-9;
     o.tile_w = 32;
-    o.tile_h = 32;
+    o.tile_h = 16;
     o.geo_passes = 16;
     if (opts) {
         o = *opts;

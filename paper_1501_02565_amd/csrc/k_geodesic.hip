@@ -30,6 +30,8 @@
 //   * A fixed number of passes is launched.  If the last one still changed
 //     a border, a single-workgroup finisher continues the same passes until
 //     the fixpoint, so the result never depends on the pass budget.
+#include <type_traits>
+
 #include "epic_dev.h"
 
 namespace epic {
@@ -43,6 +45,7 @@ struct TileLds {
     static constexpr int LW = TW + 2, LH = TH + 2, NL = LW * LH;
     u64 key[NL];
     float cost[NL];
+    u64 chg[3][LH];          // per round (mod 3): bit x of row y = pixel changed
     int border;
 };
 
@@ -53,17 +56,17 @@ struct TileLds {
 // PPT consecutive pixels, along a row in even rounds and along a column in
 // odd rounds, and sweeps it (forwards, then backwards two rounds later),
 // updating every pixel in place from its 8 (or 4) neighbours.  A straight
-// path therefore advances up to PPT pixels per round.  A round in which no
-// pixel changed is a local fixpoint (every pixel was recomputed from all of
-// its neighbours).
+// path therefore advances up to PPT pixels per round.  Per-row bitmasks
+// record which pixels changed in each round; a run whose neighbourhood did
+// not change in the previous round is skipped (its pixels cannot improve).
+// A round in which no pixel changed is a local fixpoint.
 template <int TW, int TH, int CONN>
 __device__ __forceinline__ int visit_tile(const PairDev& P, int tx, int ty, TileLds<TW, TH>& S, int* error) {
     constexpr int PPT = TW * TH / 256;
-    constexpr int LW = TileLds<TW, TH>::LW, NL = TileLds<TW, TH>::NL;
+    constexpr int LW = TileLds<TW, TH>::LW, LH = TileLds<TW, TH>::LH, NL = TileLds<TW, TH>::NL;
     constexpr int HR = TW / PPT;           // row runs per row
-    constexpr int VG = TH / PPT;           // column runs per column
-    static_assert(PPT * 256 == TW * TH && HR * PPT == TW && VG * PPT == TH && HR * TH == 256 &&
-                      VG * TW == 256, "tile shape");
+    static_assert(PPT * 256 == TW * TH && HR * PPT == TW && HR * TH == 256 && (TH / PPT) * TW == 256 &&
+                      LW <= 64, "tile shape");
     constexpr int DX[8] = {1, -1, 0, 0, 1, -1, 1, -1};
     constexpr int DY[8] = {0, 0, 1, -1, 1, 1, -1, -1};
     const int tid = threadIdx.x;
@@ -83,49 +86,90 @@ __device__ __forceinline__ int visit_tile(const PairDev& P, int tx, int ty, Tile
         S.key[i] = k;
         S.cost[i] = c;
     }
+    for (int i = tid; i < 3 * LH; i += 256) (&S.chg[0][0])[i] = 0ull;
     if (tid == 0) S.border = 0;
     __syncthreads();
-    // original values of this thread's row run (also used for write-back)
-    const int hy = tid / HR, hx = (tid % HR) * PPT;       // row run: (hx.., hy)
-    const int vx = tid % TW, vy = (tid / TW) * PPT;       // column run: (vx, vy..)
+
+    // the two runs of this thread: a row run (hx.., hy) and a column run
+    // (vx, vy..), with their step costs to the 8 neighbours
+    const int hy = tid / HR, hx = (tid % HR) * PPT;
+    const int vx = tid % TW, vy = (tid / TW) * PPT;
+    float wh[PPT][CONN], wv[PPT][CONN];
     u64 orig[PPT];
 #pragma unroll
-    for (int j = 0; j < PPT; ++j) orig[j] = S.key[(hy + 1) * LW + hx + j + 1];
+    for (int j = 0; j < PPT; ++j) {
+        const int ch = (hy + 1) * LW + hx + j + 1, cv = (vy + j + 1) * LW + vx + 1;
+        const float cph = S.cost[ch], cpv = S.cost[cv];
+#pragma unroll
+        for (int k = 0; k < CONN; ++k) {
+            const float len = (k < 4) ? 1.0f : 1.41421356237309515f;
+            wh[j][k] = len * (0.5f * (cph + S.cost[ch + DY[k] * LW + DX[k]]));
+            wv[j][k] = len * (0.5f * (cpv + S.cost[cv + DY[k] * LW + DX[k]]));
+        }
+        orig[j] = S.key[ch];
+    }
+    // neighbourhood masks of the two runs (columns of the run and its halo)
+    const u64 hmask = ((PPT + 2 >= 64) ? ~0ull : ((1ull << (PPT + 2)) - 1)) << hx;   // cols hx-1 .. hx+PPT (+1 offset)
+    const u64 vmask = 7ull << vx;                                                    // cols vx-1 .. vx+1
 
     const int round_cap = 4 * NL + 8;
     for (int round = 0;; ++round) {
         const bool rows = (round & 1) == 0;
-        const bool fwd = (round & 2) == 0;
-        const int bx = rows ? hx : vx, by = rows ? hy : vy;
-        const int sx = rows ? 1 : 0, sy = rows ? 0 : 1;
-        int changed = 0;
+        const u64* prev = S.chg[(round + 2) % 3];     // changes of the previous round
+        u64* cur = S.chg[round % 3];
+        // was anything around this run changed in the previous round?
+        bool active = round == 0;
+        if (!active) {
+            if (rows) {
+                active = ((prev[hy] | prev[hy + 1] | prev[hy + 2]) & hmask) != 0;
+            } else {
+                u64 acc = 0;
 #pragma unroll
-        for (int jj = 0; jj < PPT; ++jj) {
-            const int j = fwd ? jj : PPT - 1 - jj;
-            const int lx = bx + sx * j, ly = by + sy * j;
-            if (lx >= twe || ly >= the) continue;
-            const int ci = (ly + 1) * LW + lx + 1;
-            const float cp = S.cost[ci];
-            u64 kq[CONN];
-            float cq[CONN];
-#pragma unroll
-            for (int k = 0; k < CONN; ++k) {
-                kq[k] = S.key[ci + DY[k] * LW + DX[k]];
-                cq[k] = S.cost[ci + DY[k] * LW + DX[k]];
-            }
-            const u64 cur = S.key[ci];
-            u64 best = cur;
-#pragma unroll
-            for (int k = 0; k < CONN; ++k) {
-                const float len = (k < 4) ? 1.0f : 1.41421356237309515f;
-                const u64 cand = make_key(key_dist(kq[k]) + len * (0.5f * (cp + cq[k])), key_label(kq[k]));
-                best = cand < best ? cand : best;
-            }
-            if (best < cur) {
-                S.key[ci] = best;
-                changed = 1;
+                for (int j = 0; j < PPT + 2; ++j) acc |= prev[vy + j];
+                active = (acc & vmask) != 0;
             }
         }
+        int changed = 0;
+        if (active) {
+            // one sweep of this thread's run; ROWS and FWD are compile-time so
+            // the step-cost registers are indexed statically
+            auto sweep = [&](auto rows_c, auto fwd_c) {
+                constexpr bool ROWS = decltype(rows_c)::value, FWD = decltype(fwd_c)::value;
+#pragma unroll
+                for (int jj = 0; jj < PPT; ++jj) {
+                    const int j = FWD ? jj : PPT - 1 - jj;
+                    const int lx = ROWS ? hx + j : vx, ly = ROWS ? hy : vy + j;
+                    if (lx >= twe || ly >= the) continue;
+                    const int ci = (ly + 1) * LW + lx + 1;
+                    u64 kq[CONN];
+#pragma unroll
+                    for (int k = 0; k < CONN; ++k) kq[k] = S.key[ci + DY[k] * LW + DX[k]];
+                    const u64 now = S.key[ci];
+                    u64 best = now;
+#pragma unroll
+                    for (int k = 0; k < CONN; ++k) {
+                        const float w = ROWS ? wh[j][k] : wv[j][k];
+                        const u64 cand = make_key(key_dist(kq[k]) + w, key_label(kq[k]));
+                        best = cand < best ? cand : best;
+                    }
+                    if (best < now) {
+                        S.key[ci] = best;
+                        atomicOr(&cur[ly + 1], 1ull << (lx + 1));
+                        changed = 1;
+                    }
+                }
+            };
+            using T = std::true_type;
+            using F = std::false_type;
+            switch (round & 3) {
+                case 0: sweep(T{}, T{}); break;
+                case 1: sweep(F{}, T{}); break;
+                case 2: sweep(T{}, F{}); break;
+                default: sweep(F{}, F{}); break;
+            }
+        }
+        // clear the masks the next round will write
+        if (tid < LH) S.chg[(round + 1) % 3][tid] = 0ull;
         if (!__syncthreads_or(changed)) break;
         if (round > round_cap) {
             if (tid == 0) atomicOr(error, 2);
@@ -257,10 +301,10 @@ hipError_t launch_t(const PairDev* d_pairs, const RunDev& run, int passes, hipSt
 hipError_t launch_geodesic(const PairDev* d_pairs, const RunDev& run, int tile_w, int tile_h, int passes,
                            hipStream_t s) {
     const bool c8 = run.conn != 4;
-    if (tile_w == 64 && tile_h == 16)
-        return c8 ? launch_t<64, 16, 8>(d_pairs, run, passes, s) : launch_t<64, 16, 4>(d_pairs, run, passes, s);
-    if (tile_w == 64 && tile_h == 32)
-        return c8 ? launch_t<64, 32, 8>(d_pairs, run, passes, s) : launch_t<64, 32, 4>(d_pairs, run, passes, s);
+    if (tile_h == 16)
+        return c8 ? launch_t<32, 16, 8>(d_pairs, run, passes, s) : launch_t<32, 16, 4>(d_pairs, run, passes, s);
+    if (tile_h == 64)
+        return c8 ? launch_t<32, 64, 8>(d_pairs, run, passes, s) : launch_t<32, 64, 4>(d_pairs, run, passes, s);
     return c8 ? launch_t<32, 32, 8>(d_pairs, run, passes, s) : launch_t<32, 32, 4>(d_pairs, run, passes, s);
 }
 

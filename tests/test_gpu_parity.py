@@ -142,7 +142,7 @@ def test_repeatable(ctx):
 
 
 @pytest.mark.parametrize("opts", [dict(connectivity=4), dict(la_weight_power=1),
-                                  dict(tile=(64, 16)), dict(tile=(64, 32))])
+                                  dict(tile=(32, 16)), dict(tile=(32, 64))])
 def test_options(opts):
     import paper_1501_02565_amd as epic
     sc = random_case(150, 170, 250, seed=20, K=16)

@@ -1,0 +1,60 @@
+"""GPU: the served form.  A Poisson stream of mixed-size pairs goes through
+the continuous-batching server on two slots; every result equals the same
+request computed alone (within the parity tolerance) and matches the oracle
+on sampled requests."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import parity
+from oracle import epic_ref
+from paper_1501_02565_amd.serve import GpuExecutor, Request, Server, percentile_ms
+from scenes import layered_scene
+
+pytestmark = pytest.mark.gpu
+
+
+def _requests(n=40, seed=0):
+    rng = np.random.default_rng(seed)
+    t = np.cumsum(rng.exponential(0.002, n))
+    sizes = [(96, 128), (240, 320), (192, 256), (375, 500)]
+    out = []
+    for i in range(n):
+        H, W = sizes[i % len(sizes)]
+        N = int(rng.integers(100, max(101, H * W // 60)))
+        K = int(rng.choice([16, 50, 100]))
+        sc = layered_scene(H, W, 4, 16.0, N, 3, seed=700 + i, outlier_frac=0.05, K=K)
+        out.append(Request(i, float(t[i]), sc.H, sc.W, sc.N, sc.K, sc.a, sc.mode, sc.cost, sc.matches))
+    return out
+
+
+def test_served_stream_alone_equals_mix():
+    import torch
+    reqs = _requests()
+    ex = GpuExecutor(slots=2, slot_workspace=256 << 20)
+    try:
+        srv = Server(ex, 512 << 20, max_batch=16)
+        done = srv.run(reqs)
+        assert all(r.status == "done" for r in done)
+        assert srv.batches >= 2
+        print(f"batches {srv.batches}, overlapped {srv.overlap_events}, "
+              f"p50 {percentile_ms([r.latency for r in done], 50):.2f} ms, "
+              f"p99 {percentile_ms([r.latency for r in done], 99):.2f} ms", flush=True)
+        identical = 0
+        for r in done:
+            assert r.stats["status"] == 0
+            alone = ex.ctx[0].interp(torch.from_numpy(r.cost).cuda(), torch.from_numpy(r.matches).cuda(),
+                                     r.K, r.a, r.mode).cpu().numpy()
+            mixed = r.flow.cpu().numpy()
+            identical += int(np.array_equal(alone, mixed))
+            epe = np.linalg.norm(alone.astype(np.float64) - mixed, axis=2).mean()
+            assert epe <= parity.EPE_MEAN, (r.rid, epe)
+        print(f"bitwise identical alone vs mix: {identical}/{len(done)}", flush=True)
+        assert identical >= len(done) - 2
+        for r in done[::10]:
+            ref = epic_ref.interp(r.cost, r.matches, r.K, r.a, r.mode)[0]
+            epe = np.linalg.norm(r.flow.cpu().numpy().astype(np.float64) - ref, axis=2).mean()
+            assert epe <= parity.EPE_MEAN
+    finally:
+        ex.close()
