@@ -168,7 +168,8 @@ int epic_get_stats(epic_ctx* ctx, int pair, epic_stats* out);
 
 /* Stage outputs of one epic_interp call for testing; every output pointer
  * is a device pointer and may be NULL.
- *   D        H*W float32 geodesic distance to the nearest match
+ *   D        H*W geodesic distance to the nearest match: float32, or
+ *            float64 for a context created with precision 1
  *   L        H*W int32 nearest-match label
  *   edge_m, edge_n, edge_w   graph edges (m < n), up to max_edges of them,
  *            in no particular order; n_edges (device int) receives the

@@ -164,7 +164,9 @@ class Context:
         dev = cost.device
         if max_edges is None:
             max_edges = 16 * N + 1024
-        D = torch.empty((H, W), dtype=torch.float32, device=dev)
+        # the FP64-everywhere path reports D in double precision
+        ddt = torch.float64 if self.options.precision == 1 else torch.float32
+        D = torch.empty((H, W), dtype=ddt, device=dev)
         L = torch.empty((H, W), dtype=torch.int32, device=dev)
         em = torch.empty(max_edges, dtype=torch.int32, device=dev)
         en = torch.empty(max_edges, dtype=torch.int32, device=dev)

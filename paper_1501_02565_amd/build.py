@@ -9,8 +9,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libepic.so")
-SOURCES = ["k_prep.hip", "k_geodesic.hip", "k_graph.hip", "k_knn_fit.hip",
-           "k_assign.hip", "api.cpp"]
+SOURCES = ["k_prep.hip", "k_geodesic.hip", "k_geodesic64.hip", "k_graph.hip",
+           "k_knn_fit.hip", "k_assign.hip", "api.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -51,10 +51,17 @@ Tiling tiling_from(const epic_options& o) {
     return {32, 16};
 }
 
-size_t pair_bytes(int H, int W, int N) {
+size_t pair_bytes(int H, int W, int N, int precision) {
     const size_t HW = (size_t)H * W;
     const size_t cap = (size_t)hash_cap_for(N);
     size_t b = 0;
+    if (precision == 1) {
+        b += align_up(4 * HW);            // labels
+        b += align_up(8 * cap);           // hval64
+        b += align_up(8 * (size_t)N);     // minin64
+        b += align_up(8 * cap);           // adjw64
+        b += align_up(48 * (size_t)N);    // params64
+    }
     b += align_up(8 * HW);            // keys
     b += align_up(4 * (size_t)N);     // seed_pix
     b += align_up(8 * cap);           // hkey
@@ -136,7 +143,7 @@ size_t epic_workspace_bytes(int H, int W, int N, int K, int mode, int precision)
         return 0;
     // the smallest tiling gives the largest tile-state array and queue ring
     const size_t t = tiles_of(H, W, Tiling{32, 16});       // the smallest tile
-    return kFixed + 2 * align_up(4 * t) + pair_bytes(H, W, N);
+    return kFixed + 2 * align_up(4 * t) + pair_bytes(H, W, N, precision);
 }
 
 epic_ctx* epic_create(int device, size_t workspace_bytes, const epic_options* opts) {
@@ -240,12 +247,13 @@ int run_pairs(epic_ctx* c, const epic_request* reqs, int n, hipStream_t stream, 
         const int v = epic_validate(r.cost, r.H, r.W, r.matches, r.N, r.K, r.a, r.mode, flow_chk);
         if (v != EPIC_OK) return v;
     }
-    const Tiling tl{c->opt.tile_w, c->opt.tile_h};
+    // the FP64 transform runs on 32 x 16 tiles
+    const Tiling tl = c->opt.precision == 1 ? Tiling{32, 16} : Tiling{c->opt.tile_w, c->opt.tile_h};
     // ---- carve the workspace
     size_t total_tiles = 0, need = kFixed;
     for (int i = 0; i < n; ++i) total_tiles += tiles_of(reqs[i].H, reqs[i].W, tl);
     need += 2 * align_up(4 * total_tiles);
-    for (int i = 0; i < n; ++i) need += pair_bytes(reqs[i].H, reqs[i].W, reqs[i].N);
+    for (int i = 0; i < n; ++i) need += pair_bytes(reqs[i].H, reqs[i].W, reqs[i].N, c->opt.precision);
     if (need > c->ws_bytes) return EPIC_ERR_WORKSPACE;
     if (hipSetDevice(c->device) != hipSuccess) return EPIC_ERR_HIP;
 
@@ -323,6 +331,13 @@ int run_pairs(epic_ctx* c, const epic_request* reqs, int n, hipStream_t stream, 
         P.adj = reinterpret_cast<uint2*>(take(8 * cap));
         P.params = reinterpret_cast<float*>(take(24 * (size_t)r.N));
         P.counters = reinterpret_cast<int*>(take(4 * C_NCOUNTERS));
+        if (c->opt.precision == 1) {
+            P.labels = reinterpret_cast<u32*>(take(4 * (size_t)HW));
+            P.hval64 = reinterpret_cast<u64*>(take(8 * cap));
+            P.minin64 = reinterpret_cast<u64*>(take(8 * (size_t)r.N));
+            P.adjw64 = reinterpret_cast<double*>(take(8 * cap));
+            P.params64 = reinterpret_cast<double*>(take(48 * (size_t)r.N));
+        }
         c->last_counters[i] = P.counters;
         if (dbg && i == 0) {
             P.dbg_knn_idx = dbg->knn_idx;
@@ -342,6 +357,7 @@ int run_pairs(epic_ctx* c, const epic_request* reqs, int n, hipStream_t stream, 
     run.dirty[0] = dirty0;
     run.dirty[1] = dirty1;
     run.any = c->g_any;
+    run.any2 = c->g_any + kMaxPasses;
     run.error = c->g_error;
     run.ovf_list = ovf_list;
     run.ovf_count = c->g_error + 8;
@@ -381,7 +397,9 @@ int run_pairs(epic_ctx* c, const epic_request* reqs, int n, hipStream_t stream, 
     mark(0);
     if (e == hipSuccess) e = launch_seed(dd, run, seed_blocks, stream);
     mark(1);
-    if (e == hipSuccess) e = launch_geodesic(dd, run, tl.tw, tl.th, c->passes, stream);
+    if (e == hipSuccess)
+        e = c->opt.precision == 1 ? launch_geodesic64(dd, run, c->passes, seed_blocks, stream)
+                                  : launch_geodesic(dd, run, tl.tw, tl.th, c->passes, stream);
     mark(2);
     if (e == hipSuccess) e = launch_graph_emit(dd, run, pix_blocks, stream);
     mark(3);

@@ -20,6 +20,10 @@ constexpr u64 KEY_INF = 0x7f800000ffffffffull;   // (+inf, no label)
 constexpr u32 NO_LABEL = 0xffffffffu;
 constexpr u64 HASH_EMPTY = ~0ull;
 constexpr u32 FLOAT_INF_BITS = 0x7f800000u;
+constexpr u64 DOUBLE_INF_BITS = 0x7ff0000000000000ull;
+
+__device__ __forceinline__ double dbits(u64 k) { return __longlong_as_double((long long)k); }
+__device__ __forceinline__ u64 bitsd(double d) { return (u64)__double_as_longlong(d); }
 
 __device__ __forceinline__ float key_dist(u64 k) { return __uint_as_float((u32)(k >> 32)); }
 __device__ __forceinline__ u32 key_label(u64 k) { return (u32)k; }
@@ -75,6 +79,12 @@ struct PairDev {
     uint2* adj;             // hash_cap: CSR edges (neighbour id, weight bits)
     float* params;          // N*6
     int* counters;          // C_NCOUNTERS
+    // FP64-everywhere path only (NULL otherwise)
+    u32* labels;            // H*W nearest-match label (keys then hold double D)
+    u64* hval64;            // hash_cap: double bits of the edge weight
+    u64* minin64;           // N: double bits of the lightest incident edge
+    double* adjw64;         // hash_cap: CSR edge weights
+    double* params64;       // N*6
     // optional stage dumps (NULL = off)
     int* dbg_knn_idx;       // N*K
     float* dbg_knn_d;       // N*K
@@ -85,10 +95,17 @@ struct PairDev {
     int* dbg_n_edges;       // device int
 };
 
+// Nearest-match label of pixel i (packed in the key, or in the label array
+// of the FP64 path).
+__device__ __forceinline__ u32 label_at(const PairDev& P, long long i) {
+    return P.labels ? P.labels[i] : key_label(P.keys[i]);
+}
+
 // Globals of one launch sequence (shared by all pairs of a batch).
 struct RunDev {
     u32* dirty[2];          // per tile, by pass parity: tile needs a visit
     int* any;               // per pass: some tile border changed (kMaxPasses)
+    int* any2;              // the same for the label phase of the FP64 path
     int* error;             // global error word
     int* ovf_list;          // K-NN sources to redo with a larger table
     int* ovf_count;
@@ -125,6 +142,8 @@ hipError_t launch_clear(const PairDev* d_pairs, const RunDev& run, int total_blo
 hipError_t launch_seed(const PairDev* d_pairs, const RunDev& run, int total_blocks, hipStream_t s);
 hipError_t launch_geodesic(const PairDev* d_pairs, const RunDev& run, int tile_w, int tile_h,
                            int passes, hipStream_t s);
+hipError_t launch_geodesic64(const PairDev* d_pairs, const RunDev& run, int passes, int seed_blocks,
+                             hipStream_t s);
 hipError_t launch_graph_emit(const PairDev* d_pairs, const RunDev& run, int total_blocks, hipStream_t s);
 hipError_t launch_csr_scan(const PairDev* d_pairs, const RunDev& run, hipStream_t s);
 hipError_t launch_csr_scatter(const PairDev* d_pairs, const RunDev& run, int total_blocks, hipStream_t s);

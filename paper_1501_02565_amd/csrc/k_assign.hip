@@ -4,6 +4,8 @@
 // so the field is piecewise constant for NW and piecewise affine for LA.
 // Pixels of an image without any usable match get NaN.
 //
+// In the FP64 path the models are read in double and the flow is rounded to
+// float at the end.
 // Also: k_unpack splits the packed (D, label) keys for the debug entry point.
 #include "epic_dev.h"
 
@@ -15,10 +17,16 @@ __global__ __launch_bounds__(PIX_BLOCK) void k_assign(const PairDev* __restrict_
     const long long i = (long long)((int)blockIdx.x - P.pix_block_base) * PIX_BLOCK + threadIdx.x;
     const int W = P.W;
     if (i >= (long long)W * P.H) return;
-    const u32 m = key_label(P.keys[i]);
+    const u32 m = P.labels ? P.labels[i] : key_label(P.keys[i]);
     float2 f;
     if (m == NO_LABEL) {
         f.x = f.y = __int_as_float(0x7fc00000);
+    } else if (P.params64) {
+        const double* B = P.params64 + 6LL * m;
+        const double dx = (double)(int)(i % W) - (double)P.matches[4LL * m];
+        const double dy = (double)(int)(i / W) - (double)P.matches[4LL * m + 1];
+        f.x = (float)(B[0] * dx + B[1] * dy + B[4]);
+        f.y = (float)(B[2] * dx + B[3] * dy + B[5]);
     } else {
         const float* B = P.params + 6LL * m;
         const float2 pm = *reinterpret_cast<const float2*>(P.matches + 4LL * m);
@@ -35,6 +43,11 @@ __global__ __launch_bounds__(PIX_BLOCK) void k_unpack(const PairDev* __restrict_
     const long long i = (long long)blockIdx.x * PIX_BLOCK + threadIdx.x;
     if (i >= (long long)P.W * P.H) return;
     const u64 k = P.keys[i];
+    if (P.labels) {                 // FP64 path: D is written as double
+        if (D) reinterpret_cast<double*>(D)[i] = dbits(k);
+        if (L) L[i] = P.labels[i] == NO_LABEL ? -1 : (int)P.labels[i];
+        return;
+    }
     if (D) D[i] = key_dist(k);
     if (L) L[i] = key_label(k) == NO_LABEL ? -1 : (int)key_label(k);
 }

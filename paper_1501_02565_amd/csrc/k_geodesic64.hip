@@ -1,0 +1,313 @@
+// k_geodesic64.hip -- the geodesic Voronoi transform in double precision (the
+// FP64-everywhere path, used for comparison with the FP32 path).
+//
+// Same quantity as k_geodesic.hip: D(p) = min over matches of the
+// discretised geodesic distance of Eq. (3), L(p) = the minimising match,
+// lowest index on ties (Sec. 3.4).  A 96-bit (D, label) pair cannot be
+// relaxed with one 64-bit atomic, so the transform runs in two phases:
+//   1. distances: each pixel's state is the bit pattern of a non-negative
+//      double (ordered like the value), relaxed to the fixpoint -- the
+//      minimum over paths of the left-fold sums D(q) + len*(C(p)+C(q))/2,
+//      evaluated with explicit round-to-nearest adds and multiplies (no
+//      fused multiply-add), so every sum is rounded exactly as a plain
+//      double evaluation of the same expression;
+//   2. labels: with D fixed, L(p) = the lowest label among the neighbours q
+//      with D(q) + step(q, p) == D(p) (the predecessors on shortest
+//      paths), seeds keep their own index.  Its fixpoint is the lowest
+//      match index over all shortest paths, the lexicographic (D, label)
+//      optimum.
+// Both phases use the bulk-synchronous tiled passes of k_geodesic.hip
+// (dirty tiles, Gauss-Seidel line sweeps in LDS, change masks, a
+// single-workgroup finisher) on 32 x 16 tiles.
+#include <type_traits>
+
+#include "epic_dev.h"
+
+namespace epic {
+
+namespace {
+
+constexpr int TW = 32, TH = 16, PPT = 2, LW = TW + 2, LH = TH + 2, NL = LW * LH, HR = TW / PPT;
+enum : int { B_L = 1, B_R = 2, B_T = 4, B_B = 8, B_TL = 16, B_TR = 32, B_BL = 64, B_BR = 128 };
+
+struct Lds64 {
+    u64 dist[NL];            // double bits
+    u32 lab[NL];
+    float cost[NL];
+    u64 chg[3][LH];
+    int border;
+};
+
+__device__ __forceinline__ double step64(float cp, float cq, int k) {
+    const double half = __dmul_rn(0.5, __dadd_rn((double)cp, (double)cq));
+    return k < 4 ? half : __dmul_rn(1.4142135623730951, half);
+}
+
+// PHASE 0: distances; PHASE 1: labels.
+template <int CONN, int PHASE>
+__device__ __forceinline__ int visit64(const PairDev& P, int tx, int ty, Lds64& S, int* error) {
+    constexpr int DX[8] = {1, -1, 0, 0, 1, -1, 1, -1};
+    constexpr int DY[8] = {0, 0, 1, -1, 1, 1, -1, -1};
+    const int tid = threadIdx.x;
+    const int x0 = tx * TW, y0 = ty * TH, W = P.W, H = P.H;
+    const int twe = min(TW, W - x0), the = min(TH, H - y0);
+    for (int i = tid; i < NL; i += 256) {
+        const int ly = i / LW, lxx = i - ly * LW;
+        const int gx = x0 + lxx - 1, gy = y0 + ly - 1;
+        u64 d = DOUBLE_INF_BITS;
+        u32 l = NO_LABEL;
+        float c = 0.0f;
+        if (gx >= 0 && gy >= 0 && gx < W && gy < H) {
+            const long long gi = (long long)gy * W + gx;
+            d = P.keys[gi];
+            if (PHASE == 1) l = P.labels[gi];
+            c = P.cost[gi];
+        }
+        S.dist[i] = d;
+        S.lab[i] = l;
+        S.cost[i] = c;
+    }
+    for (int i = tid; i < 3 * LH; i += 256) (&S.chg[0][0])[i] = 0ull;
+    if (tid == 0) S.border = 0;
+    __syncthreads();
+
+    const int hy = tid / HR, hx = (tid % HR) * PPT;
+    const int vx = tid % TW, vy = (tid / TW) * PPT;
+    double wh[PPT][CONN], wv[PPT][CONN];
+    u64 orig[PPT];
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+        const int ch = (hy + 1) * LW + hx + j + 1, cv = (vy + j + 1) * LW + vx + 1;
+#pragma unroll
+        for (int k = 0; k < CONN; ++k) {
+            wh[j][k] = step64(S.cost[ch], S.cost[ch + DY[k] * LW + DX[k]], k);
+            wv[j][k] = step64(S.cost[cv], S.cost[cv + DY[k] * LW + DX[k]], k);
+        }
+        orig[j] = PHASE == 0 ? S.dist[ch] : (u64)S.lab[ch];
+    }
+    const u64 hmask = ((1ull << (PPT + 2)) - 1) << hx;
+    const u64 vmask = 7ull << vx;
+
+    const int round_cap = 4 * NL + 8;
+    for (int round = 0;; ++round) {
+        const bool rows = (round & 1) == 0;
+        const u64* prev = S.chg[(round + 2) % 3];
+        u64* cur = S.chg[round % 3];
+        bool active = round == 0;
+        if (!active) {
+            if (rows) {
+                active = ((prev[hy] | prev[hy + 1] | prev[hy + 2]) & hmask) != 0;
+            } else {
+                u64 acc = 0;
+#pragma unroll
+                for (int j = 0; j < PPT + 2; ++j) acc |= prev[vy + j];
+                active = (acc & vmask) != 0;
+            }
+        }
+        int changed = 0;
+        if (active) {
+            auto sweep = [&](auto rows_c, auto fwd_c) {
+                constexpr bool ROWS = decltype(rows_c)::value, FWD = decltype(fwd_c)::value;
+#pragma unroll
+                for (int jj = 0; jj < PPT; ++jj) {
+                    const int j = FWD ? jj : PPT - 1 - jj;
+                    const int lx = ROWS ? hx + j : vx, ly = ROWS ? hy : vy + j;
+                    if (lx >= twe || ly >= the) continue;
+                    const int ci = (ly + 1) * LW + lx + 1;
+                    if (PHASE == 0) {
+                        const double now = dbits(S.dist[ci]);
+                        double best = now;
+#pragma unroll
+                        for (int k = 0; k < CONN; ++k) {
+                            const double cand =
+                                __dadd_rn(dbits(S.dist[ci + DY[k] * LW + DX[k]]), ROWS ? wh[j][k] : wv[j][k]);
+                            best = cand < best ? cand : best;
+                        }
+                        if (best < now) {
+                            S.dist[ci] = bitsd(best);
+                            atomicOr(&cur[ly + 1], 1ull << (lx + 1));
+                            changed = 1;
+                        }
+                    } else {
+                        const double dp = dbits(S.dist[ci]);
+                        const u32 now = S.lab[ci];
+                        u32 best = now;
+#pragma unroll
+                        for (int k = 0; k < CONN; ++k) {
+                            const int q = ci + DY[k] * LW + DX[k];
+                            const bool tight = __dadd_rn(dbits(S.dist[q]), ROWS ? wh[j][k] : wv[j][k]) == dp;
+                            const u32 lq = S.lab[q];
+                            best = (tight && lq < best) ? lq : best;
+                        }
+                        if (best < now) {
+                            S.lab[ci] = best;
+                            atomicOr(&cur[ly + 1], 1ull << (lx + 1));
+                            changed = 1;
+                        }
+                    }
+                }
+            };
+            using T = std::true_type;
+            using F = std::false_type;
+            switch (round & 3) {
+                case 0: sweep(T{}, T{}); break;
+                case 1: sweep(F{}, T{}); break;
+                case 2: sweep(T{}, F{}); break;
+                default: sweep(F{}, F{}); break;
+            }
+        }
+        if (tid < LH) S.chg[(round + 1) % 3][tid] = 0ull;
+        if (!__syncthreads_or(changed)) break;
+        if (round > round_cap) {
+            if (tid == 0) atomicOr(error, 2);
+            break;
+        }
+    }
+
+    int bm = 0;
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+        const int lx = hx + j, ly = hy;
+        const int ci = (ly + 1) * LW + lx + 1;
+        const u64 v = PHASE == 0 ? S.dist[ci] : (u64)S.lab[ci];
+        if (lx < twe && ly < the && v != orig[j]) {
+            const long long gi = (long long)(y0 + ly) * W + x0 + lx;
+            if (PHASE == 0) P.keys[gi] = v; else P.labels[gi] = (u32)v;
+            const bool l = lx == 0, r = lx == twe - 1, t = ly == 0, b = ly == the - 1;
+            bm |= (l ? B_L : 0) | (r ? B_R : 0) | (t ? B_T : 0) | (b ? B_B : 0) | ((l && t) ? B_TL : 0) |
+                  ((r && t) ? B_TR : 0) | ((l && b) ? B_BL : 0) | ((r && b) ? B_BR : 0);
+        }
+    }
+    if (bm) atomicOr(&S.border, bm);
+    __syncthreads();
+    const int border = S.border;
+    __syncthreads();
+    return border;
+}
+
+template <int CONN>
+__device__ void mark64(const PairDev& P, const RunDev& run, int tx, int ty, int border, int next) {
+    u32* dirty = run.dirty[next & 1] + P.tile_base;
+    const int nx = P.tiles_x, ny = P.tiles_y;
+    auto mark = [&](int cx, int cy) {
+        if (cx >= 0 && cy >= 0 && cx < nx && cy < ny) dirty[cy * nx + cx] = 1u;
+    };
+    if (border & B_L) mark(tx - 1, ty);
+    if (border & B_R) mark(tx + 1, ty);
+    if (border & B_T) mark(tx, ty - 1);
+    if (border & B_B) mark(tx, ty + 1);
+    if (CONN == 8) {
+        if (border & B_TL) mark(tx - 1, ty - 1);
+        if (border & B_TR) mark(tx + 1, ty - 1);
+        if (border & B_BL) mark(tx - 1, ty + 1);
+        if (border & B_BR) mark(tx + 1, ty + 1);
+    }
+}
+
+}  // namespace
+
+template <int CONN, int PHASE>
+__global__ __launch_bounds__(256) void k_geo64_pass(const PairDev* __restrict__ pairs, RunDev run, int pass) {
+    __shared__ Lds64 S;
+    int* any = PHASE == 0 ? run.any : run.any2;
+    if (pass > 0 && any[pass - 1] == 0) return;
+    const int per_xcd = (run.total_tiles + 7) / 8;
+    const int tile = (int)(blockIdx.x % 8) * per_xcd + (int)(blockIdx.x / 8);
+    if (tile >= run.total_tiles) return;
+    u32* dirty = run.dirty[pass & 1];
+    if (dirty[tile] == 0u) return;
+    const int p = find_pair(run.npairs, tile, [&](int i) { return pairs[i].tile_base; });
+    const PairDev& P = pairs[p];
+    const int lt = tile - P.tile_base;
+    const int tx = lt % P.tiles_x, ty = lt / P.tiles_x;
+    __syncthreads();
+    if (threadIdx.x == 0) dirty[tile] = 0u;
+    const int border = visit64<CONN, PHASE>(P, tx, ty, S, run.error);
+    if (threadIdx.x == 0) {
+        atomicAdd(&P.counters[C_TILE_VISITS], 1);
+        if (border) {
+            mark64<CONN>(P, run, tx, ty, border, pass + 1);
+            any[pass] = 1;
+        }
+    }
+}
+
+template <int CONN, int PHASE>
+__global__ __launch_bounds__(256) void k_geo64_finish(const PairDev* __restrict__ pairs, RunDev run, int pass0) {
+    __shared__ Lds64 S;
+    __shared__ int s_any;
+    int* any = PHASE == 0 ? run.any : run.any2;
+    if (any[pass0 - 1] == 0) return;
+    for (int pass = pass0; pass < pass0 + 65536; ++pass) {
+        if (threadIdx.x == 0) s_any = 0;
+        __syncthreads();
+        u32* dirty = run.dirty[pass & 1];
+        for (int tile = 0; tile < run.total_tiles; ++tile) {
+            if (dirty[tile] == 0u) continue;
+            const int p = find_pair(run.npairs, tile, [&](int i) { return pairs[i].tile_base; });
+            const PairDev& P = pairs[p];
+            const int lt = tile - P.tile_base;
+            const int tx = lt % P.tiles_x, ty = lt / P.tiles_x;
+            __syncthreads();
+            if (threadIdx.x == 0) dirty[tile] = 0u;
+            const int border = visit64<CONN, PHASE>(P, tx, ty, S, run.error);
+            if (threadIdx.x == 0) {
+                atomicAdd(&P.counters[C_TILE_VISITS], 1);
+                if (border) {
+                    mark64<CONN>(P, run, tx, ty, border, pass + 1);
+                    s_any = 1;
+                }
+            }
+            __threadfence_block();
+            __syncthreads();
+        }
+        __syncthreads();
+        if (s_any == 0) return;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicOr(run.error, 1);
+}
+
+// Between the phases: clears the dirty flags left by phase 1 and marks the
+// tiles holding a surviving seed (the sources of the label phase).
+__global__ __launch_bounds__(256) void k_geo64_seed_tiles(const PairDev* __restrict__ pairs, RunDev run) {
+    const int p = find_pair(run.npairs, (int)blockIdx.x, [&](int i) { return pairs[i].seed_block_base; });
+    const PairDev& P = pairs[p];
+    const int m = ((int)blockIdx.x - P.seed_block_base) * blockDim.x + threadIdx.x;
+    if (m >= P.N) return;
+    const int sp = P.seed_pix[m];
+    if (sp < 0 || P.labels[sp] != (u32)m) return;
+    const int t = P.tile_base + (sp / P.W / TH) * P.tiles_x + (sp % P.W) / TW;
+    run.dirty[0][t] = 1u;
+}
+
+__global__ __launch_bounds__(256) void k_geo64_reset(RunDev run) {
+    for (int i = blockIdx.x * 256 + threadIdx.x; i < run.total_tiles; i += gridDim.x * 256) {
+        run.dirty[0][i] = 0u;
+        run.dirty[1][i] = 0u;
+    }
+}
+
+namespace {
+template <int CONN>
+hipError_t launch64_t(const PairDev* d_pairs, const RunDev& run, int passes, int seed_blocks, hipStream_t s) {
+    const int grid = 8 * ((run.total_tiles + 7) / 8);
+    for (int p = 0; p < passes; ++p)
+        hipLaunchKernelGGL((k_geo64_pass<CONN, 0>), dim3(grid), dim3(256), 0, s, d_pairs, run, p);
+    hipLaunchKernelGGL((k_geo64_finish<CONN, 0>), dim3(1), dim3(256), 0, s, d_pairs, run, passes);
+    hipLaunchKernelGGL(k_geo64_reset, dim3((run.total_tiles + 255) / 256), dim3(256), 0, s, run);
+    hipLaunchKernelGGL(k_geo64_seed_tiles, dim3(seed_blocks), dim3(256), 0, s, d_pairs, run);
+    for (int p = 0; p < passes; ++p)
+        hipLaunchKernelGGL((k_geo64_pass<CONN, 1>), dim3(grid), dim3(256), 0, s, d_pairs, run, p);
+    hipLaunchKernelGGL((k_geo64_finish<CONN, 1>), dim3(1), dim3(256), 0, s, d_pairs, run, passes);
+    return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_geodesic64(const PairDev* d_pairs, const RunDev& run, int passes, int seed_blocks,
+                             hipStream_t s) {
+    return run.conn == 4 ? launch64_t<4>(d_pairs, run, passes, seed_blocks, s)
+                         : launch64_t<8>(d_pairs, run, passes, seed_blocks, s);
+}
+
+}  // namespace epic

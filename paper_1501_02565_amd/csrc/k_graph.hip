@@ -21,6 +21,8 @@
 //                    and turns degrees into CSR row offsets.
 //   k_csr_scatter    writes both directions of every edge into CSR and the
 //                    lightest incident edge of every match.
+#include <type_traits>
+
 #include "epic_dev.h"
 
 namespace epic {
@@ -38,7 +40,8 @@ __device__ __forceinline__ u32 hash_slot(u64 key, int shift) {
 namespace {
 // Inserts (key, weight) into the pair's global hash with an atomic min on
 // the weight; the first insertion of a key raises both endpoints' degree.
-__device__ __forceinline__ void global_insert(const PairDev& P, u64 hk, u32 wb) {
+template <bool F64>
+__device__ __forceinline__ void global_insert(const PairDev& P, u64 hk, u64 wb) {
     const u32 mask = (u32)P.hash_cap - 1u;
     u32 h = hash_slot(hk, P.hash_shift);
     for (int probe = 0; probe < P.hash_cap; ++probe) {
@@ -48,13 +51,13 @@ __device__ __forceinline__ void global_insert(const PairDev& P, u64 hk, u32 wb) 
             if (prev == HASH_EMPTY) {
                 atomicAdd(&P.deg[(u32)(hk >> 32)], 1u);
                 atomicAdd(&P.deg[(u32)hk], 1u);
-                atomicMin(&P.hval[h], wb);
+                if (F64) atomicMin(&P.hval64[h], wb); else atomicMin(&P.hval[h], (u32)wb);
                 return;
             }
             cur = prev;
         }
         if (cur == hk) {
-            atomicMin(&P.hval[h], wb);
+            if (F64) atomicMin(&P.hval64[h], wb); else atomicMin(&P.hval[h], (u32)wb);
             return;
         }
         h = (h + 1u) & mask;
@@ -66,16 +69,17 @@ __device__ __forceinline__ void global_insert(const PairDev& P, u64 hk, u32 wb) 
 // Each block handles PIX_BLOCK consecutive pixels.  Candidates are first
 // reduced in a block-local LDS hash (adjacent pixels mostly share their pair
 // of cells), then each distinct edge goes to the global hash once per block.
-template <int CONN>
+template <int CONN, bool F64>
 __global__ __launch_bounds__(PIX_BLOCK) void k_graph_emit(const PairDev* __restrict__ pairs, RunDev run) {
     constexpr int LCAP = 4 * PIX_BLOCK;               // >= candidates per block
+    using V = typename std::conditional<F64, u64, u32>::type;
     __shared__ u64 lkey[LCAP];
-    __shared__ u32 lval[LCAP];
+    __shared__ V lval[LCAP];
     const int p = find_pair(run.npairs, (int)blockIdx.x, [&](int i) { return pairs[i].pix_block_base; });
     const PairDev& P = pairs[p];
     for (int i = threadIdx.x; i < LCAP; i += PIX_BLOCK) {
         lkey[i] = HASH_EMPTY;
-        lval[i] = FLOAT_INF_BITS;
+        lval[i] = F64 ? (V)DOUBLE_INF_BITS : (V)FLOAT_INF_BITS;
     }
     __syncthreads();
     const long long i = (long long)((int)blockIdx.x - P.pix_block_base) * PIX_BLOCK + threadIdx.x;
@@ -83,9 +87,8 @@ __global__ __launch_bounds__(PIX_BLOCK) void k_graph_emit(const PairDev* __restr
     if (i < (long long)W * H) {
         const int x = (int)(i % W), y = (int)(i / W);
         const u64 kp = P.keys[i];
-        const u32 lp = key_label(kp);
+        const u32 lp = F64 ? P.labels[i] : key_label(kp);
         if (lp != NO_LABEL) {
-            const float dp = key_dist(kp);
             const float cp = P.cost[i];
             // forward half-neighbourhood: (1,0), (0,1), (1,1), (-1,1)
             constexpr int HX[4] = {1, 0, 1, -1};
@@ -96,14 +99,21 @@ __global__ __launch_bounds__(PIX_BLOCK) void k_graph_emit(const PairDev* __restr
                 if (qx < 0 || qx >= W || qy >= H) continue;
                 const long long qi = (long long)qy * W + qx;
                 const u64 kq = P.keys[qi];
-                const u32 lq = key_label(kq);
+                const u32 lq = F64 ? P.labels[qi] : key_label(kq);
                 if (lq == lp || lq == NO_LABEL) continue;
-                const float len = (k < 2) ? 1.0f : 1.41421356237309515f;
-                const float w = len * (0.5f * (cp + P.cost[qi]));
-                const float cand = (dp + w) + key_dist(kq);
+                V wb;
+                if (F64) {
+                    // (D(p) + step) + D(q), each operation rounded (no fused multiply-add)
+                    const double half = __dmul_rn(0.5, __dadd_rn((double)cp, (double)P.cost[qi]));
+                    const double step = k < 2 ? half : __dmul_rn(1.4142135623730951, half);
+                    wb = (V)bitsd(__dadd_rn(__dadd_rn(dbits(kp), step), dbits(kq)));
+                } else {
+                    const float len = (k < 2) ? 1.0f : 1.41421356237309515f;
+                    const float w = len * (0.5f * (cp + P.cost[qi]));
+                    wb = (V)__float_as_uint((key_dist(kp) + w) + key_dist(kq));
+                }
                 const u32 m = min(lp, lq), n = max(lp, lq);
                 const u64 hk = ((u64)m << 32) | n;
-                const u32 wb = __float_as_uint(cand);
                 u32 h = (u32)(((hk ^ (hk >> 29)) * 0x9e3779b97f4a7c15ull) >> 54) & (LCAP - 1);
                 bool done = false;
                 for (int probe = 0; probe < LCAP; ++probe) {
@@ -115,13 +125,13 @@ __global__ __launch_bounds__(PIX_BLOCK) void k_graph_emit(const PairDev* __restr
                     }
                     h = (h + 1u) & (LCAP - 1);
                 }
-                if (!done) global_insert(P, hk, wb);
+                if (!done) global_insert<F64>(P, hk, wb);
             }
         }
     }
     __syncthreads();
     for (int j = threadIdx.x; j < LCAP; j += PIX_BLOCK)
-        if (lkey[j] != HASH_EMPTY) global_insert(P, lkey[j], lval[j]);
+        if (lkey[j] != HASH_EMPTY) global_insert<F64>(P, lkey[j], lval[j]);
 }
 
 // One workgroup of 1024 threads per pair.
@@ -136,7 +146,7 @@ __global__ __launch_bounds__(1024) void k_csr_scan(const PairDev* __restrict__ p
     int used = 0;
     for (int m = tid; m < N; m += 1024) {
         const int sp = P.seed_pix[m];
-        if (sp >= 0 && key_label(P.keys[sp]) == (u32)m) ++used;
+        if (sp >= 0 && label_at(P, sp) == (u32)m) ++used;
     }
     if (used) atomicAdd(&s_used, used);
     // exclusive scan of the degrees: each thread owns a contiguous chunk
@@ -182,7 +192,8 @@ __global__ __launch_bounds__(SLOT_BLOCK) void k_csr_scatter(const PairDev* __res
     const u64 key = P.hkey[h];
     if (key == HASH_EMPTY) return;
     const u32 m = (u32)(key >> 32), n = (u32)key;
-    const u32 wb = P.hval[h];
+    const bool f64 = run.precision == 1;
+    const u32 wb = f64 ? __float_as_uint((float)dbits(P.hval64[h])) : P.hval[h];
     const float w = __uint_as_float(wb);
     const u32 pm = P.row_ptr[m] + atomicAdd(&P.fill[m], 1u);
     const u32 pn = P.row_ptr[n] + atomicAdd(&P.fill[n], 1u);
@@ -190,6 +201,13 @@ __global__ __launch_bounds__(SLOT_BLOCK) void k_csr_scatter(const PairDev* __res
     if (pn < (u32)P.hash_cap) P.adj[pn] = make_uint2(m, wb);
     atomicMin(&P.minin[m], wb);
     atomicMin(&P.minin[n], wb);
+    if (f64) {
+        const u64 wd = P.hval64[h];
+        if (pm < (u32)P.hash_cap) P.adjw64[pm] = dbits(wd);
+        if (pn < (u32)P.hash_cap) P.adjw64[pn] = dbits(wd);
+        atomicMin(&P.minin64[m], wd);
+        atomicMin(&P.minin64[n], wd);
+    }
     if (P.dbg_em) {
         const int e = atomicAdd(P.dbg_n_edges, 1);
         if (e < P.dbg_max_edges) {
@@ -201,10 +219,14 @@ __global__ __launch_bounds__(SLOT_BLOCK) void k_csr_scatter(const PairDev* __res
 }
 
 hipError_t launch_graph_emit(const PairDev* d_pairs, const RunDev& run, int total_blocks, hipStream_t s) {
-    if (run.conn == 4)
-        hipLaunchKernelGGL(k_graph_emit<4>, dim3(total_blocks), dim3(PIX_BLOCK), 0, s, d_pairs, run);
-    else
-        hipLaunchKernelGGL(k_graph_emit<8>, dim3(total_blocks), dim3(PIX_BLOCK), 0, s, d_pairs, run);
+    const bool f64 = run.precision == 1;
+    if (run.conn == 4) {
+        if (f64) hipLaunchKernelGGL((k_graph_emit<4, true>), dim3(total_blocks), dim3(PIX_BLOCK), 0, s, d_pairs, run);
+        else hipLaunchKernelGGL((k_graph_emit<4, false>), dim3(total_blocks), dim3(PIX_BLOCK), 0, s, d_pairs, run);
+    } else {
+        if (f64) hipLaunchKernelGGL((k_graph_emit<8, true>), dim3(total_blocks), dim3(PIX_BLOCK), 0, s, d_pairs, run);
+        else hipLaunchKernelGGL((k_graph_emit<8, false>), dim3(total_blocks), dim3(PIX_BLOCK), 0, s, d_pairs, run);
+    }
     return hipGetLastError();
 }
 

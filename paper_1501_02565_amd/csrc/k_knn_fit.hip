@@ -31,6 +31,8 @@
 // A source whose visited set outgrows the small LDS table is put on an
 // overflow list and redone by a second launch with a table four times
 // larger; only if that overflows too is the pair's status set.
+#include <type_traits>
+
 #include "epic_dev.h"
 
 namespace epic {
@@ -40,6 +42,11 @@ namespace {
 __device__ __forceinline__ float wave_min(float v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o));
+    return v;
+}
+__device__ __forceinline__ double wave_min(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o));
     return v;
 }
 __device__ __forceinline__ float wave_sum(float v) {
@@ -69,37 +76,55 @@ __device__ __forceinline__ u32 node_slot(int v, int hbits) {
     return ((u32)v * 2654435761u) >> (32 - hbits);
 }
 
-template <int VCAP>
+template <int VCAP, bool F64>
 struct KnnLds {
     static constexpr int HCAP = 2 * VCAP;
+    using DT = typename std::conditional<F64, u64, u32>::type;     // distance bits
+    using RT = typename std::conditional<F64, double, float>::type;
     int node[VCAP];
-    u32 dist[VCAP];          // float bits
-    u32 minin[VCAP];         // float bits of the lightest incident edge
+    DT dist[VCAP];
+    DT minin[VCAP];          // lightest incident edge
     u32 rs[VCAP];            // adjacency start
     u32 deg[VCAP];
     unsigned char state[VCAP];   // 0 frontier, 1 settled
     unsigned short newly[VCAP];
-    u64 buf[VCAP];           // node table (HCAP ints), then sort buffer
+    u64 buf[VCAP];           // node table (HCAP ints), then sort keys
+    int snode[F64 ? VCAP : 1];   // FP64: node of each sort key
     unsigned short hidx[HCAP];
     int f_off[65];
     u32 f_start[64];
-    float f_d[64];
+    RT f_d[64];
     int nvis, nnew, ncand, ovf;
 };
 
+template <bool F64>
+__device__ __forceinline__ typename std::conditional<F64, double, float>::type from_bits(
+    typename std::conditional<F64, u64, u32>::type b) {
+    if constexpr (F64) return dbits(b); else return __uint_as_float(b);
+}
+template <bool F64>
+__device__ __forceinline__ typename std::conditional<F64, u64, u32>::type to_bits(
+    typename std::conditional<F64, double, float>::type v) {
+    if constexpr (F64) return bitsd(v); else return __float_as_uint(v);
+}
+
 // Loads a node's adjacency range and lightest edge into entry e.
-__device__ __forceinline__ void fetch_node(const PairDev& P, int v, u32* rs, u32* deg, u32* minin, int e) {
+template <int VCAP, bool F64>
+__device__ __forceinline__ void fetch_node(const PairDev& P, int v, KnnLds<VCAP, F64>& S, int e) {
     const u32 a = P.row_ptr[v], b = P.row_ptr[v + 1];
-    minin[e] = P.minin[v];
-    rs[e] = a;
-    deg[e] = b - a;
+    if constexpr (F64) S.minin[e] = P.minin64[v]; else S.minin[e] = P.minin[v];
+    S.rs[e] = a;
+    S.deg[e] = b - a;
 }
 
 // Processes source `s` of pair P; returns false when the visited set did not
 // fit the table (nothing written then).
-template <int VCAP, int KMAX>
-__device__ __forceinline__ bool knn_fit_one(const PairDev& P, const RunDev& run, int s, KnnLds<VCAP>& S) {
-    constexpr int HCAP = KnnLds<VCAP>::HCAP;
+template <int VCAP, int KMAX, bool F64>
+__device__ __forceinline__ bool knn_fit_one(const PairDev& P, const RunDev& run, int s, KnnLds<VCAP, F64>& S) {
+    using RT = typename KnnLds<VCAP, F64>::RT;
+    using DT = typename KnnLds<VCAP, F64>::DT;
+    const RT RINF = (RT)INFINITY;
+    constexpr int HCAP = KnnLds<VCAP, F64>::HCAP;
     constexpr int HBITS = (HCAP == 512) ? 9 : (HCAP == 1024) ? 10 : (HCAP == 2048) ? 11 : 12;
     static_assert((1 << HBITS) == HCAP, "hash size");
     constexpr int R = KMAX / 64;
@@ -116,38 +141,38 @@ __device__ __forceinline__ bool knn_fit_one(const PairDev& P, const RunDev& run,
         S.nvis = 1;
         S.ovf = 0;
         S.node[0] = s;
-        S.dist[0] = 0u;
+        S.dist[0] = 0;
         S.state[0] = 0;
-        fetch_node(P, s, S.rs, S.deg, S.minin, 0);
+        fetch_node<VCAP, F64>(P, s, S, 0);
         const u32 h = node_slot(s, HBITS);
         htab[h] = s;
         S.hidx[h] = 0;
     }
     __syncthreads();
 
-    float dstop;
+    RT dstop;
     for (;;) {
         const int nv = min(S.nvis, VCAP);
-        float dmin = __int_as_float(0x7f800000);
+        RT dmin = RINF;
         for (int e = lane; e < nv; e += 64)
-            if (S.state[e] == 0) dmin = fminf(dmin, __uint_as_float(S.dist[e]));
+            if (S.state[e] == 0) dmin = fmin(dmin, from_bits<F64>(S.dist[e]));
         dmin = wave_min(dmin);
         if (lane == 0) S.nnew = 0;
         __syncthreads();
         // one scan: count settled nodes below dmin, settle the final ones
         int below = 0;
         for (int e = lane; e < nv; e += 64) {
-            const float d = __uint_as_float(S.dist[e]);
+            const RT d = from_bits<F64>(S.dist[e]);
             if (S.state[e] == 1) {
                 below += d < dmin ? 1 : 0;
-            } else if (d <= dmin + __uint_as_float(S.minin[e])) {
+            } else if (d <= dmin + from_bits<F64>(S.minin[e])) {
                 S.state[e] = 1;
                 S.newly[atomicAdd(&S.nnew, 1)] = (unsigned short)e;
             }
         }
         below = wave_sum_i(below);
         __syncthreads();
-        if (below >= keff || dmin == __int_as_float(0x7f800000) || S.ovf) {
+        if (below >= keff || dmin == RINF || S.ovf) {
             dstop = dmin;    // nodes settled in this scan lie at or above dmin
             break;
         }
@@ -159,7 +184,7 @@ __device__ __forceinline__ bool knn_fit_one(const PairDev& P, const RunDev& run,
                 const int e = S.newly[base + lane];
                 dg = S.deg[e];
                 S.f_start[lane] = S.rs[e];
-                S.f_d[lane] = __uint_as_float(S.dist[e]);
+                S.f_d[lane] = from_bits<F64>(S.dist[e]);
             }
             const int incl = wave_incl_scan(dg, lane);
             const int total = __shfl(incl, 63);
@@ -170,16 +195,18 @@ __device__ __forceinline__ bool knn_fit_one(const PairDev& P, const RunDev& run,
                 const int j = j0 + lane;
                 const bool act = j < total;
                 int v = -1;
-                float cand = 0.0f;
+                RT cand = 0;
                 if (act) {
                     int lo = 0, hi = cnt - 1;       // last i with f_off[i] <= j
                     while (lo < hi) {
                         const int mid = (lo + hi + 1) >> 1;
                         if (S.f_off[mid] <= j) lo = mid; else hi = mid - 1;
                     }
-                    const uint2 ed = P.adj[S.f_start[lo] + (u32)(j - S.f_off[lo])];
+                    const u32 ei = S.f_start[lo] + (u32)(j - S.f_off[lo]);
+                    const uint2 ed = P.adj[ei];
                     v = (int)ed.x;
-                    cand = S.f_d[lo] + __uint_as_float(ed.y);
+                    if constexpr (F64) cand = S.f_d[lo] + P.adjw64[ei];
+                    else cand = S.f_d[lo] + __uint_as_float(ed.y);
                 }
                 // phase A: find or claim v's slot
                 int h = -1;
@@ -203,9 +230,9 @@ __device__ __forceinline__ bool knn_fit_one(const PairDev& P, const RunDev& run,
                     const int e = atomicAdd(&S.nvis, 1);
                     if (e < VCAP) {
                         S.node[e] = v;
-                        S.dist[e] = 0x7f800000u;
+                        S.dist[e] = to_bits<F64>(RINF);
                         S.state[e] = 0;
-                        fetch_node(P, v, S.rs, S.deg, S.minin, e);
+                        fetch_node<VCAP, F64>(P, v, S, e);
                         S.hidx[h] = (unsigned short)e;
                     } else {
                         S.hidx[h] = 0xffff;
@@ -216,7 +243,7 @@ __device__ __forceinline__ bool knn_fit_one(const PairDev& P, const RunDev& run,
                 // phase C: relax
                 if (act && h >= 0) {
                     const int e = S.hidx[h];
-                    if (e != 0xffff && S.state[e] == 0) atomicMin(&S.dist[e], __float_as_uint(cand));
+                    if (e != 0xffff && S.state[e] == 0) atomicMin(&S.dist[e], to_bits<F64>(cand));
                 }
                 __syncthreads();
             }
@@ -228,16 +255,32 @@ __device__ __forceinline__ bool knn_fit_one(const PairDev& P, const RunDev& run,
     const int nv = min(S.nvis, VCAP);
     if (lane == 0) S.ncand = 0;
     __syncthreads();
+    // sort keys: FP32 packs (distance bits, index) into one word; FP64 sorts
+    // (distance bits, index) pairs held in two arrays
+    auto key_node = [&](int j) -> int { if constexpr (F64) return S.snode[j]; else return (int)(u32)S.buf[j]; };
+    auto key_dist = [&](int j) -> RT {
+        if constexpr (F64) return dbits(S.buf[j]); else return __uint_as_float((u32)(S.buf[j] >> 32));
+    };
     for (int e = lane; e < nv; e += 64) {
-        const float d = __uint_as_float(S.dist[e]);
-        if (S.state[e] == 1 && d < dstop)
-            S.buf[atomicAdd(&S.ncand, 1)] = ((u64)S.dist[e] << 32) | (u32)S.node[e];
+        const RT d = from_bits<F64>(S.dist[e]);
+        if (S.state[e] == 1 && d < dstop) {
+            const int pos = atomicAdd(&S.ncand, 1);
+            if constexpr (F64) {
+                S.buf[pos] = S.dist[e];
+                S.snode[pos] = S.node[e];
+            } else {
+                S.buf[pos] = ((u64)S.dist[e] << 32) | (u32)S.node[e];
+            }
+        }
     }
     __syncthreads();
     const int nc = S.ncand;
     int p2 = 1;
     while (p2 < nc) p2 <<= 1;
-    for (int i = nc + lane; i < p2; i += 64) S.buf[i] = ~0ull;
+    for (int i = nc + lane; i < p2; i += 64) {
+        S.buf[i] = ~0ull;
+        if constexpr (F64) S.snode[i] = 0x7fffffff;
+    }
     __syncthreads();
     for (int k = 2; k <= p2; k <<= 1) {
         for (int j = k >> 1; j > 0; j >>= 1) {
@@ -246,9 +289,23 @@ __device__ __forceinline__ bool knn_fit_one(const PairDev& P, const RunDev& run,
                 if (ixj > i) {
                     const u64 a = S.buf[i], b = S.buf[ixj];
                     const bool up = (i & k) == 0;
-                    if (up ? (a > b) : (a < b)) {
+                    bool gt, lt;
+                    if constexpr (F64) {
+                        const int na = S.snode[i], nb = S.snode[ixj];
+                        gt = a > b || (a == b && na > nb);
+                        lt = a < b || (a == b && na < nb);
+                    } else {
+                        gt = a > b;
+                        lt = a < b;
+                    }
+                    if (up ? gt : lt) {
                         S.buf[i] = b;
                         S.buf[ixj] = a;
+                        if constexpr (F64) {
+                            const int t = S.snode[i];
+                            S.snode[i] = S.snode[ixj];
+                            S.snode[ixj] = t;
+                        }
                     }
                 }
             }
@@ -259,9 +316,8 @@ __device__ __forceinline__ bool knn_fit_one(const PairDev& P, const RunDev& run,
     if (P.dbg_knn_idx) {
         for (int j = lane; j < K; j += 64) {
             const bool ok = j < n;
-            P.dbg_knn_idx[(long long)s * K + j] = ok ? (int)(u32)S.buf[j] : -1;
-            P.dbg_knn_d[(long long)s * K + j] =
-                ok ? __uint_as_float((u32)(S.buf[j] >> 32)) : __int_as_float(0x7f800000);
+            P.dbg_knn_idx[(long long)s * K + j] = ok ? key_node(j) : -1;
+            P.dbg_knn_d[(long long)s * K + j] = ok ? (float)key_dist(j) : __int_as_float(0x7f800000);
         }
     }
 
@@ -278,9 +334,8 @@ __device__ __forceinline__ bool knn_fit_one(const PairDev& P, const RunDev& run,
         const int j = lane + 64 * r;
         dx[r] = dy[r] = du[r] = dv[r] = kk[r] = ww[r] = 0.f;
         if (j < n) {
-            const u64 key = S.buf[j];
-            const int node = (int)(u32)key;
-            const float d = __uint_as_float((u32)(key >> 32));
+            const int node = key_node(j);
+            const float d = (float)key_dist(j);
             const float4 mn = *reinterpret_cast<const float4*>(M + 4LL * node);
             dx[r] = mn.x - xm;
             dy[r] = mn.y - ym;
@@ -328,7 +383,7 @@ __device__ __forceinline__ bool knn_fit_one(const PairDev& P, const RunDev& run,
         const float disc = sqrtf((sxx - syy) * (sxx - syy) + 4.0f * sxy * sxy);
         const float l1 = 0.5f * (tr + disc);
         const float ratio = l1 > 0.f ? (det / l1) / l1 : 0.f;
-        need64 = run.precision == 1 || n < 3 || !(ratio >= run.fp64_route);
+        need64 = F64 || n < 3 || !(ratio >= run.fp64_route);
         if (!need64) {
             const float b00 = (syy * sxu - sxy * syu) / det, b01 = (sxx * syu - sxy * sxu) / det;
             const float b10 = (syy * sxv - sxy * syv) / det, b11 = (sxx * syv - sxy * sxv) / det;
@@ -337,7 +392,7 @@ __device__ __forceinline__ bool knn_fit_one(const PairDev& P, const RunDev& run,
             out[5] = vm + sv / sw - (b10 * mx + b11 * my);
         }
     }
-    if (P.mode == 0 && run.precision == 1) need64 = true;
+    if (F64) need64 = true;
     if (need64) {
         // FP64: re-accumulate from the inputs and solve (or fall back to NW)
         const double xmd = xm, ymd = ym;
@@ -349,9 +404,8 @@ __device__ __forceinline__ bool knn_fit_one(const PairDev& P, const RunDev& run,
             const int j = lane + 64 * r;
             Dx[r] = Dy[r] = Du[r] = Dv[r] = Dw[r] = 0.0;
             if (j < n) {
-                const u64 key = S.buf[j];
-                const int node = (int)(u32)key;
-                const double d = (double)__uint_as_float((u32)(key >> 32));
+                const int node = key_node(j);
+                const double d = (double)key_dist(j);
                 const double x = M[4LL * node + 0], y = M[4LL * node + 1];
                 Dx[r] = x - xmd;
                 Dy[r] = y - ymd;
@@ -397,6 +451,12 @@ __device__ __forceinline__ bool knn_fit_one(const PairDev& P, const RunDev& run,
             }
         }
         for (int i = 0; i < 6; ++i) out[i] = (float)o[i];
+        if (F64 && lane < 6) {
+            double v = o[0];
+#pragma unroll
+            for (int i = 1; i < 6; ++i) v = lane == i ? o[i] : v;
+            P.params64[6LL * s + lane] = v;
+        }
         if (lane == 0) {
             if (P.mode == 1) atomicAdd(&P.counters[C_FP64], 1);
             if (degenerate) atomicAdd(&P.counters[C_DEGENERATE], 1);
@@ -427,15 +487,15 @@ __device__ __forceinline__ bool knn_active(const PairDev& P, int s) {
     // it (its status already reports EPIC_ERR_CAPACITY)
     const bool graph_ok = (P.counters[C_OVERFLOW] & 1) == 0;
     const int sp = P.seed_pix[s];
-    return graph_ok && sp >= 0 && key_label(P.keys[sp]) == (u32)s && P.counters[C_KEFF] > 0;
+    return graph_ok && sp >= 0 && label_at(P, sp) == (u32)s && P.counters[C_KEFF] > 0;
 }
 
 }  // namespace
 
 // First launch: one block (one wavefront) per match of every pair.
-template <int VCAP, int KMAX>
+template <int VCAP, int KMAX, bool F64>
 __global__ __launch_bounds__(64) void k_knn_fit(const PairDev* __restrict__ pairs, RunDev run) {
-    __shared__ KnnLds<VCAP> S;
+    __shared__ KnnLds<VCAP, F64> S;
     const int p = find_pair(run.npairs, (int)blockIdx.x, [&](int i) { return pairs[i].src_block_base; });
     const PairDev& P = pairs[p];
     const int s = (int)blockIdx.x - P.src_block_base;
@@ -443,22 +503,22 @@ __global__ __launch_bounds__(64) void k_knn_fit(const PairDev* __restrict__ pair
         knn_fit_inactive(P, s);
         return;
     }
-    if (!knn_fit_one<VCAP, KMAX>(P, run, s, S) && threadIdx.x == 0)
+    if (!knn_fit_one<VCAP, KMAX, F64>(P, run, s, S) && threadIdx.x == 0)
         run.ovf_list[atomicAdd(run.ovf_count, 1)] = (int)blockIdx.x;
 }
 
 // Second launch: the matches whose visited set did not fit, with a larger
 // table.  A fixed grid walks the overflow list.
-template <int VCAP, int KMAX>
+template <int VCAP, int KMAX, bool F64>
 __global__ __launch_bounds__(64) void k_knn_fit_retry(const PairDev* __restrict__ pairs, RunDev run) {
-    __shared__ KnnLds<VCAP> S;
+    __shared__ KnnLds<VCAP, F64> S;
     const int count = *run.ovf_count;
     for (int i = (int)blockIdx.x; i < count; i += (int)gridDim.x) {
         const int gb = run.ovf_list[i];
         const int p = find_pair(run.npairs, gb, [&](int k) { return pairs[k].src_block_base; });
         const PairDev& P = pairs[p];
         const int s = gb - P.src_block_base;
-        if (!knn_fit_one<VCAP, KMAX>(P, run, s, S)) {
+        if (!knn_fit_one<VCAP, KMAX, F64>(P, run, s, S)) {
             knn_fit_inactive(P, s);
             if (threadIdx.x == 0) atomicOr(&P.counters[C_OVERFLOW], 2);
         }
@@ -466,19 +526,27 @@ __global__ __launch_bounds__(64) void k_knn_fit_retry(const PairDev* __restrict_
     }
 }
 
-hipError_t launch_knn_fit(const PairDev* d_pairs, const RunDev& run, int total_blocks, int kmax,
-                          hipStream_t s) {
+namespace {
+template <bool F64>
+void launch_knn_t(const PairDev* d_pairs, const RunDev& run, int total_blocks, int kmax, hipStream_t s) {
     const int retry_grid = 512;
     if (kmax <= 64) {
-        hipLaunchKernelGGL((k_knn_fit<256, 64>), dim3(total_blocks), dim3(64), 0, s, d_pairs, run);
-        hipLaunchKernelGGL((k_knn_fit_retry<1024, 64>), dim3(retry_grid), dim3(64), 0, s, d_pairs, run);
+        hipLaunchKernelGGL((k_knn_fit<256, 64, F64>), dim3(total_blocks), dim3(64), 0, s, d_pairs, run);
+        hipLaunchKernelGGL((k_knn_fit_retry<1024, 64, F64>), dim3(retry_grid), dim3(64), 0, s, d_pairs, run);
     } else if (kmax <= 128) {
-        hipLaunchKernelGGL((k_knn_fit<256, 128>), dim3(total_blocks), dim3(64), 0, s, d_pairs, run);
-        hipLaunchKernelGGL((k_knn_fit_retry<2048, 128>), dim3(retry_grid), dim3(64), 0, s, d_pairs, run);
+        hipLaunchKernelGGL((k_knn_fit<256, 128, F64>), dim3(total_blocks), dim3(64), 0, s, d_pairs, run);
+        hipLaunchKernelGGL((k_knn_fit_retry<2048, 128, F64>), dim3(retry_grid), dim3(64), 0, s, d_pairs, run);
     } else {
-        hipLaunchKernelGGL((k_knn_fit<512, 256>), dim3(total_blocks), dim3(64), 0, s, d_pairs, run);
-        hipLaunchKernelGGL((k_knn_fit_retry<2048, 256>), dim3(retry_grid), dim3(64), 0, s, d_pairs, run);
+        hipLaunchKernelGGL((k_knn_fit<512, 256, F64>), dim3(total_blocks), dim3(64), 0, s, d_pairs, run);
+        hipLaunchKernelGGL((k_knn_fit_retry<2048, 256, F64>), dim3(retry_grid), dim3(64), 0, s, d_pairs, run);
     }
+}
+}  // namespace
+
+hipError_t launch_knn_fit(const PairDev* d_pairs, const RunDev& run, int total_blocks, int kmax,
+                          hipStream_t s) {
+    if (run.precision == 1) launch_knn_t<true>(d_pairs, run, total_blocks, kmax, s);
+    else launch_knn_t<false>(d_pairs, run, total_blocks, kmax, s);
     return hipGetLastError();
 }
 

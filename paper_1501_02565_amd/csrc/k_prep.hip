@@ -20,15 +20,21 @@ __global__ __launch_bounds__(256) void k_clear(const PairDev* __restrict__ pairs
     const long long stride = (long long)P.init_blocks * blockDim.x;
     const long long i0 = (long long)lb * blockDim.x + threadIdx.x;
     const long long HW = (long long)P.H * P.W;
-    for (long long i = i0; i < HW; i += stride) P.keys[i] = KEY_INF;
+    const bool f64 = run.precision == 1;
+    for (long long i = i0; i < HW; i += stride) {
+        P.keys[i] = f64 ? DOUBLE_INF_BITS : KEY_INF;
+        if (f64) P.labels[i] = NO_LABEL;
+    }
     for (long long i = i0; i < P.hash_cap; i += stride) {
         P.hkey[i] = HASH_EMPTY;
         P.hval[i] = FLOAT_INF_BITS;
+        if (f64) P.hval64[i] = DOUBLE_INF_BITS;
     }
     for (long long i = i0; i < P.N; i += stride) {
         P.deg[i] = 0u;
         P.fill[i] = 0u;
         P.minin[i] = FLOAT_INF_BITS;
+        if (f64) P.minin64[i] = DOUBLE_INF_BITS;
     }
     const int ntiles = P.tiles_x * P.tiles_y;
     for (long long i = i0; i < ntiles; i += stride) {
@@ -37,7 +43,10 @@ __global__ __launch_bounds__(256) void k_clear(const PairDev* __restrict__ pairs
     }
     if (i0 < C_NCOUNTERS) P.counters[i0] = 0;
     if (i0 == 0 && P.dbg_n_edges) *P.dbg_n_edges = 0;
-    if (p == 0 && i0 < kMaxPasses) run.any[i0] = 0;
+    if (p == 0 && i0 < kMaxPasses) {
+        run.any[i0] = 0;
+        run.any2[i0] = 0;
+    }
     if (p == 0 && i0 == 0) {
         *run.error = 0;
         *run.ovf_count = 0;
@@ -58,7 +67,12 @@ __global__ __launch_bounds__(256) void k_seed(const PairDev* __restrict__ pairs,
         if (fx >= 0.0 && fy >= 0.0 && fx < (double)P.W && fy < (double)P.H) {
             const int ix = (int)fx, iy = (int)fy;
             pix = iy * P.W + ix;
-            atomicMin(&P.keys[pix], make_key(0.0f, (u32)m));
+            if (run.precision == 1) {
+                P.keys[pix] = 0ull;                      // D = 0.0 (double bits)
+                atomicMin(&P.labels[pix], (u32)m);
+            } else {
+                atomicMin(&P.keys[pix], make_key(0.0f, (u32)m));
+            }
             const int t = P.tile_base + (iy / run.tile_h) * P.tiles_x + ix / run.tile_w;
             run.dirty[0][t] = 1u;
         }

@@ -1,0 +1,116 @@
+"""GPU: the precision policy.  FP32 distances and fits with FP64 only for
+ill-conditioned affine fits (default); an FP64-everywhere path for
+comparison, which reproduces the FP64 oracle's distances, labels, graph and
+neighbour lists exactly; and the error of each result against the oracle."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import parity
+from oracle import epic_ref
+from scenes import config_scene, random_case
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx64():
+    import paper_1501_02565_amd as epic
+    c = epic.Context(0, precision=1)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def ctx32():
+    import paper_1501_02565_amd as epic
+    c = epic.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.mark.parametrize("case", ["random", "config1", "config2"])
+def test_fp64_everywhere_reproduces_the_oracle(ctx64, case):
+    sc = {"random": lambda: random_case(130, 150, 200, seed=31, K=16, outside=2, duplicates=3),
+          "config1": lambda: config_scene(1), "config2": lambda: config_scene(2)}[case]()
+    print(f"[case] {sc.name}", flush=True)
+    g = parity.gpu_stages(ctx64, sc)
+    r = parity.ref_stages(sc)
+    assert g["D"].dtype == np.float64
+    np.testing.assert_array_equal(g["D"], r["D"])              # bit-exact
+    np.testing.assert_array_equal(g["L"], r["L"])
+    ge = sorted(zip(g["em"].tolist(), g["en"].tolist(), g["ew"].tolist()))
+    re_ = sorted(zip(r["em"].tolist(), r["en"].tolist(), np.float32(r["ew"]).tolist()))
+    assert ge == re_
+    K = r["K"]
+    np.testing.assert_array_equal(g["knn_idx"][:, :K], r["knn_idx"])
+    np.testing.assert_array_equal(g["knn_d"][:, :K], np.float32(r["knn_d"]))
+    epe = np.linalg.norm(g["flow"].astype(np.float64) - r["flow"], axis=2)
+    print(f"FP64 path: mean EPE {epe.mean():.2e}, max {epe.max():.2e}", flush=True)
+    assert epe.mean() <= 1e-5 and epe.max() <= 1e-3
+
+
+def test_fp32_and_fp64_error_against_oracle(ctx32, ctx64):
+    """The error of each path is stated; FP64 is the more accurate."""
+    sc = config_scene(2)
+    r = parity.ref_stages(sc)
+    out = {}
+    for name, c in (("fp32", ctx32), ("fp64", ctx64)):
+        g = parity.gpu_stages(c, sc)
+        epe = np.linalg.norm(g["flow"].astype(np.float64) - r["flow"], axis=2)
+        dl = float((g["L"] != r["L"]).mean())
+        same = g["L"] == r["L"]
+        drel = np.abs(g["D"].astype(np.float64)[same] - r["D"][same]) / np.maximum(r["D"][same], 1e-30)
+        out[name] = (float(epe.mean()), float(epe.max()), float(drel.max()), dl)
+        print(f"{name}: mean EPE {epe.mean():.2e} max {epe.max():.2e}; max rel D err {drel.max():.2e}; "
+              f"label diff {dl:.2e}", flush=True)
+    assert out["fp32"][0] <= parity.EPE_MEAN and out["fp32"][2] <= parity.REL
+    assert out["fp64"][0] <= out["fp32"][0] and out["fp64"][2] == 0.0 and out["fp64"][3] == 0.0
+
+
+def _collinear_case():
+    """Matches on three horizontal lines separated by high-cost walls, so
+    every neighbourhood lies on one line: two lines are jittered vertically
+    (near-collinear, routed to FP64) and one is exactly straight
+    (degenerate, NW fallback)."""
+    rng = np.random.default_rng(5)
+    H, W = 60, 200
+    pts = []
+    for y, jit in ((10, 0.05), (30, 0.0), (50, 0.2)):
+        for x in range(5, 195, 6):
+            pts.append((x + rng.uniform(-1e-3, 1e-3), y + rng.uniform(-jit, jit)))
+    m = np.zeros((len(pts), 4), np.float32)
+    m[:, :2] = pts
+    m[:, 2] = m[:, 0] + 2.0 + 0.01 * m[:, 0]
+    m[:, 3] = m[:, 1] - 1.0
+    sc = random_case(H, W, 10, seed=6, K=8)
+    sc.matches = m
+    sc.K = 8
+    # a wall between the lines keeps each line's neighbourhoods on the line
+    sc.cost[18:22, :] = 50.0
+    sc.cost[38:42, :] = 50.0
+    return sc
+
+
+def test_ill_conditioned_fits_routed_to_fp64(ctx32):
+    import torch
+    sc = _collinear_case()
+    g = parity.gpu_stages(ctx32, sc)
+    st = g["stats"]
+    r = parity.ref_stages(sc)
+    n_deg_ref = int((r["status"] == 2).sum())
+    print(f"fp64 fits {st['n_fp64_fits']}, degenerate gpu {st['n_degenerate']} oracle {n_deg_ref}", flush=True)
+    assert st["n_fp64_fits"] > 0
+    assert st["n_degenerate"] == n_deg_ref
+    parity.check_flow(g, r)
+
+
+def test_route_everything_to_fp64_agrees():
+    import paper_1501_02565_amd as epic
+    sc = config_scene(1)
+    with epic.Context(0, fp64_route=1e30) as c:
+        g = parity.gpu_stages(c, sc)
+    assert g["stats"]["n_fp64_fits"] == g["stats"]["n_used"]
+    r = parity.ref_stages(sc)
+    parity.check_flow(g, r)
