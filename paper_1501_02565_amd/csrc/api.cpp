@@ -60,6 +60,7 @@ size_t pair_bytes(int H, int W, int N, int precision) {
         b += align_up(8 * cap);           // hval64
         b += align_up(8 * (size_t)N);     // minin64
         b += align_up(8 * cap);           // adjw64
+        b += align_up(8 * cap);           // nbmin64
         b += align_up(48 * (size_t)N);    // params64
     }
     b += align_up(8 * HW);            // keys
@@ -68,7 +69,8 @@ size_t pair_bytes(int H, int W, int N, int precision) {
     b += align_up(4 * cap);           // hval
     b += 3 * align_up(4 * (size_t)N); // deg, fill, minin
     b += align_up(4 * ((size_t)N + 1));
-    b += align_up(8 * cap);           // adjacency (neighbour, weight)
+    b += align_up(16 * cap);          // adjacency records
+    b += align_up(4 * cap);           // neighbour's lightest edge
     b += align_up(4 * (size_t)N);     // K-NN overflow list share
     b += align_up(24 * (size_t)N);    // params
     b += align_up(4 * C_NCOUNTERS);
@@ -328,7 +330,8 @@ int run_pairs(epic_ctx* c, const epic_request* reqs, int n, hipStream_t stream, 
         P.fill = reinterpret_cast<u32*>(take(4 * (size_t)r.N));
         P.minin = reinterpret_cast<u32*>(take(4 * (size_t)r.N));
         P.row_ptr = reinterpret_cast<u32*>(take(4 * ((size_t)r.N + 1)));
-        P.adj = reinterpret_cast<uint2*>(take(8 * cap));
+        P.adj = reinterpret_cast<uint4*>(take(16 * cap));
+        P.nbmin = reinterpret_cast<u32*>(take(4 * cap));
         P.params = reinterpret_cast<float*>(take(24 * (size_t)r.N));
         P.counters = reinterpret_cast<int*>(take(4 * C_NCOUNTERS));
         if (c->opt.precision == 1) {
@@ -336,6 +339,7 @@ int run_pairs(epic_ctx* c, const epic_request* reqs, int n, hipStream_t stream, 
             P.hval64 = reinterpret_cast<u64*>(take(8 * cap));
             P.minin64 = reinterpret_cast<u64*>(take(8 * (size_t)r.N));
             P.adjw64 = reinterpret_cast<double*>(take(8 * cap));
+            P.nbmin64 = reinterpret_cast<u64*>(take(8 * cap));
             P.params64 = reinterpret_cast<double*>(take(48 * (size_t)r.N));
         }
         c->last_counters[i] = P.counters;

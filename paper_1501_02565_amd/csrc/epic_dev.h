@@ -76,7 +76,9 @@ struct PairDev {
     u32* fill;              // N
     u32* row_ptr;           // N + 1
     u32* minin;             // N: float bits of the lightest incident edge
-    uint2* adj;             // hash_cap: CSR edges (neighbour id, weight bits)
+    uint4* adj;             // hash_cap: CSR edges (neighbour id, weight bits,
+                            //   neighbour's CSR start, neighbour's degree)
+    u32* nbmin;             // hash_cap: float bits of the neighbour's lightest edge
     float* params;          // N*6
     int* counters;          // C_NCOUNTERS
     // FP64-everywhere path only (NULL otherwise)
@@ -84,6 +86,7 @@ struct PairDev {
     u64* hval64;            // hash_cap: double bits of the edge weight
     u64* minin64;           // N: double bits of the lightest incident edge
     double* adjw64;         // hash_cap: CSR edge weights
+    u64* nbmin64;           // hash_cap: double bits of the neighbour's lightest edge
     double* params64;       // N*6
     // optional stage dumps (NULL = off)
     int* dbg_knn_idx;       // N*K

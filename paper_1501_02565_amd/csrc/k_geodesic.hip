@@ -38,6 +38,15 @@ namespace epic {
 
 namespace {
 
+// Minimum of two doubles as one v_min_f64.  The operands are packed keys
+// (never NaN patterns), so the IEEE-mode canonicalisation the compiler would
+// insert before a minnum is not needed.
+__device__ __forceinline__ double min_f64(double a, double b) {
+    double r;
+    __asm__("v_min_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+
 enum : int { B_L = 1, B_R = 2, B_T = 4, B_B = 8, B_TL = 16, B_TR = 32, B_BL = 64, B_BR = 128 };
 
 template <int TW, int TH>
@@ -45,7 +54,7 @@ struct TileLds {
     static constexpr int LW = TW + 2, LH = TH + 2, NL = LW * LH;
     u64 key[NL];
     float cost[NL];
-    u64 chg[3][LH];          // per round (mod 3): bit x of row y = pixel changed
+    int flag[3];             // per round (mod 3): some pixel of the tile changed
     int border;
 };
 
@@ -53,13 +62,20 @@ struct TileLds {
 // Returns (to every thread) the mask of borders with a changed pixel.
 //
 // In-tile relaxation is Gauss-Seidel over lines: each thread owns a run of
-// PPT consecutive pixels, along a row in even rounds and along a column in
-// odd rounds, and sweeps it (forwards, then backwards two rounds later),
-// updating every pixel in place from its 8 (or 4) neighbours.  A straight
-// path therefore advances up to PPT pixels per round.  Per-row bitmasks
-// record which pixels changed in each round; a run whose neighbourhood did
-// not change in the previous round is skipped (its pixels cannot improve).
-// A round in which no pixel changed is a local fixpoint.
+// PPT consecutive pixels along a row and one along a column.  A round sweeps
+// the row run forwards, the column run forwards, the row run backwards and
+// the column run backwards, updating every pixel in place from its 8 (or 4)
+// neighbours; the workgroup only meets at the end of a round.  Wavefronts
+// may then be in different sweeps at once, so a pixel's row-run and
+// column-run owners can race on it.  Every written value is the length of a
+// real path and every pixel is relaxed in every round, so a lost update only
+// costs another round: a round in which no pixel improved leaves every pixel
+// at the minimum over its neighbours, which is the fixpoint.
+//
+// A key (D bits, label) with D >= 0 read as an IEEE double is a non-negative
+// value below the NaN range whose order is the unsigned order of the key
+// (denormals are kept for doubles in these kernels), so the lexicographic
+// minimum over the neighbours is a chain of double minima.
 template <int TW, int TH, int CONN>
 __device__ __forceinline__ int visit_tile(const PairDev& P, int tx, int ty, TileLds<TW, TH>& S, int* error) {
     constexpr int PPT = TW * TH / 256;
@@ -86,7 +102,7 @@ __device__ __forceinline__ int visit_tile(const PairDev& P, int tx, int ty, Tile
         S.key[i] = k;
         S.cost[i] = c;
     }
-    for (int i = tid; i < 3 * LH; i += 256) (&S.chg[0][0])[i] = 0ull;
+    if (tid < 3) S.flag[tid] = 0;
     if (tid == 0) S.border = 0;
     __syncthreads();
 
@@ -108,69 +124,49 @@ __device__ __forceinline__ int visit_tile(const PairDev& P, int tx, int ty, Tile
         }
         orig[j] = S.key[ch];
     }
-    // neighbourhood masks of the two runs (columns of the run and its halo)
-    const u64 hmask = ((PPT + 2 >= 64) ? ~0ull : ((1ull << (PPT + 2)) - 1)) << hx;   // cols hx-1 .. hx+PPT (+1 offset)
-    const u64 vmask = 7ull << vx;                                                    // cols vx-1 .. vx+1
-
     const int round_cap = 4 * NL + 8;
     for (int round = 0;; ++round) {
-        const bool rows = (round & 1) == 0;
-        const u64* prev = S.chg[(round + 2) % 3];     // changes of the previous round
-        u64* cur = S.chg[round % 3];
-        // was anything around this run changed in the previous round?
-        bool active = round == 0;
-        if (!active) {
-            if (rows) {
-                active = ((prev[hy] | prev[hy + 1] | prev[hy + 2]) & hmask) != 0;
-            } else {
-                u64 acc = 0;
-#pragma unroll
-                for (int j = 0; j < PPT + 2; ++j) acc |= prev[vy + j];
-                active = (acc & vmask) != 0;
-            }
-        }
         int changed = 0;
-        if (active) {
-            // one sweep of this thread's run; ROWS and FWD are compile-time so
-            // the step-cost registers are indexed statically
-            auto sweep = [&](auto rows_c, auto fwd_c) {
-                constexpr bool ROWS = decltype(rows_c)::value, FWD = decltype(fwd_c)::value;
+        // one sweep of one of this thread's runs; ROWS and FWD are
+        // compile-time so the step-cost registers are indexed statically
+        auto sweep = [&](auto rows_c, auto fwd_c) {
+            constexpr bool ROWS = decltype(rows_c)::value, FWD = decltype(fwd_c)::value;
 #pragma unroll
-                for (int jj = 0; jj < PPT; ++jj) {
-                    const int j = FWD ? jj : PPT - 1 - jj;
-                    const int lx = ROWS ? hx + j : vx, ly = ROWS ? hy : vy + j;
-                    if (lx >= twe || ly >= the) continue;
-                    const int ci = (ly + 1) * LW + lx + 1;
-                    u64 kq[CONN];
+            for (int jj = 0; jj < PPT; ++jj) {
+                const int j = FWD ? jj : PPT - 1 - jj;
+                const int lx = ROWS ? hx + j : vx, ly = ROWS ? hy : vy + j;
+                if (lx >= twe || ly >= the) continue;
+                const int ci = (ly + 1) * LW + lx + 1;
+                u64 kq[CONN];
 #pragma unroll
-                    for (int k = 0; k < CONN; ++k) kq[k] = S.key[ci + DY[k] * LW + DX[k]];
-                    const u64 now = S.key[ci];
-                    u64 best = now;
+                for (int k = 0; k < CONN; ++k) kq[k] = S.key[ci + DY[k] * LW + DX[k]];
+                const u64 now = S.key[ci];
+                double best = __longlong_as_double((long long)now);
 #pragma unroll
-                    for (int k = 0; k < CONN; ++k) {
-                        const float w = ROWS ? wh[j][k] : wv[j][k];
-                        const u64 cand = make_key(key_dist(kq[k]) + w, key_label(kq[k]));
-                        best = cand < best ? cand : best;
-                    }
-                    if (best < now) {
-                        S.key[ci] = best;
-                        atomicOr(&cur[ly + 1], 1ull << (lx + 1));
-                        changed = 1;
-                    }
+                for (int k = 0; k < CONN; ++k) {
+                    const float w = ROWS ? wh[j][k] : wv[j][k];
+                    const u64 cand = make_key(key_dist(kq[k]) + w, key_label(kq[k]));
+                    best = min_f64(best, __longlong_as_double((long long)cand));
                 }
-            };
-            using T = std::true_type;
-            using F = std::false_type;
-            switch (round & 3) {
-                case 0: sweep(T{}, T{}); break;
-                case 1: sweep(F{}, T{}); break;
-                case 2: sweep(T{}, F{}); break;
-                default: sweep(F{}, F{}); break;
+                const u64 bk = (u64)__double_as_longlong(best);
+                if (bk < now) {
+                    S.key[ci] = bk;
+                    changed = 1;
+                }
             }
-        }
-        // clear the masks the next round will write
-        if (tid < LH) S.chg[(round + 1) % 3][tid] = 0ull;
-        if (!__syncthreads_or(changed)) break;
+        };
+        using T = std::true_type;
+        using F = std::false_type;
+        sweep(T{}, T{});
+        sweep(F{}, T{});
+        sweep(T{}, F{});
+        sweep(F{}, F{});
+        // flag this round's changes per wavefront (the flag of the next
+        // round was last read two rounds ago) and meet
+        if (tid == 0) S.flag[(round + 1) % 3] = 0;
+        if (__builtin_amdgcn_ballot_w64(changed != 0) != 0ull && (tid & 63) == 0) S.flag[round % 3] = 1;
+        __syncthreads();
+        if (S.flag[round % 3] == 0) break;
         if (round > round_cap) {
             if (tid == 0) atomicOr(error, 2);
             break;

@@ -35,6 +35,7 @@ struct Lds64 {
     u32 lab[NL];
     float cost[NL];
     u64 chg[3][LH];
+    int flag[3];             // per round (mod 3): some pixel of the tile changed
     int border;
 };
 
@@ -68,6 +69,7 @@ __device__ __forceinline__ int visit64(const PairDev& P, int tx, int ty, Lds64& 
         S.cost[i] = c;
     }
     for (int i = tid; i < 3 * LH; i += 256) (&S.chg[0][0])[i] = 0ull;
+    if (tid < 3) S.flag[tid] = 0;
     if (tid == 0) S.border = 0;
     __syncthreads();
 
@@ -157,7 +159,10 @@ __device__ __forceinline__ int visit64(const PairDev& P, int tx, int ty, Lds64& 
             }
         }
         if (tid < LH) S.chg[(round + 1) % 3][tid] = 0ull;
-        if (!__syncthreads_or(changed)) break;
+        if (tid == 0) S.flag[(round + 1) % 3] = 0;
+        if (__builtin_amdgcn_ballot_w64(changed != 0) != 0ull && (tid & 63) == 0) S.flag[round % 3] = 1;
+        __syncthreads();
+        if (S.flag[round % 3] == 0) break;
         if (round > round_cap) {
             if (tid == 0) atomicOr(error, 2);
             break;

@@ -19,11 +19,17 @@
 //                    insertion of an edge raises both endpoints' degree.
 //   k_csr_scan       one workgroup per pair: counts usable matches, clamps K,
 //                    and turns degrees into CSR row offsets.
-//   k_csr_scatter    writes both directions of every edge into CSR and the
-//                    lightest incident edge of every match.
+//                    Every insertion also lowers both endpoints' lightest
+//                    incident edge (the minimum over a node's candidates is
+//                    the minimum over its edges).
+//   k_csr_scatter    writes both directions of every edge into CSR.  Each
+//                    record also carries the neighbour's CSR range and
+//                    lightest incident edge, so the K-NN search learns all it
+//                    needs about a newly reached node from the edge itself.
 #include <type_traits>
 
 #include "epic_dev.h"
+#include "wave.h"
 
 namespace epic {
 
@@ -51,13 +57,22 @@ __device__ __forceinline__ void global_insert(const PairDev& P, u64 hk, u64 wb) 
             if (prev == HASH_EMPTY) {
                 atomicAdd(&P.deg[(u32)(hk >> 32)], 1u);
                 atomicAdd(&P.deg[(u32)hk], 1u);
-                if (F64) atomicMin(&P.hval64[h], wb); else atomicMin(&P.hval[h], (u32)wb);
-                return;
+                cur = hk;
+            } else {
+                cur = prev;
             }
-            cur = prev;
         }
         if (cur == hk) {
-            if (F64) atomicMin(&P.hval64[h], wb); else atomicMin(&P.hval[h], (u32)wb);
+            const u32 m = (u32)(hk >> 32), n = (u32)hk;
+            if (F64) {
+                atomicMin(&P.hval64[h], wb);
+                atomicMin(&P.minin64[m], wb);
+                atomicMin(&P.minin64[n], wb);
+            } else {
+                atomicMin(&P.hval[h], (u32)wb);
+                atomicMin(&P.minin[m], (u32)wb);
+                atomicMin(&P.minin[n], (u32)wb);
+            }
             return;
         }
         h = (h + 1u) & mask;
@@ -134,48 +149,74 @@ __global__ __launch_bounds__(PIX_BLOCK) void k_graph_emit(const PairDev* __restr
         if (lkey[j] != HASH_EMPTY) global_insert<F64>(P, lkey[j], lval[j]);
 }
 
-// One workgroup of 1024 threads per pair.
+// One workgroup of 1024 threads per pair.  Each thread sums a contiguous
+// chunk of degrees (a multiple of 4, read as uint4), the chunk sums are
+// scanned within each wavefront (DPP) and across the 16 wavefronts, and each
+// thread writes its chunk's row offsets.
 __global__ __launch_bounds__(1024) void k_csr_scan(const PairDev* __restrict__ pairs, RunDev run) {
     const PairDev& P = pairs[blockIdx.x];
-    __shared__ int s_used;
-    __shared__ u32 s_part[1024];
-    const int tid = threadIdx.x;
+    __shared__ int s_used[16];
+    __shared__ u32 s_wave[16];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int N = P.N;
-    if (tid == 0) s_used = 0;
-    __syncthreads();
     int used = 0;
     for (int m = tid; m < N; m += 1024) {
         const int sp = P.seed_pix[m];
         if (sp >= 0 && label_at(P, sp) == (u32)m) ++used;
     }
-    if (used) atomicAdd(&s_used, used);
-    // exclusive scan of the degrees: each thread owns a contiguous chunk
-    const int chunk = (N + 1023) / 1024;
-    const int b = tid * chunk, e = min(N, b + chunk);
+    used = wave::sum(used);
+    const int chunk = ((N + 1023) / 1024 + 3) & ~3;
+    const int b = min(N, tid * chunk), e = min(N, b + chunk);
     u32 sum = 0;
-    for (int m = b; m < e; ++m) sum += P.deg[m];
-    s_part[tid] = sum;
+    if (e - b == chunk) {
+        for (int m = b; m < e; m += 4) {
+            const uint4 d = *reinterpret_cast<const uint4*>(P.deg + m);
+            sum += d.x + d.y + d.z + d.w;
+        }
+    } else {
+        for (int m = b; m < e; ++m) sum += P.deg[m];
+    }
+    const u32 incl = (u32)wave::incl_scan((int)sum);
+    if (lane == 63) {
+        s_wave[wid] = incl;
+        s_used[wid] = used;
+    }
     __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-        const u32 v = tid >= off ? s_part[tid - off] : 0u;
-        __syncthreads();
-        s_part[tid] += v;
-        __syncthreads();
+    u32 base = 0;
+    for (int w = 0; w < wid; ++w) base += s_wave[w];
+    u32 run_sum = base + incl - sum;
+    if (e - b == chunk) {
+        for (int m = b; m < e; m += 4) {
+            const uint4 d = *reinterpret_cast<const uint4*>(P.deg + m);
+            uint4 o;
+            o.x = run_sum;
+            o.y = o.x + d.x;
+            o.z = o.y + d.y;
+            o.w = o.z + d.z;
+            run_sum = o.w + d.w;
+            *reinterpret_cast<uint4*>(P.row_ptr + m) = o;
+        }
+    } else {
+        for (int m = b; m < e; ++m) {
+            P.row_ptr[m] = run_sum;
+            run_sum += P.deg[m];
+        }
     }
-    u32 run_sum = s_part[tid] - sum;
-    for (int m = b; m < e; ++m) {
-        P.row_ptr[m] = run_sum;
-        run_sum += P.deg[m];
+    u32 two_e_total = 0;
+    int u_total = 0;
+    for (int w = 0; w < 16; ++w) {
+        two_e_total += s_wave[w];
+        u_total += s_used[w];
     }
-    if (tid == 1023) P.row_ptr[N] = s_part[1023];
+    if (tid == 0) P.row_ptr[N] = two_e_total;
     if (tid == 0) {
-        const int u = s_used;
+        const int u = u_total;
         P.counters[C_USED] = u;
         P.counters[C_DUPLICATE] = N - P.counters[C_OUTSIDE] - u;
         P.counters[C_KEFF] = min(P.K, u);
         int status = 0;
         if (u == 0) status = -3;                                       // EPIC_ERR_NO_MATCHES
-        const u32 two_e = s_part[1023];       // every edge counted at both ends
+        const u32 two_e = two_e_total;        // every edge counted at both ends
         P.counters[C_EDGES] = (int)(two_e / 2);
         if ((long long)two_e > (long long)P.hash_cap) P.counters[C_OVERFLOW] |= 1;
         if (P.counters[C_OVERFLOW]) status = -6;                       // EPIC_ERR_CAPACITY
@@ -195,18 +236,26 @@ __global__ __launch_bounds__(SLOT_BLOCK) void k_csr_scatter(const PairDev* __res
     const bool f64 = run.precision == 1;
     const u32 wb = f64 ? __float_as_uint((float)dbits(P.hval64[h])) : P.hval[h];
     const float w = __uint_as_float(wb);
-    const u32 pm = P.row_ptr[m] + atomicAdd(&P.fill[m], 1u);
-    const u32 pn = P.row_ptr[n] + atomicAdd(&P.fill[n], 1u);
-    if (pm < (u32)P.hash_cap) P.adj[pm] = make_uint2(n, wb);
-    if (pn < (u32)P.hash_cap) P.adj[pn] = make_uint2(m, wb);
-    atomicMin(&P.minin[m], wb);
-    atomicMin(&P.minin[n], wb);
+    const u32 rm = P.row_ptr[m], rm1 = P.row_ptr[m + 1];
+    const u32 rn = P.row_ptr[n], rn1 = P.row_ptr[n + 1];
+    const u32 pm = rm + atomicAdd(&P.fill[m], 1u);
+    const u32 pn = rn + atomicAdd(&P.fill[n], 1u);
+    const bool okm = pm < (u32)P.hash_cap, okn = pn < (u32)P.hash_cap;
+    if (okm) P.adj[pm] = make_uint4(n, wb, rn, rn1 - rn);
+    if (okn) P.adj[pn] = make_uint4(m, wb, rm, rm1 - rm);
     if (f64) {
         const u64 wd = P.hval64[h];
-        if (pm < (u32)P.hash_cap) P.adjw64[pm] = dbits(wd);
-        if (pn < (u32)P.hash_cap) P.adjw64[pn] = dbits(wd);
-        atomicMin(&P.minin64[m], wd);
-        atomicMin(&P.minin64[n], wd);
+        if (okm) {
+            P.adjw64[pm] = dbits(wd);
+            P.nbmin64[pm] = P.minin64[n];
+        }
+        if (okn) {
+            P.adjw64[pn] = dbits(wd);
+            P.nbmin64[pn] = P.minin64[m];
+        }
+    } else {
+        if (okm) P.nbmin[pm] = P.minin[n];
+        if (okn) P.nbmin[pn] = P.minin[m];
     }
     if (P.dbg_em) {
         const int e = atomicAdd(P.dbg_n_edges, 1);

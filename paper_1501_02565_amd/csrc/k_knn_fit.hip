@@ -2,17 +2,21 @@
 // per-match interpolation model (Algorithm 1, steps 4-6; Sec. 3.2-3.4).
 //
 // One wavefront per match s:
-//  1. Dijkstra from s on the match graph, with the visited set held in LDS
-//     (open-addressing node -> entry table).  When a node enters the table
-//     its adjacency range and lightest incident edge are fetched with it, so
-//     each step needs one round of global loads (the settled nodes' packed
-//     (neighbour, weight) edges).  Several frontier nodes are settled per
-//     step: a frontier node v with tentative d(v) is final once
-//     d(v) <= dmin + lightest_edge(v), where dmin is the smallest tentative
-//     distance on the frontier (no unsettled node can still lower it).  The
-//     edges of all nodes settled in a step are relaxed in parallel, one lane
-//     per edge.  Float sums are monotone, so the distances equal those of a
-//     sequential Dijkstra in the same precision.
+//  1. Dijkstra from s on the match graph.  The visited set lives in LDS:
+//     entries e (tentative distance, lightest incident edge, CSR range,
+//     node) owned by lane e % 64, and an open-addressing node -> entry
+//     table.  Several frontier nodes are settled per step: a frontier node v
+//     with tentative d(v) is final once d(v) <= dmin + lightest_edge(v),
+//     where dmin is the smallest tentative distance on the frontier (no
+//     unsettled node can still lower it).  The edges of all nodes settled in
+//     a step are relaxed together, one lane per edge, in windows of 256
+//     edges: a prefix sum of the settled nodes' degrees places their edge
+//     segments, a prefix maximum over marked segment starts tells every lane
+//     whose edge it holds.  Every CSR record carries the neighbour's CSR
+//     range and lightest edge, so one round of global loads per window is
+//     all a step needs.  Float sums are monotone, so the distances equal
+//     those of a sequential Dijkstra in the same precision, and a settled
+//     distance is never lowered again.
 //  2. The search stops once at least K settled nodes lie strictly below the
 //     frontier minimum: the K smallest (distance, index) pairs are then all
 //     settled.  They are selected by a bitonic sort of packed
@@ -28,73 +32,43 @@
 //     near-collinear neighbourhood (ratio <= deg_tau) falls back to NW.
 //  Output per match: b00 b01 b10 b11 c0 c1 with flow(p) = B (p - p_s) + c.
 //
+// Wave-wide sums, minima and scans use DPP row operations (registers only,
+// fixed combination order).  The workgroup is a single wavefront, whose LDS
+// instructions execute in issue order, so phases that hand data between
+// lanes through LDS only need to keep the compiler from reordering them.
+//
 // A source whose visited set outgrows the small LDS table is put on an
 // overflow list and redone by a second launch with a table four times
 // larger; only if that overflows too is the pair's status set.
 #include <type_traits>
 
 #include "epic_dev.h"
+#include "wave.h"
 
 namespace epic {
 
 namespace {
 
-__device__ __forceinline__ float wave_min(float v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o));
-    return v;
-}
-__device__ __forceinline__ double wave_min(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o));
-    return v;
-}
-__device__ __forceinline__ float wave_sum(float v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    return v;
-}
-__device__ __forceinline__ double wave_sum_d(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    return v;
-}
-__device__ __forceinline__ int wave_sum_i(int v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    return v;
-}
-__device__ __forceinline__ int wave_incl_scan(int v, int lane) {
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const int t = __shfl_up(v, o);
-        if (lane >= o) v += t;
-    }
-    return v;
-}
 __device__ __forceinline__ u32 node_slot(int v, int hbits) {
     return ((u32)v * 2654435761u) >> (32 - hbits);
 }
 
+// Compiler-only ordering of the wavefront's LDS accesses (see above).
+__device__ __forceinline__ void lds_order() { __asm__ __volatile__("" ::: "memory"); }
+
 template <int VCAP, bool F64>
 struct KnnLds {
     static constexpr int HCAP = 2 * VCAP;
+    static constexpr int TW = 256;                // edges per relaxation window
     using DT = typename std::conditional<F64, u64, u32>::type;     // distance bits
     using RT = typename std::conditional<F64, double, float>::type;
+    alignas(16) DT dm[2 * VCAP];  // entry e: tentative distance (2e), lightest edge (2e + 1)
+    uint2 rd[VCAP];               // entry e: CSR start, degree
     int node[VCAP];
-    DT dist[VCAP];
-    DT minin[VCAP];          // lightest incident edge
-    u32 rs[VCAP];            // adjacency start
-    u32 deg[VCAP];
-    unsigned char state[VCAP];   // 0 frontier, 1 settled
-    unsigned short newly[VCAP];
-    u64 buf[VCAP];           // node table (HCAP ints), then sort keys
-    int snode[F64 ? VCAP : 1];   // FP64: node of each sort key
-    unsigned short hidx[HCAP];
-    int f_off[65];
-    u32 f_start[64];
-    RT f_d[64];
-    int nvis, nnew, ncand, ovf;
+    u64 buf[VCAP];                // node table (HCAP ints) during the search, sort keys after
+    int snode[F64 ? VCAP : 1];    // FP64: node of each sort key
+    unsigned short hidx[HCAP];    // node table slot -> entry
+    unsigned short head[TW];      // 1 + entry whose edge segment starts at a window position
 };
 
 template <bool F64>
@@ -108,26 +82,37 @@ __device__ __forceinline__ typename std::conditional<F64, u64, u32>::type to_bit
     if constexpr (F64) return bitsd(v); else return __float_as_uint(v);
 }
 
-// Loads a node's adjacency range and lightest edge into entry e.
+// Distance and lightest edge of entry e (one LDS read).
 template <int VCAP, bool F64>
-__device__ __forceinline__ void fetch_node(const PairDev& P, int v, KnnLds<VCAP, F64>& S, int e) {
-    const u32 a = P.row_ptr[v], b = P.row_ptr[v + 1];
-    if constexpr (F64) S.minin[e] = P.minin64[v]; else S.minin[e] = P.minin[v];
-    S.rs[e] = a;
-    S.deg[e] = b - a;
+__device__ __forceinline__ void read_dm(const KnnLds<VCAP, F64>& S, int e,
+                                        typename KnnLds<VCAP, F64>::RT& d,
+                                        typename KnnLds<VCAP, F64>::RT& mi) {
+    if constexpr (F64) {
+        const ulonglong2 v = *reinterpret_cast<const ulonglong2*>(&S.dm[2 * e]);
+        d = dbits(v.x);
+        mi = dbits(v.y);
+    } else {
+        const uint2 v = *reinterpret_cast<const uint2*>(&S.dm[2 * e]);
+        d = __uint_as_float(v.x);
+        mi = __uint_as_float(v.y);
+    }
 }
 
 // Processes source `s` of pair P; returns false when the visited set did not
 // fit the table (nothing written then).
 template <int VCAP, int KMAX, bool F64>
 __device__ __forceinline__ bool knn_fit_one(const PairDev& P, const RunDev& run, int s, KnnLds<VCAP, F64>& S) {
-    using RT = typename KnnLds<VCAP, F64>::RT;
-    using DT = typename KnnLds<VCAP, F64>::DT;
+    using LdsT = KnnLds<VCAP, F64>;
+    using RT = typename LdsT::RT;
     const RT RINF = (RT)INFINITY;
-    constexpr int HCAP = KnnLds<VCAP, F64>::HCAP;
+    constexpr int HCAP = LdsT::HCAP;
+    constexpr int TW = LdsT::TW;
+    constexpr int Q = TW / 64;          // edges per lane per window
+    constexpr int R = VCAP / 64;        // entries per lane
     constexpr int HBITS = (HCAP == 512) ? 9 : (HCAP == 1024) ? 10 : (HCAP == 2048) ? 11 : 12;
     static_assert((1 << HBITS) == HCAP, "hash size");
-    constexpr int R = KMAX / 64;
+    static_assert(R <= 32, "settled mask is 32 bits");
+    constexpr int RK = KMAX / 64;
     const int lane = threadIdx.x;
     const int K = P.K;
     const int keff = P.counters[C_KEFF];
@@ -136,152 +121,261 @@ __device__ __forceinline__ bool knn_fit_one(const PairDev& P, const RunDev& run,
 
     // ------------------------------------------------------------ Dijkstra
     for (int i = lane; i < HCAP; i += 64) htab[i] = -1;
-    __syncthreads();
+    for (int i = lane; i < TW; i += 64) S.head[i] = 0;
     if (lane == 0) {
-        S.nvis = 1;
-        S.ovf = 0;
+        const u32 a = P.row_ptr[s], b = P.row_ptr[s + 1];
+        S.dm[0] = 0;
+        if constexpr (F64) S.dm[1] = P.minin64[s]; else S.dm[1] = P.minin[s];
+        S.rd[0] = make_uint2(a, b - a);
         S.node[0] = s;
-        S.dist[0] = 0;
-        S.state[0] = 0;
-        fetch_node<VCAP, F64>(P, s, S, 0);
         const u32 h = node_slot(s, HBITS);
         htab[h] = s;
         S.hidx[h] = 0;
     }
     __syncthreads();
 
-    RT dstop;
+    int nvis = 1;               // entries in use (the same in every lane)
+    bool ovf = false;
+    u32 settled = 0;            // bit r: entry lane + 64 r is settled
+    RT d[R];
+    RT dstop = RINF;
     for (;;) {
-        const int nv = min(S.nvis, VCAP);
-        RT dmin = RINF;
-        for (int e = lane; e < nv; e += 64)
-            if (S.state[e] == 0) dmin = fmin(dmin, from_bits<F64>(S.dist[e]));
-        dmin = wave_min(dmin);
-        if (lane == 0) S.nnew = 0;
-        __syncthreads();
-        // one scan: count settled nodes below dmin, settle the final ones
-        int below = 0;
-        for (int e = lane; e < nv; e += 64) {
-            const RT d = from_bits<F64>(S.dist[e]);
-            if (S.state[e] == 1) {
-                below += d < dmin ? 1 : 0;
-            } else if (d <= dmin + from_bits<F64>(S.minin[e])) {
-                S.state[e] = 1;
-                S.newly[atomicAdd(&S.nnew, 1)] = (unsigned short)e;
+        const int nv = nvis;
+        RT mi[R];
+        uint2 rdv[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            d[r] = RINF;
+            mi[r] = RINF;
+            rdv[r] = make_uint2(0u, 0u);
+            if (64 * r < nv) {
+                const int e = lane + 64 * r;
+                if (e < nv) {
+                    read_dm<VCAP, F64>(S, e, d[r], mi[r]);
+                    rdv[r] = S.rd[e];
+                }
             }
         }
-        below = wave_sum_i(below);
-        __syncthreads();
-        if (below >= keff || dmin == RINF || S.ovf) {
-            dstop = dmin;    // nodes settled in this scan lie at or above dmin
+        RT fmin = RINF;
+        int below = 0;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            if ((settled >> r) & 1u) continue;
+            fmin = fmin < d[r] ? fmin : d[r];
+        }
+        const RT dmin = wave::min(fmin);
+#pragma unroll
+        for (int r = 0; r < R; ++r) below += (((settled >> r) & 1u) && d[r] < dmin) ? 1 : 0;
+        below = wave::sum(below);
+        if (below >= keff || !(dmin < RINF)) {
+            dstop = dmin;       // nodes settled at this point lie at or above dmin
             break;
         }
-        const int nn = S.nnew;
-        for (int base = 0; base < nn; base += 64) {
-            const int cnt = min(64, nn - base);
-            int dg = 0;
-            if (lane < cnt) {
-                const int e = S.newly[base + lane];
-                dg = S.deg[e];
-                S.f_start[lane] = S.rs[e];
-                S.f_d[lane] = from_bits<F64>(S.dist[e]);
-            }
-            const int incl = wave_incl_scan(dg, lane);
-            const int total = __shfl(incl, 63);
-            if (lane < cnt) S.f_off[lane] = incl - dg;
-            if (lane == 0) S.f_off[cnt] = total;
-            __syncthreads();
-            for (int j0 = 0; j0 < total; j0 += 64) {
-                const int j = j0 + lane;
-                const bool act = j < total;
-                int v = -1;
-                RT cand = 0;
-                if (act) {
-                    int lo = 0, hi = cnt - 1;       // last i with f_off[i] <= j
-                    while (lo < hi) {
-                        const int mid = (lo + hi + 1) >> 1;
-                        if (S.f_off[mid] <= j) lo = mid; else hi = mid - 1;
-                    }
-                    const u32 ei = S.f_start[lo] + (u32)(j - S.f_off[lo]);
-                    const uint2 ed = P.adj[ei];
-                    v = (int)ed.x;
-                    if constexpr (F64) cand = S.f_d[lo] + P.adjw64[ei];
-                    else cand = S.f_d[lo] + __uint_as_float(ed.y);
-                }
-                // phase A: find or claim v's slot
-                int h = -1;
-                bool won = false;
-                if (act) {
-                    u32 hh = node_slot(v, HBITS);
-                    for (int probe = 0; probe < HCAP; ++probe) {
-                        const int cur = htab[hh];
-                        if (cur == v) { h = (int)hh; break; }
-                        if (cur == -1) {
-                            const int prev = atomicCAS(&htab[hh], -1, v);
-                            if (prev == -1) { h = (int)hh; won = true; break; }
-                            if (prev == v) { h = (int)hh; break; }
-                        }
-                        hh = (hh + 1u) & (u32)(HCAP - 1);
-                    }
-                    if (h < 0) S.ovf = 1;
-                }
-                // phase B: new nodes get an entry (with their adjacency range)
-                if (won) {
-                    const int e = atomicAdd(&S.nvis, 1);
-                    if (e < VCAP) {
-                        S.node[e] = v;
-                        S.dist[e] = to_bits<F64>(RINF);
-                        S.state[e] = 0;
-                        fetch_node<VCAP, F64>(P, v, S, e);
-                        S.hidx[h] = (unsigned short)e;
-                    } else {
-                        S.hidx[h] = 0xffff;
-                        S.ovf = 1;
-                    }
-                }
-                __syncthreads();
-                // phase C: relax
-                if (act && h >= 0) {
-                    const int e = S.hidx[h];
-                    if (e != 0xffff && S.state[e] == 0) atomicMin(&S.dist[e], to_bits<F64>(cand));
-                }
-                __syncthreads();
+        // settle the final frontier nodes; their edges are relaxed below
+        u32 newly = 0;
+        int my_edges = 0;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const bool fin = lane + 64 * r < nv && !((settled >> r) & 1u) && d[r] <= dmin + mi[r];
+            if (fin) {
+                newly |= 1u << r;
+                my_edges += (int)rdv[r].y;
             }
         }
+        settled |= newly;
+        const int incl = wave::incl_scan(my_edges);
+        const int T = __builtin_amdgcn_readlane(incl, 63);
+        int off[R];
+        {
+            int o = incl - my_edges;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                off[r] = o;
+                if ((newly >> r) & 1u) o += (int)rdv[r].y;
+            }
+        }
+        int carry_start = 0, carry_e = 0;
+        for (int wb = 0; wb < T; wb += TW) {
+            // mark the segments that start in this window
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                if (((newly >> r) & 1u) && rdv[r].y > 0u && off[r] >= wb && off[r] < wb + TW)
+                    S.head[off[r] - wb] = (unsigned short)(lane + 64 * r + 1);
+            lds_order();
+            const int nq = min(Q, (T - wb + 63) >> 6);   // chunks of 64 edges in this window
+            bool act[Q];
+            int qe[Q], qst[Q];
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                act[q] = false;
+                qe[q] = 0;
+                qst[q] = 0;
+                if (q < nq) {
+                    act[q] = wb + 64 * q + lane < T;
+                    const int hv = S.head[64 * q + lane];
+                    const int sc = wave::incl_max(hv ? (((64 * q + lane) << 16) | (hv - 1)) : -1);
+                    if (sc >= 0) {
+                        qst[q] = wb + (sc >> 16);
+                        qe[q] = sc & 0xffff;
+                    } else {
+                        qst[q] = carry_start;
+                        qe[q] = carry_e;
+                    }
+                    carry_start = __builtin_amdgcn_readlane(qst[q], 63);
+                    carry_e = __builtin_amdgcn_readlane(qe[q], 63);
+                }
+            }
+            lds_order();
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                if (((newly >> r) & 1u) && rdv[r].y > 0u && off[r] >= wb && off[r] < wb + TW)
+                    S.head[off[r] - wb] = 0;
+            // each lane's edges: source entry's CSR start and settled distance
+            RT du[Q];
+            u32 ei[Q];
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                if (q >= nq) break;
+                RT unused;
+                read_dm<VCAP, F64>(S, qe[q], du[q], unused);
+                const uint2 rr = S.rd[qe[q]];
+                ei[q] = act[q] ? rr.x + (u32)(wb + 64 * q + lane - qst[q]) : 0u;
+            }
+            uint4 rec[Q];
+            RT cand[Q], nbm[Q];
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                if (q >= nq) break;
+                rec[q] = P.adj[ei[q]];
+                if constexpr (F64) {
+                    cand[q] = du[q] + P.adjw64[ei[q]];
+                    nbm[q] = dbits(P.nbmin64[ei[q]]);
+                } else {
+                    cand[q] = du[q] + __uint_as_float(rec[q].y);
+                    nbm[q] = __uint_as_float(P.nbmin[ei[q]]);
+                }
+            }
+            // find or claim each neighbour's table slot
+            int hs[Q];
+            bool won[Q], pend[Q];
+            u32 hh[Q];
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                pend[q] = false;
+                won[q] = false;
+                hs[q] = -1;
+                hh[q] = 0;
+                if (q < nq) {
+                    pend[q] = act[q];
+                    hh[q] = node_slot((int)rec[q].x, HBITS);
+                }
+            }
+            for (int probe = 0; probe < HCAP; ++probe) {
+                bool any = false;
+#pragma unroll
+                for (int q = 0; q < Q; ++q) any = any || pend[q];
+                if (wave::ballot(any) == 0ull) break;
+                int cur[Q], prev[Q];
+#pragma unroll
+                for (int q = 0; q < Q; ++q) {
+                    if (q >= nq) break;
+                    cur[q] = pend[q] ? htab[hh[q]] : 0;
+                }
+#pragma unroll
+                for (int q = 0; q < Q; ++q) {
+                    if (q >= nq) break;
+                    prev[q] = cur[q];
+                    if (pend[q] && cur[q] == -1) prev[q] = atomicCAS(&htab[hh[q]], -1, (int)rec[q].x);
+                }
+#pragma unroll
+                for (int q = 0; q < Q; ++q) {
+                    if (q >= nq) break;
+                    if (!pend[q]) continue;
+                    if (cur[q] == -1 && prev[q] == -1) {
+                        won[q] = true;
+                        hs[q] = (int)hh[q];
+                        pend[q] = false;
+                    } else if (prev[q] == (int)rec[q].x) {
+                        hs[q] = (int)hh[q];
+                        pend[q] = false;
+                    } else {
+                        hh[q] = (hh[q] + 1u) & (u32)(HCAP - 1);
+                    }
+                }
+            }
+            {
+                bool lost = false;
+#pragma unroll
+                for (int q = 0; q < Q; ++q) lost = lost || pend[q];
+                if (wave::ballot(lost) != 0ull) ovf = true;
+            }
+            // new nodes get entries (with their distance and CSR range)
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                if (q >= nq) break;
+                const u64 m = wave::ballot(won[q]);
+                const int e = nvis + wave::lanes_below(m);
+                nvis += __popcll(m);
+                if (won[q]) {
+                    if (e < VCAP) {
+                        S.dm[2 * e] = to_bits<F64>(cand[q]);
+                        S.dm[2 * e + 1] = to_bits<F64>(nbm[q]);
+                        S.rd[e] = make_uint2(rec[q].z, rec[q].w);
+                        S.node[e] = (int)rec[q].x;
+                        S.hidx[hs[q]] = (unsigned short)e;
+                    } else {
+                        S.hidx[hs[q]] = 0xffff;
+                    }
+                }
+            }
+            if (nvis > VCAP) ovf = true;
+            lds_order();
+            // relax the nodes that were already in the table
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                if (q >= nq) break;
+                if (act[q] && hs[q] >= 0 && !won[q]) {
+                    const int e = S.hidx[hs[q]];
+                    if (e != 0xffff) atomicMin(&S.dm[2 * e], to_bits<F64>(cand[q]));
+                }
+            }
+            lds_order();
+        }
+        if (ovf) break;
     }
-    if (S.ovf) return false;
+    if (ovf) return false;
 
     // ---------------------------------------- select the K nearest (sorted)
-    const int nv = min(S.nvis, VCAP);
-    if (lane == 0) S.ncand = 0;
-    __syncthreads();
-    // sort keys: FP32 packs (distance bits, index) into one word; FP64 sorts
-    // (distance bits, index) pairs held in two arrays
-    auto key_node = [&](int j) -> int { if constexpr (F64) return S.snode[j]; else return (int)(u32)S.buf[j]; };
-    auto key_dist = [&](int j) -> RT {
-        if constexpr (F64) return dbits(S.buf[j]); else return __uint_as_float((u32)(S.buf[j] >> 32));
-    };
-    for (int e = lane; e < nv; e += 64) {
-        const RT d = from_bits<F64>(S.dist[e]);
-        if (S.state[e] == 1 && d < dstop) {
-            const int pos = atomicAdd(&S.ncand, 1);
+    // Candidates: settled entries strictly below dstop, sorted in LDS: FP32
+    // as packed (distance bits, index) words, FP64 as (distance bits, index)
+    // pairs held in two arrays.
+    __syncthreads();                 // the node table (aliasing buf) is dead from here
+    int nc = 0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const bool c = ((settled >> r) & 1u) && d[r] < dstop;
+        const u64 m = wave::ballot(c);
+        const int pos = nc + wave::lanes_below(m);
+        nc += __popcll(m);
+        if (c) {
+            const int e = lane + 64 * r;
             if constexpr (F64) {
-                S.buf[pos] = S.dist[e];
+                S.buf[pos] = bitsd(d[r]);
                 S.snode[pos] = S.node[e];
             } else {
-                S.buf[pos] = ((u64)S.dist[e] << 32) | (u32)S.node[e];
+                S.buf[pos] = ((u64)__float_as_uint(d[r]) << 32) | (u32)S.node[e];
             }
         }
     }
-    __syncthreads();
-    const int nc = S.ncand;
-    int p2 = 1;
+    int p2 = 64;
     while (p2 < nc) p2 <<= 1;
     for (int i = nc + lane; i < p2; i += 64) {
         S.buf[i] = ~0ull;
         if constexpr (F64) S.snode[i] = 0x7fffffff;
     }
     __syncthreads();
+    int knode[RK];
+    RT kdist[RK];
     for (int k = 2; k <= p2; k <<= 1) {
         for (int j = k >> 1; j > 0; j >>= 1) {
             for (int i = lane; i < p2; i += 64) {
@@ -289,22 +383,20 @@ __device__ __forceinline__ bool knn_fit_one(const PairDev& P, const RunDev& run,
                 if (ixj > i) {
                     const u64 a = S.buf[i], b = S.buf[ixj];
                     const bool up = (i & k) == 0;
-                    bool gt, lt;
                     if constexpr (F64) {
                         const int na = S.snode[i], nb = S.snode[ixj];
-                        gt = a > b || (a == b && na > nb);
-                        lt = a < b || (a == b && na < nb);
+                        const bool gt = a > b || (a == b && na > nb);
+                        const bool lt = a < b || (a == b && na < nb);
+                        if (up ? gt : lt) {
+                            S.buf[i] = b;
+                            S.buf[ixj] = a;
+                            S.snode[i] = nb;
+                            S.snode[ixj] = na;
+                        }
                     } else {
-                        gt = a > b;
-                        lt = a < b;
-                    }
-                    if (up ? gt : lt) {
-                        S.buf[i] = b;
-                        S.buf[ixj] = a;
-                        if constexpr (F64) {
-                            const int t = S.snode[i];
-                            S.snode[i] = S.snode[ixj];
-                            S.snode[ixj] = t;
+                        if (up ? a > b : a < b) {
+                            S.buf[i] = b;
+                            S.buf[ixj] = a;
                         }
                     }
                 }
@@ -312,12 +404,28 @@ __device__ __forceinline__ bool knn_fit_one(const PairDev& P, const RunDev& run,
             __syncthreads();
         }
     }
+#pragma unroll
+    for (int r = 0; r < RK; ++r) {
+        const int jj = lane + 64 * r;
+        const u64 kb = jj < p2 ? S.buf[jj] : ~0ull;
+        if constexpr (F64) {
+            knode[r] = jj < p2 ? S.snode[jj] : 0x7fffffff;
+            kdist[r] = dbits(kb);
+        } else {
+            knode[r] = (int)(u32)kb;
+            kdist[r] = __uint_as_float((u32)(kb >> 32));
+        }
+    }
     const int n = min(keff, nc);
     if (P.dbg_knn_idx) {
-        for (int j = lane; j < K; j += 64) {
-            const bool ok = j < n;
-            P.dbg_knn_idx[(long long)s * K + j] = ok ? key_node(j) : -1;
-            P.dbg_knn_d[(long long)s * K + j] = ok ? (float)key_dist(j) : __int_as_float(0x7f800000);
+#pragma unroll
+        for (int r = 0; r < RK; ++r) {
+            const int jj = lane + 64 * r;
+            if (jj < K) {
+                const bool ok = jj < n;
+                P.dbg_knn_idx[(long long)s * K + jj] = ok ? knode[r] : -1;
+                P.dbg_knn_d[(long long)s * K + jj] = ok ? (float)kdist[r] : __int_as_float(0x7f800000);
+            }
         }
     }
 
@@ -327,21 +435,21 @@ __device__ __forceinline__ bool knn_fit_one(const PairDev& P, const RunDev& run,
     const float um = M[4LL * s + 2] - xm, vm = M[4LL * s + 3] - ym;
     const float a = P.a;
     const int wpow = run.la_wpow;
-    float dx[R], dy[R], du[R], dv[R], kk[R], ww[R];
+    float dx[RK], dy[RK], du[RK], dv[RK], kk[RK], ww[RK];
     float tk = 0.f, tu = 0.f, tv = 0.f, sw = 0.f, sx = 0.f, sy = 0.f;
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
+    for (int r = 0; r < RK; ++r) {
         const int j = lane + 64 * r;
         dx[r] = dy[r] = du[r] = dv[r] = kk[r] = ww[r] = 0.f;
         if (j < n) {
-            const int node = key_node(j);
-            const float d = (float)key_dist(j);
+            const int node = knode[r];
+            const float dj = (float)kdist[r];
             const float4 mn = *reinterpret_cast<const float4*>(M + 4LL * node);
             dx[r] = mn.x - xm;
             dy[r] = mn.y - ym;
             du[r] = (mn.z - mn.x) - um;
             dv[r] = (mn.w - mn.y) - vm;
-            kk[r] = expf(-a * d);
+            kk[r] = expf(-a * dj);
             ww[r] = wpow == 1 ? kk[r] : kk[r] * kk[r];
             tk += kk[r];
             tu += kk[r] * du[r];
@@ -351,19 +459,19 @@ __device__ __forceinline__ bool knn_fit_one(const PairDev& P, const RunDev& run,
             sy += ww[r] * dy[r];
         }
     }
-    tk = wave_sum(tk);
-    tu = wave_sum(tu);
-    tv = wave_sum(tv);
+    tk = wave::sum(tk);
+    tu = wave::sum(tu);
+    tv = wave::sum(tv);
     float out[6] = {0.f, 0.f, 0.f, 0.f, um + tu / tk, vm + tv / tk};
     bool need64 = false;
     if (P.mode == 1) {
-        sw = wave_sum(sw);
-        sx = wave_sum(sx);
-        sy = wave_sum(sy);
+        sw = wave::sum(sw);
+        sx = wave::sum(sx);
+        sy = wave::sum(sy);
         const float mx = sx / sw, my = sy / sw;
         float sxx = 0.f, sxy = 0.f, syy = 0.f, sxu = 0.f, syu = 0.f, sxv = 0.f, syv = 0.f, su = 0.f, sv = 0.f;
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
+        for (int r = 0; r < RK; ++r) {
             const float ex = dx[r] - mx, ey = dy[r] - my, w = ww[r];
             sxx += w * ex * ex;
             sxy += w * ex * ey;
@@ -375,9 +483,9 @@ __device__ __forceinline__ bool knn_fit_one(const PairDev& P, const RunDev& run,
             su += w * du[r];
             sv += w * dv[r];
         }
-        sxx = wave_sum(sxx); sxy = wave_sum(sxy); syy = wave_sum(syy);
-        sxu = wave_sum(sxu); syu = wave_sum(syu); sxv = wave_sum(sxv); syv = wave_sum(syv);
-        su = wave_sum(su); sv = wave_sum(sv);
+        sxx = wave::sum(sxx); sxy = wave::sum(sxy); syy = wave::sum(syy);
+        sxu = wave::sum(sxu); syu = wave::sum(syu); sxv = wave::sum(sxv); syv = wave::sum(syv);
+        su = wave::sum(su); sv = wave::sum(sv);
         const float det = sxx * syy - sxy * sxy;
         const float tr = sxx + syy;
         const float disc = sqrtf((sxx - syy) * (sxx - syy) + 4.0f * sxy * sxy);
@@ -397,44 +505,44 @@ __device__ __forceinline__ bool knn_fit_one(const PairDev& P, const RunDev& run,
         // FP64: re-accumulate from the inputs and solve (or fall back to NW)
         const double xmd = xm, ymd = ym;
         const double umd = (double)M[4LL * s + 2] - xmd, vmd = (double)M[4LL * s + 3] - ymd;
-        double Dx[R], Dy[R], Du[R], Dv[R], Dw[R];
+        double Dx[RK], Dy[RK], Du[RK], Dv[RK], Dw[RK];
         double Tk = 0, Tu = 0, Tv = 0, Sw = 0, Sx = 0, Sy = 0;
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
+        for (int r = 0; r < RK; ++r) {
             const int j = lane + 64 * r;
             Dx[r] = Dy[r] = Du[r] = Dv[r] = Dw[r] = 0.0;
             if (j < n) {
-                const int node = key_node(j);
-                const double d = (double)key_dist(j);
+                const int node = knode[r];
+                const double dj = (double)kdist[r];
                 const double x = M[4LL * node + 0], y = M[4LL * node + 1];
                 Dx[r] = x - xmd;
                 Dy[r] = y - ymd;
                 Du[r] = ((double)M[4LL * node + 2] - x) - umd;
                 Dv[r] = ((double)M[4LL * node + 3] - y) - vmd;
-                const double k = exp(-(double)a * d);
+                const double k = exp(-(double)a * dj);
                 Dw[r] = wpow == 1 ? k : k * k;
                 Tk += k; Tu += k * Du[r]; Tv += k * Dv[r];
                 Sw += Dw[r]; Sx += Dw[r] * Dx[r]; Sy += Dw[r] * Dy[r];
             }
         }
-        Tk = wave_sum_d(Tk); Tu = wave_sum_d(Tu); Tv = wave_sum_d(Tv);
+        Tk = wave::sum(Tk); Tu = wave::sum(Tu); Tv = wave::sum(Tv);
         double o[6] = {0, 0, 0, 0, umd + Tu / Tk, vmd + Tv / Tk};
         bool degenerate = false;
         if (P.mode == 1) {
-            Sw = wave_sum_d(Sw); Sx = wave_sum_d(Sx); Sy = wave_sum_d(Sy);
+            Sw = wave::sum(Sw); Sx = wave::sum(Sx); Sy = wave::sum(Sy);
             const double mx = Sx / Sw, my = Sy / Sw;
             double sxx = 0, sxy = 0, syy = 0, sxu = 0, syu = 0, sxv = 0, syv = 0, su = 0, sv = 0;
 #pragma unroll
-            for (int r = 0; r < R; ++r) {
+            for (int r = 0; r < RK; ++r) {
                 const double ex = Dx[r] - mx, ey = Dy[r] - my, w = Dw[r];
                 sxx += w * ex * ex; sxy += w * ex * ey; syy += w * ey * ey;
                 sxu += w * ex * Du[r]; syu += w * ey * Du[r];
                 sxv += w * ex * Dv[r]; syv += w * ey * Dv[r];
                 su += w * Du[r]; sv += w * Dv[r];
             }
-            sxx = wave_sum_d(sxx); sxy = wave_sum_d(sxy); syy = wave_sum_d(syy);
-            sxu = wave_sum_d(sxu); syu = wave_sum_d(syu); sxv = wave_sum_d(sxv); syv = wave_sum_d(syv);
-            su = wave_sum_d(su); sv = wave_sum_d(sv);
+            sxx = wave::sum(sxx); sxy = wave::sum(sxy); syy = wave::sum(syy);
+            sxu = wave::sum(sxu); syu = wave::sum(syu); sxv = wave::sum(sxv); syv = wave::sum(syv);
+            su = wave::sum(su); sv = wave::sum(sv);
             // covariance normalised by the weight sum; eigenvalues l1 >= l2
             const double cxx = sxx / Sw, cxy = sxy / Sw, cyy = syy / Sw;
             const double tr = cxx + cyy;

@@ -1,0 +1,130 @@
+// wave.h -- wavefront-wide reductions and scans for 64-lane waves on gfx950,
+// built from DPP row operations (quad permutes, row mirrors, row shifts and
+// the row broadcasts of GFX9) and a final readlane.  They stay in registers
+// (no LDS traffic) and combine lanes in a fixed order, so results are
+// deterministic.  All 64 lanes must be active.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace epic {
+namespace wave {
+
+typedef unsigned long long u64_t;
+
+// DPP controls (GFX9 encoding)
+constexpr int QP_XOR1 = 0xB1;        // quad_perm [1,0,3,2]
+constexpr int QP_XOR2 = 0x4E;        // quad_perm [2,3,0,1]
+constexpr int ROW_HALF_MIRROR = 0x141;
+constexpr int ROW_MIRROR = 0x140;
+constexpr int ROW_SHR1 = 0x111, ROW_SHR2 = 0x112, ROW_SHR4 = 0x114, ROW_SHR8 = 0x118;
+constexpr int ROW_BCAST15 = 0x142, ROW_BCAST31 = 0x143;
+
+template <int CTRL, int ROWMASK = 0xF>
+__device__ __forceinline__ int dpp(int old, int v) {
+    return __builtin_amdgcn_update_dpp(old, v, CTRL, ROWMASK, 0xF, false);
+}
+template <int CTRL, int ROWMASK = 0xF>
+__device__ __forceinline__ float dppf(float old, float v) {
+    return __int_as_float(dpp<CTRL, ROWMASK>(__float_as_int(old), __float_as_int(v)));
+}
+template <int CTRL, int ROWMASK = 0xF>
+__device__ __forceinline__ double dppd(double old, double v) {
+    const long long o = __double_as_longlong(old), x = __double_as_longlong(v);
+    const int lo = dpp<CTRL, ROWMASK>((int)(o & 0xffffffff), (int)(x & 0xffffffff));
+    const int hi = dpp<CTRL, ROWMASK>((int)(o >> 32), (int)(x >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+__device__ __forceinline__ float readlane63(float v) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+__device__ __forceinline__ double readlane63(double v) {
+    const long long x = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(x & 0xffffffff), 63);
+    const int hi = __builtin_amdgcn_readlane((int)(x >> 32), 63);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Sum over the 64 lanes, returned to every lane.
+__device__ __forceinline__ float sum(float v) {
+    v += dppf<QP_XOR1>(0.0f, v);
+    v += dppf<QP_XOR2>(0.0f, v);
+    v += dppf<ROW_HALF_MIRROR>(0.0f, v);
+    v += dppf<ROW_MIRROR>(0.0f, v);          // every lane: its row's sum
+    v += dppf<ROW_BCAST15, 0xA>(0.0f, v);    // rows 1, 3 += rows 0, 2
+    v += dppf<ROW_BCAST31, 0xC>(0.0f, v);    // rows 2, 3 += rows 0 + 1
+    return readlane63(v);
+}
+__device__ __forceinline__ double sum(double v) {
+    v += dppd<QP_XOR1>(0.0, v);
+    v += dppd<QP_XOR2>(0.0, v);
+    v += dppd<ROW_HALF_MIRROR>(0.0, v);
+    v += dppd<ROW_MIRROR>(0.0, v);
+    v += dppd<ROW_BCAST15, 0xA>(0.0, v);
+    v += dppd<ROW_BCAST31, 0xC>(0.0, v);
+    return readlane63(v);
+}
+__device__ __forceinline__ int sum(int v) {
+    v += dpp<QP_XOR1>(0, v);
+    v += dpp<QP_XOR2>(0, v);
+    v += dpp<ROW_HALF_MIRROR>(0, v);
+    v += dpp<ROW_MIRROR>(0, v);
+    v += dpp<ROW_BCAST15, 0xA>(0, v);
+    v += dpp<ROW_BCAST31, 0xC>(0, v);
+    return __builtin_amdgcn_readlane(v, 63);
+}
+
+// Minimum over the 64 lanes, returned to every lane.
+__device__ __forceinline__ float min(float v) {
+    const float inf = __int_as_float(0x7f800000);
+    v = fminf(v, dppf<QP_XOR1>(inf, v));
+    v = fminf(v, dppf<QP_XOR2>(inf, v));
+    v = fminf(v, dppf<ROW_HALF_MIRROR>(inf, v));
+    v = fminf(v, dppf<ROW_MIRROR>(inf, v));
+    v = fminf(v, dppf<ROW_BCAST15, 0xA>(inf, v));
+    v = fminf(v, dppf<ROW_BCAST31, 0xC>(inf, v));
+    return readlane63(v);
+}
+__device__ __forceinline__ double min(double v) {
+    const double inf = __longlong_as_double(0x7ff0000000000000ll);
+    v = fmin(v, dppd<QP_XOR1>(inf, v));
+    v = fmin(v, dppd<QP_XOR2>(inf, v));
+    v = fmin(v, dppd<ROW_HALF_MIRROR>(inf, v));
+    v = fmin(v, dppd<ROW_MIRROR>(inf, v));
+    v = fmin(v, dppd<ROW_BCAST15, 0xA>(inf, v));
+    v = fmin(v, dppd<ROW_BCAST31, 0xC>(inf, v));
+    return readlane63(v);
+}
+
+// Inclusive prefix sum over lanes 0..63.
+__device__ __forceinline__ int incl_scan(int v) {
+    v += dpp<ROW_SHR1>(0, v);
+    v += dpp<ROW_SHR2>(0, v);
+    v += dpp<ROW_SHR4>(0, v);
+    v += dpp<ROW_SHR8>(0, v);                 // scan within each row of 16
+    v += dpp<ROW_BCAST15, 0xA>(0, v);
+    v += dpp<ROW_BCAST31, 0xC>(0, v);
+    return v;
+}
+
+// Inclusive prefix maximum over lanes 0..63 (values >= -1; -1 is neutral).
+__device__ __forceinline__ int incl_max(int v) {
+    v = max(v, dpp<ROW_SHR1>(-1, v));
+    v = max(v, dpp<ROW_SHR2>(-1, v));
+    v = max(v, dpp<ROW_SHR4>(-1, v));
+    v = max(v, dpp<ROW_SHR8>(-1, v));
+    v = max(v, dpp<ROW_BCAST15, 0xA>(-1, v));
+    v = max(v, dpp<ROW_BCAST31, 0xC>(-1, v));
+    return v;
+}
+
+__device__ __forceinline__ u64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
+
+// Number of lanes below this one whose bit is set in m.
+__device__ __forceinline__ int lanes_below(u64_t m) {
+    return (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+}
+
+}  // namespace wave
+}  // namespace epic
