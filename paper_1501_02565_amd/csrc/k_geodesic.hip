@@ -61,35 +61,45 @@ struct TileLds {
 // Visits one tile: load with halo, relax to a local fixpoint, write back.
 // Returns (to every thread) the mask of borders with a changed pixel.
 //
-// In-tile relaxation is Gauss-Seidel over lines: each thread owns a run of
-// PPT consecutive pixels along a row and one along a column.  A round sweeps
-// the row run forwards, the column run forwards, the row run backwards and
-// the column run backwards, updating every pixel in place from its 8 (or 4)
-// neighbours; the workgroup only meets at the end of a round.  Wavefronts
-// may then be in different sweeps at once, so a pixel's row-run and
-// column-run owners can race on it.  Every written value is the length of a
-// real path and every pixel is relaxed in every round, so a lost update only
-// costs another round: a round in which no pixel improved leaves every pixel
-// at the minimum over its neighbours, which is the fixpoint.
+// In-tile relaxation is Gauss-Seidel over lines: each of the NT threads owns
+// a run of PPT consecutive pixels along a row and one along a column.  A
+// round sweeps the row run forwards, the column run forwards, the row run
+// backwards and the column run backwards, updating every pixel in place from
+// its 8 (or 4) neighbours; the workgroup only meets at the end of a round.
+// A sweep keeps the 3 x 3 window around the current pixel in registers and
+// slides it: each step reads only the three keys ahead (issued before the
+// current pixel is computed), and the pixel behind is the value just
+// computed.  Wavefronts may be in different sweeps at once, so a pixel's
+// row-run and column-run owners can race on it, and window values may be a
+// few steps old.  Every written value is the length of a real path and every
+// pixel is relaxed in every round, so a lost or late update only costs
+// another round: a round in which no pixel improved leaves every pixel at
+// the minimum over its neighbours, which is the fixpoint.
 //
 // A key (D bits, label) with D >= 0 read as an IEEE double is a non-negative
 // value below the NaN range whose order is the unsigned order of the key
 // (denormals are kept for doubles in these kernels), so the lexicographic
 // minimum over the neighbours is a chain of double minima.
-template <int TW, int TH, int CONN>
+// Index k of the neighbour at (dx, dy) in DX/DY order, or -1.
+constexpr int nb_index(int dx, int dy) {
+    return dx == 1 && dy == 0 ? 0 : dx == -1 && dy == 0 ? 1 : dx == 0 && dy == 1 ? 2 : dx == 0 && dy == -1 ? 3
+         : dx == 1 && dy == 1 ? 4 : dx == -1 && dy == 1 ? 5 : dx == 1 && dy == -1 ? 6 : dx == -1 && dy == -1 ? 7 : -1;
+}
+
+template <int TW, int TH, int CONN, int NT>
 __device__ __forceinline__ int visit_tile(const PairDev& P, int tx, int ty, TileLds<TW, TH>& S, int* error) {
-    constexpr int PPT = TW * TH / 256;
+    constexpr int PPT = TW * TH / NT;
     constexpr int LW = TileLds<TW, TH>::LW, LH = TileLds<TW, TH>::LH, NL = TileLds<TW, TH>::NL;
     constexpr int HR = TW / PPT;           // row runs per row
-    static_assert(PPT * 256 == TW * TH && HR * PPT == TW && HR * TH == 256 && (TH / PPT) * TW == 256 &&
-                      LW <= 64, "tile shape");
+    static_assert(PPT * NT == TW * TH && HR * PPT == TW && HR * TH == NT && (TH / PPT) * TW == NT &&
+                      TH % PPT == 0, "tile shape");
     constexpr int DX[8] = {1, -1, 0, 0, 1, -1, 1, -1};
     constexpr int DY[8] = {0, 0, 1, -1, 1, 1, -1, -1};
     const int tid = threadIdx.x;
     const int x0 = tx * TW, y0 = ty * TH, W = P.W, H = P.H;
     const int twe = min(TW, W - x0), the = min(TH, H - y0);
 
-    for (int i = tid; i < NL; i += 256) {
+    for (int i = tid; i < NL; i += NT) {
         const int ly = i / LW, lxx = i - ly * LW;
         const int gx = x0 + lxx - 1, gy = y0 + ly - 1;
         u64 k = KEY_INF;
@@ -131,28 +141,54 @@ __device__ __forceinline__ int visit_tile(const PairDev& P, int tx, int ty, Tile
         // compile-time so the step-cost registers are indexed statically
         auto sweep = [&](auto rows_c, auto fwd_c) {
             constexpr bool ROWS = decltype(rows_c)::value, FWD = decltype(fwd_c)::value;
+            constexpr int SA = (FWD ? 1 : -1) * (ROWS ? 1 : LW);   // one step along the run
+            constexpr int SB = ROWS ? LW : 1;                     // one step across it
+            const int j0 = FWD ? 0 : PPT - 1;
+            int c = ROWS ? (hy + 1) * LW + hx + j0 + 1 : (vy + j0 + 1) * LW + vx + 1;
+            // win[a + 1][b + 1]: the key a steps along and b steps across
+            u64 win[3][3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int b = 0; b < 3; ++b) win[a][b] = S.key[c + (a - 1) * SA + (b - 1) * SB];
 #pragma unroll
             for (int jj = 0; jj < PPT; ++jj) {
                 const int j = FWD ? jj : PPT - 1 - jj;
-                const int lx = ROWS ? hx + j : vx, ly = ROWS ? hy : vy + j;
-                if (lx >= twe || ly >= the) continue;
-                const int ci = (ly + 1) * LW + lx + 1;
-                u64 kq[CONN];
+                u64 nxt[3] = {0, 0, 0};
+                if (jj + 1 < PPT) {
 #pragma unroll
-                for (int k = 0; k < CONN; ++k) kq[k] = S.key[ci + DY[k] * LW + DX[k]];
-                const u64 now = S.key[ci];
+                    for (int b = 0; b < 3; ++b) nxt[b] = S.key[c + 2 * SA + (b - 1) * SB];
+                }
+                const int lx = ROWS ? hx + j : vx, ly = ROWS ? hy : vy + j;
+                const u64 now = win[1][1];
                 double best = __longlong_as_double((long long)now);
 #pragma unroll
-                for (int k = 0; k < CONN; ++k) {
-                    const float w = ROWS ? wh[j][k] : wv[j][k];
-                    const u64 cand = make_key(key_dist(kq[k]) + w, key_label(kq[k]));
-                    best = min_f64(best, __longlong_as_double((long long)cand));
+                for (int a = -1; a <= 1; ++a) {
+#pragma unroll
+                    for (int b = -1; b <= 1; ++b) {
+                        const int al = FWD ? a : -a;           // along, in +x / +y terms
+                        const int k = ROWS ? nb_index(al, b) : nb_index(b, al);
+                        if (k < 0 || k >= CONN) continue;
+                        const u64 q = win[a + 1][b + 1];
+                        const float w = ROWS ? wh[j][k] : wv[j][k];
+                        const u64 cand = make_key(key_dist(q) + w, key_label(q));
+                        best = min_f64(best, __longlong_as_double((long long)cand));
+                    }
                 }
-                const u64 bk = (u64)__double_as_longlong(best);
+                u64 bk = (u64)__double_as_longlong(best);
+                if (lx >= twe || ly >= the) bk = now;            // outside a ragged tile
                 if (bk < now) {
-                    S.key[ci] = bk;
+                    S.key[c] = bk;
                     changed = 1;
                 }
+#pragma unroll
+                for (int b = 0; b < 3; ++b) {
+                    win[0][b] = win[1][b];
+                    win[1][b] = win[2][b];
+                    win[2][b] = nxt[b];
+                }
+                win[0][1] = bk;
+                c += SA;
             }
         };
         using T = std::true_type;
@@ -216,8 +252,8 @@ __device__ void mark_neighbours(const PairDev& P, const RunDev& run, int tx, int
 }  // namespace
 
 // One pass over all tiles of all pairs.
-template <int TW, int TH, int CONN>
-__global__ __launch_bounds__(256) void k_geo_pass(const PairDev* __restrict__ pairs, RunDev run, int pass) {
+template <int TW, int TH, int CONN, int NT>
+__global__ __launch_bounds__(NT) void k_geo_pass(const PairDev* __restrict__ pairs, RunDev run, int pass) {
     __shared__ TileLds<TW, TH> S;
     if (pass > 0 && run.any[pass - 1] == 0) return;          // converged
     // XCD-aware: blocks b, b+8, b+16, ... share an XCD; give each XCD a
@@ -233,7 +269,7 @@ __global__ __launch_bounds__(256) void k_geo_pass(const PairDev* __restrict__ pa
     const int tx = lt % P.tiles_x, ty = lt / P.tiles_x;
     __syncthreads();
     if (threadIdx.x == 0) dirty[tile] = 0u;                  // reused two passes later
-    const int border = visit_tile<TW, TH, CONN>(P, tx, ty, S, run.error);
+    const int border = visit_tile<TW, TH, CONN, NT>(P, tx, ty, S, run.error);
     if (threadIdx.x == 0) {
         atomicAdd(&P.counters[C_TILE_VISITS], 1);
         if (border) {
@@ -245,8 +281,8 @@ __global__ __launch_bounds__(256) void k_geo_pass(const PairDev* __restrict__ pa
 
 // Continues the passes in one workgroup until no border changes (only runs
 // when the launched passes did not reach the fixpoint).
-template <int TW, int TH, int CONN>
-__global__ __launch_bounds__(256) void k_geo_finish(const PairDev* __restrict__ pairs, RunDev run, int pass0) {
+template <int TW, int TH, int CONN, int NT>
+__global__ __launch_bounds__(NT) void k_geo_finish(const PairDev* __restrict__ pairs, RunDev run, int pass0) {
     __shared__ TileLds<TW, TH> S;
     __shared__ int s_any;
     if (run.any[pass0 - 1] == 0) return;
@@ -262,7 +298,7 @@ __global__ __launch_bounds__(256) void k_geo_finish(const PairDev* __restrict__ 
             const int tx = lt % P.tiles_x, ty = lt / P.tiles_x;
             __syncthreads();
             if (threadIdx.x == 0) dirty[tile] = 0u;
-            const int border = visit_tile<TW, TH, CONN>(P, tx, ty, S, run.error);
+            const int border = visit_tile<TW, TH, CONN, NT>(P, tx, ty, S, run.error);
             if (threadIdx.x == 0) {
                 atomicAdd(&P.counters[C_TILE_VISITS], 1);
                 if (border) {
@@ -281,27 +317,33 @@ __global__ __launch_bounds__(256) void k_geo_finish(const PairDev* __restrict__ 
 }
 
 namespace {
-template <int TW, int TH, int CONN>
+template <int TW, int TH, int CONN, int NT>
 hipError_t launch_t(const PairDev* d_pairs, const RunDev& run, int passes, hipStream_t s) {
     const int grid = 8 * ((run.total_tiles + 7) / 8);
     for (int p = 0; p < passes; ++p) {
-        hipLaunchKernelGGL((k_geo_pass<TW, TH, CONN>), dim3(grid), dim3(256), 0, s, d_pairs, run, p);
+        hipLaunchKernelGGL((k_geo_pass<TW, TH, CONN, NT>), dim3(grid), dim3(NT), 0, s, d_pairs, run, p);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL((k_geo_finish<TW, TH, CONN>), dim3(1), dim3(256), 0, s, d_pairs, run, passes);
+    hipLaunchKernelGGL((k_geo_finish<TW, TH, CONN, NT>), dim3(1), dim3(NT), 0, s, d_pairs, run, passes);
     return hipGetLastError();
 }
+
+// Threads per tile: runs of 2 pixels (32 x 16), 8 (32 x 32, 32 x 64)
+constexpr int kThreads16 = 256, kThreads32 = 128, kThreads64 = 256;
 }  // namespace
 
 hipError_t launch_geodesic(const PairDev* d_pairs, const RunDev& run, int tile_w, int tile_h, int passes,
                            hipStream_t s) {
     const bool c8 = run.conn != 4;
     if (tile_h == 16)
-        return c8 ? launch_t<32, 16, 8>(d_pairs, run, passes, s) : launch_t<32, 16, 4>(d_pairs, run, passes, s);
+        return c8 ? launch_t<32, 16, 8, kThreads16>(d_pairs, run, passes, s)
+                  : launch_t<32, 16, 4, kThreads16>(d_pairs, run, passes, s);
     if (tile_h == 64)
-        return c8 ? launch_t<32, 64, 8>(d_pairs, run, passes, s) : launch_t<32, 64, 4>(d_pairs, run, passes, s);
-    return c8 ? launch_t<32, 32, 8>(d_pairs, run, passes, s) : launch_t<32, 32, 4>(d_pairs, run, passes, s);
+        return c8 ? launch_t<32, 64, 8, kThreads64>(d_pairs, run, passes, s)
+                  : launch_t<32, 64, 4, kThreads64>(d_pairs, run, passes, s);
+    return c8 ? launch_t<32, 32, 8, kThreads32>(d_pairs, run, passes, s)
+              : launch_t<32, 32, 4, kThreads32>(d_pairs, run, passes, s);
 }
 
 }  // namespace epic

@@ -9,7 +9,7 @@
 //     with tentative d(v) is final once d(v) <= dmin + lightest_edge(v),
 //     where dmin is the smallest tentative distance on the frontier (no
 //     unsettled node can still lower it).  The edges of all nodes settled in
-//     a step are relaxed together, one lane per edge, in windows of 256
+//     a step are relaxed together, one lane per edge, in windows of 128
 //     edges: a prefix sum of the settled nodes' degrees places their edge
 //     segments, a prefix maximum over marked segment starts tells every lane
 //     whose edge it holds.  Every CSR record carries the neighbour's CSR
@@ -59,7 +59,7 @@ __device__ __forceinline__ void lds_order() { __asm__ __volatile__("" ::: "memor
 template <int VCAP, bool F64>
 struct KnnLds {
     static constexpr int HCAP = 2 * VCAP;
-    static constexpr int TW = 256;                // edges per relaxation window
+    static constexpr int TW = 128;                // edges per relaxation window
     using DT = typename std::conditional<F64, u64, u32>::type;     // distance bits
     using RT = typename std::conditional<F64, double, float>::type;
     alignas(16) DT dm[2 * VCAP];  // entry e: tentative distance (2e), lightest edge (2e + 1)
@@ -235,7 +235,6 @@ __device__ __forceinline__ bool knn_fit_one(const PairDev& P, const RunDev& run,
             u32 ei[Q];
 #pragma unroll
             for (int q = 0; q < Q; ++q) {
-                if (q >= nq) break;
                 RT unused;
                 read_dm<VCAP, F64>(S, qe[q], du[q], unused);
                 const uint2 rr = S.rd[qe[q]];
@@ -245,7 +244,6 @@ __device__ __forceinline__ bool knn_fit_one(const PairDev& P, const RunDev& run,
             RT cand[Q], nbm[Q];
 #pragma unroll
             for (int q = 0; q < Q; ++q) {
-                if (q >= nq) break;
                 rec[q] = P.adj[ei[q]];
                 if constexpr (F64) {
                     cand[q] = du[q] + P.adjw64[ei[q]];
@@ -261,14 +259,10 @@ __device__ __forceinline__ bool knn_fit_one(const PairDev& P, const RunDev& run,
             u32 hh[Q];
 #pragma unroll
             for (int q = 0; q < Q; ++q) {
-                pend[q] = false;
+                pend[q] = act[q];
                 won[q] = false;
                 hs[q] = -1;
-                hh[q] = 0;
-                if (q < nq) {
-                    pend[q] = act[q];
-                    hh[q] = node_slot((int)rec[q].x, HBITS);
-                }
+                hh[q] = node_slot((int)rec[q].x, HBITS);
             }
             for (int probe = 0; probe < HCAP; ++probe) {
                 bool any = false;
@@ -278,19 +272,16 @@ __device__ __forceinline__ bool knn_fit_one(const PairDev& P, const RunDev& run,
                 int cur[Q], prev[Q];
 #pragma unroll
                 for (int q = 0; q < Q; ++q) {
-                    if (q >= nq) break;
-                    cur[q] = pend[q] ? htab[hh[q]] : 0;
+                        cur[q] = pend[q] ? htab[hh[q]] : 0;
                 }
 #pragma unroll
                 for (int q = 0; q < Q; ++q) {
-                    if (q >= nq) break;
-                    prev[q] = cur[q];
+                        prev[q] = cur[q];
                     if (pend[q] && cur[q] == -1) prev[q] = atomicCAS(&htab[hh[q]], -1, (int)rec[q].x);
                 }
 #pragma unroll
                 for (int q = 0; q < Q; ++q) {
-                    if (q >= nq) break;
-                    if (!pend[q]) continue;
+                        if (!pend[q]) continue;
                     if (cur[q] == -1 && prev[q] == -1) {
                         won[q] = true;
                         hs[q] = (int)hh[q];
@@ -312,7 +303,6 @@ __device__ __forceinline__ bool knn_fit_one(const PairDev& P, const RunDev& run,
             // new nodes get entries (with their distance and CSR range)
 #pragma unroll
             for (int q = 0; q < Q; ++q) {
-                if (q >= nq) break;
                 const u64 m = wave::ballot(won[q]);
                 const int e = nvis + wave::lanes_below(m);
                 nvis += __popcll(m);
@@ -333,7 +323,6 @@ __device__ __forceinline__ bool knn_fit_one(const PairDev& P, const RunDev& run,
             // relax the nodes that were already in the table
 #pragma unroll
             for (int q = 0; q < Q; ++q) {
-                if (q >= nq) break;
                 if (act[q] && hs[q] >= 0 && !won[q]) {
                     const int e = S.hidx[hs[q]];
                     if (e != 0xffff) atomicMin(&S.dm[2 * e], to_bits<F64>(cand[q]));
