@@ -202,7 +202,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tile", default="32x16", help="geodesic tile WxH")
-    ap.add_argument("--passes", type=int, default=16, help="geodesic passes per call")
+    ap.add_argument("--passes", type=int, default=0,
+                    help="geodesic passes per call (0 = automatic budget)")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batch-reps", type=int, default=10)
     ap.add_argument("--no-served", action="store_true")
@@ -257,6 +258,20 @@ def main():
     ms_step = el / args.steps * 1e3
     mpix = args.steps * HW / el / 1e6
     log(f"bench: {ms_step:.4f} ms/step, {mpix:.1f} Mpix/s")
+
+    # the same call replayed as a captured HIP graph (launch sequence
+    # recorded once; inputs resident, identical work per step)
+    g = ctx.capture([(cost, matches, sc.K, sc.a, sc.mode)], outs=[flow])
+    for _ in range(args.warmup):
+        g.launch()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        g.launch()
+    torch.cuda.synchronize()
+    graph_ms = (time.perf_counter() - t0) / args.steps * 1e3
+    g.close()
+    log(f"bench: graph replay {graph_ms:.4f} ms/step, {HW / graph_ms / 1e3:.1f} Mpix/s")
 
     # ------------------------------------- per-stage HIP events (same stream)
     ctx.profile(True)
@@ -318,7 +333,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": sc.name, "H": sc.H, "W": sc.W, "N": sc.N, "K": sc.K,
                    "a": sc.a, "mode": "LA", "mean_epe_vs_oracle_px": float(epe.mean()),
-                   "stage_ms": {k: round(v, 5) for k, v in stages.items()}},
+                   "stage_ms": {k: round(v, 5) for k, v in stages.items()},
+                   "graph_replay_ms_per_step": round(graph_ms, 5)},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "batched": batched,

@@ -83,10 +83,13 @@ typedef struct epic_options {
     int   tile_w, tile_h;   /* geodesic-transform tile (0 = default 32 x 16;
                                supported: 32x16, 32x32, 32x64; tile_w is 32)   */
     int   geo_passes;       /* bulk-synchronous passes of the geodesic
-                               transform launched per call (0 = default 16,
-                               at most 64); a single-workgroup finisher
-                               completes the transform if they do not reach
-                               the fixpoint, so this only affects speed        */
+                               transform launched per call, at most 63;
+                               0 (default) = automatic: the passes the last
+                               finished call needed plus 2 (16 before the
+                               first; the FP64 path uses 16).  A
+                               single-workgroup finisher completes the
+                               transform if they do not reach the fixpoint,
+                               so this only affects speed, never results     */
 } epic_options;
 
 typedef struct epic_ctx epic_ctx;

@@ -52,13 +52,15 @@ def _check_tensor(t, name, dtype, shape_tail=None):
 
 class Context:
     """Owns one epic_ctx: a device workspace allocated once (``workspace``
-    bytes, default enough for a 2048 x 1080 image with 40000 matches)."""
+    bytes, default enough for a 2048 x 1080 image with 40000 matches).
+    ``passes`` is the geodesic pass budget per call (0 = automatic, from the
+    passes the previous call needed); it never changes results."""
 
     def __init__(self, device: int = 0, workspace: int | None = None, *,
                  connectivity: int = 8, la_weight_power: int = 2,
                  precision: int = 0, fp64_route: float = 1e-3,
                  degenerate_tau: float = 1e-9, tile: tuple[int, int] = (32, 16),
-                 passes: int = 16):
+                 passes: int = 0):
         torch = _torch()
         L = _lib.load()
         self.device = int(device)

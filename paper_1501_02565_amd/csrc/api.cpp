@@ -21,6 +21,9 @@ using namespace epic;
 namespace {
 
 constexpr int kMaxPairs = 1024;      // pairs per call
+constexpr int kAutoPassesStart = 16;    // automatic budget before any call finished
+constexpr int kAutoPassesMargin = 2;    // passes launched beyond the last call's need
+constexpr int kAutoPassesMin = 4;
 constexpr int kRing = 4;             // descriptor upload slots
 constexpr size_t kAlign = 256;
 constexpr int kMaxK = 256;
@@ -100,7 +103,9 @@ struct epic_ctx {
     std::vector<int*> last_counters;
     int* g_any = nullptr;
     int* g_error = nullptr;
-    int passes = 16;                    // geodesic passes launched per call
+    int passes = 16;                    // geodesic passes launched per call (fixed budget)
+    bool auto_passes = true;            // budget from the passes the last call needed
+    int* h_passes_used = nullptr;       // pinned, written by the transform's finisher
     // stage timing
     bool prof = false;
     hipEvent_t prof_ev[kProfRing][kStages + 1]{};
@@ -165,7 +170,7 @@ epic_ctx* epic_create(int device, size_t workspace_bytes, const epic_options* op
     o.degenerate_tau = 1e-9;
     o.tile_w = 32;
     o.tile_h = 16;
-    o.geo_passes = 16;
+    o.geo_passes = 0;
     if (opts) {
         o = *opts;
         if (o.connectivity != 4) o.connectivity = 8;
@@ -176,10 +181,11 @@ epic_ctx* epic_create(int device, size_t workspace_bytes, const epic_options* op
         const Tiling t = tiling_from(o);
         o.tile_w = t.tw;
         o.tile_h = t.th;
-        if (o.geo_passes <= 0) o.geo_passes = 16;
+        if (o.geo_passes < 0) o.geo_passes = 0;
         if (o.geo_passes > kMaxPasses - 1) o.geo_passes = kMaxPasses - 1;
     }
-    c->passes = o.geo_passes;
+    c->auto_passes = o.geo_passes == 0;
+    c->passes = c->auto_passes ? kAutoPassesStart : o.geo_passes;
     c->opt = o;
     auto fail = [&](const char* what) {
         g_last_error = what;
@@ -195,6 +201,9 @@ epic_ctx* epic_create(int device, size_t workspace_bytes, const epic_options* op
     for (int i = 0; i < kRing; ++i)
         if (hipEventCreateWithFlags(&c->ring_ev[i], hipEventDisableTiming) != hipSuccess)
             return fail("event creation failed");
+    if (hipHostMalloc((void**)&c->h_passes_used, sizeof(int), hipHostMallocDefault) != hipSuccess)
+        return fail("pinned counter allocation failed");
+    *c->h_passes_used = 0;
     c->g_error = reinterpret_cast<int*>(c->ws);
     c->g_any = reinterpret_cast<int*>(c->ws) + 256;         // kMaxPasses ints
     return c;
@@ -212,6 +221,7 @@ void epic_destroy(epic_ctx* c) {
         for (int i = 0; i <= kStages; ++i)
             if (c->prof_ev[r][i]) hipEventDestroy(c->prof_ev[r][i]);
     if (c->h_desc) hipHostFree(c->h_desc);
+    if (c->h_passes_used) hipHostFree(c->h_passes_used);
     if (c->ws) hipFree(c->ws);
     delete c;
 }
@@ -363,6 +373,7 @@ int run_pairs(epic_ctx* c, const epic_request* reqs, int n, hipStream_t stream, 
     run.any = c->g_any;
     run.any2 = c->g_any + kMaxPasses;
     run.error = c->g_error;
+    run.passes_used = c->h_passes_used;
     run.ovf_list = ovf_list;
     run.ovf_count = c->g_error + 8;
     run.total_tiles = tile_base;
@@ -401,9 +412,18 @@ int run_pairs(epic_ctx* c, const epic_request* reqs, int n, hipStream_t stream, 
     mark(0);
     if (e == hipSuccess) e = launch_seed(dd, run, seed_blocks, stream);
     mark(1);
+    // Automatic budget: the passes the last finished transform needed, plus
+    // a margin (the value may come from an older call while the last one is
+    // still running; any budget gives the same result, the finisher
+    // completes the transform).  The FP64 path keeps a fixed budget.
+    int passes = c->passes;
+    if (c->auto_passes && c->opt.precision == 0) {
+        const int used = *reinterpret_cast<volatile int*>(c->h_passes_used);
+        if (used > 0) passes = std::min(kMaxPasses - 1, std::max(kAutoPassesMin, used + kAutoPassesMargin));
+    }
     if (e == hipSuccess)
         e = c->opt.precision == 1 ? launch_geodesic64(dd, run, c->passes, seed_blocks, stream)
-                                  : launch_geodesic(dd, run, tl.tw, tl.th, c->passes, stream);
+                                  : launch_geodesic(dd, run, tl.tw, tl.th, passes, stream);
     mark(2);
     if (e == hipSuccess) e = launch_graph_emit(dd, run, pix_blocks, stream);
     mark(3);

@@ -110,6 +110,7 @@ struct RunDev {
     int* any;               // per pass: some tile border changed (kMaxPasses)
     int* any2;              // the same for the label phase of the FP64 path
     int* error;             // global error word
+    int* passes_used;       // host-visible: passes the last transform needed (may be null)
     int* ovf_list;          // K-NN sources to redo with a larger table
     int* ovf_count;
     int total_tiles;

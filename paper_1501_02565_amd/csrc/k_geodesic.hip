@@ -285,7 +285,15 @@ template <int TW, int TH, int CONN, int NT>
 __global__ __launch_bounds__(NT) void k_geo_finish(const PairDev* __restrict__ pairs, RunDev run, int pass0) {
     __shared__ TileLds<TW, TH> S;
     __shared__ int s_any;
-    if (run.any[pass0 - 1] == 0) return;
+    // passes that changed something so far (they form a prefix): the
+    // transform needs one more than that, which is reported for the
+    // automatic pass budget of later calls
+    int changed = 0;
+    for (int q = 0; q < pass0; ++q) changed += run.any[q] != 0 ? 1 : 0;
+    if (run.any[pass0 - 1] == 0) {
+        if (threadIdx.x == 0 && run.passes_used) *run.passes_used = changed + 1;
+        return;
+    }
     for (int pass = pass0; pass < pass0 + 65536; ++pass) {
         if (threadIdx.x == 0) s_any = 0;
         __syncthreads();
@@ -310,7 +318,11 @@ __global__ __launch_bounds__(NT) void k_geo_finish(const PairDev* __restrict__ p
             __syncthreads();
         }
         __syncthreads();
-        if (s_any == 0) return;
+        if (s_any == 0) {
+            if (threadIdx.x == 0 && run.passes_used) *run.passes_used = changed + 1;
+            return;
+        }
+        ++changed;
         __syncthreads();
     }
     if (threadIdx.x == 0) atomicOr(run.error, 1);

@@ -161,3 +161,25 @@ def test_workspace_too_small():
         with pytest.raises(epic.EpicError) as ei:
             c.interp(torch.from_numpy(sc.cost).cuda(), torch.from_numpy(sc.matches).cuda(), 8, 1.0, 1)
         assert ei.value.status == epic.ERR_WORKSPACE
+
+
+def test_pass_budget_does_not_change_results():
+    """The geodesic pass budget (fixed small, fixed large, automatic over
+    repeated calls) only changes how much work the finisher does: flows are
+    bitwise identical."""
+    import torch
+    import paper_1501_02565_amd as epic
+    sc = random_case(180, 230, 400, seed=22, K=16)
+    _announce(f"{sc.name} pass budgets")
+    c = torch.from_numpy(sc.cost).cuda()
+    m = torch.from_numpy(sc.matches).cuda()
+    ws = epic.workspace_bytes(sc.H, sc.W, sc.N, sc.K)
+    flows = []
+    for passes, calls in ((1, 1), (3, 1), (16, 1), (0, 4)):
+        with epic.Context(0, ws, passes=passes) as ctx:
+            for _ in range(calls):
+                f = ctx.interp(c, m, sc.K, sc.a, sc.mode).clone()
+                torch.cuda.synchronize()
+                flows.append(f)
+    for f in flows[1:]:
+        assert torch.equal(flows[0], f)
