@@ -295,6 +295,7 @@ int run_pairs(epic_ctx* c, const epic_request* reqs, int n, hipStream_t stream, 
     for (int i = 0; i < n; ++i) total_n += reqs[i].N;
     int* ovf_list = reinterpret_cast<int*>(take(4 * (size_t)total_n));
     int tile_base = 0, pix_blocks = 0, seed_blocks = 0, src_blocks = 0, slot_blocks = 0, init_blocks = 0;
+    int emit_blocks = 0;
     int kmax = 1;
     c->last_counters.assign(n, nullptr);
     for (int i = 0; i < n; ++i) {
@@ -318,6 +319,8 @@ int run_pairs(epic_ctx* c, const epic_request* reqs, int n, hipStream_t stream, 
         const long long HW = (long long)r.H * r.W;
         P.pix_block_base = pix_blocks;
         pix_blocks += (int)((HW + PIX_BLOCK - 1) / PIX_BLOCK);
+        P.emit_block_base = emit_blocks;
+        emit_blocks += ((r.W + EMIT_TW - 1) / EMIT_TW) * ((r.H + EMIT_TH - 1) / EMIT_TH);
         P.seed_block_base = seed_blocks;
         seed_blocks += (r.N + PIX_BLOCK - 1) / PIX_BLOCK;
         P.src_block_base = src_blocks;
@@ -425,7 +428,7 @@ int run_pairs(epic_ctx* c, const epic_request* reqs, int n, hipStream_t stream, 
         e = c->opt.precision == 1 ? launch_geodesic64(dd, run, c->passes, seed_blocks, stream)
                                   : launch_geodesic(dd, run, tl.tw, tl.th, passes, stream);
     mark(2);
-    if (e == hipSuccess) e = launch_graph_emit(dd, run, pix_blocks, stream);
+    if (e == hipSuccess) e = launch_graph_emit(dd, run, emit_blocks, stream);
     mark(3);
     if (e == hipSuccess) e = launch_csr_scan(dd, run, stream);
     mark(4);

@@ -60,6 +60,7 @@ struct PairDev {
     int tiles_x, tiles_y;
     int tile_base;          // first global tile id of this pair
     int pix_block_base;     // first block of pixel-parallel grids
+    int emit_block_base;    // first block of the graph-emit grid (EMIT_TW x EMIT_TH tiles)
     int src_block_base;     // first block of the per-match grid (one match per block)
     int seed_block_base;    // first block of the seeding grid (PIX_BLOCK matches per block)
     int slot_block_base;    // first block of the hash-slot grid
@@ -140,6 +141,7 @@ __device__ __forceinline__ int find_pair(int npairs, int idx, F base_of) {
 // host-side launchers (one per stage; defined next to their kernels)
 // ---------------------------------------------------------------------------
 constexpr int PIX_BLOCK = 256;      // pixels per block of pixel-parallel kernels
+constexpr int EMIT_TW = 32, EMIT_TH = 8;   // pixel tile of one graph-emit block
 constexpr int SLOT_BLOCK = 256;     // hash slots per block
 
 hipError_t launch_clear(const PairDev* d_pairs, const RunDev& run, int total_blocks, hipStream_t s);

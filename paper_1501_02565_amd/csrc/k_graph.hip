@@ -81,26 +81,31 @@ __device__ __forceinline__ void global_insert(const PairDev& P, u64 hk, u64 wb) 
 }
 }  // namespace
 
-// Each block handles PIX_BLOCK consecutive pixels.  Candidates are first
-// reduced in a block-local LDS hash (adjacent pixels mostly share their pair
-// of cells), then each distinct edge goes to the global hash once per block.
+// Each block handles one EMIT_TW x EMIT_TH tile of pixels.  Candidates are
+// first reduced in a block-local LDS hash (adjacent pixels mostly share their
+// pair of cells), then each distinct edge goes to the global hash once per
+// block; a compact tile meets far fewer cell boundaries than a pixel strip of
+// the same size, so few edges reach the global hash per block.
 template <int CONN, bool F64>
 __global__ __launch_bounds__(PIX_BLOCK) void k_graph_emit(const PairDev* __restrict__ pairs, RunDev run) {
     constexpr int LCAP = 4 * PIX_BLOCK;               // >= candidates per block
     using V = typename std::conditional<F64, u64, u32>::type;
     __shared__ u64 lkey[LCAP];
     __shared__ V lval[LCAP];
-    const int p = find_pair(run.npairs, (int)blockIdx.x, [&](int i) { return pairs[i].pix_block_base; });
+    static_assert(EMIT_TW * EMIT_TH == PIX_BLOCK, "emit tile");
+    const int p = find_pair(run.npairs, (int)blockIdx.x, [&](int i) { return pairs[i].emit_block_base; });
     const PairDev& P = pairs[p];
     for (int i = threadIdx.x; i < LCAP; i += PIX_BLOCK) {
         lkey[i] = HASH_EMPTY;
         lval[i] = F64 ? (V)DOUBLE_INF_BITS : (V)FLOAT_INF_BITS;
     }
     __syncthreads();
-    const long long i = (long long)((int)blockIdx.x - P.pix_block_base) * PIX_BLOCK + threadIdx.x;
     const int W = P.W, H = P.H;
-    if (i < (long long)W * H) {
-        const int x = (int)(i % W), y = (int)(i / W);
+    const int tb = (int)blockIdx.x - P.emit_block_base, etx = (W + EMIT_TW - 1) / EMIT_TW;
+    const int x = (tb % etx) * EMIT_TW + (int)threadIdx.x % EMIT_TW;
+    const int y = (tb / etx) * EMIT_TH + (int)threadIdx.x / EMIT_TW;
+    const long long i = (long long)y * W + x;
+    if (x < W && y < H) {
         const u64 kp = P.keys[i];
         const u32 lp = F64 ? P.labels[i] : key_label(kp);
         if (lp != NO_LABEL) {
