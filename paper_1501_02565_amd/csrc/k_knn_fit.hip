@@ -122,6 +122,9 @@ __device__ __forceinline__ bool knn_fit_one(const PairDev& P, const RunDev& run,
     // ------------------------------------------------------------ Dijkstra
     for (int i = lane; i < HCAP; i += 64) htab[i] = -1;
     for (int i = lane; i < TW; i += 64) S.head[i] = 0;
+    for (int i = lane; i < 2 * VCAP; i += 64) S.dm[i] = to_bits<F64>(RINF);
+    for (int i = lane; i < VCAP; i += 64) S.rd[i] = make_uint2(0u, 0u);
+    __syncthreads();
     if (lane == 0) {
         const u32 a = P.row_ptr[s], b = P.row_ptr[s + 1];
         S.dm[0] = 0;
@@ -143,18 +146,13 @@ __device__ __forceinline__ bool knn_fit_one(const PairDev& P, const RunDev& run,
         const int nv = nvis;
         RT mi[R];
         uint2 rdv[R];
+        // entries not in use read as (inf, inf, 0, 0): the table is filled
+        // with them at the start, so the reads need no predicate
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            d[r] = RINF;
-            mi[r] = RINF;
-            rdv[r] = make_uint2(0u, 0u);
-            if (64 * r < nv) {
-                const int e = lane + 64 * r;
-                if (e < nv) {
-                    read_dm<VCAP, F64>(S, e, d[r], mi[r]);
-                    rdv[r] = S.rd[e];
-                }
-            }
+            const int e = lane + 64 * r;
+            read_dm<VCAP, F64>(S, e, d[r], mi[r]);
+            rdv[r] = S.rd[e];
         }
         RT fmin = RINF;
         int below = 0;
@@ -163,7 +161,8 @@ __device__ __forceinline__ bool knn_fit_one(const PairDev& P, const RunDev& run,
             if ((settled >> r) & 1u) continue;
             fmin = fmin < d[r] ? fmin : d[r];
         }
-        const RT dmin = wave::min(fmin);
+        RT dmin;
+        if constexpr (F64) dmin = wave::min(fmin); else dmin = wave::min_nonneg(fmin);
 #pragma unroll
         for (int r = 0; r < R; ++r) below += (((settled >> r) & 1u) && d[r] < dmin) ? 1 : 0;
         below = wave::sum(below);
@@ -213,10 +212,12 @@ __device__ __forceinline__ bool knn_fit_one(const PairDev& P, const RunDev& run,
                 if (q < nq) {
                     act[q] = wb + 64 * q + lane < T;
                     const int hv = S.head[64 * q + lane];
-                    const int sc = wave::incl_max(hv ? (((64 * q + lane) << 16) | (hv - 1)) : -1);
-                    if (sc >= 0) {
-                        qst[q] = wb + (sc >> 16);
-                        qe[q] = sc & 0xffff;
+                    // (window position, entry) of the last segment start at
+                    // or before this lane, plus one (0: none in this chunk)
+                    const unsigned sc = wave::incl_max(hv ? ((unsigned)(64 * q + lane) << 16) + (unsigned)hv : 0u);
+                    if (sc != 0u) {
+                        qst[q] = wb + (int)(sc >> 16);
+                        qe[q] = (int)(sc & 0xffffu) - 1;
                     } else {
                         qst[q] = carry_start;
                         qe[q] = carry_e;

@@ -108,15 +108,33 @@ __device__ __forceinline__ int incl_scan(int v) {
     return v;
 }
 
-// Inclusive prefix maximum over lanes 0..63 (values >= -1; -1 is neutral).
-__device__ __forceinline__ int incl_max(int v) {
-    v = max(v, dpp<ROW_SHR1>(-1, v));
-    v = max(v, dpp<ROW_SHR2>(-1, v));
-    v = max(v, dpp<ROW_SHR4>(-1, v));
-    v = max(v, dpp<ROW_SHR8>(-1, v));
-    v = max(v, dpp<ROW_BCAST15, 0xA>(-1, v));
-    v = max(v, dpp<ROW_BCAST31, 0xC>(-1, v));
+// Inclusive prefix maximum over lanes 0..63 of unsigned values (0 is
+// neutral, so every step is one DPP-fused maximum).
+__device__ __forceinline__ unsigned incl_max(unsigned v) {
+    v = max(v, (unsigned)dpp<ROW_SHR1>(0, (int)v));
+    v = max(v, (unsigned)dpp<ROW_SHR2>(0, (int)v));
+    v = max(v, (unsigned)dpp<ROW_SHR4>(0, (int)v));
+    v = max(v, (unsigned)dpp<ROW_SHR8>(0, (int)v));
+    v = max(v, (unsigned)dpp<ROW_BCAST15, 0xA>(0, (int)v));
+    v = max(v, (unsigned)dpp<ROW_BCAST31, 0xC>(0, (int)v));
     return v;
+}
+
+// Maximum of unsigned values over the 64 lanes, returned to every lane.
+__device__ __forceinline__ unsigned max_u32(unsigned v) {
+    v = max(v, (unsigned)dpp<QP_XOR1>(0, (int)v));
+    v = max(v, (unsigned)dpp<QP_XOR2>(0, (int)v));
+    v = max(v, (unsigned)dpp<ROW_HALF_MIRROR>(0, (int)v));
+    v = max(v, (unsigned)dpp<ROW_MIRROR>(0, (int)v));
+    v = max(v, (unsigned)dpp<ROW_BCAST15, 0xA>(0, (int)v));
+    v = max(v, (unsigned)dpp<ROW_BCAST31, 0xC>(0, (int)v));
+    return (unsigned)__builtin_amdgcn_readlane((int)v, 63);
+}
+
+// Minimum of non-negative floats (or +inf) over the 64 lanes: their bits
+// order like the values, and min = ~max(~bits) keeps the neutral value 0.
+__device__ __forceinline__ float min_nonneg(float v) {
+    return __uint_as_float(~max_u32(~__float_as_uint(v)));
 }
 
 __device__ __forceinline__ u64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
