@@ -106,9 +106,14 @@ def batched_form(args, np, torch, epic):
              for sc in scs]
     px = sum(sc.H * sc.W for sc in scs)
     need = sum(epic.workspace_bytes(sc.H, sc.W, sc.N, sc.K) for sc in scs)
-    best = tune.tune(probs, need, reps=5, use_cache=False)
-    log(f"bench: tuned {best['tile']} passes {best['passes']} ({best['ms']:.3f} ms); trials "
-        + ", ".join(f"{t['tile']}/{t['passes']}: {t['ms']:.3f}" for t in best["trials"]))
+    if args.batch_config:
+        tw, th, ps = (int(v) for v in args.batch_config.replace("/", "x").split("x"))
+        best = {"tile": (tw, th), "passes": ps, "ms": float("nan"), "trials": []}
+        log(f"bench: batch configuration {best['tile']} passes {ps} (not tuned)")
+    else:
+        best = tune.tune(probs, need, reps=5, use_cache=False)
+        log(f"bench: tuned {best['tile']} passes {best['passes']} ({best['ms']:.3f} ms); trials "
+            + ", ".join(f"{t['tile']}/{t['passes']}: {t['ms']:.3f}" for t in best["trials"]))
     with epic.Context(0, need, tile=best["tile"], passes=best["passes"]) as ctx:
         g = ctx.capture(probs)
         for _ in range(3):
@@ -124,14 +129,16 @@ def batched_form(args, np, torch, epic):
         stats = [ctx.stats(i) for i in range(len(scs))]
         g.close()
         # the plain single-pair form on the same pairs and GPU
-        for c, m, K, a, mode in probs[:4]:
-            ctx.interp(c, m, K, a, mode)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for c, m, K, a, mode in probs:
-            ctx.interp(c, m, K, a, mode)
-        torch.cuda.synchronize()
-        ms_plain = (time.perf_counter() - t0) * 1e3
+        ms_plain = float("nan")
+        if not args.no_plain:
+            for c, m, K, a, mode in probs[:4]:
+                ctx.interp(c, m, K, a, mode)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for c, m, K, a, mode in probs:
+                ctx.interp(c, m, K, a, mode)
+            torch.cuda.synchronize()
+            ms_plain = (time.perf_counter() - t0) * 1e3
     assert all(st["status"] == 0 for st in stats), stats
     epes = []
     for i in (0, 21, 42, 63):
@@ -139,8 +146,9 @@ def batched_form(args, np, torch, epic):
         epes.append(float(np.linalg.norm(flows[i].astype(np.float64) - ref, axis=2).mean()))
     out = {"workload": f"batch of 64 mixed pairs, {px / 1e6:.2f} Mpx, {sum(sc.N for sc in scs)} matches",
            "mpix_s": round(px / ms_batch / 1e3, 2), "ms_per_batch": round(ms_batch, 4),
-           "plain_mpix_s": round(px / ms_plain / 1e3, 2), "plain_ms": round(ms_plain, 4),
-           "speedup_vs_plain": round(ms_plain / ms_batch, 3),
+           "plain_mpix_s": None if args.no_plain else round(px / ms_plain / 1e3, 2),
+           "plain_ms": None if args.no_plain else round(ms_plain, 4),
+           "speedup_vs_plain": None if args.no_plain else round(ms_plain / ms_batch, 3),
            "tuned": {"tile": list(best["tile"]), "passes": best["passes"]},
            "sampled_mean_epe_vs_oracle_px": epes}
     log(f"bench: batched {out}")
@@ -206,6 +214,10 @@ def main():
                     help="geodesic passes per call (0 = automatic budget)")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batch-reps", type=int, default=10)
+    ap.add_argument("--batch-config", default="",
+                    help="batched form: fixed WxH/passes (e.g. 32x16/12) instead of autotuning")
+    ap.add_argument("--no-plain", action="store_true",
+                    help="batched form: skip the single-pair comparison loop")
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--served-requests", type=int, default=2000)
     ap.add_argument("--served-budget", type=int, default=8 << 30)
