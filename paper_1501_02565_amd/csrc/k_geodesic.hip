@@ -86,22 +86,34 @@ constexpr int nb_index(int dx, int dy) {
          : dx == 1 && dy == 1 ? 4 : dx == -1 && dy == 1 ? 5 : dx == 1 && dy == -1 ? 6 : dx == -1 && dy == -1 ? 7 : -1;
 }
 
-template <int TW, int TH, int CONN, int NT>
-__device__ __forceinline__ int visit_tile(const PairDev& P, int tx, int ty, TileLds<TW, TH>& S, int* error) {
-    constexpr int PPT = TW * TH / NT;
-    constexpr int LW = TileLds<TW, TH>::LW, LH = TileLds<TW, TH>::LH, NL = TileLds<TW, TH>::NL;
-    constexpr int HR = TW / PPT;           // row runs per row
-    static_assert(PPT * NT == TW * TH && HR * PPT == TW && HR * TH == NT && (TH / PPT) * TW == NT &&
-                      TH % PPT == 0, "tile shape");
+//
+// The region relaxed is the tile widened by MX columns and MY rows on each
+// side (both 0 in the normal passes); only the tile itself is written back.
+// The first pass uses a margin so that seeds just outside a tile already
+// shape its distances, which saves most of the passes that would otherwise
+// carry them in one tile at a time.
+template <int TW, int TH, int MX, int MY, int CONN, int NT>
+__device__ __forceinline__ int visit_tile(const PairDev& P, int tx, int ty,
+                                          TileLds<TW + 2 * MX, TH + 2 * MY>& S, int* error) {
+    constexpr int RW = TW + 2 * MX, RH = TH + 2 * MY;     // region relaxed
+    constexpr int PPT = RW * RH / NT;
+    constexpr int LW = TileLds<RW, RH>::LW, LH = TileLds<RW, RH>::LH, NL = TileLds<RW, RH>::NL;
+    constexpr int HR = RW / PPT;           // row runs per row
+    static_assert(PPT * NT == RW * RH && HR * PPT == RW && HR * RH == NT && (RH / PPT) * RW == NT &&
+                      RH % PPT == 0, "tile shape");
     constexpr int DX[8] = {1, -1, 0, 0, 1, -1, 1, -1};
     constexpr int DY[8] = {0, 0, 1, -1, 1, 1, -1, -1};
     const int tid = threadIdx.x;
     const int x0 = tx * TW, y0 = ty * TH, W = P.W, H = P.H;
+    const int rx0 = x0 - MX, ry0 = y0 - MY;               // region origin (may be < 0)
     const int twe = min(TW, W - x0), the = min(TH, H - y0);
+    // region pixels inside the image: lx in [vx0, vx1), ly in [vy0, vy1)
+    const int vx0 = MX == 0 ? 0 : max(0, -rx0), vy0 = MY == 0 ? 0 : max(0, -ry0);
+    const int vx1 = min(RW, W - rx0), vy1 = min(RH, H - ry0);
 
     for (int i = tid; i < NL; i += NT) {
         const int ly = i / LW, lxx = i - ly * LW;
-        const int gx = x0 + lxx - 1, gy = y0 + ly - 1;
+        const int gx = rx0 + lxx - 1, gy = ry0 + ly - 1;
         u64 k = KEY_INF;
         float c = 0.0f;
         if (gx >= 0 && gy >= 0 && gx < W && gy < H) {
@@ -119,7 +131,7 @@ __device__ __forceinline__ int visit_tile(const PairDev& P, int tx, int ty, Tile
     // the two runs of this thread: a row run (hx.., hy) and a column run
     // (vx, vy..), with their step costs to the 8 neighbours
     const int hy = tid / HR, hx = (tid % HR) * PPT;
-    const int vx = tid % TW, vy = (tid / TW) * PPT;
+    const int vx = tid % RW, vy = (tid / RW) * PPT;
     float wh[PPT][CONN], wv[PPT][CONN];
     u64 orig[PPT];
 #pragma unroll
@@ -176,7 +188,7 @@ __device__ __forceinline__ int visit_tile(const PairDev& P, int tx, int ty, Tile
                     }
                 }
                 u64 bk = (u64)__double_as_longlong(best);
-                if (lx >= twe || ly >= the) bk = now;            // outside a ragged tile
+                if (lx < vx0 || lx >= vx1 || ly < vy0 || ly >= vy1) bk = now;   // outside the image
                 if (bk < now) {
                     S.key[c] = bk;
                     changed = 1;
@@ -213,9 +225,9 @@ __device__ __forceinline__ int visit_tile(const PairDev& P, int tx, int ty, Tile
     int bm = 0;
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
-        const int lx = hx + j, ly = hy;
-        const u64 k = S.key[(ly + 1) * LW + lx + 1];
-        if (lx < twe && ly < the && k != orig[j]) {
+        const int lx = hx + j - MX, ly = hy - MY;          // tile coordinates
+        const u64 k = S.key[(hy + 1) * LW + hx + j + 1];
+        if (lx >= 0 && ly >= 0 && lx < twe && ly < the && k != orig[j]) {
             P.keys[(long long)(y0 + ly) * W + x0 + lx] = k;
             const bool l = lx == 0, r = lx == twe - 1, t = ly == 0, b = ly == the - 1;
             bm |= (l ? B_L : 0) | (r ? B_R : 0) | (t ? B_T : 0) | (b ? B_B : 0) | ((l && t) ? B_TL : 0) |
@@ -269,12 +281,35 @@ __global__ __launch_bounds__(NT) void k_geo_pass(const PairDev* __restrict__ pai
     const int tx = lt % P.tiles_x, ty = lt / P.tiles_x;
     __syncthreads();
     if (threadIdx.x == 0) dirty[tile] = 0u;                  // reused two passes later
-    const int border = visit_tile<TW, TH, CONN, NT>(P, tx, ty, S, run.error);
+    const int border = visit_tile<TW, TH, 0, 0, CONN, NT>(P, tx, ty, S, run.error);
     if (threadIdx.x == 0) {
         atomicAdd(&P.counters[C_TILE_VISITS], 1);
         if (border) {
             mark_neighbours<CONN>(P, run, tx, ty, border, pass + 1);
             run.any[pass] = 1;
+        }
+    }
+}
+
+// The first pass: every tile, relaxed over the tile and a margin of MX
+// columns and MY rows around it (seeds from the start, written by k_seed).
+template <int TW, int TH, int MX, int MY, int CONN, int NT>
+__global__ __launch_bounds__(NT) void k_geo_first(const PairDev* __restrict__ pairs, RunDev run) {
+    __shared__ TileLds<TW + 2 * MX, TH + 2 * MY> S;
+    const int per_xcd = (run.total_tiles + 7) / 8;
+    const int tile = (int)(blockIdx.x % 8) * per_xcd + (int)(blockIdx.x / 8);
+    if (tile >= run.total_tiles) return;
+    const int p = find_pair(run.npairs, tile, [&](int i) { return pairs[i].tile_base; });
+    const PairDev& P = pairs[p];
+    const int lt = tile - P.tile_base;
+    const int tx = lt % P.tiles_x, ty = lt / P.tiles_x;
+    if (threadIdx.x == 0) run.dirty[0][tile] = 0u;           // reused by pass 2
+    const int border = visit_tile<TW, TH, MX, MY, CONN, NT>(P, tx, ty, S, run.error);
+    if (threadIdx.x == 0) {
+        atomicAdd(&P.counters[C_TILE_VISITS], 1);
+        if (border) {
+            mark_neighbours<CONN>(P, run, tx, ty, border, 1);
+            run.any[0] = 1;
         }
     }
 }
@@ -306,7 +341,7 @@ __global__ __launch_bounds__(NT) void k_geo_finish(const PairDev* __restrict__ p
             const int tx = lt % P.tiles_x, ty = lt / P.tiles_x;
             __syncthreads();
             if (threadIdx.x == 0) dirty[tile] = 0u;
-            const int border = visit_tile<TW, TH, CONN, NT>(P, tx, ty, S, run.error);
+            const int border = visit_tile<TW, TH, 0, 0, CONN, NT>(P, tx, ty, S, run.error);
             if (threadIdx.x == 0) {
                 atomicAdd(&P.counters[C_TILE_VISITS], 1);
                 if (border) {
@@ -329,10 +364,20 @@ __global__ __launch_bounds__(NT) void k_geo_finish(const PairDev* __restrict__ p
 }
 
 namespace {
+// First-pass margin (columns, rows) and its threads: a 32 x 16 tile becomes
+// a 40 x 24 region relaxed by 240 threads (runs of 4 pixels), 32 x 32 a
+// 40 x 40 region (320 threads, runs of 5), 32 x 64 a 40 x 72 region (360
+// threads, runs of 8).
+constexpr int kMarginX = 4, kMarginY = 4;
+constexpr int first_threads(int th) { return th == 16 ? 240 : th == 32 ? 320 : 360; }
+
 template <int TW, int TH, int CONN, int NT>
 hipError_t launch_t(const PairDev* d_pairs, const RunDev& run, int passes, hipStream_t s) {
     const int grid = 8 * ((run.total_tiles + 7) / 8);
-    for (int p = 0; p < passes; ++p) {
+    constexpr int NT0 = first_threads(TH);
+    hipLaunchKernelGGL((k_geo_first<TW, TH, kMarginX, kMarginY, CONN, NT0>), dim3(grid), dim3(NT0), 0, s,
+                       d_pairs, run);
+    for (int p = 1; p < passes; ++p) {
         hipLaunchKernelGGL((k_geo_pass<TW, TH, CONN, NT>), dim3(grid), dim3(NT), 0, s, d_pairs, run, p);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;

@@ -366,11 +366,14 @@ __device__ __forceinline__ bool knn_fit_one(const PairDev& P, const RunDev& run,
     __syncthreads();
     int knode[RK];
     RT kdist[RK];
+    // each lane takes compare-exchange pairs (i, i + j): pair t has i = t
+    // with a zero bit inserted at the position of j
     for (int k = 2; k <= p2; k <<= 1) {
         for (int j = k >> 1; j > 0; j >>= 1) {
-            for (int i = lane; i < p2; i += 64) {
-                const int ixj = i ^ j;
-                if (ixj > i) {
+            for (int t = lane; t < (p2 >> 1); t += 64) {
+                const int i = ((t & ~(j - 1)) << 1) | (t & (j - 1));
+                const int ixj = i | j;
+                {
                     const u64 a = S.buf[i], b = S.buf[ixj];
                     const bool up = (i & k) == 0;
                     if constexpr (F64) {
