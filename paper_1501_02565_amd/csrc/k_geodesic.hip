@@ -47,6 +47,18 @@ __device__ __forceinline__ double min_f64(double a, double b) {
     return r;
 }
 
+// Minimum of the first n (compile-time after unrolling) of c[] as a
+// balanced tree of min_f64.
+template <int N>
+__device__ __forceinline__ double tree_min(double (&c)[N], int n) {
+#pragma unroll
+    for (int w = 1; w < N; w <<= 1)
+#pragma unroll
+        for (int i = 0; i + w < N; i += 2 * w)
+            if (i + w < n) c[i] = min_f64(c[i], c[i + w]);
+    return c[0];
+}
+
 enum : int { B_L = 1, B_R = 2, B_T = 4, B_B = 8, B_TL = 16, B_TR = 32, B_BL = 64, B_BR = 128 };
 
 template <int TW, int TH>
@@ -55,6 +67,7 @@ struct TileLds {
     u64 key[NL];
     float cost[NL];
     int flag[3];             // per round (mod 3): some pixel of the tile changed
+    int rowchg[LH];          // last round in which a pixel of the row changed
     int border;
 };
 
@@ -74,7 +87,9 @@ struct TileLds {
 // few steps old.  Every written value is the length of a real path and every
 // pixel is relaxed in every round, so a lost or late update only costs
 // another round: a round in which no pixel improved leaves every pixel at
-// the minimum over its neighbours, which is the fixpoint.
+// the minimum over its neighbours, which is the fixpoint.  A wavefront whose
+// runs saw no change within one row since the previous round started skips
+// its sweeps (per-row change rounds, written with plain stores).
 //
 // A key (D bits, label) with D >= 0 read as an IEEE double is a non-negative
 // value below the NaN range whose order is the unsigned order of the key
@@ -125,6 +140,7 @@ __device__ __forceinline__ int visit_tile(const PairDev& P, int tx, int ty,
         S.cost[i] = c;
     }
     if (tid < 3) S.flag[tid] = 0;
+    for (int i = tid; i < LH; i += NT) S.rowchg[i] = -1;
     if (tid == 0) S.border = 0;
     __syncthreads();
 
@@ -173,7 +189,14 @@ __device__ __forceinline__ int visit_tile(const PairDev& P, int tx, int ty,
                 }
                 const int lx = ROWS ? hx + j : vx, ly = ROWS ? hy : vy + j;
                 const u64 now = win[1][1];
-                double best = __longlong_as_double((long long)now);
+                // candidates from keys read from LDS are reduced as a tree;
+                // the one from the pixel just computed (behind, jj > 0) is
+                // taken last, so consecutive pixels overlap
+                constexpr int NC = CONN + 1;
+                double cand[NC];
+                int nc = 0;
+                cand[nc++] = __longlong_as_double((long long)now);
+                double behind = cand[0];
 #pragma unroll
                 for (int a = -1; a <= 1; ++a) {
 #pragma unroll
@@ -183,14 +206,17 @@ __device__ __forceinline__ int visit_tile(const PairDev& P, int tx, int ty,
                         if (k < 0 || k >= CONN) continue;
                         const u64 q = win[a + 1][b + 1];
                         const float w = ROWS ? wh[j][k] : wv[j][k];
-                        const u64 cand = make_key(key_dist(q) + w, key_label(q));
-                        best = min_f64(best, __longlong_as_double((long long)cand));
+                        const double cd = __longlong_as_double((long long)make_key(key_dist(q) + w, key_label(q)));
+                        if (a == -1 && b == 0 && jj > 0) behind = cd; else cand[nc++] = cd;
                     }
                 }
+                double best = tree_min<NC>(cand, nc);
+                if (jj > 0) best = min_f64(best, behind);
                 u64 bk = (u64)__double_as_longlong(best);
                 if (lx < vx0 || lx >= vx1 || ly < vy0 || ly >= vy1) bk = now;   // outside the image
                 if (bk < now) {
                     S.key[c] = bk;
+                    S.rowchg[ly + 1] = round;
                     changed = 1;
                 }
 #pragma unroll
@@ -205,10 +231,23 @@ __device__ __forceinline__ int visit_tile(const PairDev& P, int tx, int ty,
         };
         using T = std::true_type;
         using F = std::false_type;
-        sweep(T{}, T{});
-        sweep(F{}, T{});
-        sweep(T{}, F{});
-        sweep(F{}, F{});
+        // a wavefront skips its row (column) sweeps when no pixel within
+        // one row of its runs changed since the start of the previous round:
+        // then none of its pixels can improve
+        bool act_h = round == 0, act_v = round == 0;
+        if (round != 0) {
+            act_h = max(max(S.rowchg[hy], S.rowchg[hy + 1]), S.rowchg[hy + 2]) >= round - 1;
+            int m = S.rowchg[vy];
+#pragma unroll
+            for (int j = 1; j < PPT + 2; ++j) m = max(m, S.rowchg[vy + j]);
+            act_v = m >= round - 1;
+        }
+        const bool wave_h = __builtin_amdgcn_ballot_w64(act_h) != 0ull;
+        const bool wave_v = __builtin_amdgcn_ballot_w64(act_v) != 0ull;
+        if (wave_h) sweep(T{}, T{});
+        if (wave_v) sweep(F{}, T{});
+        if (wave_h) sweep(T{}, F{});
+        if (wave_v) sweep(F{}, F{});
         // flag this round's changes per wavefront (the flag of the next
         // round was last read two rounds ago) and meet
         if (tid == 0) S.flag[(round + 1) % 3] = 0;
@@ -364,19 +403,19 @@ __global__ __launch_bounds__(NT) void k_geo_finish(const PairDev* __restrict__ p
 }
 
 namespace {
-// First-pass margin (columns, rows) and its threads: a 32 x 16 tile becomes
-// a 40 x 24 region relaxed by 240 threads (runs of 4 pixels), 32 x 32 a
-// 40 x 40 region (320 threads, runs of 5), 32 x 64 a 40 x 72 region (360
-// threads, runs of 8).
-constexpr int kMarginX = 4, kMarginY = 4;
-constexpr int first_threads(int th) { return th == 16 ? 240 : th == 32 ? 320 : 360; }
+// First-pass margin (pixels on each side) and threads: a 32 x 16 tile
+// becomes a 36 x 20 region relaxed by 360 threads (runs of 2 pixels), 32 x 32
+// a 40 x 40 region (800 threads, runs of 2), 32 x 64 a 40 x 72 region (720
+// threads, runs of 4).  Margins of 2 to 4 measured alike on 32 x 16 tiles;
+// wider ones make the first pass the longest.
+constexpr int first_margin(int th) { return th == 16 ? 2 : 4; }
+constexpr int first_threads(int th) { return th == 16 ? 360 : th == 32 ? 800 : 720; }
 
 template <int TW, int TH, int CONN, int NT>
 hipError_t launch_t(const PairDev* d_pairs, const RunDev& run, int passes, hipStream_t s) {
     const int grid = 8 * ((run.total_tiles + 7) / 8);
-    constexpr int NT0 = first_threads(TH);
-    hipLaunchKernelGGL((k_geo_first<TW, TH, kMarginX, kMarginY, CONN, NT0>), dim3(grid), dim3(NT0), 0, s,
-                       d_pairs, run);
+    constexpr int NT0 = first_threads(TH), M0 = first_margin(TH);
+    hipLaunchKernelGGL((k_geo_first<TW, TH, M0, M0, CONN, NT0>), dim3(grid), dim3(NT0), 0, s, d_pairs, run);
     for (int p = 1; p < passes; ++p) {
         hipLaunchKernelGGL((k_geo_pass<TW, TH, CONN, NT>), dim3(grid), dim3(NT), 0, s, d_pairs, run, p);
         const hipError_t e = hipGetLastError();
