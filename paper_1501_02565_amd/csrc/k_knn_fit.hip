@@ -265,29 +265,22 @@ __device__ __forceinline__ bool knn_fit_one(const PairDev& P, const RunDev& run,
                 hs[q] = -1;
                 hh[q] = node_slot((int)rec[q].x, HBITS);
             }
+            // one compare-and-swap per probe: it returns -1 (this lane claimed
+            // the slot), v (already there) or another node (next slot)
             for (int probe = 0; probe < HCAP; ++probe) {
                 bool any = false;
 #pragma unroll
                 for (int q = 0; q < Q; ++q) any = any || pend[q];
                 if (wave::ballot(any) == 0ull) break;
-                int cur[Q], prev[Q];
+                int prev[Q];
+#pragma unroll
+                for (int q = 0; q < Q; ++q)
+                    prev[q] = pend[q] ? atomicCAS(&htab[hh[q]], -1, (int)rec[q].x) : 0;
 #pragma unroll
                 for (int q = 0; q < Q; ++q) {
-                        cur[q] = pend[q] ? htab[hh[q]] : 0;
-                }
-#pragma unroll
-                for (int q = 0; q < Q; ++q) {
-                        prev[q] = cur[q];
-                    if (pend[q] && cur[q] == -1) prev[q] = atomicCAS(&htab[hh[q]], -1, (int)rec[q].x);
-                }
-#pragma unroll
-                for (int q = 0; q < Q; ++q) {
-                        if (!pend[q]) continue;
-                    if (cur[q] == -1 && prev[q] == -1) {
-                        won[q] = true;
-                        hs[q] = (int)hh[q];
-                        pend[q] = false;
-                    } else if (prev[q] == (int)rec[q].x) {
+                    if (!pend[q]) continue;
+                    if (prev[q] == -1 || prev[q] == (int)rec[q].x) {
+                        won[q] = prev[q] == -1;
                         hs[q] = (int)hh[q];
                         pend[q] = false;
                     } else {
@@ -356,6 +349,18 @@ __device__ __forceinline__ bool knn_fit_one(const PairDev& P, const RunDev& run,
                 S.buf[pos] = ((u64)__float_as_uint(d[r]) << 32) | (u32)S.node[e];
             }
         }
+    }
+    // fetch the match rows of the candidates now, so that the fit's loads
+    // of the K nearest (a subset) hit the cache after the sort
+    {
+        float acc = 0.0f;
+        for (int i = lane; i < nc; i += 64) {
+            int node;
+            if constexpr (F64) node = S.snode[i]; else node = (int)(u32)S.buf[i];
+            acc += P.matches[4LL * node];
+        }
+        // a sum of finite values never has these bits: keeps the loads
+        if (__float_as_uint(acc) == 0xffffffffu) S.node[0] = -2;
     }
     int p2 = 64;
     while (p2 < nc) p2 <<= 1;
