@@ -269,8 +269,32 @@ __device__ __forceinline__ int visit_tile(const PairDev& P, int tx, int ty,
         if (lx >= 0 && ly >= 0 && lx < twe && ly < the && k != orig[j]) {
             P.keys[(long long)(y0 + ly) * W + x0 + lx] = k;
             const bool l = lx == 0, r = lx == twe - 1, t = ly == 0, b = ly == the - 1;
-            bm |= (l ? B_L : 0) | (r ? B_R : 0) | (t ? B_T : 0) | (b ? B_B : 0) | ((l && t) ? B_TL : 0) |
-                  ((r && t) ? B_TR : 0) | ((l && b) ? B_BL : 0) | ((r && b) ? B_BR : 0);
+            if (MX != 0 || MY != 0) {
+                // first pass: the neighbours' values are not known yet
+                bm |= (l ? B_L : 0) | (r ? B_R : 0) | (t ? B_T : 0) | (b ? B_B : 0) | ((l && t) ? B_TL : 0) |
+                      ((r && t) ? B_TR : 0) | ((l && b) ? B_BL : 0) | ((r && b) ? B_BR : 0);
+            } else if (l || r || t || b) {
+                // a neighbour tile only needs a visit if this pixel improves
+                // one of its pixels next to it; the halo holds their values
+                // as loaded (never lower than now), so the test never misses
+                const int ci = (hy + 1) * LW + hx + j + 1;
+                const float dp = key_dist(k), cp = S.cost[ci];
+#pragma unroll
+                for (int kk = 0; kk < CONN; ++kk) {
+                    const int qx = lx + DX[kk], qy = ly + DY[kk];
+                    const bool out = qx < 0 || qy < 0 || qx >= twe || qy >= the;
+                    if (!out) continue;
+                    const int qi = ci + DY[kk] * LW + DX[kk];
+                    const float len = (kk < 4) ? 1.0f : 1.41421356237309515f;
+                    const u64 cand = make_key(dp + len * (0.5f * (cp + S.cost[qi])), key_label(k));
+                    if (cand < S.key[qi]) {
+                        const bool ql = qx < 0, qr = qx >= twe, qt = qy < 0, qb = qy >= the;
+                        bm |= (ql && !qt && !qb) ? B_L : (qr && !qt && !qb) ? B_R
+                            : (qt && !ql && !qr) ? B_T : (qb && !ql && !qr) ? B_B
+                            : (ql && qt) ? B_TL : (qr && qt) ? B_TR : (ql && qb) ? B_BL : B_BR;
+                    }
+                }
+            }
         }
     }
     if (bm) atomicOr(&S.border, bm);
