@@ -428,12 +428,13 @@ __global__ __launch_bounds__(NT) void k_geo_finish(const PairDev* __restrict__ p
 
 namespace {
 // First-pass margin (pixels on each side) and threads: a 32 x 16 tile
-// becomes a 36 x 20 region relaxed by 360 threads (runs of 2 pixels), 32 x 32
+// becomes a 36 x 20 region relaxed by 180 threads (runs of 4 pixels), 32 x 32
 // a 40 x 40 region (800 threads, runs of 2), 32 x 64 a 40 x 72 region (720
 // threads, runs of 4).  Margins of 2 to 4 measured alike on 32 x 16 tiles;
-// wider ones make the first pass the longest.
+// wider ones make the first pass the longest.  Runs of 4 take as long as
+// runs of 2 on one pair with half the wavefronts, which helps batches.
 constexpr int first_margin(int th) { return th == 16 ? 2 : 4; }
-constexpr int first_threads(int th) { return th == 16 ? 360 : th == 32 ? 800 : 720; }
+constexpr int first_threads(int th) { return th == 16 ? 180 : th == 32 ? 800 : 720; }
 
 template <int TW, int TH, int CONN, int NT>
 hipError_t launch_t(const PairDev* d_pairs, const RunDev& run, int passes, hipStream_t s) {
