@@ -16,9 +16,9 @@
 //      paths), seeds keep their own index.  Its fixpoint is the lowest
 //      match index over all shortest paths, the lexicographic (D, label)
 //      optimum.
-// Both phases use the bulk-synchronous tiled passes of k_geodesic.hip
-// (dirty tiles, Gauss-Seidel line sweeps in LDS, change masks, a
-// single-workgroup finisher) on 32 x 16 tiles.
+// Both phases use bulk-synchronous tiled passes like k_geodesic.hip (dirty
+// tiles, rounds of four Gauss-Seidel line sweeps in LDS, a single-workgroup
+// finisher) on 32 x 16 tiles.
 #include <type_traits>
 
 #include "epic_dev.h"
@@ -34,8 +34,8 @@ struct Lds64 {
     u64 dist[NL];            // double bits
     u32 lab[NL];
     float cost[NL];
-    u64 chg[3][LH];
     int flag[3];             // per round (mod 3): some pixel of the tile changed
+    int rowchg[LH];          // last round in which a pixel of the row changed
     int border;
 };
 
@@ -68,8 +68,8 @@ __device__ __forceinline__ int visit64(const PairDev& P, int tx, int ty, Lds64& 
         S.lab[i] = l;
         S.cost[i] = c;
     }
-    for (int i = tid; i < 3 * LH; i += 256) (&S.chg[0][0])[i] = 0ull;
     if (tid < 3) S.flag[tid] = 0;
+    for (int i = tid; i < LH; i += 256) S.rowchg[i] = -1;
     if (tid == 0) S.border = 0;
     __syncthreads();
 
@@ -87,78 +87,72 @@ __device__ __forceinline__ int visit64(const PairDev& P, int tx, int ty, Lds64& 
         }
         orig[j] = PHASE == 0 ? S.dist[ch] : (u64)S.lab[ch];
     }
-    const u64 hmask = ((1ull << (PPT + 2)) - 1) << hx;
-    const u64 vmask = 7ull << vx;
-
     const int round_cap = 4 * NL + 8;
     for (int round = 0;; ++round) {
-        const bool rows = (round & 1) == 0;
-        const u64* prev = S.chg[(round + 2) % 3];
-        u64* cur = S.chg[round % 3];
-        bool active = round == 0;
-        if (!active) {
-            if (rows) {
-                active = ((prev[hy] | prev[hy + 1] | prev[hy + 2]) & hmask) != 0;
-            } else {
-                u64 acc = 0;
-#pragma unroll
-                for (int j = 0; j < PPT + 2; ++j) acc |= prev[vy + j];
-                active = (acc & vmask) != 0;
-            }
-        }
         int changed = 0;
-        if (active) {
-            auto sweep = [&](auto rows_c, auto fwd_c) {
-                constexpr bool ROWS = decltype(rows_c)::value, FWD = decltype(fwd_c)::value;
+        auto sweep = [&](auto rows_c, auto fwd_c) {
+            constexpr bool ROWS = decltype(rows_c)::value, FWD = decltype(fwd_c)::value;
 #pragma unroll
-                for (int jj = 0; jj < PPT; ++jj) {
-                    const int j = FWD ? jj : PPT - 1 - jj;
-                    const int lx = ROWS ? hx + j : vx, ly = ROWS ? hy : vy + j;
-                    if (lx >= twe || ly >= the) continue;
-                    const int ci = (ly + 1) * LW + lx + 1;
-                    if (PHASE == 0) {
-                        const double now = dbits(S.dist[ci]);
-                        double best = now;
+            for (int jj = 0; jj < PPT; ++jj) {
+                const int j = FWD ? jj : PPT - 1 - jj;
+                const int lx = ROWS ? hx + j : vx, ly = ROWS ? hy : vy + j;
+                if (lx >= twe || ly >= the) continue;
+                const int ci = (ly + 1) * LW + lx + 1;
+                if (PHASE == 0) {
+                    const double now = dbits(S.dist[ci]);
+                    double best = now;
 #pragma unroll
-                        for (int k = 0; k < CONN; ++k) {
-                            const double cand =
-                                __dadd_rn(dbits(S.dist[ci + DY[k] * LW + DX[k]]), ROWS ? wh[j][k] : wv[j][k]);
-                            best = cand < best ? cand : best;
-                        }
-                        if (best < now) {
-                            S.dist[ci] = bitsd(best);
-                            atomicOr(&cur[ly + 1], 1ull << (lx + 1));
-                            changed = 1;
-                        }
-                    } else {
-                        const double dp = dbits(S.dist[ci]);
-                        const u32 now = S.lab[ci];
-                        u32 best = now;
+                    for (int k = 0; k < CONN; ++k) {
+                        const double cand =
+                            __dadd_rn(dbits(S.dist[ci + DY[k] * LW + DX[k]]), ROWS ? wh[j][k] : wv[j][k]);
+                        best = cand < best ? cand : best;
+                    }
+                    if (best < now) {
+                        S.dist[ci] = bitsd(best);
+                        S.rowchg[ly + 1] = round;
+                        changed = 1;
+                    }
+                } else {
+                    const double dp = dbits(S.dist[ci]);
+                    const u32 now = S.lab[ci];
+                    u32 best = now;
 #pragma unroll
-                        for (int k = 0; k < CONN; ++k) {
-                            const int q = ci + DY[k] * LW + DX[k];
-                            const bool tight = __dadd_rn(dbits(S.dist[q]), ROWS ? wh[j][k] : wv[j][k]) == dp;
-                            const u32 lq = S.lab[q];
-                            best = (tight && lq < best) ? lq : best;
-                        }
-                        if (best < now) {
-                            S.lab[ci] = best;
-                            atomicOr(&cur[ly + 1], 1ull << (lx + 1));
-                            changed = 1;
-                        }
+                    for (int k = 0; k < CONN; ++k) {
+                        const int q = ci + DY[k] * LW + DX[k];
+                        const bool tight = __dadd_rn(dbits(S.dist[q]), ROWS ? wh[j][k] : wv[j][k]) == dp;
+                        const u32 lq = S.lab[q];
+                        best = (tight && lq < best) ? lq : best;
+                    }
+                    if (best < now) {
+                        S.lab[ci] = best;
+                        S.rowchg[ly + 1] = round;
+                        changed = 1;
                     }
                 }
-            };
-            using T = std::true_type;
-            using F = std::false_type;
-            switch (round & 3) {
-                case 0: sweep(T{}, T{}); break;
-                case 1: sweep(F{}, T{}); break;
-                case 2: sweep(T{}, F{}); break;
-                default: sweep(F{}, F{}); break;
             }
+        };
+        // rounds of four sweeps (rows and columns, both directions) with one
+        // barrier; a wavefront skips its sweeps when no pixel within one row
+        // of its runs changed since the previous round started; racing
+        // plain stores only cost further rounds (every value written is a
+        // valid distance or label, all pixels are relaxed until a round
+        // changes nothing)
+        bool act_h = round == 0, act_v = round == 0;
+        if (round != 0) {
+            act_h = max(max(S.rowchg[hy], S.rowchg[hy + 1]), S.rowchg[hy + 2]) >= round - 1;
+            int mrow = S.rowchg[vy];
+#pragma unroll
+            for (int j = 1; j < PPT + 2; ++j) mrow = max(mrow, S.rowchg[vy + j]);
+            act_v = mrow >= round - 1;
         }
-        if (tid < LH) S.chg[(round + 1) % 3][tid] = 0ull;
+        const bool wave_h = __builtin_amdgcn_ballot_w64(act_h) != 0ull;
+        const bool wave_v = __builtin_amdgcn_ballot_w64(act_v) != 0ull;
+        using T = std::true_type;
+        using F = std::false_type;
+        if (wave_h) sweep(T{}, T{});
+        if (wave_v) sweep(F{}, T{});
+        if (wave_h) sweep(T{}, F{});
+        if (wave_v) sweep(F{}, F{});
         if (tid == 0) S.flag[(round + 1) % 3] = 0;
         if (__builtin_amdgcn_ballot_w64(changed != 0) != 0ull && (tid & 63) == 0) S.flag[round % 3] = 1;
         __syncthreads();

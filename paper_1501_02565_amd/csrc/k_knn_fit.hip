@@ -433,72 +433,75 @@ __device__ __forceinline__ bool knn_fit_one(const PairDev& P, const RunDev& run,
     const float um = M[4LL * s + 2] - xm, vm = M[4LL * s + 3] - ym;
     const float a = P.a;
     const int wpow = run.la_wpow;
-    float dx[RK], dy[RK], du[RK], dv[RK], kk[RK], ww[RK];
-    float tk = 0.f, tu = 0.f, tv = 0.f, sw = 0.f, sx = 0.f, sy = 0.f;
-#pragma unroll
-    for (int r = 0; r < RK; ++r) {
-        const int j = lane + 64 * r;
-        dx[r] = dy[r] = du[r] = dv[r] = kk[r] = ww[r] = 0.f;
-        if (j < n) {
-            const int node = knode[r];
-            const float dj = (float)kdist[r];
-            const float4 mn = *reinterpret_cast<const float4*>(M + 4LL * node);
-            dx[r] = mn.x - xm;
-            dy[r] = mn.y - ym;
-            du[r] = (mn.z - mn.x) - um;
-            dv[r] = (mn.w - mn.y) - vm;
-            kk[r] = expf(-a * dj);
-            ww[r] = wpow == 1 ? kk[r] : kk[r] * kk[r];
-            tk += kk[r];
-            tu += kk[r] * du[r];
-            tv += kk[r] * dv[r];
-            sw += ww[r];
-            sx += ww[r] * dx[r];
-            sy += ww[r] * dy[r];
-        }
-    }
-    tk = wave::sum(tk);
-    tu = wave::sum(tu);
-    tv = wave::sum(tv);
-    float out[6] = {0.f, 0.f, 0.f, 0.f, um + tu / tk, vm + tv / tk};
-    bool need64 = false;
-    if (P.mode == 1) {
-        sw = wave::sum(sw);
-        sx = wave::sum(sx);
-        sy = wave::sum(sy);
-        const float mx = sx / sw, my = sy / sw;
-        float sxx = 0.f, sxy = 0.f, syy = 0.f, sxu = 0.f, syu = 0.f, sxv = 0.f, syv = 0.f, su = 0.f, sv = 0.f;
+    float out[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    bool need64 = F64;
+    if constexpr (!F64) {      // the FP64-everywhere path goes straight to FP64
+        float dx[RK], dy[RK], du[RK], dv[RK], kk[RK], ww[RK];
+        float tk = 0.f, tu = 0.f, tv = 0.f, sw = 0.f, sx = 0.f, sy = 0.f;
 #pragma unroll
         for (int r = 0; r < RK; ++r) {
-            const float ex = dx[r] - mx, ey = dy[r] - my, w = ww[r];
-            sxx += w * ex * ex;
-            sxy += w * ex * ey;
-            syy += w * ey * ey;
-            sxu += w * ex * du[r];
-            syu += w * ey * du[r];
-            sxv += w * ex * dv[r];
-            syv += w * ey * dv[r];
-            su += w * du[r];
-            sv += w * dv[r];
+            const int j = lane + 64 * r;
+            dx[r] = dy[r] = du[r] = dv[r] = kk[r] = ww[r] = 0.f;
+            if (j < n) {
+                const int node = knode[r];
+                const float dj = (float)kdist[r];
+                const float4 mn = *reinterpret_cast<const float4*>(M + 4LL * node);
+                dx[r] = mn.x - xm;
+                dy[r] = mn.y - ym;
+                du[r] = (mn.z - mn.x) - um;
+                dv[r] = (mn.w - mn.y) - vm;
+                kk[r] = expf(-a * dj);
+                ww[r] = wpow == 1 ? kk[r] : kk[r] * kk[r];
+                tk += kk[r];
+                tu += kk[r] * du[r];
+                tv += kk[r] * dv[r];
+                sw += ww[r];
+                sx += ww[r] * dx[r];
+                sy += ww[r] * dy[r];
+            }
         }
-        sxx = wave::sum(sxx); sxy = wave::sum(sxy); syy = wave::sum(syy);
-        sxu = wave::sum(sxu); syu = wave::sum(syu); sxv = wave::sum(sxv); syv = wave::sum(syv);
-        su = wave::sum(su); sv = wave::sum(sv);
-        const float det = sxx * syy - sxy * sxy;
-        const float tr = sxx + syy;
-        const float disc = sqrtf((sxx - syy) * (sxx - syy) + 4.0f * sxy * sxy);
-        const float l1 = 0.5f * (tr + disc);
-        const float ratio = l1 > 0.f ? (det / l1) / l1 : 0.f;
-        need64 = F64 || n < 3 || !(ratio >= run.fp64_route);
-        if (!need64) {
-            const float b00 = (syy * sxu - sxy * syu) / det, b01 = (sxx * syu - sxy * sxu) / det;
-            const float b10 = (syy * sxv - sxy * syv) / det, b11 = (sxx * syv - sxy * sxv) / det;
-            out[0] = b00; out[1] = b01; out[2] = b10; out[3] = b11;
-            out[4] = um + su / sw - (b00 * mx + b01 * my);
-            out[5] = vm + sv / sw - (b10 * mx + b11 * my);
+        tk = wave::sum(tk);
+        tu = wave::sum(tu);
+        tv = wave::sum(tv);
+        out[4] = um + tu / tk;
+        out[5] = vm + tv / tk;
+        if (P.mode == 1) {
+            sw = wave::sum(sw);
+            sx = wave::sum(sx);
+            sy = wave::sum(sy);
+            const float mx = sx / sw, my = sy / sw;
+            float sxx = 0.f, sxy = 0.f, syy = 0.f, sxu = 0.f, syu = 0.f, sxv = 0.f, syv = 0.f, su = 0.f, sv = 0.f;
+#pragma unroll
+            for (int r = 0; r < RK; ++r) {
+                const float ex = dx[r] - mx, ey = dy[r] - my, w = ww[r];
+                sxx += w * ex * ex;
+                sxy += w * ex * ey;
+                syy += w * ey * ey;
+                sxu += w * ex * du[r];
+                syu += w * ey * du[r];
+                sxv += w * ex * dv[r];
+                syv += w * ey * dv[r];
+                su += w * du[r];
+                sv += w * dv[r];
+            }
+            sxx = wave::sum(sxx); sxy = wave::sum(sxy); syy = wave::sum(syy);
+            sxu = wave::sum(sxu); syu = wave::sum(syu); sxv = wave::sum(sxv); syv = wave::sum(syv);
+            su = wave::sum(su); sv = wave::sum(sv);
+            const float det = sxx * syy - sxy * sxy;
+            const float tr = sxx + syy;
+            const float disc = sqrtf((sxx - syy) * (sxx - syy) + 4.0f * sxy * sxy);
+            const float l1 = 0.5f * (tr + disc);
+            const float ratio = l1 > 0.f ? (det / l1) / l1 : 0.f;
+            need64 = n < 3 || !(ratio >= run.fp64_route);
+            if (!need64) {
+                const float b00 = (syy * sxu - sxy * syu) / det, b01 = (sxx * syu - sxy * sxu) / det;
+                const float b10 = (syy * sxv - sxy * syv) / det, b11 = (sxx * syv - sxy * sxv) / det;
+                out[0] = b00; out[1] = b01; out[2] = b10; out[3] = b11;
+                out[4] = um + su / sw - (b00 * mx + b01 * my);
+                out[5] = vm + sv / sw - (b10 * mx + b11 * my);
+            }
         }
     }
-    if (F64) need64 = true;
     if (need64) {
         // FP64: re-accumulate from the inputs and solve (or fall back to NW)
         const double xmd = xm, ymd = ym;
