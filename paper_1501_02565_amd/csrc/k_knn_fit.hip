@@ -115,7 +115,7 @@ __device__ __forceinline__ bool knn_fit_one(const PairDev& P, const RunDev& run,
     constexpr int RK = KMAX / 64;
     const int lane = threadIdx.x;
     const int K = P.K;
-    const int keff = P.counters[C_KEFF];
+    const int keff = __builtin_amdgcn_readfirstlane(P.counters[C_KEFF]);
     int* htab = reinterpret_cast<int*>(S.buf);
     float* prm = P.params + 6LL * s;
 
@@ -138,34 +138,59 @@ __device__ __forceinline__ bool knn_fit_one(const PairDev& P, const RunDev& run,
     __syncthreads();
 
     int nvis = 1;               // entries in use (the same in every lane)
+    int nsettled = 0;           // settled entries (the same in every lane)
     bool ovf = false;
     u32 settled = 0;            // bit r: entry lane + 64 r is settled
-    RT d[R];
+    // per group r: the raw (distance, lightest edge) bits and CSR range of
+    // entry lane + 64 r, kept across steps as loaded
+    using DT2 = typename std::conditional<F64, ulonglong2, uint2>::type;
+    DT2 dmr[R];
+    uint2 rdv[R];
+    RT d[R], mi[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        dmr[r].x = dmr[r].y = to_bits<F64>(RINF);
+        rdv[r] = make_uint2(0u, 0u);
+    }
     RT dstop = RINF;
     for (;;) {
-        const int nv = nvis;
-        RT mi[R];
-        uint2 rdv[R];
+        // nvis and nsettled are the same in every lane; readfirstlane lets
+        // the compiler keep them (and the branches on them) scalar
+        const int nv = __builtin_amdgcn_readfirstlane(nvis);
+        nsettled = __builtin_amdgcn_readfirstlane(nsettled);
+        // only the groups of 64 entries that are in use are read and
+        // scanned (a uniform bound); d[r] of the others stays infinite
+        const int ru = (nv + 63) >> 6;
         // entries not in use read as (inf, inf, 0, 0): the table is filled
-        // with them at the start, so the reads need no predicate
+        // with them at the start, so the reads need no predicate; groups
+        // beyond ru keep those values from before the loop
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            const int e = lane + 64 * r;
-            read_dm<VCAP, F64>(S, e, d[r], mi[r]);
-            rdv[r] = S.rd[e];
+            if (r < ru) {
+                const int e = lane + 64 * r;
+                dmr[r] = *reinterpret_cast<const DT2*>(&S.dm[2 * e]);
+                rdv[r] = S.rd[e];
+            }
+            d[r] = from_bits<F64>(dmr[r].x);
+            mi[r] = from_bits<F64>(dmr[r].y);
         }
         RT fmin = RINF;
-        int below = 0;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            if ((settled >> r) & 1u) continue;
+            if (r >= ru || ((settled >> r) & 1u)) continue;
             fmin = fmin < d[r] ? fmin : d[r];
         }
         RT dmin;
         if constexpr (F64) dmin = wave::min(fmin); else dmin = wave::min_nonneg(fmin);
+        // settled entries strictly below the frontier minimum (only counted
+        // once enough entries are settled at all)
+        int below = 0;
+        if (nsettled >= keff) {
 #pragma unroll
-        for (int r = 0; r < R; ++r) below += (((settled >> r) & 1u) && d[r] < dmin) ? 1 : 0;
-        below = wave::sum(below);
+            for (int r = 0; r < R; ++r)
+                if (r < ru) below += (((settled >> r) & 1u) && d[r] < dmin) ? 1 : 0;
+            below = wave::sum(below);
+        }
         if (below >= keff || !(dmin < RINF)) {
             dstop = dmin;       // nodes settled at this point lie at or above dmin
             break;
@@ -175,7 +200,9 @@ __device__ __forceinline__ bool knn_fit_one(const PairDev& P, const RunDev& run,
         int my_edges = 0;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
+            if (r >= ru) continue;
             const bool fin = lane + 64 * r < nv && !((settled >> r) & 1u) && d[r] <= dmin + mi[r];
+            nsettled += __popcll(wave::ballot(fin));
             if (fin) {
                 newly |= 1u << r;
                 my_edges += (int)rdv[r].y;
@@ -190,7 +217,7 @@ __device__ __forceinline__ bool knn_fit_one(const PairDev& P, const RunDev& run,
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 off[r] = o;
-                if ((newly >> r) & 1u) o += (int)rdv[r].y;
+                if (r < ru && ((newly >> r) & 1u)) o += (int)rdv[r].y;
             }
         }
         int carry_start = 0, carry_e = 0;
@@ -198,7 +225,7 @@ __device__ __forceinline__ bool knn_fit_one(const PairDev& P, const RunDev& run,
             // mark the segments that start in this window
 #pragma unroll
             for (int r = 0; r < R; ++r)
-                if (((newly >> r) & 1u) && rdv[r].y > 0u && off[r] >= wb && off[r] < wb + TW)
+                if (r < ru && ((newly >> r) & 1u) && rdv[r].y > 0u && off[r] >= wb && off[r] < wb + TW)
                     S.head[off[r] - wb] = (unsigned short)(lane + 64 * r + 1);
             lds_order();
             const int nq = min(Q, (T - wb + 63) >> 6);   // chunks of 64 edges in this window
@@ -229,7 +256,7 @@ __device__ __forceinline__ bool knn_fit_one(const PairDev& P, const RunDev& run,
             lds_order();
 #pragma unroll
             for (int r = 0; r < R; ++r)
-                if (((newly >> r) & 1u) && rdv[r].y > 0u && off[r] >= wb && off[r] < wb + TW)
+                if (r < ru && ((newly >> r) & 1u) && rdv[r].y > 0u && off[r] >= wb && off[r] < wb + TW)
                     S.head[off[r] - wb] = 0;
             // each lane's edges: source entry's CSR start and settled distance
             RT du[Q];
