@@ -99,6 +99,35 @@ struct PairDev {
     int* dbg_n_edges;       // device int
 };
 
+// Global-memory view of a pointer.  Pointers read out of a PairDev (which
+// lives in device memory) are generic to the compiler, which then emits flat
+// memory instructions: those also count on the LDS counter, so every wait for
+// a load waits for outstanding LDS traffic too, and they need 64-bit VGPR
+// addresses.  Through an address-space-1 pointer the loads and stores are
+// global instructions.
+#define EPIC_GLOBAL __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ EPIC_GLOBAL T* gmem(T* p) { return (EPIC_GLOBAL T*)p; }
+// The HIP vector classes cannot be copied from or to address-space-1
+// objects; these go through the compiler's own vector types.
+typedef unsigned int gu32x4 __attribute__((ext_vector_type(4)));
+typedef float gf32x4 __attribute__((ext_vector_type(4)));
+typedef float gf32x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint4 gload(const uint4* p) {
+    const gu32x4 v = *(const EPIC_GLOBAL gu32x4*)p;
+    return make_uint4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ float4 gload(const float4* p) {
+    const gf32x4 v = *(const EPIC_GLOBAL gf32x4*)p;
+    return make_float4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ float2 gload(const float2* p) {
+    const gf32x2 v = *(const EPIC_GLOBAL gf32x2*)p;
+    return make_float2(v.x, v.y);
+}
+__device__ __forceinline__ void gstore(uint4* p, uint4 v) { *(EPIC_GLOBAL gu32x4*)p = gu32x4{v.x, v.y, v.z, v.w}; }
+__device__ __forceinline__ void gstore(float2* p, float2 v) { *(EPIC_GLOBAL gf32x2*)p = gf32x2{v.x, v.y}; }
+
 // Nearest-match label of pixel i (packed in the key, or in the label array
 // of the FP64 path).
 __device__ __forceinline__ u32 label_at(const PairDev& P, long long i) {

@@ -17,24 +17,24 @@ __global__ __launch_bounds__(PIX_BLOCK) void k_assign(const PairDev* __restrict_
     const long long i = (long long)((int)blockIdx.x - P.pix_block_base) * PIX_BLOCK + threadIdx.x;
     const int W = P.W;
     if (i >= (long long)W * P.H) return;
-    const u32 m = P.labels ? P.labels[i] : key_label(P.keys[i]);
+    const u32 m = P.labels ? gmem(P.labels)[i] : key_label(gmem(P.keys)[i]);
     float2 f;
     if (m == NO_LABEL) {
         f.x = f.y = __int_as_float(0x7fc00000);
     } else if (P.params64) {
-        const double* B = P.params64 + 6LL * m;
-        const double dx = (double)(int)(i % W) - (double)P.matches[4LL * m];
-        const double dy = (double)(int)(i / W) - (double)P.matches[4LL * m + 1];
+        const EPIC_GLOBAL double* B = gmem(P.params64) + 6LL * m;
+        const double dx = (double)(int)(i % W) - (double)gmem(P.matches)[4LL * m];
+        const double dy = (double)(int)(i / W) - (double)gmem(P.matches)[4LL * m + 1];
         f.x = (float)(B[0] * dx + B[1] * dy + B[4]);
         f.y = (float)(B[2] * dx + B[3] * dy + B[5]);
     } else {
-        const float* B = P.params + 6LL * m;
-        const float2 pm = *reinterpret_cast<const float2*>(P.matches + 4LL * m);
+        const EPIC_GLOBAL float* B = gmem(P.params) + 6LL * m;
+        const float2 pm = gload(reinterpret_cast<const float2*>(P.matches + 4LL * m));
         const float dx = (float)(int)(i % W) - pm.x, dy = (float)(int)(i / W) - pm.y;
         f.x = B[0] * dx + B[1] * dy + B[4];
         f.y = B[2] * dx + B[3] * dy + B[5];
     }
-    reinterpret_cast<float2*>(P.flow)[i] = f;
+    gstore(reinterpret_cast<float2*>(P.flow) + i, f);
 }
 
 __global__ __launch_bounds__(PIX_BLOCK) void k_unpack(const PairDev* __restrict__ pairs, RunDev run, float* D,

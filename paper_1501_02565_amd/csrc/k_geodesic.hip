@@ -133,8 +133,8 @@ __device__ __forceinline__ int visit_tile(const PairDev& P, int tx, int ty,
         float c = 0.0f;
         if (gx >= 0 && gy >= 0 && gx < W && gy < H) {
             const long long gi = (long long)gy * W + gx;
-            k = P.keys[gi];
-            c = P.cost[gi];
+            k = gmem(P.keys)[gi];
+            c = gmem(P.cost)[gi];
         }
         S.key[i] = k;
         S.cost[i] = c;
@@ -267,7 +267,7 @@ __device__ __forceinline__ int visit_tile(const PairDev& P, int tx, int ty,
         const int lx = hx + j - MX, ly = hy - MY;          // tile coordinates
         const u64 k = S.key[(hy + 1) * LW + hx + j + 1];
         if (lx >= 0 && ly >= 0 && lx < twe && ly < the && k != orig[j]) {
-            P.keys[(long long)(y0 + ly) * W + x0 + lx] = k;
+            gmem(P.keys)[(long long)(y0 + ly) * W + x0 + lx] = k;
             const bool l = lx == 0, r = lx == twe - 1, t = ly == 0, b = ly == the - 1;
             if (MX != 0 || MY != 0) {
                 // first pass: the neighbours' values are not known yet
@@ -307,7 +307,7 @@ __device__ __forceinline__ int visit_tile(const PairDev& P, int tx, int ty,
 // Marks the tiles behind changed borders dirty for pass `next`.
 template <int CONN>
 __device__ void mark_neighbours(const PairDev& P, const RunDev& run, int tx, int ty, int border, int next) {
-    u32* dirty = run.dirty[next & 1] + P.tile_base;
+    EPIC_GLOBAL u32* dirty = gmem(run.dirty[next & 1]) + P.tile_base;
     const int nx = P.tiles_x, ny = P.tiles_y;
     auto mark = [&](int cx, int cy) {
         if (cx >= 0 && cy >= 0 && cx < nx && cy < ny) dirty[cy * nx + cx] = 1u;

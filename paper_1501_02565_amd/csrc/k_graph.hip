@@ -106,10 +106,10 @@ __global__ __launch_bounds__(PIX_BLOCK) void k_graph_emit(const PairDev* __restr
     const int y = (tb / etx) * EMIT_TH + (int)threadIdx.x / EMIT_TW;
     const long long i = (long long)y * W + x;
     if (x < W && y < H) {
-        const u64 kp = P.keys[i];
-        const u32 lp = F64 ? P.labels[i] : key_label(kp);
+        const u64 kp = gmem(P.keys)[i];
+        const u32 lp = F64 ? gmem(P.labels)[i] : key_label(kp);
         if (lp != NO_LABEL) {
-            const float cp = P.cost[i];
+            const float cp = gmem(P.cost)[i];
             // forward half-neighbourhood: (1,0), (0,1), (1,1), (-1,1)
             constexpr int HX[4] = {1, 0, 1, -1};
             constexpr int HY[4] = {0, 1, 1, 1};
@@ -118,18 +118,18 @@ __global__ __launch_bounds__(PIX_BLOCK) void k_graph_emit(const PairDev* __restr
                 const int qx = x + HX[k], qy = y + HY[k];
                 if (qx < 0 || qx >= W || qy >= H) continue;
                 const long long qi = (long long)qy * W + qx;
-                const u64 kq = P.keys[qi];
-                const u32 lq = F64 ? P.labels[qi] : key_label(kq);
+                const u64 kq = gmem(P.keys)[qi];
+                const u32 lq = F64 ? gmem(P.labels)[qi] : key_label(kq);
                 if (lq == lp || lq == NO_LABEL) continue;
                 V wb;
                 if (F64) {
                     // (D(p) + step) + D(q), each operation rounded (no fused multiply-add)
-                    const double half = __dmul_rn(0.5, __dadd_rn((double)cp, (double)P.cost[qi]));
+                    const double half = __dmul_rn(0.5, __dadd_rn((double)cp, (double)gmem(P.cost)[qi]));
                     const double step = k < 2 ? half : __dmul_rn(1.4142135623730951, half);
                     wb = (V)bitsd(__dadd_rn(__dadd_rn(dbits(kp), step), dbits(kq)));
                 } else {
                     const float len = (k < 2) ? 1.0f : 1.41421356237309515f;
-                    const float w = len * (0.5f * (cp + P.cost[qi]));
+                    const float w = len * (0.5f * (cp + gmem(P.cost)[qi]));
                     wb = (V)__float_as_uint((key_dist(kp) + w) + key_dist(kq));
                 }
                 const u32 m = min(lp, lq), n = max(lp, lq);
@@ -235,31 +235,31 @@ __global__ __launch_bounds__(SLOT_BLOCK) void k_csr_scatter(const PairDev* __res
     const PairDev& P = pairs[p];
     const int h = ((int)blockIdx.x - P.slot_block_base) * SLOT_BLOCK + threadIdx.x;
     if (h >= P.hash_cap) return;
-    const u64 key = P.hkey[h];
+    const u64 key = gmem(P.hkey)[h];
     if (key == HASH_EMPTY) return;
     const u32 m = (u32)(key >> 32), n = (u32)key;
     const bool f64 = run.precision == 1;
-    const u32 wb = f64 ? __float_as_uint((float)dbits(P.hval64[h])) : P.hval[h];
+    const u32 wb = f64 ? __float_as_uint((float)dbits(gmem(P.hval64)[h])) : gmem(P.hval)[h];
     const float w = __uint_as_float(wb);
-    const u32 rm = P.row_ptr[m], rm1 = P.row_ptr[m + 1];
-    const u32 rn = P.row_ptr[n], rn1 = P.row_ptr[n + 1];
+    const u32 rm = gmem(P.row_ptr)[m], rm1 = gmem(P.row_ptr)[m + 1];
+    const u32 rn = gmem(P.row_ptr)[n], rn1 = gmem(P.row_ptr)[n + 1];
     const u32 pm = rm + atomicAdd(&P.fill[m], 1u);
     const u32 pn = rn + atomicAdd(&P.fill[n], 1u);
     const bool okm = pm < (u32)P.hash_cap, okn = pn < (u32)P.hash_cap;
-    if (okm) P.adj[pm] = make_uint4(n, wb, rn, rn1 - rn);
-    if (okn) P.adj[pn] = make_uint4(m, wb, rm, rm1 - rm);
+    if (okm) gstore(P.adj + pm, make_uint4(n, wb, rn, rn1 - rn));
+    if (okn) gstore(P.adj + pn, make_uint4(m, wb, rm, rm1 - rm));
     if (f64) {
-        const u64 wd = P.hval64[h];
+        const u64 wd = gmem(P.hval64)[h];
         if (okm) {
-            P.adjw64[pm] = dbits(wd);
-            P.nbmin64[pm] = P.minin64[n];
+            gmem(P.adjw64)[pm] = dbits(wd);
+            gmem(P.nbmin64)[pm] = gmem(P.minin64)[n];
         }
         if (okn) {
-            P.adjw64[pn] = dbits(wd);
-            P.nbmin64[pn] = P.minin64[m];
+            gmem(P.adjw64)[pn] = dbits(wd);
+            gmem(P.nbmin64)[pn] = gmem(P.minin64)[m];
         }
     } else {
-        if (okm) P.nbmin[pm] = P.minin[n];
+        if (okm) gmem(P.nbmin)[pm] = gmem(P.minin)[n];
         if (okn) P.nbmin[pn] = P.minin[m];
     }
     if (P.dbg_em) {

@@ -117,7 +117,7 @@ __device__ __forceinline__ bool knn_fit_one(const PairDev& P, const RunDev& run,
     const int K = P.K;
     const int keff = __builtin_amdgcn_readfirstlane(P.counters[C_KEFF]);
     int* htab = reinterpret_cast<int*>(S.buf);
-    float* prm = P.params + 6LL * s;
+    EPIC_GLOBAL float* prm = gmem(P.params) + 6LL * s;
 
     // ------------------------------------------------------------ Dijkstra
     for (int i = lane; i < HCAP; i += 64) htab[i] = -1;
@@ -126,9 +126,9 @@ __device__ __forceinline__ bool knn_fit_one(const PairDev& P, const RunDev& run,
     for (int i = lane; i < VCAP; i += 64) S.rd[i] = make_uint2(0u, 0u);
     __syncthreads();
     if (lane == 0) {
-        const u32 a = P.row_ptr[s], b = P.row_ptr[s + 1];
+        const u32 a = gmem(P.row_ptr)[s], b = gmem(P.row_ptr)[s + 1];
         S.dm[0] = 0;
-        if constexpr (F64) S.dm[1] = P.minin64[s]; else S.dm[1] = P.minin[s];
+        if constexpr (F64) S.dm[1] = gmem(P.minin64)[s]; else S.dm[1] = gmem(P.minin)[s];
         S.rd[0] = make_uint2(a, b - a);
         S.node[0] = s;
         const u32 h = node_slot(s, HBITS);
@@ -272,13 +272,13 @@ __device__ __forceinline__ bool knn_fit_one(const PairDev& P, const RunDev& run,
             RT cand[Q], nbm[Q];
 #pragma unroll
             for (int q = 0; q < Q; ++q) {
-                rec[q] = P.adj[ei[q]];
+                rec[q] = gload(P.adj + ei[q]);
                 if constexpr (F64) {
-                    cand[q] = du[q] + P.adjw64[ei[q]];
-                    nbm[q] = dbits(P.nbmin64[ei[q]]);
+                    cand[q] = du[q] + gmem(P.adjw64)[ei[q]];
+                    nbm[q] = dbits(gmem(P.nbmin64)[ei[q]]);
                 } else {
                     cand[q] = du[q] + __uint_as_float(rec[q].y);
-                    nbm[q] = __uint_as_float(P.nbmin[ei[q]]);
+                    nbm[q] = __uint_as_float(gmem(P.nbmin)[ei[q]]);
                 }
             }
             // find or claim each neighbour's table slot
@@ -384,7 +384,7 @@ __device__ __forceinline__ bool knn_fit_one(const PairDev& P, const RunDev& run,
         for (int i = lane; i < nc; i += 64) {
             int node;
             if constexpr (F64) node = S.snode[i]; else node = (int)(u32)S.buf[i];
-            acc += P.matches[4LL * node];
+            acc += gmem(P.matches)[4LL * node];
         }
         // a sum of finite values never has these bits: keeps the loads
         if (__float_as_uint(acc) == 0xffffffffu) S.node[0] = -2;
@@ -448,14 +448,14 @@ __device__ __forceinline__ bool knn_fit_one(const PairDev& P, const RunDev& run,
             const int jj = lane + 64 * r;
             if (jj < K) {
                 const bool ok = jj < n;
-                P.dbg_knn_idx[(long long)s * K + jj] = ok ? knode[r] : -1;
-                P.dbg_knn_d[(long long)s * K + jj] = ok ? (float)kdist[r] : __int_as_float(0x7f800000);
+                gmem(P.dbg_knn_idx)[(long long)s * K + jj] = ok ? knode[r] : -1;
+                gmem(P.dbg_knn_d)[(long long)s * K + jj] = ok ? (float)kdist[r] : __int_as_float(0x7f800000);
             }
         }
     }
 
     // ----------------------------------------------------------------- fit
-    const float* M = P.matches;
+    const EPIC_GLOBAL float* M = gmem(P.matches);
     const float xm = M[4LL * s + 0], ym = M[4LL * s + 1];
     const float um = M[4LL * s + 2] - xm, vm = M[4LL * s + 3] - ym;
     const float a = P.a;
@@ -472,7 +472,7 @@ __device__ __forceinline__ bool knn_fit_one(const PairDev& P, const RunDev& run,
             if (j < n) {
                 const int node = knode[r];
                 const float dj = (float)kdist[r];
-                const float4 mn = *reinterpret_cast<const float4*>(M + 4LL * node);
+                const float4 mn = gload(reinterpret_cast<const float4*>(P.matches + 4LL * node));
                 dx[r] = mn.x - xm;
                 dy[r] = mn.y - ym;
                 du[r] = (mn.z - mn.x) - um;
@@ -591,7 +591,7 @@ __device__ __forceinline__ bool knn_fit_one(const PairDev& P, const RunDev& run,
             double v = o[0];
 #pragma unroll
             for (int i = 1; i < 6; ++i) v = lane == i ? o[i] : v;
-            P.params64[6LL * s + lane] = v;
+            gmem(P.params64)[6LL * s + lane] = v;
         }
         if (lane == 0) {
             if (P.mode == 1) atomicAdd(&P.counters[C_FP64], 1);
