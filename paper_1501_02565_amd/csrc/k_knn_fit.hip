@@ -68,7 +68,8 @@ struct KnnLds {
     u64 buf[VCAP];                // node table (HCAP ints) during the search, sort keys after
     int snode[F64 ? VCAP : 1];    // FP64: node of each sort key
     unsigned short hidx[HCAP];    // node table slot -> entry
-    unsigned short head[TW];      // 1 + entry whose edge segment starts at a window position
+    u32 head[TW];                 // (window stamp << 12) | (1 + entry) of the edge segment
+                                  // starting at a window position
 };
 
 template <bool F64>
@@ -112,6 +113,7 @@ __device__ __forceinline__ bool knn_fit_one(const PairDev& P, const RunDev& run,
     constexpr int HBITS = (HCAP == 512) ? 9 : (HCAP == 1024) ? 10 : (HCAP == 2048) ? 11 : 12;
     static_assert((1 << HBITS) == HCAP, "hash size");
     static_assert(R <= 32, "settled mask is 32 bits");
+    static_assert(VCAP < 4096 && TW <= 128, "head mark layout");
     constexpr int RK = KMAX / 64;
     const int lane = threadIdx.x;
     const int K = P.K;
@@ -121,7 +123,7 @@ __device__ __forceinline__ bool knn_fit_one(const PairDev& P, const RunDev& run,
 
     // ------------------------------------------------------------ Dijkstra
     for (int i = lane; i < HCAP; i += 64) htab[i] = -1;
-    for (int i = lane; i < TW; i += 64) S.head[i] = 0;
+    for (int i = lane; i < TW; i += 64) S.head[i] = 0u;
     for (int i = lane; i < 2 * VCAP; i += 64) S.dm[i] = to_bits<F64>(RINF);
     for (int i = lane; i < VCAP; i += 64) S.rd[i] = make_uint2(0u, 0u);
     __syncthreads();
@@ -138,6 +140,7 @@ __device__ __forceinline__ bool knn_fit_one(const PairDev& P, const RunDev& run,
     __syncthreads();
 
     int nvis = 1;               // entries in use (the same in every lane)
+    int stamp = 0;              // relaxation windows so far (head marks)
     int nsettled = 0;           // settled entries (the same in every lane)
     bool ovf = false;
     u32 settled = 0;            // bit r: entry lane + 64 r is settled
@@ -222,11 +225,19 @@ __device__ __forceinline__ bool knn_fit_one(const PairDev& P, const RunDev& run,
         }
         int carry_start = 0, carry_e = 0;
         for (int wb = 0; wb < T; wb += TW) {
-            // mark the segments that start in this window
+            // mark the segments that start in this window; marks carry the
+            // window's stamp, so stale ones from earlier windows are ignored
+            // and the array is never cleared (except when the stamp wraps)
+            if (++stamp == (1 << 20)) {
+                for (int i = lane; i < TW; i += 64) S.head[i] = 0u;
+                lds_order();
+                stamp = 1;
+            }
+            const u32 stamp_hi = (u32)stamp << 12;
 #pragma unroll
             for (int r = 0; r < R; ++r)
                 if (r < ru && ((newly >> r) & 1u) && rdv[r].y > 0u && off[r] >= wb && off[r] < wb + TW)
-                    S.head[off[r] - wb] = (unsigned short)(lane + 64 * r + 1);
+                    S.head[off[r] - wb] = stamp_hi | (u32)(lane + 64 * r + 1);
             lds_order();
             const int nq = min(Q, (T - wb + 63) >> 6);   // chunks of 64 edges in this window
             bool act[Q];
@@ -238,13 +249,14 @@ __device__ __forceinline__ bool knn_fit_one(const PairDev& P, const RunDev& run,
                 qst[q] = 0;
                 if (q < nq) {
                     act[q] = wb + 64 * q + lane < T;
-                    const int hv = S.head[64 * q + lane];
+                    const u32 hv = S.head[64 * q + lane];
                     // (window position, entry) of the last segment start at
                     // or before this lane, plus one (0: none in this chunk)
-                    const unsigned sc = wave::incl_max(hv ? ((unsigned)(64 * q + lane) << 16) + (unsigned)hv : 0u);
+                    const u32 sc = wave::incl_max((hv >> 12) == (u32)stamp
+                                                      ? ((u32)(64 * q + lane) << 12) | (hv & 0xfffu) : 0u);
                     if (sc != 0u) {
-                        qst[q] = wb + (int)(sc >> 16);
-                        qe[q] = (int)(sc & 0xffffu) - 1;
+                        qst[q] = wb + (int)(sc >> 12);
+                        qe[q] = (int)(sc & 0xfffu) - 1;
                     } else {
                         qst[q] = carry_start;
                         qe[q] = carry_e;
@@ -253,11 +265,6 @@ __device__ __forceinline__ bool knn_fit_one(const PairDev& P, const RunDev& run,
                     carry_e = __builtin_amdgcn_readlane(qe[q], 63);
                 }
             }
-            lds_order();
-#pragma unroll
-            for (int r = 0; r < R; ++r)
-                if (r < ru && ((newly >> r) & 1u) && rdv[r].y > 0u && off[r] >= wb && off[r] < wb + TW)
-                    S.head[off[r] - wb] = 0;
             // each lane's edges: source entry's CSR start and settled distance
             RT du[Q];
             u32 ei[Q];
@@ -281,36 +288,31 @@ __device__ __forceinline__ bool knn_fit_one(const PairDev& P, const RunDev& run,
                     nbm[q] = __uint_as_float(gmem(P.nbmin)[ei[q]]);
                 }
             }
-            // find or claim each neighbour's table slot
-            int hs[Q];
-            bool won[Q], pend[Q];
-            u32 hh[Q];
+            // find or claim each neighbour's table slot with one
+            // compare-and-swap per probe: it returns -1 (this lane claimed
+            // the slot), v (already there) or another node (next slot).
+            // res: 0 while probing, else 1 + slot, bit 30 set when this lane
+            // claimed it; RES_IDLE for lanes without an edge.
+            constexpr u32 RES_WON = 1u << 30, RES_IDLE = ~0u;
+            u32 res[Q], hh[Q];
 #pragma unroll
             for (int q = 0; q < Q; ++q) {
-                pend[q] = act[q];
-                won[q] = false;
-                hs[q] = -1;
+                res[q] = act[q] ? 0u : RES_IDLE;
                 hh[q] = node_slot((int)rec[q].x, HBITS);
             }
-            // one compare-and-swap per probe: it returns -1 (this lane claimed
-            // the slot), v (already there) or another node (next slot)
             for (int probe = 0; probe < HCAP; ++probe) {
                 bool any = false;
 #pragma unroll
-                for (int q = 0; q < Q; ++q) any = any || pend[q];
+                for (int q = 0; q < Q; ++q) any = any || res[q] == 0u;
                 if (wave::ballot(any) == 0ull) break;
-                int prev[Q];
+                int prev[Q];            // all chunks' compare-and-swaps in flight together
 #pragma unroll
                 for (int q = 0; q < Q; ++q)
-                    prev[q] = pend[q] ? atomicCAS(&htab[hh[q]], -1, (int)rec[q].x) : 0;
+                    prev[q] = res[q] == 0u ? atomicCAS(&htab[hh[q]], -1, (int)rec[q].x) : 0;
 #pragma unroll
                 for (int q = 0; q < Q; ++q) {
-                    if (!pend[q]) continue;
-                    if (prev[q] == -1 || prev[q] == (int)rec[q].x) {
-                        won[q] = prev[q] == -1;
-                        hs[q] = (int)hh[q];
-                        pend[q] = false;
-                    } else {
+                    if (res[q] == 0u) {
+                        res[q] = prev[q] == -1 ? (hh[q] + 1u) | RES_WON : prev[q] == (int)rec[q].x ? hh[q] + 1u : 0u;
                         hh[q] = (hh[q] + 1u) & (u32)(HCAP - 1);
                     }
                 }
@@ -318,24 +320,26 @@ __device__ __forceinline__ bool knn_fit_one(const PairDev& P, const RunDev& run,
             {
                 bool lost = false;
 #pragma unroll
-                for (int q = 0; q < Q; ++q) lost = lost || pend[q];
+                for (int q = 0; q < Q; ++q) lost = lost || res[q] == 0u;
                 if (wave::ballot(lost) != 0ull) ovf = true;
             }
             // new nodes get entries (with their distance and CSR range)
 #pragma unroll
             for (int q = 0; q < Q; ++q) {
-                const u64 m = wave::ballot(won[q]);
+                const bool won = res[q] != RES_IDLE && (res[q] & RES_WON) != 0u;
+                const u64 m = wave::ballot(won);
                 const int e = nvis + wave::lanes_below(m);
                 nvis += __popcll(m);
-                if (won[q]) {
+                if (won) {
+                    const u32 hs = (res[q] & (RES_WON - 1u)) - 1u;
                     if (e < VCAP) {
                         S.dm[2 * e] = to_bits<F64>(cand[q]);
                         S.dm[2 * e + 1] = to_bits<F64>(nbm[q]);
                         S.rd[e] = make_uint2(rec[q].z, rec[q].w);
                         S.node[e] = (int)rec[q].x;
-                        S.hidx[hs[q]] = (unsigned short)e;
+                        S.hidx[hs] = (unsigned short)e;
                     } else {
-                        S.hidx[hs[q]] = 0xffff;
+                        S.hidx[hs] = 0xffff;
                     }
                 }
             }
@@ -344,8 +348,8 @@ __device__ __forceinline__ bool knn_fit_one(const PairDev& P, const RunDev& run,
             // relax the nodes that were already in the table
 #pragma unroll
             for (int q = 0; q < Q; ++q) {
-                if (act[q] && hs[q] >= 0 && !won[q]) {
-                    const int e = S.hidx[hs[q]];
+                if (res[q] != RES_IDLE && res[q] != 0u && (res[q] & RES_WON) == 0u) {
+                    const int e = S.hidx[res[q] - 1u];
                     if (e != 0xffff) atomicMin(&S.dm[2 * e], to_bits<F64>(cand[q]));
                 }
             }
