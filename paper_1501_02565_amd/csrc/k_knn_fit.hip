@@ -423,7 +423,8 @@ __device__ __forceinline__ bool knn_fit_one(const PairDev& P, const RunDev& run,
                             S.snode[ixj] = na;
                         }
                     } else {
-                        if (up ? a > b : a < b) {
+                        // keys are distinct except the padding, whose swap is harmless
+                        if ((a > b) == up) {
                             S.buf[i] = b;
                             S.buf[ixj] = a;
                         }
