@@ -120,6 +120,8 @@ __device__ __forceinline__ bool knn_fit_one(const PairDev& P, const RunDev& run,
     const int keff = __builtin_amdgcn_readfirstlane(P.counters[C_KEFF]);
     int* htab = reinterpret_cast<int*>(S.buf);
     EPIC_GLOBAL float* prm = gmem(P.params) + 6LL * s;
+    // the match's own row, fetched now so that its latency hides behind the search
+    const float4 me = gload(reinterpret_cast<const float4*>(P.matches) + s);
 
     // ------------------------------------------------------------ Dijkstra
     for (int i = lane; i < HCAP; i += 64) htab[i] = -1;
@@ -381,18 +383,6 @@ __device__ __forceinline__ bool knn_fit_one(const PairDev& P, const RunDev& run,
             }
         }
     }
-    // fetch the match rows of the candidates now, so that the fit's loads
-    // of the K nearest (a subset) hit the cache after the sort
-    {
-        float acc = 0.0f;
-        for (int i = lane; i < nc; i += 64) {
-            int node;
-            if constexpr (F64) node = S.snode[i]; else node = (int)(u32)S.buf[i];
-            acc += gmem(P.matches)[4LL * node];
-        }
-        // a sum of finite values never has these bits: keeps the loads
-        if (__float_as_uint(acc) == 0xffffffffu) S.node[0] = -2;
-    }
     int p2 = 64;
     while (p2 < nc) p2 <<= 1;
     for (int i = nc + lane; i < p2; i += 64) {
@@ -460,9 +450,16 @@ __device__ __forceinline__ bool knn_fit_one(const PairDev& P, const RunDev& run,
     }
 
     // ----------------------------------------------------------------- fit
-    const EPIC_GLOBAL float* M = gmem(P.matches);
-    const float xm = M[4LL * s + 0], ym = M[4LL * s + 1];
-    const float um = M[4LL * s + 2] - xm, vm = M[4LL * s + 3] - ym;
+    const float xm = me.x, ym = me.y;
+    const float um = me.z - xm, vm = me.w - ym;
+    // the K nearest rows, all loads in flight at once (lanes beyond n load
+    // the match's own row and do not use it)
+    float4 mrow[RK];
+#pragma unroll
+    for (int r = 0; r < RK; ++r) {
+        const int node = lane + 64 * r < n ? knode[r] : s;
+        mrow[r] = gload(reinterpret_cast<const float4*>(P.matches) + node);
+    }
     const float a = P.a;
     const int wpow = run.la_wpow;
     float out[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
@@ -475,9 +472,8 @@ __device__ __forceinline__ bool knn_fit_one(const PairDev& P, const RunDev& run,
             const int j = lane + 64 * r;
             dx[r] = dy[r] = du[r] = dv[r] = kk[r] = ww[r] = 0.f;
             if (j < n) {
-                const int node = knode[r];
                 const float dj = (float)kdist[r];
-                const float4 mn = gload(reinterpret_cast<const float4*>(P.matches + 4LL * node));
+                const float4 mn = mrow[r];
                 dx[r] = mn.x - xm;
                 dy[r] = mn.y - ym;
                 du[r] = (mn.z - mn.x) - um;
@@ -537,7 +533,7 @@ __device__ __forceinline__ bool knn_fit_one(const PairDev& P, const RunDev& run,
     if (need64) {
         // FP64: re-accumulate from the inputs and solve (or fall back to NW)
         const double xmd = xm, ymd = ym;
-        const double umd = (double)M[4LL * s + 2] - xmd, vmd = (double)M[4LL * s + 3] - ymd;
+        const double umd = (double)me.z - xmd, vmd = (double)me.w - ymd;
         double Dx[RK], Dy[RK], Du[RK], Dv[RK], Dw[RK];
         double Tk = 0, Tu = 0, Tv = 0, Sw = 0, Sx = 0, Sy = 0;
 #pragma unroll
@@ -545,13 +541,12 @@ __device__ __forceinline__ bool knn_fit_one(const PairDev& P, const RunDev& run,
             const int j = lane + 64 * r;
             Dx[r] = Dy[r] = Du[r] = Dv[r] = Dw[r] = 0.0;
             if (j < n) {
-                const int node = knode[r];
                 const double dj = (double)kdist[r];
-                const double x = M[4LL * node + 0], y = M[4LL * node + 1];
+                const double x = mrow[r].x, y = mrow[r].y;
                 Dx[r] = x - xmd;
                 Dy[r] = y - ymd;
-                Du[r] = ((double)M[4LL * node + 2] - x) - umd;
-                Dv[r] = ((double)M[4LL * node + 3] - y) - vmd;
+                Du[r] = ((double)mrow[r].z - x) - umd;
+                Dv[r] = ((double)mrow[r].w - y) - vmd;
                 const double k = exp(-(double)a * dj);
                 Dw[r] = wpow == 1 ? k : k * k;
                 Tk += k; Tu += k * Du[r]; Tv += k * Dv[r];
