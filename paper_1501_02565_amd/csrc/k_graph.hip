@@ -165,9 +165,20 @@ __global__ __launch_bounds__(1024) void k_csr_scan(const PairDev* __restrict__ p
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int N = P.N;
     int used = 0;
-    for (int m = tid; m < N; m += 1024) {
-        const int sp = P.seed_pix[m];
-        if (sp >= 0 && label_at(P, sp) == (u32)m) ++used;
+    // four strided matches per step, their loads issued together
+    for (int m0 = tid; m0 < N; m0 += 4 * 1024) {
+        int sp[4];
+        u32 lb[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int m = m0 + 1024 * j;
+            sp[j] = m < N ? gmem(P.seed_pix)[m] : -1;
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            lb[j] = sp[j] >= 0 ? (P.labels ? gmem(P.labels)[sp[j]] : key_label(gmem(P.keys)[sp[j]])) : NO_LABEL;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) used += (sp[j] >= 0 && lb[j] == (u32)(m0 + 1024 * j)) ? 1 : 0;
     }
     used = wave::sum(used);
     const int chunk = ((N + 1023) / 1024 + 3) & ~3;
