@@ -112,7 +112,6 @@ __device__ __forceinline__ bool knn_fit_one(const PairDev& P, const RunDev& run,
     constexpr int R = VCAP / 64;        // entries per lane
     constexpr int HBITS = (HCAP == 512) ? 9 : (HCAP == 1024) ? 10 : (HCAP == 2048) ? 11 : 12;
     static_assert((1 << HBITS) == HCAP, "hash size");
-    static_assert(R <= 32, "settled mask is 32 bits");
     static_assert(VCAP < 4096 && TW <= 128, "head mark layout");
     constexpr int RK = KMAX / 64;
     const int lane = threadIdx.x;
@@ -145,7 +144,11 @@ __device__ __forceinline__ bool knn_fit_one(const PairDev& P, const RunDev& run,
     int stamp = 0;              // relaxation windows so far (head marks)
     int nsettled = 0;           // settled entries (the same in every lane)
     bool ovf = false;
-    u32 settled = 0;            // bit r: entry lane + 64 r is settled
+    // per group r: the lanes whose entry lane + 64 r is settled, as a lane
+    // mask (uniform: the per-lane tests are mask selects, updates scalar)
+    u64 smask[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) smask[r] = 0ull;
     // per group r: the raw (distance, lightest edge) bits and CSR range of
     // entry lane + 64 r, kept across steps as loaded
     using DT2 = typename std::conditional<F64, ulonglong2, uint2>::type;
@@ -179,11 +182,13 @@ __device__ __forceinline__ bool knn_fit_one(const PairDev& P, const RunDev& run,
             d[r] = from_bits<F64>(dmr[r].x);
             mi[r] = from_bits<F64>(dmr[r].y);
         }
+        // frontier minimum (entries not in use are infinite)
         RT fmin = RINF;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            if (r >= ru || ((settled >> r) & 1u)) continue;
-            fmin = fmin < d[r] ? fmin : d[r];
+            const RT dv = __builtin_amdgcn_inverse_ballot_w64(smask[r]) ? RINF : d[r];
+            if constexpr (F64) fmin = fmin < dv ? fmin : dv;
+            else fmin = __uint_as_float(min(__float_as_uint(fmin), __float_as_uint(dv)));   // d >= 0
         }
         RT dmin;
         if constexpr (F64) dmin = wave::min(fmin); else dmin = wave::min_nonneg(fmin);
@@ -193,27 +198,26 @@ __device__ __forceinline__ bool knn_fit_one(const PairDev& P, const RunDev& run,
         if (nsettled >= keff) {
 #pragma unroll
             for (int r = 0; r < R; ++r)
-                if (r < ru) below += (((settled >> r) & 1u) && d[r] < dmin) ? 1 : 0;
-            below = wave::sum(below);
+                if (r < ru) below += __popcll(wave::ballot(d[r] < dmin) & smask[r]);
         }
         if (below >= keff || !(dmin < RINF)) {
             dstop = dmin;       // nodes settled at this point lie at or above dmin
             break;
         }
         // settle the final frontier nodes; their edges are relaxed below
-        u32 newly = 0;
+        u64 newly[R];
         int my_edges = 0;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
+            newly[r] = 0ull;
             if (r >= ru) continue;
-            const bool fin = lane + 64 * r < nv && !((settled >> r) & 1u) && d[r] <= dmin + mi[r];
-            nsettled += __popcll(wave::ballot(fin));
-            if (fin) {
-                newly |= 1u << r;
-                my_edges += (int)rdv[r].y;
-            }
+            const int nin = nv - 64 * r;                       // entries of group r in use, >= 1
+            const u64 valid = nin >= 64 ? ~0ull : (1ull << nin) - 1ull;
+            newly[r] = wave::ballot(d[r] <= dmin + mi[r]) & valid & ~smask[r];
+            nsettled += __popcll(newly[r]);
+            smask[r] |= newly[r];
+            if (__builtin_amdgcn_inverse_ballot_w64(newly[r])) my_edges += (int)rdv[r].y;
         }
-        settled |= newly;
         const int incl = wave::incl_scan(my_edges);
         const int T = __builtin_amdgcn_readlane(incl, 63);
         int off[R];
@@ -222,7 +226,7 @@ __device__ __forceinline__ bool knn_fit_one(const PairDev& P, const RunDev& run,
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 off[r] = o;
-                if (r < ru && ((newly >> r) & 1u)) o += (int)rdv[r].y;
+                if (r < ru && __builtin_amdgcn_inverse_ballot_w64(newly[r])) o += (int)rdv[r].y;
             }
         }
         int carry_start = 0, carry_e = 0;
@@ -238,7 +242,8 @@ __device__ __forceinline__ bool knn_fit_one(const PairDev& P, const RunDev& run,
             const u32 stamp_hi = (u32)stamp << 12;
 #pragma unroll
             for (int r = 0; r < R; ++r)
-                if (r < ru && ((newly >> r) & 1u) && rdv[r].y > 0u && off[r] >= wb && off[r] < wb + TW)
+                if (r < ru && __builtin_amdgcn_inverse_ballot_w64(newly[r]) && rdv[r].y > 0u && off[r] >= wb &&
+                    off[r] < wb + TW)
                     S.head[off[r] - wb] = stamp_hi | (u32)(lane + 64 * r + 1);
             lds_order();
             const int nq = min(Q, (T - wb + 63) >> 6);   // chunks of 64 edges in this window
@@ -369,7 +374,7 @@ __device__ __forceinline__ bool knn_fit_one(const PairDev& P, const RunDev& run,
     int nc = 0;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        const bool c = ((settled >> r) & 1u) && d[r] < dstop;
+        const bool c = __builtin_amdgcn_inverse_ballot_w64(smask[r]) && d[r] < dstop;
         const u64 m = wave::ballot(c);
         const int pos = nc + wave::lanes_below(m);
         nc += __popcll(m);
