@@ -84,8 +84,9 @@ typedef struct epic_options {
                                supported: 32x16, 32x32, 32x64; tile_w is 32)   */
     int   geo_passes;       /* bulk-synchronous passes of the geodesic
                                transform launched per call, at most 63;
-                               0 (default) = automatic: the passes the last
-                               finished call needed plus 2 (16 before the
+                               0 (default) = automatic: the most passes
+                               the last 8 finished calls needed, plus 1
+                               when those needs differed (16 before the
                                first; the FP64 path uses 16).  A
                                single-workgroup finisher completes the
                                transform if they do not reach the fixpoint,

@@ -54,7 +54,7 @@ class Context:
     """Owns one epic_ctx: a device workspace allocated once (``workspace``
     bytes, default enough for a 2048 x 1080 image with 40000 matches).
     ``passes`` is the geodesic pass budget per call (0 = automatic, from the
-    passes the previous call needed); it never changes results."""
+    passes the recent calls needed); it never changes results."""
 
     def __init__(self, device: int = 0, workspace: int | None = None, *,
                  connectivity: int = 8, la_weight_power: int = 2,

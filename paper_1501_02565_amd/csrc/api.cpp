@@ -22,7 +22,7 @@ namespace {
 
 constexpr int kMaxPairs = 1024;      // pairs per call
 constexpr int kAutoPassesStart = 16;    // automatic budget before any call finished
-constexpr int kAutoPassesMargin = 2;    // passes launched beyond the last call's need
+constexpr int kAutoPassesHistory = 8;   // recent needs the automatic budget covers
 constexpr int kAutoPassesMin = 4;
 constexpr int kRing = 4;             // descriptor upload slots
 constexpr size_t kAlign = 256;
@@ -106,6 +106,8 @@ struct epic_ctx {
     int passes = 16;                    // geodesic passes launched per call (fixed budget)
     bool auto_passes = true;            // budget from the passes the last call needed
     int* h_passes_used = nullptr;       // pinned, written by the transform's finisher
+    int used_hist[kAutoPassesHistory]{};  // needs seen at the last calls (0: none yet)
+    int used_next = 0;
     // stage timing
     bool prof = false;
     hipEvent_t prof_ev[kProfRing][kStages + 1]{};
@@ -389,10 +391,15 @@ int run_pairs(epic_ctx* c, const epic_request* reqs, int n, hipStream_t stream, 
     run.fp64_route = c->opt.fp64_route;
     run.deg_tau = c->opt.degenerate_tau;
 
-    hipError_t e = hipMemcpyAsync(dd, hd, sizeof(PairDev) * n, hipMemcpyHostToDevice, stream);
-    if (e == hipSuccess && slot >= 0) e = hipEventRecord(c->ring_ev[slot], stream);
-    if (e != hipSuccess) return EPIC_ERR_HIP;
-    if (slot >= 0) c->ring_used[slot] = true;
+    // small tables travel in the first kernel's arguments (no upload copy)
+    const bool inline_desc = n <= kInlinePairs;
+    hipError_t e = hipSuccess;
+    if (!inline_desc) {
+        e = hipMemcpyAsync(dd, hd, sizeof(PairDev) * n, hipMemcpyHostToDevice, stream);
+        if (e == hipSuccess && slot >= 0) e = hipEventRecord(c->ring_ev[slot], stream);
+        if (e != hipSuccess) return EPIC_ERR_HIP;
+        if (slot >= 0) c->ring_used[slot] = true;
+    }
 
     hipEvent_t* ev = nullptr;
     if (c->prof && !tgt) {
@@ -411,18 +418,30 @@ int run_pairs(epic_ctx* c, const epic_request* reqs, int n, hipStream_t stream, 
     auto mark = [&](int stage) {
         if (ev && e == hipSuccess) e = hipEventRecord(ev[stage + 1], stream);
     };
-    if (e == hipSuccess) e = launch_clear(dd, run, init_blocks, stream);
+    if (e == hipSuccess) e = launch_clear(dd, run, init_blocks, inline_desc ? hd : nullptr, n, stream);
     mark(0);
     if (e == hipSuccess) e = launch_seed(dd, run, seed_blocks, stream);
     mark(1);
-    // Automatic budget: the passes the last finished transform needed, plus
-    // a margin (the value may come from an older call while the last one is
-    // still running; any budget gives the same result, the finisher
-    // completes the transform).  The FP64 path keeps a fixed budget.
+    // Automatic budget: the largest number of passes the recently finished
+    // transforms needed (read when each call is issued; the value may come
+    // from an older call while the last one is still running), plus one when
+    // those needs varied.  Any budget gives the same result: the finisher
+    // completes a transform the launched passes did not.  The FP64 path keeps
+    // a fixed budget.
     int passes = c->passes;
     if (c->auto_passes && c->opt.precision == 0) {
         const int used = *reinterpret_cast<volatile int*>(c->h_passes_used);
-        if (used > 0) passes = std::min(kMaxPasses - 1, std::max(kAutoPassesMin, used + kAutoPassesMargin));
+        if (used > 0) {
+            c->used_hist[c->used_next] = used;
+            c->used_next = (c->used_next + 1) % kAutoPassesHistory;
+            int hi = 0, lo = 1 << 30;
+            for (int h : c->used_hist)
+                if (h > 0) {
+                    hi = std::max(hi, h);
+                    lo = std::min(lo, h);
+                }
+            passes = std::min(kMaxPasses - 1, std::max(kAutoPassesMin, hi + (hi == lo ? 0 : 1)));
+        }
     }
     if (e == hipSuccess)
         e = c->opt.precision == 1 ? launch_geodesic64(dd, run, c->passes, seed_blocks, stream)

@@ -155,6 +155,15 @@ struct RunDev {
 
 constexpr int kMaxPasses = 64;   // passes launched per call, at most
 
+// Descriptor tables of up to kInlinePairs pairs travel in the first kernel's
+// arguments (which the launch copies anyway); that kernel writes them to the
+// device table the later kernels read.  Larger tables are uploaded with a copy.
+constexpr int kInlinePairs = 8;
+struct DescInline {
+    int n;                          // 0: the device table is already uploaded
+    PairDev p[kInlinePairs];
+};
+
 // Binary search: the pair whose base <= idx (bases ascending).
 template <typename F>
 __device__ __forceinline__ int find_pair(int npairs, int idx, F base_of) {
@@ -173,7 +182,8 @@ constexpr int PIX_BLOCK = 256;      // pixels per block of pixel-parallel kernel
 constexpr int EMIT_TW = 32, EMIT_TH = 8;   // pixel tile of one graph-emit block
 constexpr int SLOT_BLOCK = 256;     // hash slots per block
 
-hipError_t launch_clear(const PairDev* d_pairs, const RunDev& run, int total_blocks, hipStream_t s);
+hipError_t launch_clear(const PairDev* d_pairs, const RunDev& run, int total_blocks, const PairDev* inline_host,
+                        int n_inline, hipStream_t s);
 hipError_t launch_seed(const PairDev* d_pairs, const RunDev& run, int total_blocks, hipStream_t s);
 hipError_t launch_geodesic(const PairDev* d_pairs, const RunDev& run, int tile_w, int tile_h,
                            int passes, hipStream_t s);

@@ -11,11 +11,20 @@
 namespace epic {
 
 // Clears the per-pair workspace with grid-stride loops; each pair owns
-// init_blocks consecutive blocks of the grid.
-__global__ __launch_bounds__(256) void k_clear(const PairDev* __restrict__ pairs, RunDev run) {
+// init_blocks consecutive blocks of the grid.  With an inline descriptor
+// table, the descriptors come from the arguments and block 0 also writes
+// them to the device table.
+__global__ __launch_bounds__(256) void k_clear(PairDev* __restrict__ pairs, RunDev run, DescInline inl) {
+    const PairDev* table = inl.n > 0 ? inl.p : pairs;
+    if (inl.n > 0 && blockIdx.x == 0) {
+        const u32* src = reinterpret_cast<const u32*>(inl.p);
+        EPIC_GLOBAL u32* dst = reinterpret_cast<EPIC_GLOBAL u32*>(gmem(pairs));
+        const int words = inl.n * (int)(sizeof(PairDev) / 4);
+        for (int i = threadIdx.x; i < words; i += blockDim.x) dst[i] = src[i];
+    }
     const int p = find_pair(run.npairs, (int)blockIdx.x,
-                            [&](int i) { return pairs[i].init_block_base; });
-    const PairDev& P = pairs[p];
+                            [&](int i) { return table[i].init_block_base; });
+    const PairDev& P = table[p];
     const int lb = (int)blockIdx.x - P.init_block_base;
     const long long stride = (long long)P.init_blocks * blockDim.x;
     const long long i0 = (long long)lb * blockDim.x + threadIdx.x;
@@ -81,8 +90,13 @@ __global__ __launch_bounds__(256) void k_seed(const PairDev* __restrict__ pairs,
     P.seed_pix[m] = pix;
 }
 
-hipError_t launch_clear(const PairDev* d_pairs, const RunDev& run, int total_blocks, hipStream_t s) {
-    hipLaunchKernelGGL(k_clear, dim3(total_blocks), dim3(256), 0, s, d_pairs, run);
+hipError_t launch_clear(const PairDev* d_pairs, const RunDev& run, int total_blocks, const PairDev* inline_host,
+                        int n_inline, hipStream_t s) {
+    DescInline inl;
+    inl.n = inline_host ? n_inline : 0;
+    if (inl.n > kInlinePairs) return hipErrorInvalidValue;
+    for (int i = 0; i < inl.n; ++i) inl.p[i] = inline_host[i];
+    hipLaunchKernelGGL(k_clear, dim3(total_blocks), dim3(256), 0, s, const_cast<PairDev*>(d_pairs), run, inl);
     return hipGetLastError();
 }
 
