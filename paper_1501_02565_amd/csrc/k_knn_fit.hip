@@ -496,13 +496,16 @@ __device__ __forceinline__ bool knn_fit_one(const PairDev& P, const RunDev& run,
         tk = wave::sum(tk);
         tu = wave::sum(tu);
         tv = wave::sum(tv);
-        out[4] = um + tu / tk;
-        out[5] = vm + tv / tk;
+        // one division per distinct denominator, then products
+        const float itk = 1.0f / tk;
+        out[4] = um + tu * itk;
+        out[5] = vm + tv * itk;
         if (P.mode == 1) {
             sw = wave::sum(sw);
             sx = wave::sum(sx);
             sy = wave::sum(sy);
-            const float mx = sx / sw, my = sy / sw;
+            const float isw = 1.0f / sw;
+            const float mx = sx * isw, my = sy * isw;
             float sxx = 0.f, sxy = 0.f, syy = 0.f, sxu = 0.f, syu = 0.f, sxv = 0.f, syv = 0.f, su = 0.f, sv = 0.f;
 #pragma unroll
             for (int r = 0; r < RK; ++r) {
@@ -524,14 +527,15 @@ __device__ __forceinline__ bool knn_fit_one(const PairDev& P, const RunDev& run,
             const float tr = sxx + syy;
             const float disc = sqrtf((sxx - syy) * (sxx - syy) + 4.0f * sxy * sxy);
             const float l1 = 0.5f * (tr + disc);
-            const float ratio = l1 > 0.f ? (det / l1) / l1 : 0.f;
+            const float ratio = l1 > 0.f ? det / (l1 * l1) : 0.f;
             need64 = n < 3 || !(ratio >= run.fp64_route);
             if (!need64) {
-                const float b00 = (syy * sxu - sxy * syu) / det, b01 = (sxx * syu - sxy * sxu) / det;
-                const float b10 = (syy * sxv - sxy * syv) / det, b11 = (sxx * syv - sxy * sxv) / det;
+                const float idet = 1.0f / det;
+                const float b00 = (syy * sxu - sxy * syu) * idet, b01 = (sxx * syu - sxy * sxu) * idet;
+                const float b10 = (syy * sxv - sxy * syv) * idet, b11 = (sxx * syv - sxy * sxv) * idet;
                 out[0] = b00; out[1] = b01; out[2] = b10; out[3] = b11;
-                out[4] = um + su / sw - (b00 * mx + b01 * my);
-                out[5] = vm + sv / sw - (b10 * mx + b11 * my);
+                out[4] = um + su * isw - (b00 * mx + b01 * my);
+                out[5] = vm + sv * isw - (b10 * mx + b11 * my);
             }
         }
     }

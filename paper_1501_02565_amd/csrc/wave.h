@@ -46,14 +46,17 @@ __device__ __forceinline__ double readlane63(double v) {
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-// Sum over the 64 lanes, returned to every lane.
+// Sum over the 64 lanes, returned to every lane.  Only lane 63 is read at
+// the end, so the row broadcasts run on all rows (rows 0-2 may end up
+// holding partial or doubled sums; row 3 gets rows 0 + 1, then 2, exactly
+// once) and every step is one DPP add with out-of-row reads giving 0.
 __device__ __forceinline__ float sum(float v) {
     v += dppf<QP_XOR1>(0.0f, v);
     v += dppf<QP_XOR2>(0.0f, v);
     v += dppf<ROW_HALF_MIRROR>(0.0f, v);
     v += dppf<ROW_MIRROR>(0.0f, v);          // every lane: its row's sum
-    v += dppf<ROW_BCAST15, 0xA>(0.0f, v);    // rows 1, 3 += rows 0, 2
-    v += dppf<ROW_BCAST31, 0xC>(0.0f, v);    // rows 2, 3 += rows 0 + 1
+    v += dppf<ROW_BCAST15>(0.0f, v);         // row 3 += row 2 (row 1 += row 0)
+    v += dppf<ROW_BCAST31>(0.0f, v);         // row 3 += row 1
     return readlane63(v);
 }
 __device__ __forceinline__ double sum(double v) {
@@ -61,8 +64,8 @@ __device__ __forceinline__ double sum(double v) {
     v += dppd<QP_XOR2>(0.0, v);
     v += dppd<ROW_HALF_MIRROR>(0.0, v);
     v += dppd<ROW_MIRROR>(0.0, v);
-    v += dppd<ROW_BCAST15, 0xA>(0.0, v);
-    v += dppd<ROW_BCAST31, 0xC>(0.0, v);
+    v += dppd<ROW_BCAST15>(0.0, v);
+    v += dppd<ROW_BCAST31>(0.0, v);
     return readlane63(v);
 }
 __device__ __forceinline__ int sum(int v) {
