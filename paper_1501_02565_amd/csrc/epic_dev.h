@@ -179,7 +179,9 @@ __device__ __forceinline__ int find_pair(int npairs, int idx, F base_of) {
 // host-side launchers (one per stage; defined next to their kernels)
 // ---------------------------------------------------------------------------
 constexpr int PIX_BLOCK = 256;      // pixels per block of pixel-parallel kernels
-constexpr int EMIT_TW = 32, EMIT_TH = 8;   // pixel tile of one graph-emit block
+constexpr int EMIT_TW = 32, EMIT_TH = 16;  // pixel tile of one graph-emit block
+constexpr int EMIT_NT = EMIT_TW * EMIT_TH; // one thread per pixel
+constexpr int EMIT_LCAP = 4 * EMIT_NT;     // block-local edge slots
 constexpr int SLOT_BLOCK = 256;     // hash slots per block
 
 hipError_t launch_clear(const PairDev* d_pairs, const RunDev& run, int total_blocks, const PairDev* inline_host,

@@ -87,15 +87,14 @@ __device__ __forceinline__ void global_insert(const PairDev& P, u64 hk, u64 wb) 
 // block; a compact tile meets far fewer cell boundaries than a pixel strip of
 // the same size, so few edges reach the global hash per block.
 template <int CONN, bool F64>
-__global__ __launch_bounds__(PIX_BLOCK) void k_graph_emit(const PairDev* __restrict__ pairs, RunDev run) {
-    constexpr int LCAP = 4 * PIX_BLOCK;               // >= candidates per block
+__global__ __launch_bounds__(EMIT_NT) void k_graph_emit(const PairDev* __restrict__ pairs, RunDev run) {
+    constexpr int LCAP = EMIT_LCAP;                   // block-local edge slots (overflow goes global)
     using V = typename std::conditional<F64, u64, u32>::type;
     __shared__ u64 lkey[LCAP];
     __shared__ V lval[LCAP];
-    static_assert(EMIT_TW * EMIT_TH == PIX_BLOCK, "emit tile");
     const int p = find_pair(run.npairs, (int)blockIdx.x, [&](int i) { return pairs[i].emit_block_base; });
     const PairDev& P = pairs[p];
-    for (int i = threadIdx.x; i < LCAP; i += PIX_BLOCK) {
+    for (int i = threadIdx.x; i < LCAP; i += EMIT_NT) {
         lkey[i] = HASH_EMPTY;
         lval[i] = F64 ? (V)DOUBLE_INF_BITS : (V)FLOAT_INF_BITS;
     }
@@ -150,7 +149,7 @@ __global__ __launch_bounds__(PIX_BLOCK) void k_graph_emit(const PairDev* __restr
         }
     }
     __syncthreads();
-    for (int j = threadIdx.x; j < LCAP; j += PIX_BLOCK)
+    for (int j = threadIdx.x; j < LCAP; j += EMIT_NT)
         if (lkey[j] != HASH_EMPTY) global_insert<F64>(P, lkey[j], lval[j]);
 }
 
@@ -286,11 +285,11 @@ __global__ __launch_bounds__(SLOT_BLOCK) void k_csr_scatter(const PairDev* __res
 hipError_t launch_graph_emit(const PairDev* d_pairs, const RunDev& run, int total_blocks, hipStream_t s) {
     const bool f64 = run.precision == 1;
     if (run.conn == 4) {
-        if (f64) hipLaunchKernelGGL((k_graph_emit<4, true>), dim3(total_blocks), dim3(PIX_BLOCK), 0, s, d_pairs, run);
-        else hipLaunchKernelGGL((k_graph_emit<4, false>), dim3(total_blocks), dim3(PIX_BLOCK), 0, s, d_pairs, run);
+        if (f64) hipLaunchKernelGGL((k_graph_emit<4, true>), dim3(total_blocks), dim3(EMIT_NT), 0, s, d_pairs, run);
+        else hipLaunchKernelGGL((k_graph_emit<4, false>), dim3(total_blocks), dim3(EMIT_NT), 0, s, d_pairs, run);
     } else {
-        if (f64) hipLaunchKernelGGL((k_graph_emit<8, true>), dim3(total_blocks), dim3(PIX_BLOCK), 0, s, d_pairs, run);
-        else hipLaunchKernelGGL((k_graph_emit<8, false>), dim3(total_blocks), dim3(PIX_BLOCK), 0, s, d_pairs, run);
+        if (f64) hipLaunchKernelGGL((k_graph_emit<8, true>), dim3(total_blocks), dim3(EMIT_NT), 0, s, d_pairs, run);
+        else hipLaunchKernelGGL((k_graph_emit<8, false>), dim3(total_blocks), dim3(EMIT_NT), 0, s, d_pairs, run);
     }
     return hipGetLastError();
 }
