@@ -17,8 +17,9 @@
 //                    open-addressing hash with an atomic min on the weight
 //                    (positive floats order like their bits).  The first
 //                    insertion of an edge raises both endpoints' degree.
-//   k_csr_scan       one workgroup per pair: counts usable matches, clamps K,
-//                    and turns degrees into CSR row offsets.
+//   k_csr_scan       one workgroup per pair: clamps K to the usable matches
+//                    (counted by the seeding) and turns degrees into CSR row
+//                    offsets.
 //                    Every insertion also lowers both endpoints' lightest
 //                    incident edge (the minimum over a node's candidates is
 //                    the minimum over its edges).
@@ -159,27 +160,9 @@ __global__ __launch_bounds__(EMIT_NT) void k_graph_emit(const PairDev* __restric
 // thread writes its chunk's row offsets.
 __global__ __launch_bounds__(1024) void k_csr_scan(const PairDev* __restrict__ pairs, RunDev run) {
     const PairDev& P = pairs[blockIdx.x];
-    __shared__ int s_used[16];
     __shared__ u32 s_wave[16];
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int N = P.N;
-    int used = 0;
-    // four strided matches per step, their loads issued together
-    for (int m0 = tid; m0 < N; m0 += 4 * 1024) {
-        int sp[4];
-        u32 lb[4];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int m = m0 + 1024 * j;
-            sp[j] = m < N ? gmem(P.seed_pix)[m] : -1;
-        }
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-            lb[j] = sp[j] >= 0 ? (P.labels ? gmem(P.labels)[sp[j]] : key_label(gmem(P.keys)[sp[j]])) : NO_LABEL;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) used += (sp[j] >= 0 && lb[j] == (u32)(m0 + 1024 * j)) ? 1 : 0;
-    }
-    used = wave::sum(used);
     const int chunk = ((N + 1023) / 1024 + 3) & ~3;
     const int b = min(N, tid * chunk), e = min(N, b + chunk);
     u32 sum = 0;
@@ -192,10 +175,7 @@ __global__ __launch_bounds__(1024) void k_csr_scan(const PairDev* __restrict__ p
         for (int m = b; m < e; ++m) sum += P.deg[m];
     }
     const u32 incl = (u32)wave::incl_scan((int)sum);
-    if (lane == 63) {
-        s_wave[wid] = incl;
-        s_used[wid] = used;
-    }
+    if (lane == 63) s_wave[wid] = incl;
     __syncthreads();
     u32 base = 0;
     for (int w = 0; w < wid; ++w) base += s_wave[w];
@@ -218,15 +198,10 @@ __global__ __launch_bounds__(1024) void k_csr_scan(const PairDev* __restrict__ p
         }
     }
     u32 two_e_total = 0;
-    int u_total = 0;
-    for (int w = 0; w < 16; ++w) {
-        two_e_total += s_wave[w];
-        u_total += s_used[w];
-    }
+    for (int w = 0; w < 16; ++w) two_e_total += s_wave[w];
     if (tid == 0) P.row_ptr[N] = two_e_total;
     if (tid == 0) {
-        const int u = u_total;
-        P.counters[C_USED] = u;
+        const int u = P.counters[C_USED];     // distinct seed pixels (counted by the seeding)
         P.counters[C_DUPLICATE] = N - P.counters[C_OUTSIDE] - u;
         P.counters[C_KEFF] = min(P.K, u);
         int status = 0;

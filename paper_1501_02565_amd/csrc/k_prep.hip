@@ -4,7 +4,8 @@
 // pixels, Sec. 3.1 of the paper): pixel (floor(x+0.5), floor(y+0.5)), decided
 // in double precision.  Matches outside the image are dropped; when several
 // matches fall on one pixel, the 64-bit atomic min on the packed key
-// (D = 0, label) keeps the lowest match index.  The tile holding a seed is
+// (D = 0, label) keeps the lowest match index, and the match that claims an
+// empty pixel counts it (usable matches = distinct seed pixels).  The tile holding a seed is
 // marked dirty for the geodesic transform.
 #include "epic_dev.h"
 
@@ -67,27 +68,37 @@ __global__ __launch_bounds__(256) void k_seed(const PairDev* __restrict__ pairs,
                             [&](int i) { return pairs[i].seed_block_base; });
     const PairDev& P = pairs[p];
     const int m = ((int)blockIdx.x - P.seed_block_base) * blockDim.x + threadIdx.x;
-    if (m >= P.N) return;
-    const double x = P.matches[4LL * m + 0];
-    const double y = P.matches[4LL * m + 1];
     int pix = -1;
-    if (isfinite(x) && isfinite(y)) {
-        const double fx = floor(x + 0.5), fy = floor(y + 0.5);
-        if (fx >= 0.0 && fy >= 0.0 && fx < (double)P.W && fy < (double)P.H) {
-            const int ix = (int)fx, iy = (int)fy;
-            pix = iy * P.W + ix;
-            if (run.precision == 1) {
-                P.keys[pix] = 0ull;                      // D = 0.0 (double bits)
-                atomicMin(&P.labels[pix], (u32)m);
-            } else {
-                atomicMin(&P.keys[pix], make_key(0.0f, (u32)m));
+    bool first = false;        // this match claimed an empty pixel
+    if (m < P.N) {
+        const double x = P.matches[4LL * m + 0];
+        const double y = P.matches[4LL * m + 1];
+        if (isfinite(x) && isfinite(y)) {
+            const double fx = floor(x + 0.5), fy = floor(y + 0.5);
+            if (fx >= 0.0 && fy >= 0.0 && fx < (double)P.W && fy < (double)P.H) {
+                const int ix = (int)fx, iy = (int)fy;
+                pix = iy * P.W + ix;
+                if (run.precision == 1) {
+                    P.keys[pix] = 0ull;                      // D = 0.0 (double bits)
+                    first = atomicMin(&P.labels[pix], (u32)m) == NO_LABEL;
+                } else {
+                    first = atomicMin(&P.keys[pix], make_key(0.0f, (u32)m)) == KEY_INF;
+                }
+                const int t = P.tile_base + (iy / run.tile_h) * P.tiles_x + ix / run.tile_w;
+                run.dirty[0][t] = 1u;
             }
-            const int t = P.tile_base + (iy / run.tile_h) * P.tiles_x + ix / run.tile_w;
-            run.dirty[0][t] = 1u;
         }
+        P.seed_pix[m] = pix;
     }
-    if (pix < 0) atomicAdd(&P.counters[C_OUTSIDE], 1);
-    P.seed_pix[m] = pix;
+    // the usable matches are the lowest-indexed ones of the distinct seed
+    // pixels, counted by their first claims; one counter update per
+    // wavefront (updates of one address from every thread serialise)
+    const u64 nf = __builtin_amdgcn_ballot_w64(first);
+    const u64 no = __builtin_amdgcn_ballot_w64(m < P.N && pix < 0);
+    if ((threadIdx.x & 63) == 0) {
+        if (nf) atomicAdd(&P.counters[C_USED], (int)__popcll(nf));
+        if (no) atomicAdd(&P.counters[C_OUTSIDE], (int)__popcll(no));
+    }
 }
 
 hipError_t launch_clear(const PairDev* d_pairs, const RunDev& run, int total_blocks, const PairDev* inline_host,

@@ -40,9 +40,12 @@ def ctx():
     c.close()
 
 
-def test_batch_equals_single(ctx):
+# up to 8 pairs the descriptor table travels in the first kernel's
+# arguments; 9 takes the upload path
+@pytest.mark.parametrize("n", [8, 9])
+def test_batch_equals_single(ctx, n):
     import torch
-    scs = _mixed()
+    scs = _mixed(n)
     probs = [_dev(sc) for sc in scs]
     flows = [f.cpu().numpy() for f in ctx.interp_batch(probs)]
     stats = [ctx.stats(i) for i in range(len(scs))]
@@ -58,11 +61,12 @@ def test_batch_equals_single(ctx):
     assert identical >= len(scs) - 1
 
 
-def test_graph_replay_matches_eager(ctx):
+@pytest.mark.parametrize("n", [5, 9])
+def test_graph_replay_matches_eager(ctx, n):
     """Replays of the captured graph, with eager work and synchronisation in
     between, reproduce the eager batch every time."""
     import torch
-    scs = _mixed(5)
+    scs = _mixed(n)
     probs = [_dev(sc) for sc in scs]
     eager = [f.clone() for f in ctx.interp_batch(probs)]
     torch.cuda.synchronize()
