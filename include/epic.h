@@ -60,7 +60,9 @@ typedef enum {
     EPIC_ERR_NO_MATCHES = -3,  /* no match lies in the image (flow is filled with NaN) */
     EPIC_ERR_HIP = -4,         /* a HIP runtime call failed                          */
     EPIC_ERR_BUDGET = -5,      /* request exceeds the memory budget it was given     */
-    EPIC_ERR_CAPACITY = -6,    /* a fixed-capacity device structure overflowed       */
+    EPIC_ERR_CAPACITY = -6,    /* a fixed-capacity device structure overflowed (the
+                                  match-graph hash, or, on the FP32 path, a match
+                                  whose cell touches more than 65535 others)       */
     EPIC_ERR_CONVERGENCE = -7  /* the geodesic transform hit its iteration bound     */
 } epic_status;
 

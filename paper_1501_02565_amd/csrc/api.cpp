@@ -73,7 +73,6 @@ size_t pair_bytes(int H, int W, int N, int precision) {
     b += 3 * align_up(4 * (size_t)N); // deg, fill, minin
     b += align_up(4 * ((size_t)N + 1));
     b += align_up(16 * cap);          // adjacency records
-    b += align_up(4 * cap);           // neighbour's lightest edge
     b += align_up(4 * (size_t)N);     // K-NN overflow list share
     b += align_up(24 * (size_t)N);    // params
     b += align_up(4 * C_NCOUNTERS);
@@ -346,7 +345,6 @@ int run_pairs(epic_ctx* c, const epic_request* reqs, int n, hipStream_t stream, 
         P.minin = reinterpret_cast<u32*>(take(4 * (size_t)r.N));
         P.row_ptr = reinterpret_cast<u32*>(take(4 * ((size_t)r.N + 1)));
         P.adj = reinterpret_cast<uint4*>(take(16 * cap));
-        P.nbmin = reinterpret_cast<u32*>(take(4 * cap));
         P.params = reinterpret_cast<float*>(take(24 * (size_t)r.N));
         P.counters = reinterpret_cast<int*>(take(4 * C_NCOUNTERS));
         if (c->opt.precision == 1) {

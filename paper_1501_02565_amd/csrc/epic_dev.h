@@ -78,8 +78,9 @@ struct PairDev {
     u32* row_ptr;           // N + 1
     u32* minin;             // N: float bits of the lightest incident edge
     uint4* adj;             // hash_cap: CSR edges (neighbour id, weight bits,
-                            //   neighbour's CSR start, neighbour's degree)
-    u32* nbmin;             // hash_cap: float bits of the neighbour's lightest edge
+                            //   neighbour's CSR start, neighbour's degree in the low
+                            //   16 bits and the high 16 bits of its lightest edge's
+                            //   float bits in the high 16; FP64 path: the degree alone)
     float* params;          // N*6
     int* counters;          // C_NCOUNTERS
     // FP64-everywhere path only (NULL otherwise)

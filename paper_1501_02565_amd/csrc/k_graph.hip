@@ -161,21 +161,30 @@ __global__ __launch_bounds__(EMIT_NT) void k_graph_emit(const PairDev* __restric
 __global__ __launch_bounds__(1024) void k_csr_scan(const PairDev* __restrict__ pairs, RunDev run) {
     const PairDev& P = pairs[blockIdx.x];
     __shared__ u32 s_wave[16];
+    __shared__ int s_big[16];
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int N = P.N;
     const int chunk = ((N + 1023) / 1024 + 3) & ~3;
     const int b = min(N, tid * chunk), e = min(N, b + chunk);
-    u32 sum = 0;
+    u32 sum = 0, dor = 0;    // dor: OR of the degrees (FP32 records hold 16 bits)
     if (e - b == chunk) {
         for (int m = b; m < e; m += 4) {
             const uint4 d = *reinterpret_cast<const uint4*>(P.deg + m);
             sum += d.x + d.y + d.z + d.w;
+            dor |= d.x | d.y | d.z | d.w;
         }
     } else {
-        for (int m = b; m < e; ++m) sum += P.deg[m];
+        for (int m = b; m < e; ++m) {
+            sum += P.deg[m];
+            dor |= P.deg[m];
+        }
     }
     const u32 incl = (u32)wave::incl_scan((int)sum);
-    if (lane == 63) s_wave[wid] = incl;
+    const bool big = wave::ballot(dor > 0xffffu) != 0ull;
+    if (lane == 63) {
+        s_wave[wid] = incl;
+        s_big[wid] = big ? 1 : 0;
+    }
     __syncthreads();
     u32 base = 0;
     for (int w = 0; w < wid; ++w) base += s_wave[w];
@@ -209,6 +218,9 @@ __global__ __launch_bounds__(1024) void k_csr_scan(const PairDev* __restrict__ p
         const u32 two_e = two_e_total;        // every edge counted at both ends
         P.counters[C_EDGES] = (int)(two_e / 2);
         if ((long long)two_e > (long long)P.hash_cap) P.counters[C_OVERFLOW] |= 1;
+        int any_big = 0;
+        for (int w = 0; w < 16; ++w) any_big |= s_big[w];
+        if (any_big && P.minin64 == nullptr) P.counters[C_OVERFLOW] |= 1;   // a degree above 65535
         if (P.counters[C_OVERFLOW]) status = -6;                       // EPIC_ERR_CAPACITY
         if (*run.error) status = -7;                                   // EPIC_ERR_CONVERGENCE
         P.counters[C_STATUS] = status;
@@ -231,8 +243,12 @@ __global__ __launch_bounds__(SLOT_BLOCK) void k_csr_scatter(const PairDev* __res
     const u32 pm = rm + atomicAdd(&P.fill[m], 1u);
     const u32 pn = rn + atomicAdd(&P.fill[n], 1u);
     const bool okm = pm < (u32)P.hash_cap, okn = pn < (u32)P.hash_cap;
-    if (okm) gstore(P.adj + pm, make_uint4(n, wb, rn, rn1 - rn));
-    if (okn) gstore(P.adj + pn, make_uint4(m, wb, rm, rm1 - rm));
+    // FP32 path: the neighbour's degree (below 2^16, checked by the scan) and
+    // its lightest edge truncated to 16 bits (a lower bound) share a word
+    const u32 wn = f64 ? rn1 - rn : (rn1 - rn) | (gmem(P.minin)[n] & 0xffff0000u);
+    const u32 wm = f64 ? rm1 - rm : (rm1 - rm) | (gmem(P.minin)[m] & 0xffff0000u);
+    if (okm) gstore(P.adj + pm, make_uint4(n, wb, rn, wn));
+    if (okn) gstore(P.adj + pn, make_uint4(m, wb, rm, wm));
     if (f64) {
         const u64 wd = gmem(P.hval64)[h];
         if (okm) {
@@ -243,9 +259,6 @@ __global__ __launch_bounds__(SLOT_BLOCK) void k_csr_scatter(const PairDev* __res
             gmem(P.adjw64)[pn] = dbits(wd);
             gmem(P.nbmin64)[pn] = gmem(P.minin64)[m];
         }
-    } else {
-        if (okm) gmem(P.nbmin)[pm] = gmem(P.minin)[n];
-        if (okn) P.nbmin[pn] = P.minin[m];
     }
     if (P.dbg_em) {
         const int e = atomicAdd(P.dbg_n_edges, 1);

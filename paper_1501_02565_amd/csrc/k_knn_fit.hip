@@ -291,8 +291,12 @@ __device__ __forceinline__ bool knn_fit_one(const PairDev& P, const RunDev& run,
                     cand[q] = du[q] + gmem(P.adjw64)[ei[q]];
                     nbm[q] = dbits(gmem(P.nbmin64)[ei[q]]);
                 } else {
+                    // the record carries the neighbour's lightest edge rounded
+                    // down to 16 bits: a lower bound, which is all the settle
+                    // test needs
                     cand[q] = du[q] + __uint_as_float(rec[q].y);
-                    nbm[q] = __uint_as_float(gmem(P.nbmin)[ei[q]]);
+                    nbm[q] = __uint_as_float(rec[q].w & 0xffff0000u);
+                    rec[q].w &= 0xffffu;
                 }
             }
             // find or claim each neighbour's table slot with one
