@@ -28,7 +28,7 @@ namespace epic {
 namespace {
 
 constexpr int TW = 32, TH = 16, PPT = 2, LW = TW + 2, LH = TH + 2, NL = LW * LH, HR = TW / PPT;
-enum : int { B_L = 1, B_R = 2, B_T = 4, B_B = 8, B_TL = 16, B_TR = 32, B_BL = 64, B_BR = 128 };
+enum : int { B_L = 1, B_R = 2, B_T = 4, B_B = 8, B_TL = 16, B_TR = 32, B_BL = 64, B_BR = 128, B_SELF = 256 };
 
 struct Lds64 {
     u64 dist[NL];            // double bits
@@ -46,7 +46,8 @@ __device__ __forceinline__ double step64(float cp, float cq, int k) {
 
 // PHASE 0: distances; PHASE 1: labels.
 template <int CONN, int PHASE>
-__device__ __forceinline__ int visit64(const PairDev& P, int tx, int ty, Lds64& S, int* error) {
+__device__ __forceinline__ int visit64(const PairDev& P, int tx, int ty, Lds64& S, int* error,
+                                       int soft_cap = 1 << 30) {
     constexpr int DX[8] = {1, -1, 0, 0, 1, -1, 1, -1};
     constexpr int DY[8] = {0, 0, 1, -1, 1, 1, -1, -1};
     const int tid = threadIdx.x;
@@ -88,6 +89,7 @@ __device__ __forceinline__ int visit64(const PairDev& P, int tx, int ty, Lds64& 
         orig[j] = PHASE == 0 ? S.dist[ch] : (u64)S.lab[ch];
     }
     const int round_cap = 4 * NL + 8;
+    bool unconverged = false;
     for (int round = 0;; ++round) {
         int changed = 0;
         auto sweep = [&](auto rows_c, auto fwd_c) {
@@ -157,6 +159,10 @@ __device__ __forceinline__ int visit64(const PairDev& P, int tx, int ty, Lds64& 
         if (__builtin_amdgcn_ballot_w64(changed != 0) != 0ull && (tid & 63) == 0) S.flag[round % 3] = 1;
         __syncthreads();
         if (S.flag[round % 3] == 0) break;
+        if (round + 1 >= soft_cap) {       // stop early; the next pass continues
+            unconverged = true;
+            break;
+        }
         if (round > round_cap) {
             if (tid == 0) atomicOr(error, 2);
             break;
@@ -179,7 +185,7 @@ __device__ __forceinline__ int visit64(const PairDev& P, int tx, int ty, Lds64& 
     }
     if (bm) atomicOr(&S.border, bm);
     __syncthreads();
-    const int border = S.border;
+    const int border = S.border | (unconverged ? B_SELF : 0);
     __syncthreads();
     return border;
 }
@@ -191,6 +197,7 @@ __device__ void mark64(const PairDev& P, const RunDev& run, int tx, int ty, int 
     auto mark = [&](int cx, int cy) {
         if (cx >= 0 && cy >= 0 && cx < nx && cy < ny) dirty[cy * nx + cx] = 1u;
     };
+    if (border & B_SELF) mark(tx, ty);
     if (border & B_L) mark(tx - 1, ty);
     if (border & B_R) mark(tx + 1, ty);
     if (border & B_T) mark(tx, ty - 1);
@@ -204,6 +211,11 @@ __device__ void mark64(const PairDev& P, const RunDev& run, int tx, int ty, int 
 }
 
 }  // namespace
+
+// Rounds after which a visit of a pass stops and marks its own tile for the
+// next pass (values only ever decrease, so stopping early never changes the
+// result; a pass no longer waits for its few slowest tiles).
+constexpr int kPass64Rounds = 5;
 
 template <int CONN, int PHASE>
 __global__ __launch_bounds__(256) void k_geo64_pass(const PairDev* __restrict__ pairs, RunDev run, int pass) {
@@ -221,7 +233,7 @@ __global__ __launch_bounds__(256) void k_geo64_pass(const PairDev* __restrict__ 
     const int tx = lt % P.tiles_x, ty = lt / P.tiles_x;
     __syncthreads();
     if (threadIdx.x == 0) dirty[tile] = 0u;
-    const int border = visit64<CONN, PHASE>(P, tx, ty, S, run.error);
+    const int border = visit64<CONN, PHASE>(P, tx, ty, S, run.error, kPass64Rounds);
     if (threadIdx.x == 0) {
         atomicAdd(&P.counters[C_TILE_VISITS], 1);
         if (border) {
