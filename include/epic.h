@@ -89,7 +89,8 @@ typedef struct epic_options {
                                0 (default) = automatic: the most passes
                                the last 8 finished calls needed, plus 1
                                when those needs differed (16 before the
-                               first; the FP64 path uses 16).  A
+                               first; the FP64 path keeps this per phase of
+                               its transform).  A
                                single-workgroup finisher completes the
                                transform if they do not reach the fixpoint,
                                so this only affects speed, never results     */

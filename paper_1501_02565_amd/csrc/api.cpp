@@ -104,9 +104,9 @@ struct epic_ctx {
     int* g_error = nullptr;
     int passes = 16;                    // geodesic passes launched per call (fixed budget)
     bool auto_passes = true;            // budget from the passes the last call needed
-    int* h_passes_used = nullptr;       // pinned, written by the transform's finisher
-    int used_hist[kAutoPassesHistory]{};  // needs seen at the last calls (0: none yet)
-    int used_next = 0;
+    int* h_passes_used = nullptr;       // pinned, 2 ints, written by the transform's finisher(s)
+    int used_hist[2][kAutoPassesHistory]{};  // needs seen at the last calls, per FP64 phase (0: none yet)
+    int used_next[2]{};
     // stage timing
     bool prof = false;
     hipEvent_t prof_ev[kProfRing][kStages + 1]{};
@@ -202,9 +202,9 @@ epic_ctx* epic_create(int device, size_t workspace_bytes, const epic_options* op
     for (int i = 0; i < kRing; ++i)
         if (hipEventCreateWithFlags(&c->ring_ev[i], hipEventDisableTiming) != hipSuccess)
             return fail("event creation failed");
-    if (hipHostMalloc((void**)&c->h_passes_used, sizeof(int), hipHostMallocDefault) != hipSuccess)
+    if (hipHostMalloc((void**)&c->h_passes_used, 2 * sizeof(int), hipHostMallocDefault) != hipSuccess)
         return fail("pinned counter allocation failed");
-    *c->h_passes_used = 0;
+    c->h_passes_used[0] = c->h_passes_used[1] = 0;
     c->g_error = reinterpret_cast<int*>(c->ws);
     c->g_any = reinterpret_cast<int*>(c->ws) + 256;         // kMaxPasses ints
     return c;
@@ -423,27 +423,28 @@ int run_pairs(epic_ctx* c, const epic_request* reqs, int n, hipStream_t stream, 
     // Automatic budget: the largest number of passes the recently finished
     // transforms needed (read when each call is issued; the value may come
     // from an older call while the last one is still running), plus one when
-    // those needs varied.  Any budget gives the same result: the finisher
-    // completes a transform the launched passes did not.  The FP64 path keeps
-    // a fixed budget.
-    int passes = c->passes;
-    if (c->auto_passes && c->opt.precision == 0) {
-        const int used = *reinterpret_cast<volatile int*>(c->h_passes_used);
-        if (used > 0) {
-            c->used_hist[c->used_next] = used;
-            c->used_next = (c->used_next + 1) % kAutoPassesHistory;
-            int hi = 0, lo = 1 << 30;
-            for (int h : c->used_hist)
-                if (h > 0) {
-                    hi = std::max(hi, h);
-                    lo = std::min(lo, h);
-                }
-            passes = std::min(kMaxPasses - 1, std::max(kAutoPassesMin, hi + (hi == lo ? 0 : 1)));
-        }
-    }
+    // those needs varied; the FP64 path keeps one history per phase.  Any
+    // budget gives the same result: the finisher completes a transform the
+    // launched passes did not.
+    auto budget = [&](int phase) {
+        int passes = c->passes;
+        if (!c->auto_passes) return passes;
+        const int used = reinterpret_cast<volatile int*>(c->h_passes_used)[phase];
+        if (used <= 0) return passes;
+        int* hist = c->used_hist[phase];
+        hist[c->used_next[phase]] = used;
+        c->used_next[phase] = (c->used_next[phase] + 1) % kAutoPassesHistory;
+        int hi = 0, lo = 1 << 30;
+        for (int k = 0; k < kAutoPassesHistory; ++k)
+            if (hist[k] > 0) {
+                hi = std::max(hi, hist[k]);
+                lo = std::min(lo, hist[k]);
+            }
+        return std::min(kMaxPasses - 1, std::max(kAutoPassesMin, hi + (hi == lo ? 0 : 1)));
+    };
     if (e == hipSuccess)
-        e = c->opt.precision == 1 ? launch_geodesic64(dd, run, c->passes, seed_blocks, stream)
-                                  : launch_geodesic(dd, run, tl.tw, tl.th, passes, stream);
+        e = c->opt.precision == 1 ? launch_geodesic64(dd, run, budget(0), budget(1), seed_blocks, stream)
+                                  : launch_geodesic(dd, run, tl.tw, tl.th, budget(0), stream);
     mark(2);
     if (e == hipSuccess) e = launch_graph_emit(dd, run, emit_blocks, stream);
     mark(3);

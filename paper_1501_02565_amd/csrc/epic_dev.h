@@ -141,7 +141,8 @@ struct RunDev {
     int* any;               // per pass: some tile border changed (kMaxPasses)
     int* any2;              // the same for the label phase of the FP64 path
     int* error;             // global error word
-    int* passes_used;       // host-visible: passes the last transform needed (may be null)
+    int* passes_used;       // host-visible, 2 ints: passes the last transform needed
+                            //   (FP64 path: distance phase, label phase); may be null
     int* ovf_list;          // K-NN sources to redo with a larger table
     int* ovf_count;
     int total_tiles;
@@ -190,7 +191,7 @@ hipError_t launch_clear(const PairDev* d_pairs, const RunDev& run, int total_blo
 hipError_t launch_seed(const PairDev* d_pairs, const RunDev& run, int total_blocks, hipStream_t s);
 hipError_t launch_geodesic(const PairDev* d_pairs, const RunDev& run, int tile_w, int tile_h,
                            int passes, hipStream_t s);
-hipError_t launch_geodesic64(const PairDev* d_pairs, const RunDev& run, int passes, int seed_blocks,
+hipError_t launch_geodesic64(const PairDev* d_pairs, const RunDev& run, int passes0, int passes1, int seed_blocks,
                              hipStream_t s);
 hipError_t launch_graph_emit(const PairDev* d_pairs, const RunDev& run, int total_blocks, hipStream_t s);
 hipError_t launch_csr_scan(const PairDev* d_pairs, const RunDev& run, hipStream_t s);

@@ -248,7 +248,14 @@ __global__ __launch_bounds__(256) void k_geo64_finish(const PairDev* __restrict_
     __shared__ Lds64 S;
     __shared__ int s_any;
     int* any = PHASE == 0 ? run.any : run.any2;
-    if (any[pass0 - 1] == 0) return;
+    // passes that changed something (a prefix): the phase needs one more,
+    // which is reported for the automatic budget of later calls
+    int changed = 0;
+    for (int q = 0; q < pass0; ++q) changed += any[q] != 0 ? 1 : 0;
+    if (any[pass0 - 1] == 0) {
+        if (threadIdx.x == 0 && run.passes_used) run.passes_used[PHASE] = changed + 1;
+        return;
+    }
     for (int pass = pass0; pass < pass0 + 65536; ++pass) {
         if (threadIdx.x == 0) s_any = 0;
         __syncthreads();
@@ -273,7 +280,11 @@ __global__ __launch_bounds__(256) void k_geo64_finish(const PairDev* __restrict_
             __syncthreads();
         }
         __syncthreads();
-        if (s_any == 0) return;
+        if (s_any == 0) {
+            if (threadIdx.x == 0 && run.passes_used) run.passes_used[PHASE] = changed + 1;
+            return;
+        }
+        ++changed;
         __syncthreads();
     }
     if (threadIdx.x == 0) atomicOr(run.error, 1);
@@ -301,24 +312,25 @@ __global__ __launch_bounds__(256) void k_geo64_reset(RunDev run) {
 
 namespace {
 template <int CONN>
-hipError_t launch64_t(const PairDev* d_pairs, const RunDev& run, int passes, int seed_blocks, hipStream_t s) {
+hipError_t launch64_t(const PairDev* d_pairs, const RunDev& run, int passes0, int passes1, int seed_blocks,
+                      hipStream_t s) {
     const int grid = 8 * ((run.total_tiles + 7) / 8);
-    for (int p = 0; p < passes; ++p)
+    for (int p = 0; p < passes0; ++p)
         hipLaunchKernelGGL((k_geo64_pass<CONN, 0>), dim3(grid), dim3(256), 0, s, d_pairs, run, p);
-    hipLaunchKernelGGL((k_geo64_finish<CONN, 0>), dim3(1), dim3(256), 0, s, d_pairs, run, passes);
+    hipLaunchKernelGGL((k_geo64_finish<CONN, 0>), dim3(1), dim3(256), 0, s, d_pairs, run, passes0);
     hipLaunchKernelGGL(k_geo64_reset, dim3((run.total_tiles + 255) / 256), dim3(256), 0, s, run);
     hipLaunchKernelGGL(k_geo64_seed_tiles, dim3(seed_blocks), dim3(256), 0, s, d_pairs, run);
-    for (int p = 0; p < passes; ++p)
+    for (int p = 0; p < passes1; ++p)
         hipLaunchKernelGGL((k_geo64_pass<CONN, 1>), dim3(grid), dim3(256), 0, s, d_pairs, run, p);
-    hipLaunchKernelGGL((k_geo64_finish<CONN, 1>), dim3(1), dim3(256), 0, s, d_pairs, run, passes);
+    hipLaunchKernelGGL((k_geo64_finish<CONN, 1>), dim3(1), dim3(256), 0, s, d_pairs, run, passes1);
     return hipGetLastError();
 }
 }  // namespace
 
-hipError_t launch_geodesic64(const PairDev* d_pairs, const RunDev& run, int passes, int seed_blocks,
+hipError_t launch_geodesic64(const PairDev* d_pairs, const RunDev& run, int passes0, int passes1, int seed_blocks,
                              hipStream_t s) {
-    return run.conn == 4 ? launch64_t<4>(d_pairs, run, passes, seed_blocks, s)
-                         : launch64_t<8>(d_pairs, run, passes, seed_blocks, s);
+    return run.conn == 4 ? launch64_t<4>(d_pairs, run, passes0, passes1, seed_blocks, s)
+                         : launch64_t<8>(d_pairs, run, passes0, passes1, seed_blocks, s);
 }
 
 }  // namespace epic
