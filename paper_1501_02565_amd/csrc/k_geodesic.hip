@@ -127,18 +127,31 @@ __device__ __forceinline__ int visit_tile(const PairDev& P, int tx, int ty,
     const int vx0 = MX == 0 ? 0 : max(0, -rx0), vy0 = MY == 0 ? 0 : max(0, -ry0);
     const int vx1 = min(RW, W - rx0), vy1 = min(RH, H - ry0);
 
-    for (int i = tid; i < NL; i += NT) {
+    // all of a thread's loads are issued before the first is stored, so the
+    // tile costs one memory round trip, not one per element
+    constexpr int LI = (NL + NT - 1) / NT;
+    u64 lk[LI];
+    float lc[LI];
+#pragma unroll
+    for (int it = 0; it < LI; ++it) {
+        const int i = tid + it * NT;
         const int ly = i / LW, lxx = i - ly * LW;
         const int gx = rx0 + lxx - 1, gy = ry0 + ly - 1;
-        u64 k = KEY_INF;
-        float c = 0.0f;
-        if (gx >= 0 && gy >= 0 && gx < W && gy < H) {
+        lk[it] = KEY_INF;
+        lc[it] = 0.0f;
+        if (i < NL && gx >= 0 && gy >= 0 && gx < W && gy < H) {
             const long long gi = (long long)gy * W + gx;
-            k = gmem(P.keys)[gi];
-            c = gmem(P.cost)[gi];
+            lk[it] = gmem(P.keys)[gi];
+            lc[it] = gmem(P.cost)[gi];
         }
-        S.key[i] = k;
-        S.cost[i] = c;
+    }
+#pragma unroll
+    for (int it = 0; it < LI; ++it) {
+        const int i = tid + it * NT;
+        if (i < NL) {
+            S.key[i] = lk[it];
+            S.cost[i] = lc[it];
+        }
     }
     if (tid < 3) S.flag[tid] = 0;
     for (int i = tid; i < LH; i += NT) S.rowchg[i] = -1;

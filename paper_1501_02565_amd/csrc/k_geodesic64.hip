@@ -53,21 +53,34 @@ __device__ __forceinline__ int visit64(const PairDev& P, int tx, int ty, Lds64& 
     const int tid = threadIdx.x;
     const int x0 = tx * TW, y0 = ty * TH, W = P.W, H = P.H;
     const int twe = min(TW, W - x0), the = min(TH, H - y0);
-    for (int i = tid; i < NL; i += 256) {
+    // all of a thread's loads are issued before the first is stored
+    constexpr int LI = (NL + 255) / 256;
+    u64 ld[LI];
+    u32 ll[LI];
+    float lc[LI];
+#pragma unroll
+    for (int it = 0; it < LI; ++it) {
+        const int i = tid + it * 256;
         const int ly = i / LW, lxx = i - ly * LW;
         const int gx = x0 + lxx - 1, gy = y0 + ly - 1;
-        u64 d = DOUBLE_INF_BITS;
-        u32 l = NO_LABEL;
-        float c = 0.0f;
-        if (gx >= 0 && gy >= 0 && gx < W && gy < H) {
+        ld[it] = DOUBLE_INF_BITS;
+        ll[it] = NO_LABEL;
+        lc[it] = 0.0f;
+        if (i < NL && gx >= 0 && gy >= 0 && gx < W && gy < H) {
             const long long gi = (long long)gy * W + gx;
-            d = P.keys[gi];
-            if (PHASE == 1) l = P.labels[gi];
-            c = P.cost[gi];
+            ld[it] = gmem(P.keys)[gi];
+            if (PHASE == 1) ll[it] = gmem(P.labels)[gi];
+            lc[it] = gmem(P.cost)[gi];
         }
-        S.dist[i] = d;
-        S.lab[i] = l;
-        S.cost[i] = c;
+    }
+#pragma unroll
+    for (int it = 0; it < LI; ++it) {
+        const int i = tid + it * 256;
+        if (i < NL) {
+            S.dist[i] = ld[it];
+            S.lab[i] = ll[it];
+            S.cost[i] = lc[it];
+        }
     }
     if (tid < 3) S.flag[tid] = 0;
     for (int i = tid; i < LH; i += 256) S.rowchg[i] = -1;
