@@ -361,10 +361,10 @@ template <int TW, int TH, int CONN, int NT>
 __global__ __launch_bounds__(NT) void k_geo_pass(const PairDev* __restrict__ pairs, RunDev run, int pass) {
     __shared__ TileLds<TW, TH> S;
     if (pass > 0 && run.any[pass - 1] == 0) return;          // converged
-    // XCD-aware: blocks b, b+8, b+16, ... share an XCD; give each XCD a
-    // contiguous run of tiles (rows of tiles are contiguous in the ids)
-    const int per_xcd = (run.total_tiles + 7) / 8;
-    const int tile = (int)(blockIdx.x % 8) * per_xcd + (int)(blockIdx.x / 8);
+    // block b takes tile b: consecutive tiles go to different XCDs (blocks
+    // are dealt to the 8 XCDs in turn), so the dirty tiles of a later pass,
+    // which cluster in space, are spread over all of them
+    const int tile = (int)blockIdx.x;
     if (tile >= run.total_tiles) return;
     u32* dirty = run.dirty[pass & 1];
     if (dirty[tile] == 0u) return;

@@ -235,8 +235,9 @@ __global__ __launch_bounds__(256) void k_geo64_pass(const PairDev* __restrict__ 
     __shared__ Lds64 S;
     int* any = PHASE == 0 ? run.any : run.any2;
     if (pass > 0 && any[pass - 1] == 0) return;
-    const int per_xcd = (run.total_tiles + 7) / 8;
-    const int tile = (int)(blockIdx.x % 8) * per_xcd + (int)(blockIdx.x / 8);
+    // block b takes tile b: the dirty tiles, which cluster in space, are
+    // spread over the XCDs (blocks are dealt to them in turn)
+    const int tile = (int)blockIdx.x;
     if (tile >= run.total_tiles) return;
     u32* dirty = run.dirty[pass & 1];
     if (dirty[tile] == 0u) return;
