@@ -90,7 +90,8 @@ typedef struct epic_options {
                                the last 8 finished calls needed, plus 1
                                when those needs differed (16 before the
                                first; the FP64 path keeps this per phase of
-                               its transform).  A
+                               its transform and launches at least 16 when
+                               the needs differed).  A
                                single-workgroup finisher completes the
                                transform if they do not reach the fixpoint,
                                so this only affects speed, never results     */

@@ -440,7 +440,10 @@ int run_pairs(epic_ctx* c, const epic_request* reqs, int n, hipStream_t stream, 
                 hi = std::max(hi, hist[k]);
                 lo = std::min(lo, hist[k]);
             }
-        return std::min(kMaxPasses - 1, std::max(kAutoPassesMin, hi + (hi == lo ? 0 : 1)));
+        // FP64: when the needs vary, never fewer than the starting budget (its
+        // single-workgroup finisher costs far more than idle passes)
+        const int floor_ = (c->opt.precision == 1 && hi != lo) ? kAutoPassesStart : kAutoPassesMin;
+        return std::min(kMaxPasses - 1, std::max(floor_, hi + (hi == lo ? 0 : 1)));
     };
     if (e == hipSuccess)
         e = c->opt.precision == 1 ? launch_geodesic64(dd, run, budget(0), budget(1), seed_blocks, stream)
