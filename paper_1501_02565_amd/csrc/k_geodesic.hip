@@ -11,7 +11,8 @@
 //   * The image is cut into TW x TH tiles.  A tile is dirty when a pixel of
 //     its 1-pixel halo (or a seed inside it) changed since its last visit.
 //   * One pass is one launch over all tiles.  A dirty tile is loaded with
-//     its halo into LDS, relaxed to a local fixpoint, written back, and the
+//     its halo into LDS, relaxed to a local fixpoint (or for a capped number
+//     of rounds, after which it marks itself dirty), written back, and the
 //     neighbours behind every changed border are marked dirty for the next
 //     pass.  Passes communicate only through memory across launches, so
 //     plain cached loads and stores are coherent; no workgroup waits for
@@ -24,9 +25,11 @@
 //     integer min: any relaxation order reaches the same fixpoint D (the
 //     minimum over paths of the left-fold float sums); labels agree with the
 //     lexicographic optimum except where rounded sums tie exactly.
-//   * Blocks are mapped to tiles so that each XCD (blocks are dealt to the
-//     8 XCDs round-robin) works on a contiguous band of tile rows; most halo
-//     traffic then stays in one XCD's L2.
+//   * In the first pass (every tile busy) blocks are mapped to tiles so that
+//     each XCD (blocks are dealt to the 8 XCDs round-robin) works on a
+//     contiguous band of tile rows, keeping most halo traffic in one XCD's
+//     L2; the later passes map block b to tile b, which spreads their
+//     spatially clustered dirty tiles over all XCDs.
 //   * A fixed number of passes is launched.  If the last one still changed
 //     a border, a single-workgroup finisher continues the same passes until
 //     the fixpoint, so the result never depends on the pass budget.
