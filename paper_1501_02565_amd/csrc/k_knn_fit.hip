@@ -9,7 +9,7 @@
 //     with tentative d(v) is final once d(v) <= dmin + lightest_edge(v),
 //     where dmin is the smallest tentative distance on the frontier (no
 //     unsettled node can still lower it).  The edges of all nodes settled in
-//     a step are relaxed together, one lane per edge, in windows of 128
+//     a step are relaxed together, one lane per edge, in windows of 64
 //     edges: a prefix sum of the settled nodes' degrees places their edge
 //     segments, a prefix maximum over marked segment starts tells every lane
 //     whose edge it holds.  Every CSR record carries the neighbour's CSR
@@ -59,7 +59,7 @@ __device__ __forceinline__ void lds_order() { __asm__ __volatile__("" ::: "memor
 template <int VCAP, bool F64>
 struct KnnLds {
     static constexpr int HCAP = 2 * VCAP;
-    static constexpr int TW = 128;                // edges per relaxation window
+    static constexpr int TW = 64;                 // edges per relaxation window (one per lane)
     using DT = typename std::conditional<F64, u64, u32>::type;     // distance bits
     using RT = typename std::conditional<F64, double, float>::type;
     alignas(16) DT dm[2 * VCAP];  // entry e: tentative distance (2e), lightest edge (2e + 1)
