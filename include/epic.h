@@ -31,8 +31,9 @@
  *     allocated once, in epic_create; no call allocates device memory.
  *   - Coordinates: pixel (x = column, y = row), integer pixel centres,
  *     origin at the top-left pixel.  Row-major images.
- *   - cost: H*W float32, every value finite and > 0 (not checked on the
- *     device; other values give undefined results).
+ *   - cost: H*W float32, every value finite and > 0 (checked on the device
+ *     only with the debug_validate option; without it other values give
+ *     undefined results).
  *   - matches: N*4 float32 rows (x, y, x', y').  A match is placed on the
  *     pixel floor(x+0.5), floor(y+0.5) (matches are pixels, Sec. 3.1);
  *     matches outside the image are dropped, and when several matches fall
@@ -63,7 +64,9 @@ typedef enum {
     EPIC_ERR_CAPACITY = -6,    /* a fixed-capacity device structure overflowed (the
                                   match-graph hash, or, on the FP32 path, a match
                                   whose cell touches more than 65535 others)       */
-    EPIC_ERR_CONVERGENCE = -7  /* the geodesic transform hit its iteration bound     */
+    EPIC_ERR_CONVERGENCE = -7, /* the geodesic transform hit its iteration bound     */
+    EPIC_ERR_COST = -8         /* debug_validate found a cost value that is not
+                                  finite and > 0 (the flow is filled with NaN)     */
 } epic_status;
 
 /* Options; NULL selects the defaults shown. */
@@ -95,6 +98,13 @@ typedef struct epic_options {
                                single-workgroup finisher completes the
                                transform if they do not reach the fixpoint,
                                so this only affects speed, never results     */
+    int   debug_validate;   /* 0 (default); 1: every call first checks on the
+                               device that each cost value is finite and > 0
+                               (one extra read of the cost map).  A pair whose
+                               map fails is not interpolated: it reports
+                               EPIC_ERR_COST and n_bad_cost in epic_stats and
+                               its flow is filled with NaN; the other pairs of
+                               a batch are unaffected                          */
 } epic_options;
 
 typedef struct epic_ctx epic_ctx;
@@ -171,6 +181,8 @@ typedef struct epic_stats {
     int n_degenerate;      /* LA fits that fell back to NW                  */
     int n_fp64_fits;       /* affine fits solved in FP64                    */
     int tile_visits;       /* tiles processed by the geodesic transform     */
+    int n_bad_cost;        /* cost values not finite and > 0 (counted only
+                              with debug_validate)                          */
 } epic_stats;
 int epic_get_stats(epic_ctx* ctx, int pair, epic_stats* out);
 

@@ -15,7 +15,7 @@ import ctypes
 
 from . import _lib
 from ._lib import (LA, NW, OK, EpicError, ERR_ARG, ERR_BUDGET, ERR_CAPACITY,  # noqa: F401
-                   ERR_CONVERGENCE, ERR_HIP, ERR_NO_MATCHES, ERR_WORKSPACE)
+                   ERR_CONVERGENCE, ERR_COST, ERR_HIP, ERR_NO_MATCHES, ERR_WORKSPACE)
 
 __all__ = ["Context", "workspace_bytes", "LA", "NW", "EpicError"]
 
@@ -54,13 +54,15 @@ class Context:
     """Owns one epic_ctx: a device workspace allocated once (``workspace``
     bytes, default enough for a 2048 x 1080 image with 40000 matches).
     ``passes`` is the geodesic pass budget per call (0 = automatic, from the
-    passes the recent calls needed); it never changes results."""
+    passes the recent calls needed); it never changes results.
+    ``debug_validate`` makes every call check the cost map on the device
+    (finite and > 0); a pair that fails reports ERR_COST in its stats."""
 
     def __init__(self, device: int = 0, workspace: int | None = None, *,
                  connectivity: int = 8, la_weight_power: int = 2,
                  precision: int = 0, fp64_route: float = 1e-3,
                  degenerate_tau: float = 1e-9, tile: tuple[int, int] = (32, 16),
-                 passes: int = 0):
+                 passes: int = 0, debug_validate: bool = False):
         torch = _torch()
         L = _lib.load()
         self.device = int(device)
@@ -69,7 +71,7 @@ class Context:
         self.workspace = int(workspace)
         self.options = _lib.Options(connectivity, la_weight_power, precision,
                                     fp64_route, degenerate_tau, tile[0], tile[1],
-                                    passes)
+                                    passes, int(bool(debug_validate)))
         torch.cuda.init()
         with torch.cuda.device(self.device):
             self._ctx = L.epic_create(self.device, self.workspace,

@@ -127,6 +127,7 @@ const char* epic_strerror(int s) {
         case EPIC_ERR_BUDGET: return "request exceeds its memory budget";
         case EPIC_ERR_CAPACITY: return "fixed-capacity device structure overflowed";
         case EPIC_ERR_CONVERGENCE: return "geodesic transform did not converge within its bound";
+        case EPIC_ERR_COST: return "cost map holds a value that is not finite and > 0";
         default: return "unknown status";
     }
 }
@@ -172,6 +173,7 @@ epic_ctx* epic_create(int device, size_t workspace_bytes, const epic_options* op
     o.tile_w = 32;
     o.tile_h = 16;
     o.geo_passes = 0;
+    o.debug_validate = 0;
     if (opts) {
         o = *opts;
         if (o.connectivity != 4) o.connectivity = 8;
@@ -184,6 +186,7 @@ epic_ctx* epic_create(int device, size_t workspace_bytes, const epic_options* op
         o.tile_h = t.th;
         if (o.geo_passes < 0) o.geo_passes = 0;
         if (o.geo_passes > kMaxPasses - 1) o.geo_passes = kMaxPasses - 1;
+        if (o.debug_validate != 1) o.debug_validate = 0;
     }
     c->auto_passes = o.geo_passes == 0;
     c->passes = c->auto_passes ? kAutoPassesStart : o.geo_passes;
@@ -418,6 +421,9 @@ int run_pairs(epic_ctx* c, const epic_request* reqs, int n, hipStream_t stream, 
     };
     if (e == hipSuccess) e = launch_clear(dd, run, init_blocks, inline_desc ? hd : nullptr, n, stream);
     mark(0);
+    // a pair whose cost map fails the check is not seeded (it then takes the
+    // path of a pair without usable matches)
+    if (e == hipSuccess && c->opt.debug_validate) e = launch_check_cost(dd, run, pix_blocks, stream);
     if (e == hipSuccess) e = launch_seed(dd, run, seed_blocks, stream);
     mark(1);
     // Automatic budget: the largest number of passes the recently finished
@@ -620,6 +626,7 @@ int epic_get_stats(epic_ctx* ctx, int pair, epic_stats* out) {
     out->n_degenerate = cnt[C_DEGENERATE];
     out->n_fp64_fits = cnt[C_FP64];
     out->tile_visits = cnt[C_TILE_VISITS];
+    out->n_bad_cost = cnt[C_BADCOST];
     return EPIC_OK;
 }
 

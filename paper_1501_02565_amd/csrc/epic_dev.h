@@ -43,6 +43,7 @@ enum Counter {
     C_KEFF = 7,        // K clamped to the usable matches
     C_OVERFLOW = 8,    // bit 0 graph hash, bit 1 Dijkstra visited table
     C_TILE_VISITS = 9,
+    C_BADCOST = 10,    // cost values not finite and > 0 (checked on request)
     C_NCOUNTERS = 16
 };
 
@@ -189,6 +190,7 @@ constexpr int SLOT_BLOCK = 256;     // hash slots per block
 hipError_t launch_clear(const PairDev* d_pairs, const RunDev& run, int total_blocks, const PairDev* inline_host,
                         int n_inline, hipStream_t s);
 hipError_t launch_seed(const PairDev* d_pairs, const RunDev& run, int total_blocks, hipStream_t s);
+hipError_t launch_check_cost(const PairDev* d_pairs, const RunDev& run, int total_blocks, hipStream_t s);
 hipError_t launch_geodesic(const PairDev* d_pairs, const RunDev& run, int tile_w, int tile_h,
                            int passes, hipStream_t s);
 hipError_t launch_geodesic64(const PairDev* d_pairs, const RunDev& run, int passes0, int passes1, int seed_blocks,

@@ -223,6 +223,10 @@ __global__ __launch_bounds__(1024) void k_csr_scan(const PairDev* __restrict__ p
         if (any_big && P.minin64 == nullptr) P.counters[C_OVERFLOW] |= 1;   // a degree above 65535
         if (P.counters[C_OVERFLOW]) status = -6;                       // EPIC_ERR_CAPACITY
         if (*run.error) status = -7;                                   // EPIC_ERR_CONVERGENCE
+        if (P.counters[C_BADCOST]) {                                   // EPIC_ERR_COST: not seeded
+            status = -8;
+            P.counters[C_DUPLICATE] = 0;
+        }
         P.counters[C_STATUS] = status;
     }
 }

@@ -1,4 +1,5 @@
-// k_prep.hip -- per-call workspace clearing and match seeding.
+// k_prep.hip -- per-call workspace clearing, the optional check of the cost
+// map, and match seeding.
 //
 // Seeding places every match on the pixel that contains it (matches are
 // pixels, Sec. 3.1 of the paper): pixel (floor(x+0.5), floor(y+0.5)), decided
@@ -68,12 +69,13 @@ __global__ __launch_bounds__(256) void k_seed(const PairDev* __restrict__ pairs,
                             [&](int i) { return pairs[i].seed_block_base; });
     const PairDev& P = pairs[p];
     const int m = ((int)blockIdx.x - P.seed_block_base) * blockDim.x + threadIdx.x;
+    const bool rejected = P.counters[C_BADCOST] != 0;   // the cost map failed its check
     int pix = -1;
     bool first = false;        // this match claimed an empty pixel
     if (m < P.N) {
         const double x = P.matches[4LL * m + 0];
         const double y = P.matches[4LL * m + 1];
-        if (isfinite(x) && isfinite(y)) {
+        if (!rejected && isfinite(x) && isfinite(y)) {
             const double fx = floor(x + 0.5), fy = floor(y + 0.5);
             if (fx >= 0.0 && fy >= 0.0 && fx < (double)P.W && fy < (double)P.H) {
                 const int ix = (int)fx, iy = (int)fy;
@@ -94,11 +96,32 @@ __global__ __launch_bounds__(256) void k_seed(const PairDev* __restrict__ pairs,
     // pixels, counted by their first claims; one counter update per
     // wavefront (updates of one address from every thread serialise)
     const u64 nf = __builtin_amdgcn_ballot_w64(first);
-    const u64 no = __builtin_amdgcn_ballot_w64(m < P.N && pix < 0);
+    const u64 no = __builtin_amdgcn_ballot_w64(m < P.N && pix < 0 && !rejected);
     if ((threadIdx.x & 63) == 0) {
         if (nf) atomicAdd(&P.counters[C_USED], (int)__popcll(nf));
         if (no) atomicAdd(&P.counters[C_OUTSIDE], (int)__popcll(no));
     }
+}
+
+// Optional check of the cost map: counts the values that are not finite and
+// > 0 (one counter update per wavefront).  A nonzero count makes the seeding
+// place no match of that pair.
+__global__ __launch_bounds__(PIX_BLOCK) void k_check_cost(const PairDev* __restrict__ pairs, RunDev run) {
+    const int p = find_pair(run.npairs, (int)blockIdx.x, [&](int i) { return pairs[i].pix_block_base; });
+    const PairDev& P = pairs[p];
+    const long long i = (long long)((int)blockIdx.x - P.pix_block_base) * PIX_BLOCK + threadIdx.x;
+    bool bad = false;
+    if (i < (long long)P.W * P.H) {
+        const float c = gmem(P.cost)[i];
+        bad = !(c > 0.0f && c <= 3.402823466e38f);   // NaN, zero, negative or infinite
+    }
+    const u64 b = __builtin_amdgcn_ballot_w64(bad);
+    if ((threadIdx.x & 63) == 0 && b) atomicAdd(&P.counters[C_BADCOST], (int)__popcll(b));
+}
+
+hipError_t launch_check_cost(const PairDev* d_pairs, const RunDev& run, int total_blocks, hipStream_t s) {
+    hipLaunchKernelGGL(k_check_cost, dim3(total_blocks), dim3(PIX_BLOCK), 0, s, d_pairs, run);
+    return hipGetLastError();
 }
 
 hipError_t launch_clear(const PairDev* d_pairs, const RunDev& run, int total_blocks, const PairDev* inline_host,

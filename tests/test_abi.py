@@ -86,10 +86,36 @@ def test_workspace_bytes(lib):
 
 
 def test_strerror(lib):
-    for code in range(-7, 1):
+    for code in range(-8, 1):
         s = lib.epic_strerror(code).decode()
         assert s and s != "unknown status"
     assert lib.epic_strerror(42).decode() == "unknown status"
+
+
+def _struct_fields(name):
+    """Field names of `typedef struct ... { ... } name;` in the header, in order."""
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    body = re.search(r"typedef struct \w*\s*\{([^}]*)\}\s*" + name + r"\s*;", text).group(1)
+    names = []
+    for decl in body.split(";"):
+        decl = decl.strip()
+        if decl:
+            names += [v.strip().lstrip("*") for v in decl.split(None, 1)[1].replace("*", " ").split(",")]
+    return [n.split()[-1] for n in names]
+
+
+def test_binding_structs_follow_the_header():
+    from paper_1501_02565_amd import _lib
+    for cname, cls in (("epic_options", _lib.Options), ("epic_stats", _lib.Stats),
+                       ("epic_request", _lib.Request)):
+        assert _struct_fields(cname) == [f for f, _ in cls._fields_], cname
+
+
+def test_status_codes_follow_the_header():
+    from paper_1501_02565_amd import _lib
+    text = open(HEADER).read()
+    for name, value in re.findall(r"EPIC_(OK|ERR_[A-Z_]+)\s*=\s*(-?\d+)", text):
+        assert getattr(_lib, name) == int(value), name
 
 
 def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):

@@ -1,0 +1,90 @@
+"""GPU: the debug_validate option.  A context created with it checks every
+cost map on the device (finite and > 0).  A valid map gives exactly the
+result of a context without the check; a map with bad values reports
+ERR_COST with their count and a NaN flow, leaves the other pairs of a batch
+untouched, and leaves the context usable.  Needs an MI355X."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+from scenes import random_case
+
+pytestmark = pytest.mark.gpu
+
+
+def _announce(name):
+    print(f"\n[case] {name}", flush=True)
+
+
+def _dev(sc):
+    import torch
+    return (torch.from_numpy(np.ascontiguousarray(sc.cost)).cuda(),
+            torch.from_numpy(np.ascontiguousarray(sc.matches)).cuda())
+
+
+def _spoil(cost):
+    """A copy of `cost` with a zero, a negative, a NaN and both infinities."""
+    bad = cost.copy()
+    H, W = bad.shape
+    spots = [(0, 0), (H // 2, W // 3), (H - 1, W - 1), (1, W - 2), (H // 3, 1)]
+    for (y, x), v in zip(spots, [0.0, -0.25, np.nan, np.inf, -np.inf]):
+        bad[y, x] = v
+    return bad, len(set(spots))
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_validation_flags_bad_costs(precision):
+    import torch
+    import paper_1501_02565_amd as epic
+    sc = random_case(70, 90, 60, seed=41, K=8)
+    bad_np, n_bad = _spoil(sc.cost)
+    cost, matches = _dev(sc)
+    bad = torch.from_numpy(bad_np).cuda()
+    with epic.Context(0, precision=precision) as plain, \
+            epic.Context(0, precision=precision, debug_validate=True) as chk:
+        _announce(f"{sc.name} precision={precision} valid cost")
+        ref = plain.interp(cost, matches, K=8, a=1.0, mode=epic.LA).cpu().numpy()
+        out = chk.interp(cost, matches, K=8, a=1.0, mode=epic.LA).cpu().numpy()
+        st = chk.stats(0)
+        assert st["status"] == 0 and st["n_bad_cost"] == 0, st
+        np.testing.assert_array_equal(out, ref)
+
+        _announce(f"{sc.name} precision={precision} {n_bad} bad cost values")
+        out = chk.interp(bad, matches, K=8, a=1.0, mode=epic.LA).cpu().numpy()
+        st = chk.stats(0)
+        print(st, flush=True)
+        assert st["status"] == epic.ERR_COST and st["n_bad_cost"] == n_bad, st
+        assert st["n_used"] == 0 and st["n_outside"] == 0 and st["n_duplicate"] == 0, st
+        assert np.isnan(out).all()
+
+        _announce(f"{sc.name} precision={precision} valid cost after a rejected one")
+        out = chk.interp(cost, matches, K=8, a=1.0, mode=epic.LA).cpu().numpy()
+        assert chk.stats(0)["status"] == 0
+        np.testing.assert_array_equal(out, ref)
+
+
+def test_validation_in_a_batch():
+    """One pair of a batch with a bad map: only that pair is rejected."""
+    import torch
+    import paper_1501_02565_amd as epic
+    scs = [random_case(40 + 9 * i, 50 + 13 * i, 30 + 10 * i, seed=50 + i, K=6) for i in range(3)]
+    bad_np, n_bad = _spoil(scs[1].cost)
+    probs = []
+    for i, sc in enumerate(scs):
+        cost, matches = _dev(sc)
+        if i == 1:
+            cost = torch.from_numpy(bad_np).cuda()
+        probs.append((cost, matches, 6, 1.0, epic.LA))
+    _announce("batch of 3, pair 1 with bad cost values")
+    with epic.Context(0) as plain, epic.Context(0, debug_validate=True) as chk:
+        flows = [f.cpu().numpy() for f in chk.interp_batch(probs)]
+        stats = [chk.stats(i) for i in range(3)]
+        print(stats, flush=True)
+        assert stats[1]["status"] == epic.ERR_COST and stats[1]["n_bad_cost"] == n_bad
+        assert np.isnan(flows[1]).all()
+        for i in (0, 2):
+            assert stats[i]["status"] == 0 and stats[i]["n_bad_cost"] == 0, stats[i]
+            cost, matches, K, a, mode = probs[i]
+            ref = plain.interp(cost, matches, K=K, a=a, mode=mode).cpu().numpy()
+            np.testing.assert_array_equal(flows[i], ref)
