@@ -47,21 +47,19 @@ __device__ __forceinline__ u32 hash_slot(u64 key, int shift) {
 namespace {
 // Inserts (key, weight) into the pair's global hash with an atomic min on
 // the weight; the first insertion of a key raises both endpoints' degree.
+// Each probe is one compare-and-swap (it claims an empty slot or returns
+// the key already there), so a slot costs one round trip, not a load and a
+// swap.
 template <bool F64>
 __device__ __forceinline__ void global_insert(const PairDev& P, u64 hk, u64 wb) {
     const u32 mask = (u32)P.hash_cap - 1u;
     u32 h = hash_slot(hk, P.hash_shift);
     for (int probe = 0; probe < P.hash_cap; ++probe) {
-        u64 cur = P.hkey[h];
+        u64 cur = atomicCAS(&P.hkey[h], HASH_EMPTY, hk);
         if (cur == HASH_EMPTY) {
-            const u64 prev = atomicCAS(&P.hkey[h], HASH_EMPTY, hk);
-            if (prev == HASH_EMPTY) {
-                atomicAdd(&P.deg[(u32)(hk >> 32)], 1u);
-                atomicAdd(&P.deg[(u32)hk], 1u);
-                cur = hk;
-            } else {
-                cur = prev;
-            }
+            atomicAdd(&P.deg[(u32)(hk >> 32)], 1u);
+            atomicAdd(&P.deg[(u32)hk], 1u);
+            cur = hk;
         }
         if (cur == hk) {
             const u32 m = (u32)(hk >> 32), n = (u32)hk;
@@ -86,19 +84,24 @@ __device__ __forceinline__ void global_insert(const PairDev& P, u64 hk, u64 wb) 
 // first reduced in a block-local LDS hash (adjacent pixels mostly share their
 // pair of cells), then each distinct edge goes to the global hash once per
 // block; a compact tile meets far fewer cell boundaries than a pixel strip of
-// the same size, so few edges reach the global hash per block.
+// the same size, so few edges reach the global hash per block.  The occupied
+// local slots are listed first, so the block's inserts run on distinct
+// threads at once instead of in sequence on the threads that own several.
 template <int CONN, bool F64>
 __global__ __launch_bounds__(EMIT_NT) void k_graph_emit(const PairDev* __restrict__ pairs, RunDev run) {
     constexpr int LCAP = EMIT_LCAP;                   // block-local edge slots (overflow goes global)
     using V = typename std::conditional<F64, u64, u32>::type;
     __shared__ u64 lkey[LCAP];
     __shared__ V lval[LCAP];
+    __shared__ unsigned short s_list[LCAP];
+    __shared__ int s_cnt;
     const int p = find_pair(run.npairs, (int)blockIdx.x, [&](int i) { return pairs[i].emit_block_base; });
     const PairDev& P = pairs[p];
     for (int i = threadIdx.x; i < LCAP; i += EMIT_NT) {
         lkey[i] = HASH_EMPTY;
         lval[i] = F64 ? (V)DOUBLE_INF_BITS : (V)FLOAT_INF_BITS;
     }
+    if (threadIdx.x == 0) s_cnt = 0;
     __syncthreads();
     const int W = P.W, H = P.H;
     const int tb = (int)blockIdx.x - P.emit_block_base, etx = (W + EMIT_TW - 1) / EMIT_TW;
@@ -151,7 +154,13 @@ __global__ __launch_bounds__(EMIT_NT) void k_graph_emit(const PairDev* __restric
     }
     __syncthreads();
     for (int j = threadIdx.x; j < LCAP; j += EMIT_NT)
-        if (lkey[j] != HASH_EMPTY) global_insert<F64>(P, lkey[j], lval[j]);
+        if (lkey[j] != HASH_EMPTY) s_list[atomicAdd(&s_cnt, 1)] = (unsigned short)j;
+    __syncthreads();
+    const int cnt = s_cnt;
+    for (int k = threadIdx.x; k < cnt; k += EMIT_NT) {
+        const int j = s_list[k];
+        global_insert<F64>(P, lkey[j], lval[j]);
+    }
 }
 
 // One workgroup of 1024 threads per pair.  Each thread sums a contiguous
