@@ -90,6 +90,8 @@ __device__ __forceinline__ void global_insert(const PairDev& P, u64 hk, u64 wb) 
 template <int CONN, bool F64>
 __global__ __launch_bounds__(EMIT_NT) void k_graph_emit(const PairDev* __restrict__ pairs, RunDev run) {
     constexpr int LCAP = EMIT_LCAP;                   // block-local edge slots (overflow goes global)
+    constexpr int LBITS = __builtin_ctz(LCAP);
+    static_assert((1 << LBITS) == LCAP && LCAP <= 65536, "local hash: a power of two, 16-bit slot list");
     using V = typename std::conditional<F64, u64, u32>::type;
     __shared__ u64 lkey[LCAP];
     __shared__ V lval[LCAP];
@@ -109,35 +111,49 @@ __global__ __launch_bounds__(EMIT_NT) void k_graph_emit(const PairDev* __restric
     const int y = (tb / etx) * EMIT_TH + (int)threadIdx.x / EMIT_TW;
     const long long i = (long long)y * W + x;
     if (x < W && y < H) {
+        // forward half-neighbourhood: (1,0), (0,1), (1,1), (-1,1); all loads
+        // are issued before any is used (outside neighbours read the pixel
+        // itself and are skipped)
+        constexpr int HX[4] = {1, 0, 1, -1};
+        constexpr int HY[4] = {0, 1, 1, 1};
+        constexpr int NK = CONN == 8 ? 4 : 2;
         const u64 kp = gmem(P.keys)[i];
+        const float cp = gmem(P.cost)[i];
         const u32 lp = F64 ? gmem(P.labels)[i] : key_label(kp);
-        if (lp != NO_LABEL) {
-            const float cp = gmem(P.cost)[i];
-            // forward half-neighbourhood: (1,0), (0,1), (1,1), (-1,1)
-            constexpr int HX[4] = {1, 0, 1, -1};
-            constexpr int HY[4] = {0, 1, 1, 1};
+        u64 kqa[NK];
+        float cqa[NK];
+        u32 lqa[NK];
+        bool in[NK];
 #pragma unroll
-            for (int k = 0; k < (CONN == 8 ? 4 : 2); ++k) {
-                const int qx = x + HX[k], qy = y + HY[k];
-                if (qx < 0 || qx >= W || qy >= H) continue;
-                const long long qi = (long long)qy * W + qx;
-                const u64 kq = gmem(P.keys)[qi];
-                const u32 lq = F64 ? gmem(P.labels)[qi] : key_label(kq);
+        for (int k = 0; k < NK; ++k) {
+            const int qx = x + HX[k], qy = y + HY[k];
+            in[k] = qx >= 0 && qx < W && qy < H;
+            const long long qi = in[k] ? (long long)qy * W + qx : i;
+            kqa[k] = gmem(P.keys)[qi];
+            cqa[k] = gmem(P.cost)[qi];
+            if (F64) lqa[k] = gmem(P.labels)[qi];
+        }
+        if (lp != NO_LABEL) {
+#pragma unroll
+            for (int k = 0; k < NK; ++k) {
+                if (!in[k]) continue;
+                const u64 kq = kqa[k];
+                const u32 lq = F64 ? lqa[k] : key_label(kq);
                 if (lq == lp || lq == NO_LABEL) continue;
                 V wb;
                 if (F64) {
                     // (D(p) + step) + D(q), each operation rounded (no fused multiply-add)
-                    const double half = __dmul_rn(0.5, __dadd_rn((double)cp, (double)gmem(P.cost)[qi]));
+                    const double half = __dmul_rn(0.5, __dadd_rn((double)cp, (double)cqa[k]));
                     const double step = k < 2 ? half : __dmul_rn(1.4142135623730951, half);
                     wb = (V)bitsd(__dadd_rn(__dadd_rn(dbits(kp), step), dbits(kq)));
                 } else {
                     const float len = (k < 2) ? 1.0f : 1.41421356237309515f;
-                    const float w = len * (0.5f * (cp + gmem(P.cost)[qi]));
+                    const float w = len * (0.5f * (cp + cqa[k]));
                     wb = (V)__float_as_uint((key_dist(kp) + w) + key_dist(kq));
                 }
                 const u32 m = min(lp, lq), n = max(lp, lq);
                 const u64 hk = ((u64)m << 32) | n;
-                u32 h = (u32)(((hk ^ (hk >> 29)) * 0x9e3779b97f4a7c15ull) >> 54) & (LCAP - 1);
+                u32 h = (u32)(((hk ^ (hk >> 29)) * 0x9e3779b97f4a7c15ull) >> (64 - LBITS));
                 bool done = false;
                 for (int probe = 0; probe < LCAP; ++probe) {
                     const u64 prev = atomicCAS(&lkey[h], HASH_EMPTY, hk);
