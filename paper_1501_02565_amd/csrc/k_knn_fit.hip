@@ -99,6 +99,53 @@ __device__ __forceinline__ void read_dm(const KnnLds<VCAP, F64>& S, int e,
     }
 }
 
+// Value of v in lane (this lane xor j); j is a power of two below 64 that
+// the callers' unrolled loops make a constant.
+__device__ __forceinline__ u64 xor_lane_u64(u64 v, int j) {
+    switch (j) {
+        case 1: return wave::xor_lane<1>(v);
+        case 2: return wave::xor_lane<2>(v);
+        case 4: return wave::xor_lane<4>(v);
+        case 8: return wave::xor_lane<8>(v);
+        case 16: return wave::xor_lane<16>(v);
+        default: return wave::xor_lane<32>(v);
+    }
+}
+
+// Lanes l of a wavefront with bit j of l clear, as a mask (j a power of two
+// below 64): 0x5555..., 0x3333..., 0x0f0f..., ...
+__device__ __forceinline__ constexpr u64 low_lanes(int j) { return ~0ull / ((1ull << j) + 1ull); }
+
+// Ascending bitonic sort of 64 E keys held in registers, key lane + 64 r in
+// v[r] (E = 1 or 2).  Exchanges across lanes go through DPP, swizzle and
+// permute moves; the distance-64 exchange swaps the two registers of a lane.
+// Which lanes keep the smaller key of a pair is a lane mask fixed by the step.
+template <int E>
+__device__ __forceinline__ void bitonic_regs(u64 (&v)[2], int lane) {
+#pragma unroll
+    for (int k = 2; k <= 64 * E; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            if (j == 64) {                  // k = 128: ascending everywhere
+                const u64 a = v[0], b = v[1];
+                const bool lt = a < b;
+                v[0] = lt ? a : b;
+                v[1] = lt ? b : a;
+            } else {
+#pragma unroll
+                for (int r = 0; r < E; ++r) {
+                    const u64 a = v[r], b = xor_lane_u64(a, j);
+                    // the lower index of an ascending pair (or the upper of a
+                    // descending one) keeps the smaller key
+                    const u64 asc = k < 64 ? low_lanes(k) : (((64 * r) & k) == 0 ? ~0ull : 0ull);
+                    const bool keep_min = __builtin_amdgcn_inverse_ballot_w64(~(low_lanes(j) ^ asc));
+                    v[r] = ((a < b) == keep_min) ? a : b;
+                }
+            }
+        }
+    }
+}
+
 // Processes source `s` of pair P; returns false when the visited set did not
 // fit the table (nothing written then).
 template <int VCAP, int KMAX, bool F64>
@@ -394,55 +441,75 @@ __device__ __forceinline__ bool knn_fit_one(const PairDev& P, const RunDev& run,
     }
     int p2 = 64;
     while (p2 < nc) p2 <<= 1;
-    for (int i = nc + lane; i < p2; i += 64) {
-        S.buf[i] = ~0ull;
-        if constexpr (F64) S.snode[i] = 0x7fffffff;
-    }
-    __syncthreads();
     int knode[RK];
     RT kdist[RK];
-    // each lane takes compare-exchange pairs (i, i + j): pair t has i = t
-    // with a zero bit inserted at the position of j
-    for (int k = 2; k <= p2; k <<= 1) {
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            for (int t = lane; t < (p2 >> 1); t += 64) {
-                const int i = ((t & ~(j - 1)) << 1) | (t & (j - 1));
-                const int ixj = i | j;
-                {
-                    const u64 a = S.buf[i], b = S.buf[ixj];
-                    const bool up = (i & k) == 0;
-                    if constexpr (F64) {
-                        const int na = S.snode[i], nb = S.snode[ixj];
-                        const bool gt = a > b || (a == b && na > nb);
-                        const bool lt = a < b || (a == b && na < nb);
-                        if (up ? gt : lt) {
-                            S.buf[i] = b;
-                            S.buf[ixj] = a;
-                            S.snode[i] = nb;
-                            S.snode[ixj] = na;
-                        }
-                    } else {
-                        // keys are distinct except the padding, whose swap is harmless
-                        if ((a > b) == up) {
-                            S.buf[i] = b;
-                            S.buf[ixj] = a;
+    bool sorted = false;
+    if constexpr (!F64 && VCAP <= 256) {
+        // up to 128 keys (the usual case): sorted in registers
+        static_assert(RK <= 2, "register sort holds two keys per lane");
+        if (p2 <= 128) {
+            __syncthreads();
+            u64 v[2];
+            v[0] = lane < nc ? S.buf[lane] : ~0ull;
+            v[1] = lane + 64 < nc ? S.buf[lane + 64] : ~0ull;
+            if (p2 == 64) bitonic_regs<1>(v, lane); else bitonic_regs<2>(v, lane);
+#pragma unroll
+            for (int r = 0; r < RK; ++r) {
+                knode[r] = (int)(u32)v[r];
+                kdist[r] = __uint_as_float((u32)(v[r] >> 32));
+            }
+            sorted = true;
+        }
+    }
+    if (!sorted) {
+        for (int i = nc + lane; i < p2; i += 64) {
+            S.buf[i] = ~0ull;
+            if constexpr (F64) S.snode[i] = 0x7fffffff;
+        }
+        __syncthreads();
+        // each lane takes compare-exchange pairs (i, i + j): pair t has i = t
+        // with a zero bit inserted at the position of j
+        for (int k = 2; k <= p2; k <<= 1) {
+            for (int j = k >> 1; j > 0; j >>= 1) {
+                for (int t = lane; t < (p2 >> 1); t += 64) {
+                    const int i = ((t & ~(j - 1)) << 1) | (t & (j - 1));
+                    const int ixj = i | j;
+                    {
+                        const u64 a = S.buf[i], b = S.buf[ixj];
+                        const bool up = (i & k) == 0;
+                        if constexpr (F64) {
+                            const int na = S.snode[i], nb = S.snode[ixj];
+                            const bool gt = a > b || (a == b && na > nb);
+                            const bool lt = a < b || (a == b && na < nb);
+                            if (up ? gt : lt) {
+                                S.buf[i] = b;
+                                S.buf[ixj] = a;
+                                S.snode[i] = nb;
+                                S.snode[ixj] = na;
+                            }
+                        } else {
+                            // keys are distinct except the padding, whose swap is harmless
+                            if ((a > b) == up) {
+                                S.buf[i] = b;
+                                S.buf[ixj] = a;
+                            }
                         }
                     }
                 }
+                __syncthreads();
             }
-            __syncthreads();
         }
-    }
 #pragma unroll
-    for (int r = 0; r < RK; ++r) {
-        const int jj = lane + 64 * r;
-        const u64 kb = jj < p2 ? S.buf[jj] : ~0ull;
-        if constexpr (F64) {
-            knode[r] = jj < p2 ? S.snode[jj] : 0x7fffffff;
-            kdist[r] = dbits(kb);
-        } else {
-            knode[r] = (int)(u32)kb;
-            kdist[r] = __uint_as_float((u32)(kb >> 32));
+        for (int r = 0; r < RK; ++r) {
+            const int jj = lane + 64 * r;
+            const u64 kb = jj < p2 ? S.buf[jj] : ~0ull;
+            if constexpr (F64) {
+                knode[r] = jj < p2 ? S.snode[jj] : 0x7fffffff;
+                kdist[r] = dbits(kb);
+            } else {
+                knode[r] = (int)(u32)kb;
+                kdist[r] = __uint_as_float((u32)(kb >> 32));
+            }
         }
     }
     const int n = min(keff, nc);

@@ -18,6 +18,7 @@ constexpr int QP_XOR2 = 0x4E;        // quad_perm [2,3,0,1]
 constexpr int ROW_HALF_MIRROR = 0x141;
 constexpr int ROW_MIRROR = 0x140;
 constexpr int ROW_SHR1 = 0x111, ROW_SHR2 = 0x112, ROW_SHR4 = 0x114, ROW_SHR8 = 0x118;
+constexpr int ROW_SHL4 = 0x104, ROW_ROR8 = 0x128;
 constexpr int ROW_BCAST15 = 0x142, ROW_BCAST31 = 0x143;
 
 template <int CTRL, int ROWMASK = 0xF>
@@ -141,6 +142,35 @@ __device__ __forceinline__ float min_nonneg(float v) {
 }
 
 __device__ __forceinline__ u64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
+
+// The value held by lane (this lane xor J), J a power of two below 64:
+// quad permutes for 1 and 2, row shifts that write alternate groups of four
+// lanes for 4, a half-row rotation for 8, a swizzle within 32 lanes for 16
+// and a lane permute for 32.
+template <int J>
+__device__ __forceinline__ int xor_lane(int v) {
+    static_assert(J == 1 || J == 2 || J == 4 || J == 8 || J == 16 || J == 32, "lane distance");
+    if constexpr (J == 1) {
+        return __builtin_amdgcn_mov_dpp(v, QP_XOR1, 0xF, 0xF, false);
+    } else if constexpr (J == 2) {
+        return __builtin_amdgcn_mov_dpp(v, QP_XOR2, 0xF, 0xF, false);
+    } else if constexpr (J == 4) {
+        // lanes 0-3 and 8-11 of each row read 4 lanes up, the others 4 down
+        const int t = __builtin_amdgcn_mov_dpp(v, ROW_SHL4, 0xF, 0x5, false);
+        return __builtin_amdgcn_update_dpp(t, v, ROW_SHR4, 0xF, 0xA, false);
+    } else if constexpr (J == 8) {
+        return __builtin_amdgcn_mov_dpp(v, ROW_ROR8, 0xF, 0xF, false);
+    } else if constexpr (J == 16) {
+        return __builtin_amdgcn_ds_swizzle(v, 0x401F);    // and 0x1f, or 0, xor 0x10
+    } else {
+        return __builtin_amdgcn_ds_bpermute((int)((__lane_id() ^ 32u) << 2), v);
+    }
+}
+template <int J>
+__device__ __forceinline__ u64_t xor_lane(u64_t v) {
+    const int lo = xor_lane<J>((int)(unsigned)v), hi = xor_lane<J>((int)(unsigned)(v >> 32));
+    return ((u64_t)(unsigned)hi << 32) | (unsigned)lo;
+}
 
 // Number of lanes below this one whose bit is set in m.
 __device__ __forceinline__ int lanes_below(u64_t m) {
