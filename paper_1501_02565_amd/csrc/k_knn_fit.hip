@@ -567,15 +567,17 @@ __device__ __forceinline__ bool knn_fit_one(const PairDev& P, const RunDev& run,
         tk = wave::sum(tk);
         tu = wave::sum(tu);
         tv = wave::sum(tv);
-        // one division per distinct denominator, then products
-        const float itk = 1.0f / tk;
+        // one hardware reciprocal per distinct denominator (1 ulp; the
+        // denominators are sums of weights >= 1, or a determinant whose
+        // ill-conditioned cases go to FP64), then products
+        const float itk = __builtin_amdgcn_rcpf(tk);
         out[4] = um + tu * itk;
         out[5] = vm + tv * itk;
         if (P.mode == 1) {
             sw = wave::sum(sw);
             sx = wave::sum(sx);
             sy = wave::sum(sy);
-            const float isw = 1.0f / sw;
+            const float isw = __builtin_amdgcn_rcpf(sw);
             const float mx = sx * isw, my = sy * isw;
             float sxx = 0.f, sxy = 0.f, syy = 0.f, sxu = 0.f, syu = 0.f, sxv = 0.f, syv = 0.f, su = 0.f, sv = 0.f;
 #pragma unroll
@@ -596,12 +598,12 @@ __device__ __forceinline__ bool knn_fit_one(const PairDev& P, const RunDev& run,
             su = wave::sum(su); sv = wave::sum(sv);
             const float det = sxx * syy - sxy * sxy;
             const float tr = sxx + syy;
-            const float disc = sqrtf((sxx - syy) * (sxx - syy) + 4.0f * sxy * sxy);
+            const float disc = __builtin_amdgcn_sqrtf((sxx - syy) * (sxx - syy) + 4.0f * sxy * sxy);
             const float l1 = 0.5f * (tr + disc);
             const float ratio = l1 > 0.f ? det / (l1 * l1) : 0.f;
             need64 = n < 3 || !(ratio >= run.fp64_route);
             if (!need64) {
-                const float idet = 1.0f / det;
+                const float idet = __builtin_amdgcn_rcpf(det);
                 const float b00 = (syy * sxu - sxy * syu) * idet, b01 = (sxx * syu - sxy * sxu) * idet;
                 const float b10 = (syy * sxv - sxy * syv) * idet, b11 = (sxx * syv - sxy * sxv) * idet;
                 out[0] = b00; out[1] = b01; out[2] = b10; out[3] = b11;
