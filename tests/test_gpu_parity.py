@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 
 import parity
-from scenes import config_scene, random_case
+from scenes import config_scene, random_case, serve_scene
 
 pytestmark = pytest.mark.gpu
 
@@ -43,6 +43,16 @@ def test_config_scenes(ctx, i, mode):
     1242x375 road scene (NW and LA)."""
     sc = config_scene(i, mode=mode)
     _announce(f"{sc.name} mode={mode}")
+    res = parity.full_check(ctx, sc, knn_tol=0.001)
+    print(res, flush=True)
+
+
+@pytest.mark.parametrize("K", [100, 50])
+def test_largest_served_size(ctx, K):
+    """The largest request of the served stream: 2048 x 1080 pixels with
+    40000 matches, every stage against the oracle."""
+    sc = serve_scene(dict(H=1080, W=2048, N=40000, K=K, seed=7001 + K))
+    _announce(sc.name)
     res = parity.full_check(ctx, sc, knn_tol=0.001)
     print(res, flush=True)
 
