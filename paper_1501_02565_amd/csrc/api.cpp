@@ -452,7 +452,7 @@ int run_pairs(epic_ctx* c, const epic_request* reqs, int n, hipStream_t stream, 
         return std::min(kMaxPasses - 1, std::max(floor_, hi + (hi == lo ? 0 : 1)));
     };
     if (e == hipSuccess)
-        e = c->opt.precision == 1 ? launch_geodesic64(dd, run, budget(0), budget(1), seed_blocks, stream)
+        e = c->opt.precision == 1 ? launch_geodesic64(dd, run, budget(0), budget(1), stream)
                                   : launch_geodesic(dd, run, tl.tw, tl.th, budget(0), stream);
     mark(2);
     if (e == hipSuccess) e = launch_graph_emit(dd, run, emit_blocks, stream);

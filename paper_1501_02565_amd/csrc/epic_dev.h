@@ -193,8 +193,7 @@ hipError_t launch_seed(const PairDev* d_pairs, const RunDev& run, int total_bloc
 hipError_t launch_check_cost(const PairDev* d_pairs, const RunDev& run, int total_blocks, hipStream_t s);
 hipError_t launch_geodesic(const PairDev* d_pairs, const RunDev& run, int tile_w, int tile_h,
                            int passes, hipStream_t s);
-hipError_t launch_geodesic64(const PairDev* d_pairs, const RunDev& run, int passes0, int passes1, int seed_blocks,
-                             hipStream_t s);
+hipError_t launch_geodesic64(const PairDev* d_pairs, const RunDev& run, int passes0, int passes1, hipStream_t s);
 hipError_t launch_graph_emit(const PairDev* d_pairs, const RunDev& run, int total_blocks, hipStream_t s);
 hipError_t launch_csr_scan(const PairDev* d_pairs, const RunDev& run, hipStream_t s);
 hipError_t launch_csr_scatter(const PairDev* d_pairs, const RunDev& run, int total_blocks, hipStream_t s);

@@ -16,9 +16,10 @@
 //      paths), seeds keep their own index.  Its fixpoint is the lowest
 //      match index over all shortest paths, the lexicographic (D, label)
 //      optimum.
-// Both phases use bulk-synchronous tiled passes like k_geodesic.hip (dirty
-// tiles, rounds of four Gauss-Seidel line sweeps in LDS, a single-workgroup
-// finisher) on 32 x 16 tiles.
+// Both phases use bulk-synchronous tiled passes like k_geodesic.hip (a first
+// pass over every tile with a 2-pixel margin, then dirty tiles, rounds of
+// four Gauss-Seidel line sweeps in LDS, a single-workgroup finisher) on
+// 32 x 16 tiles.
 #include <type_traits>
 
 #include "epic_dev.h"
@@ -27,10 +28,13 @@ namespace epic {
 
 namespace {
 
-constexpr int TW = 32, TH = 16, PPT = 2, LW = TW + 2, LH = TH + 2, NL = LW * LH, HR = TW / PPT;
+constexpr int TW = 32, TH = 16;
 enum : int { B_L = 1, B_R = 2, B_T = 4, B_B = 8, B_TL = 16, B_TR = 32, B_BL = 64, B_BR = 128, B_SELF = 256 };
 
+// A region of RW x RH pixels relaxed in LDS, with a one-pixel halo.
+template <int RW, int RH>
 struct Lds64 {
+    static constexpr int LW = RW + 2, LH = RH + 2, NL = LW * LH;
     u64 dist[NL];            // double bits
     u32 lab[NL];
     float cost[NL];
@@ -44,25 +48,38 @@ __device__ __forceinline__ double step64(float cp, float cq, int k) {
     return k < 4 ? half : __dmul_rn(1.4142135623730951, half);
 }
 
-// PHASE 0: distances; PHASE 1: labels.
-template <int CONN, int PHASE>
-__device__ __forceinline__ int visit64(const PairDev& P, int tx, int ty, Lds64& S, int* error,
-                                       int soft_cap = 1 << 30) {
+// PHASE 0: distances; PHASE 1: labels.  The region relaxed is the tile
+// widened by MX columns and MY rows on each side (0 in the normal passes;
+// the first pass of each phase uses a margin, so that seeds just outside a
+// tile shape it at once); only the tile itself is written back.
+template <int CONN, int PHASE, int MX = 0, int MY = 0, int NT = 256>
+__device__ __forceinline__ int visit64(const PairDev& P, int tx, int ty, Lds64<TW + 2 * MX, TH + 2 * MY>& S,
+                                       int* error, int soft_cap = 1 << 30) {
+    constexpr int RW = TW + 2 * MX, RH = TH + 2 * MY;
+    using L = Lds64<RW, RH>;
+    constexpr int LW = L::LW, LH = L::LH, NL = L::NL;
+    constexpr int PPT = RW * RH / NT, HR = RW / PPT;       // pixels per run, row runs per row
+    static_assert(PPT * NT == RW * RH && HR * PPT == RW && HR * RH == NT && (RH / PPT) * RW == NT &&
+                      RH % PPT == 0, "region shape");
     constexpr int DX[8] = {1, -1, 0, 0, 1, -1, 1, -1};
     constexpr int DY[8] = {0, 0, 1, -1, 1, 1, -1, -1};
     const int tid = threadIdx.x;
     const int x0 = tx * TW, y0 = ty * TH, W = P.W, H = P.H;
+    const int rx0 = x0 - MX, ry0 = y0 - MY;                 // region origin (may be < 0)
     const int twe = min(TW, W - x0), the = min(TH, H - y0);
+    // region pixels inside the image: lx in [vx0, vx1), ly in [vy0, vy1)
+    const int vx0 = MX == 0 ? 0 : max(0, -rx0), vy0 = MY == 0 ? 0 : max(0, -ry0);
+    const int vx1 = min(RW, W - rx0), vy1 = min(RH, H - ry0);
     // all of a thread's loads are issued before the first is stored
-    constexpr int LI = (NL + 255) / 256;
+    constexpr int LI = (NL + NT - 1) / NT;
     u64 ld[LI];
     u32 ll[LI];
     float lc[LI];
 #pragma unroll
     for (int it = 0; it < LI; ++it) {
-        const int i = tid + it * 256;
+        const int i = tid + it * NT;
         const int ly = i / LW, lxx = i - ly * LW;
-        const int gx = x0 + lxx - 1, gy = y0 + ly - 1;
+        const int gx = rx0 + lxx - 1, gy = ry0 + ly - 1;
         ld[it] = DOUBLE_INF_BITS;
         ll[it] = NO_LABEL;
         lc[it] = 0.0f;
@@ -75,7 +92,7 @@ __device__ __forceinline__ int visit64(const PairDev& P, int tx, int ty, Lds64& 
     }
 #pragma unroll
     for (int it = 0; it < LI; ++it) {
-        const int i = tid + it * 256;
+        const int i = tid + it * NT;
         if (i < NL) {
             S.dist[i] = ld[it];
             S.lab[i] = ll[it];
@@ -83,12 +100,12 @@ __device__ __forceinline__ int visit64(const PairDev& P, int tx, int ty, Lds64& 
         }
     }
     if (tid < 3) S.flag[tid] = 0;
-    for (int i = tid; i < LH; i += 256) S.rowchg[i] = -1;
+    for (int i = tid; i < LH; i += NT) S.rowchg[i] = -1;
     if (tid == 0) S.border = 0;
     __syncthreads();
 
     const int hy = tid / HR, hx = (tid % HR) * PPT;
-    const int vx = tid % TW, vy = (tid / TW) * PPT;
+    const int vx = tid % RW, vy = (tid / RW) * PPT;
     double wh[PPT][CONN], wv[PPT][CONN];
     u64 orig[PPT];
 #pragma unroll
@@ -111,7 +128,7 @@ __device__ __forceinline__ int visit64(const PairDev& P, int tx, int ty, Lds64& 
             for (int jj = 0; jj < PPT; ++jj) {
                 const int j = FWD ? jj : PPT - 1 - jj;
                 const int lx = ROWS ? hx + j : vx, ly = ROWS ? hy : vy + j;
-                if (lx >= twe || ly >= the) continue;
+                if (lx < vx0 || lx >= vx1 || ly < vy0 || ly >= vy1) continue;   // outside the image
                 const int ci = (ly + 1) * LW + lx + 1;
                 if (PHASE == 0) {
                     const double now = dbits(S.dist[ci]);
@@ -185,10 +202,11 @@ __device__ __forceinline__ int visit64(const PairDev& P, int tx, int ty, Lds64& 
     int bm = 0;
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
-        const int lx = hx + j, ly = hy;
-        const int ci = (ly + 1) * LW + lx + 1;
+        const int rlx = hx + j, rly = hy;                    // region coordinates
+        const int ci = (rly + 1) * LW + rlx + 1;
+        const int lx = rlx - MX, ly = rly - MY;              // tile coordinates
         const u64 v = PHASE == 0 ? S.dist[ci] : (u64)S.lab[ci];
-        if (lx < twe && ly < the && v != orig[j]) {
+        if (lx >= 0 && ly >= 0 && lx < twe && ly < the && v != orig[j]) {
             const long long gi = (long long)(y0 + ly) * W + x0 + lx;
             if (PHASE == 0) P.keys[gi] = v; else P.labels[gi] = (u32)v;
             const bool l = lx == 0, r = lx == twe - 1, t = ly == 0, b = ly == the - 1;
@@ -232,7 +250,7 @@ constexpr int kPass64Rounds = 5;
 
 template <int CONN, int PHASE>
 __global__ __launch_bounds__(256) void k_geo64_pass(const PairDev* __restrict__ pairs, RunDev run, int pass) {
-    __shared__ Lds64 S;
+    __shared__ Lds64<TW, TH> S;
     int* any = PHASE == 0 ? run.any : run.any2;
     if (pass > 0 && any[pass - 1] == 0) return;
     // block b takes tile b: the dirty tiles, which cluster in space, are
@@ -257,9 +275,39 @@ __global__ __launch_bounds__(256) void k_geo64_pass(const PairDev* __restrict__ 
     }
 }
 
+// The first pass of each phase: every tile, relaxed over the tile and a
+// margin of kFirst64Margin pixels around it (360 threads, runs of 2
+// pixels), capped at kFirst64Rounds rounds; tiles are dealt to the XCDs in
+// contiguous bands, so neighbouring regions share an L2.  Visiting every
+// tile also starts the label phase from all seeds at once.
+constexpr int kFirst64Margin = 2, kFirst64Threads = 360, kFirst64Rounds = 4;
+
+template <int CONN, int PHASE>
+__global__ __launch_bounds__(kFirst64Threads) void k_geo64_first(const PairDev* __restrict__ pairs, RunDev run) {
+    __shared__ Lds64<TW + 2 * kFirst64Margin, TH + 2 * kFirst64Margin> S;
+    int* any = PHASE == 0 ? run.any : run.any2;
+    const int per_xcd = (run.total_tiles + 7) / 8;
+    const int tile = (int)(blockIdx.x % 8) * per_xcd + (int)(blockIdx.x / 8);
+    if (tile >= run.total_tiles) return;
+    const int p = find_pair(run.npairs, tile, [&](int i) { return pairs[i].tile_base; });
+    const PairDev& P = pairs[p];
+    const int lt = tile - P.tile_base;
+    const int tx = lt % P.tiles_x, ty = lt / P.tiles_x;
+    if (threadIdx.x == 0) run.dirty[0][tile] = 0u;       // this pass visits every tile
+    const int border = visit64<CONN, PHASE, kFirst64Margin, kFirst64Margin, kFirst64Threads>(
+        P, tx, ty, S, run.error, kFirst64Rounds);
+    if (threadIdx.x == 0) {
+        atomicAdd(&P.counters[C_TILE_VISITS], 1);
+        if (border) {
+            mark64<CONN>(P, run, tx, ty, border, 1);
+            any[0] = 1;
+        }
+    }
+}
+
 template <int CONN, int PHASE>
 __global__ __launch_bounds__(256) void k_geo64_finish(const PairDev* __restrict__ pairs, RunDev run, int pass0) {
-    __shared__ Lds64 S;
+    __shared__ Lds64<TW, TH> S;
     __shared__ int s_any;
     int* any = PHASE == 0 ? run.any : run.any2;
     // passes that changed something (a prefix): the phase needs one more,
@@ -304,19 +352,7 @@ __global__ __launch_bounds__(256) void k_geo64_finish(const PairDev* __restrict_
     if (threadIdx.x == 0) atomicOr(run.error, 1);
 }
 
-// Between the phases: clears the dirty flags left by phase 1 and marks the
-// tiles holding a surviving seed (the sources of the label phase).
-__global__ __launch_bounds__(256) void k_geo64_seed_tiles(const PairDev* __restrict__ pairs, RunDev run) {
-    const int p = find_pair(run.npairs, (int)blockIdx.x, [&](int i) { return pairs[i].seed_block_base; });
-    const PairDev& P = pairs[p];
-    const int m = ((int)blockIdx.x - P.seed_block_base) * blockDim.x + threadIdx.x;
-    if (m >= P.N) return;
-    const int sp = P.seed_pix[m];
-    if (sp < 0 || P.labels[sp] != (u32)m) return;
-    const int t = P.tile_base + (sp / P.W / TH) * P.tiles_x + (sp % P.W) / TW;
-    run.dirty[0][t] = 1u;
-}
-
+// Between the phases: clears the dirty flags the distance phase left.
 __global__ __launch_bounds__(256) void k_geo64_reset(RunDev run) {
     for (int i = blockIdx.x * 256 + threadIdx.x; i < run.total_tiles; i += gridDim.x * 256) {
         run.dirty[0][i] = 0u;
@@ -326,25 +362,24 @@ __global__ __launch_bounds__(256) void k_geo64_reset(RunDev run) {
 
 namespace {
 template <int CONN>
-hipError_t launch64_t(const PairDev* d_pairs, const RunDev& run, int passes0, int passes1, int seed_blocks,
-                      hipStream_t s) {
+hipError_t launch64_t(const PairDev* d_pairs, const RunDev& run, int passes0, int passes1, hipStream_t s) {
     const int grid = 8 * ((run.total_tiles + 7) / 8);
-    for (int p = 0; p < passes0; ++p)
+    hipLaunchKernelGGL((k_geo64_first<CONN, 0>), dim3(grid), dim3(kFirst64Threads), 0, s, d_pairs, run);
+    for (int p = 1; p < passes0; ++p)
         hipLaunchKernelGGL((k_geo64_pass<CONN, 0>), dim3(grid), dim3(256), 0, s, d_pairs, run, p);
     hipLaunchKernelGGL((k_geo64_finish<CONN, 0>), dim3(1), dim3(256), 0, s, d_pairs, run, passes0);
     hipLaunchKernelGGL(k_geo64_reset, dim3((run.total_tiles + 255) / 256), dim3(256), 0, s, run);
-    hipLaunchKernelGGL(k_geo64_seed_tiles, dim3(seed_blocks), dim3(256), 0, s, d_pairs, run);
-    for (int p = 0; p < passes1; ++p)
+    hipLaunchKernelGGL((k_geo64_first<CONN, 1>), dim3(grid), dim3(kFirst64Threads), 0, s, d_pairs, run);
+    for (int p = 1; p < passes1; ++p)
         hipLaunchKernelGGL((k_geo64_pass<CONN, 1>), dim3(grid), dim3(256), 0, s, d_pairs, run, p);
     hipLaunchKernelGGL((k_geo64_finish<CONN, 1>), dim3(1), dim3(256), 0, s, d_pairs, run, passes1);
     return hipGetLastError();
 }
 }  // namespace
 
-hipError_t launch_geodesic64(const PairDev* d_pairs, const RunDev& run, int passes0, int passes1, int seed_blocks,
-                             hipStream_t s) {
-    return run.conn == 4 ? launch64_t<4>(d_pairs, run, passes0, passes1, seed_blocks, s)
-                         : launch64_t<8>(d_pairs, run, passes0, passes1, seed_blocks, s);
+hipError_t launch_geodesic64(const PairDev* d_pairs, const RunDev& run, int passes0, int passes1, hipStream_t s) {
+    return run.conn == 4 ? launch64_t<4>(d_pairs, run, passes0, passes1, s)
+                         : launch64_t<8>(d_pairs, run, passes0, passes1, s);
 }
 
 }  // namespace epic
