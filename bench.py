@@ -163,12 +163,19 @@ def served_form(args, np, torch, epic, precision):
     stream = serve_stream(args.served_requests)
     pool = {}
     reqs = []
+    def pinned(a):
+        # request inputs arrive in page-locked host memory (a DMA-able receive
+        # buffer), so their upload runs on the slot's stream
+        t = torch.empty(a.shape, dtype=torch.float32, pin_memory=True)
+        t.numpy()[...] = a
+        return t
     for i, r in enumerate(stream):
         key = (r["H"], r["W"], r["K"])
         if key not in pool:
-            pool[key] = serve_scene(r)
-        sc = pool[key]
-        reqs.append(Request(i, r["arrival"], sc.H, sc.W, sc.N, sc.K, sc.a, sc.mode, sc.cost, sc.matches))
+            sc = serve_scene(r)
+            pool[key] = (sc, pinned(sc.cost), pinned(sc.matches))
+        sc, pc, pm = pool[key]
+        reqs.append(Request(i, r["arrival"], sc.H, sc.W, sc.N, sc.K, sc.a, sc.mode, pc.numpy(), pm.numpy()))
     ex = GpuExecutor(slots=2, slot_workspace=args.served_budget // 2, precision=precision)
     srv = Server(ex, args.served_budget, max_batch=64)
     # warm up every kernel variant once

@@ -233,8 +233,10 @@ class GpuExecutor:
         with torch.cuda.stream(s):
             probs = []
             for r in reqs:
-                c = torch.from_numpy(r.cost).to(self.device, non_blocking=False)
-                m = torch.from_numpy(r.matches).to(self.device, non_blocking=False)
+                # asynchronous on the slot's stream when the host arrays are
+                # pinned (pageable ones are copied before the call returns)
+                c = torch.from_numpy(r.cost).to(self.device, non_blocking=True)
+                m = torch.from_numpy(r.matches).to(self.device, non_blocking=True)
                 r.flow = torch.empty((r.H, r.W, 2), dtype=torch.float32, device=self.device)
                 probs.append((c, m, r.K, r.a, r.mode))
             self.ctx[slot].interp_batch(probs, outs=[r.flow for r in reqs], stream=s)
