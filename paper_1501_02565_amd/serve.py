@@ -69,17 +69,23 @@ class Server:
     budget:     device bytes available for admitted requests.
     max_batch:  most requests in one batch.
     clock/sleep: time source (seconds) and idle wait.
+    idle_s: wait between polls while work runs or waits (0 = yield and poll
+    again at once).  wake_early_s: an idle server sleeps until this long
+    before the next arrival and polls from there, so a sleep that overshoots
+    does not delay the admission.
     """
 
     def __init__(self, executor, budget: int, max_batch: int = 64,
                  clock: Callable[[], float] = time.perf_counter,
-                 sleep: Callable[[float], None] = time.sleep, idle_s: float = 50e-6):
+                 sleep: Callable[[float], None] = time.sleep, idle_s: float = 50e-6,
+                 wake_early_s: float = 0.0):
         self.ex = executor
         self.budget = int(budget)
         self.max_batch = int(max_batch)
         self.clock = clock
         self.sleep = sleep
         self.idle_s = idle_s
+        self.wake_early_s = wake_early_s
         self.used = 0
         self.running = {}            # slot -> list[Request]
         self.batches = 0
@@ -151,8 +157,9 @@ class Server:
                     launched = True
             if not launched:
                 if nxt < len(reqs) and not waiting and not self.running:
-                    # idle until the next arrival
-                    self.sleep(max(0.0, reqs[nxt].arrival - (self.clock() - t0)))
+                    # idle until (just before) the next arrival
+                    dt = reqs[nxt].arrival - (self.clock() - t0)
+                    self.sleep(dt - self.wake_early_s if dt > self.wake_early_s else self.idle_s)
                 else:
                     self.sleep(self.idle_s)
         return reqs
