@@ -64,6 +64,10 @@ def load():
         raise RuntimeError(
             f"{LIB_PATH} is missing: build the HIP library first "
             "(python -c 'import __graft_entry__ as g; g.build()')")
+    # torch first: the library then binds the HIP runtime torch already
+    # loaded (it shares torch's device memory and streams); loaded first, it
+    # would bring in a second runtime that does not see torch's device
+    import torch  # noqa: F401
     L = ctypes.CDLL(LIB_PATH)
     P, i32, f32, f64, sz = (ctypes.c_void_p, ctypes.c_int, ctypes.c_float,
                             ctypes.c_double, ctypes.c_size_t)

@@ -118,6 +118,22 @@ def test_status_codes_follow_the_header():
         assert getattr(_lib, name) == int(value), name
 
 
+def test_binding_loads_one_hip_runtime():
+    """Loading the library first (before any torch import) must still leave
+    a single HIP runtime in the process: the one torch uses."""
+    import ast
+    import subprocess
+    import sys
+    code = ("import sys; sys.path.insert(0, %r)\n"
+            "from paper_1501_02565_amd import _lib\n"
+            "_lib.load()\n"
+            "print(sorted({l.split()[-1] for l in open('/proc/self/maps') if 'libamdhip64' in l}))\n" % ROOT)
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0, out.stderr
+    libs = ast.literal_eval(out.stdout.strip().splitlines()[-1])
+    assert len(libs) == 1, libs
+
+
 def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
     from paper_1501_02565_amd import _lib
     monkeypatch.setattr(_lib, "LIB_PATH", str(tmp_path / "missing.so"))
