@@ -235,8 +235,8 @@ def main():
                     help="skip the single-pair measurement (profiling the batched form)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        log("bench.py: this build runs on one GPU only (--gpus 1); "
-            "multi-GPU sharding is design-only")
+        log("bench.py: the library runs on one GPU (--gpus 1); sharding over "
+            "several GPUs is not implemented")
         sys.exit(2)
 
     import numpy as np
