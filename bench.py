@@ -107,14 +107,18 @@ def batched_form(args, np, torch, epic):
     px = sum(sc.H * sc.W for sc in scs)
     need = sum(epic.workspace_bytes(sc.H, sc.W, sc.N, sc.K) for sc in scs)
     if args.batch_config:
-        tw, th, ps = (int(v) for v in args.batch_config.replace("/", "x").split("x"))
-        best = {"tile": (tw, th), "passes": ps, "ms": float("nan"), "trials": []}
-        log(f"bench: batch configuration {best['tile']} passes {ps} (not tuned)")
+        # WxH/passes[/threads]
+        vals = [int(v) for v in args.batch_config.replace("/", "x").split("x")]
+        best = {"tile": (vals[0], vals[1]), "passes": vals[2], "threads": vals[3] if len(vals) > 3 else 0,
+                "ms": float("nan"), "trials": []}
+        log(f"bench: batch configuration {best['tile']} passes {best['passes']} threads {best['threads']} "
+            "(not tuned)")
     else:
         best = tune.tune(probs, need, reps=5, use_cache=False)
-        log(f"bench: tuned {best['tile']} passes {best['passes']} ({best['ms']:.3f} ms); trials "
-            + ", ".join(f"{t['tile']}/{t['passes']}: {t['ms']:.3f}" for t in best["trials"]))
-    with epic.Context(0, need, tile=best["tile"], passes=best["passes"]) as ctx:
+        log(f"bench: tuned {best['tile']} passes {best['passes']} threads {best['threads']} "
+            f"({best['ms']:.3f} ms); trials "
+            + ", ".join(f"{t['tile']}/{t['passes']}/{t['threads']}: {t['ms']:.3f}" for t in best["trials"]))
+    with epic.Context(0, need, tile=best["tile"], passes=best["passes"], geo_threads=best["threads"]) as ctx:
         g = ctx.capture(probs)
         for _ in range(3):
             g.launch()
@@ -149,7 +153,7 @@ def batched_form(args, np, torch, epic):
            "plain_mpix_s": None if args.no_plain else round(px / ms_plain / 1e3, 2),
            "plain_ms": None if args.no_plain else round(ms_plain, 4),
            "speedup_vs_plain": None if args.no_plain else round(ms_plain / ms_batch, 3),
-           "tuned": {"tile": list(best["tile"]), "passes": best["passes"]},
+           "tuned": {"tile": list(best["tile"]), "passes": best["passes"], "threads": best["threads"]},
            "sampled_mean_epe_vs_oracle_px": epes}
     log(f"bench: batched {out}")
     return out
@@ -223,7 +227,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batch-reps", type=int, default=10)
     ap.add_argument("--batch-config", default="",
-                    help="batched form: fixed WxH/passes (e.g. 32x16/12) instead of autotuning")
+                    help="batched form: fixed WxH/passes[/threads] (e.g. 32x16/12) instead of autotuning")
     ap.add_argument("--no-plain", action="store_true",
                     help="batched form: skip the single-pair comparison loop")
     ap.add_argument("--no-served", action="store_true")

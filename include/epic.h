@@ -98,6 +98,12 @@ typedef struct epic_options {
                                single-workgroup finisher completes the
                                transform if they do not reach the fixpoint,
                                so this only affects speed, never results     */
+    int   geo_threads;      /* threads per tile in the transform's passes after
+                               the first: 0 (default: 256 for 32x16 tiles,
+                               128 for 32x32, 256 for 32x64); 128 or 256 are
+                               accepted with 32x16 tiles (runs of 4 or 2
+                               pixels), other values give the default.  Only
+                               speed depends on it                          */
     int   debug_validate;   /* 0 (default); 1: every call first checks on the
                                device that each cost value is finite and > 0
                                (one extra read of the cost map).  A pair whose

@@ -55,6 +55,9 @@ class Context:
     bytes, default enough for a 2048 x 1080 image with 40000 matches).
     ``passes`` is the geodesic pass budget per call (0 = automatic, from the
     passes the recent calls needed); it never changes results.
+    ``geo_threads`` sets the threads per tile of the transform's later passes
+    (0 = default; 128 or 256 with 32 x 16 tiles); like ``passes`` it only
+    changes the speed.
     ``debug_validate`` makes every call check the cost map on the device
     (finite and > 0); a pair that fails reports ERR_COST in its stats."""
 
@@ -62,7 +65,7 @@ class Context:
                  connectivity: int = 8, la_weight_power: int = 2,
                  precision: int = 0, fp64_route: float = 1e-3,
                  degenerate_tau: float = 1e-9, tile: tuple[int, int] = (32, 16),
-                 passes: int = 0, debug_validate: bool = False):
+                 passes: int = 0, geo_threads: int = 0, debug_validate: bool = False):
         torch = _torch()
         L = _lib.load()
         self.device = int(device)
@@ -71,7 +74,7 @@ class Context:
         self.workspace = int(workspace)
         self.options = _lib.Options(connectivity, la_weight_power, precision,
                                     fp64_route, degenerate_tau, tile[0], tile[1],
-                                    passes, int(bool(debug_validate)))
+                                    passes, int(geo_threads), int(bool(debug_validate)))
         torch.cuda.init()
         with torch.cuda.device(self.device):
             self._ctx = L.epic_create(self.device, self.workspace,

@@ -32,6 +32,7 @@ class Options(ctypes.Structure):
                 ("tile_w", ctypes.c_int),
                 ("tile_h", ctypes.c_int),
                 ("geo_passes", ctypes.c_int),
+                ("geo_threads", ctypes.c_int),
                 ("debug_validate", ctypes.c_int)]
 
 

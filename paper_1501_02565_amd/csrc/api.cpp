@@ -173,6 +173,7 @@ epic_ctx* epic_create(int device, size_t workspace_bytes, const epic_options* op
     o.tile_w = 32;
     o.tile_h = 16;
     o.geo_passes = 0;
+    o.geo_threads = 0;
     o.debug_validate = 0;
     if (opts) {
         o = *opts;
@@ -187,6 +188,7 @@ epic_ctx* epic_create(int device, size_t workspace_bytes, const epic_options* op
         if (o.geo_passes < 0) o.geo_passes = 0;
         if (o.geo_passes > kMaxPasses - 1) o.geo_passes = kMaxPasses - 1;
         if (o.debug_validate != 1) o.debug_validate = 0;
+        if (!(o.tile_h == 16 && (o.geo_threads == 128 || o.geo_threads == 256))) o.geo_threads = 0;
     }
     c->auto_passes = o.geo_passes == 0;
     c->passes = c->auto_passes ? kAutoPassesStart : o.geo_passes;
@@ -453,7 +455,7 @@ int run_pairs(epic_ctx* c, const epic_request* reqs, int n, hipStream_t stream, 
     };
     if (e == hipSuccess)
         e = c->opt.precision == 1 ? launch_geodesic64(dd, run, budget(0), budget(1), stream)
-                                  : launch_geodesic(dd, run, tl.tw, tl.th, budget(0), stream);
+                                  : launch_geodesic(dd, run, tl.tw, tl.th, c->opt.geo_threads, budget(0), stream);
     mark(2);
     if (e == hipSuccess) e = launch_graph_emit(dd, run, emit_blocks, stream);
     mark(3);

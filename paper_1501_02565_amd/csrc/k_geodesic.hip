@@ -488,9 +488,12 @@ hipError_t launch_t(const PairDev* d_pairs, const RunDev& run, int passes, hipSt
 constexpr int kThreads16 = 256, kThreads32 = 128, kThreads64 = 256;
 }  // namespace
 
-hipError_t launch_geodesic(const PairDev* d_pairs, const RunDev& run, int tile_w, int tile_h, int passes,
-                           hipStream_t s) {
+hipError_t launch_geodesic(const PairDev* d_pairs, const RunDev& run, int tile_w, int tile_h, int threads,
+                           int passes, hipStream_t s) {
     const bool c8 = run.conn != 4;
+    if (tile_h == 16 && threads == 128)      // runs of 4 pixels in the later passes
+        return c8 ? launch_t<32, 16, 8, 128>(d_pairs, run, passes, s)
+                  : launch_t<32, 16, 4, 128>(d_pairs, run, passes, s);
     if (tile_h == 16)
         return c8 ? launch_t<32, 16, 8, kThreads16>(d_pairs, run, passes, s)
                   : launch_t<32, 16, 4, kThreads16>(d_pairs, run, passes, s);

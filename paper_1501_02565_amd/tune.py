@@ -1,8 +1,8 @@
 """Autotuner for the batched form.
 
 For a batch of pairs, tries the launch configurations the library exposes
-(geodesic tile shape and number of bulk-synchronous passes launched per
-call), times each as a captured HIP graph replay on the GPU, and keeps the
+(geodesic tile shape, number of bulk-synchronous passes launched per call
+and threads per tile of the later passes), times each as a captured HIP graph replay on the GPU, and keeps the
 fastest.  Results are cached in a JSON file keyed by a shape bucket (the
 multiset of (W, H, N rounded, K) of the batch), so a served or batched
 workload tunes once.
@@ -14,7 +14,10 @@ import json
 import os
 import time
 
+# (tile, passes) or (tile, passes, threads per tile of the later passes; 0 =
+# the library's default)
 DEFAULT_CANDIDATES = [((32, 16), 12), ((32, 16), 16), ((32, 16), 24),
+                      ((32, 16), 12, 128), ((32, 16), 16, 128),
                       ((32, 32), 12), ((32, 32), 16), ((32, 64), 12)]
 
 
@@ -71,25 +74,28 @@ def time_graph(ctx, problems, reps=10, warmup=2):
 
 def tune(problems, workspace, candidates=None, reps=10, use_cache=True, device=0, **ctx_opts):
     """problems: list of (cost, matches, K, a, mode) CUDA tensors.
-    Returns dict(tile=(w, h), passes=p, ms=best_ms, trials=[...])."""
+    Returns dict(tile=(w, h), passes=p, threads=t, ms=best_ms, trials=[...])."""
     import paper_1501_02565_amd as epic
     shapes = [(c.shape[0], c.shape[1], m.shape[0], K) for c, m, K, _, _ in problems]
     key = bucket_key(shapes)
     cache = load_cache() if use_cache else {}
     if key in cache:
         r = cache[key]
-        return dict(tile=tuple(r["tile"]), passes=r["passes"], ms=r["ms"], trials=r.get("trials", []),
-                    cached=True)
+        return dict(tile=tuple(r["tile"]), passes=r["passes"], threads=r.get("threads", 0), ms=r["ms"],
+                    trials=r.get("trials", []), cached=True)
     trials = []
     t0 = time.perf_counter()
-    for tile, passes in (candidates or DEFAULT_CANDIDATES):
-        with epic.Context(device, workspace, tile=tile, passes=passes, **ctx_opts) as ctx:
+    for cand in (candidates or DEFAULT_CANDIDATES):
+        tile, passes = cand[0], cand[1]
+        threads = cand[2] if len(cand) > 2 else 0
+        with epic.Context(device, workspace, tile=tile, passes=passes, geo_threads=threads, **ctx_opts) as ctx:
             ms = time_graph(ctx, problems, reps=reps)
-        trials.append(dict(tile=list(tile), passes=passes, ms=ms))
+        trials.append(dict(tile=list(tile), passes=passes, threads=threads, ms=ms))
     best = min(trials, key=lambda t: t["ms"])
-    out = dict(tile=tuple(best["tile"]), passes=best["passes"], ms=best["ms"], trials=trials,
-               cached=False, tune_s=time.perf_counter() - t0)
+    out = dict(tile=tuple(best["tile"]), passes=best["passes"], threads=best["threads"], ms=best["ms"],
+               trials=trials, cached=False, tune_s=time.perf_counter() - t0)
     if use_cache:
-        cache[key] = dict(tile=best["tile"], passes=best["passes"], ms=best["ms"], trials=trials)
+        cache[key] = dict(tile=best["tile"], passes=best["passes"], threads=best["threads"], ms=best["ms"],
+                          trials=trials)
         save_cache(cache)
     return out

@@ -175,8 +175,8 @@ def test_workspace_too_small():
 
 def test_pass_budget_does_not_change_results():
     """The geodesic pass budget (fixed small, fixed large, automatic over
-    repeated calls) only changes how much work the finisher does: flows are
-    bitwise identical."""
+    repeated calls) and the threads per tile of the later passes only change
+    how the work is done: flows are bitwise identical."""
     import torch
     import paper_1501_02565_amd as epic
     sc = random_case(180, 230, 400, seed=22, K=16)
@@ -185,8 +185,9 @@ def test_pass_budget_does_not_change_results():
     m = torch.from_numpy(sc.matches).cuda()
     ws = epic.workspace_bytes(sc.H, sc.W, sc.N, sc.K)
     flows = []
-    for passes, calls in ((1, 1), (3, 1), (16, 1), (0, 4)):
-        with epic.Context(0, ws, passes=passes) as ctx:
+    for passes, calls, threads in ((1, 1, 0), (3, 1, 0), (16, 1, 0), (0, 4, 0), (3, 1, 128), (0, 2, 128),
+                                   (2, 1, 256)):
+        with epic.Context(0, ws, passes=passes, geo_threads=threads) as ctx:
             for _ in range(calls):
                 f = ctx.interp(c, m, sc.K, sc.a, sc.mode).clone()
                 torch.cuda.synchronize()
