@@ -210,8 +210,30 @@ __device__ __forceinline__ int visit64(const PairDev& P, int tx, int ty, Lds64<T
             const long long gi = (long long)(y0 + ly) * W + x0 + lx;
             if (PHASE == 0) P.keys[gi] = v; else P.labels[gi] = (u32)v;
             const bool l = lx == 0, r = lx == twe - 1, t = ly == 0, b = ly == the - 1;
-            bm |= (l ? B_L : 0) | (r ? B_R : 0) | (t ? B_T : 0) | (b ? B_B : 0) | ((l && t) ? B_TL : 0) |
-                  ((r && t) ? B_TR : 0) | ((l && b) ? B_BL : 0) | ((r && b) ? B_BR : 0);
+            if (MX != 0 || MY != 0 || PHASE == 1) {
+                // first pass (the neighbours' values are not known yet) and
+                // label phase: every neighbour behind a changed border
+                bm |= (l ? B_L : 0) | (r ? B_R : 0) | (t ? B_T : 0) | (b ? B_B : 0) | ((l && t) ? B_TL : 0) |
+                      ((r && t) ? B_TR : 0) | ((l && b) ? B_BL : 0) | ((r && b) ? B_BR : 0);
+            } else if (l || r || t || b) {
+                // distance phase: a neighbour tile only needs a visit if this
+                // pixel shortens one of its pixels next to it; the halo holds
+                // their distances as loaded, never lower than now
+#pragma unroll
+                for (int kk = 0; kk < CONN; ++kk) {
+                    const int qx = lx + DX[kk], qy = ly + DY[kk];
+                    const bool out = qx < 0 || qy < 0 || qx >= twe || qy >= the;
+                    if (!out) continue;
+                    const int qi = ci + DY[kk] * LW + DX[kk];
+                    const double w = step64(S.cost[ci], S.cost[qi], kk);
+                    if (__dadd_rn(dbits(v), w) < dbits(S.dist[qi])) {
+                        const bool ql = qx < 0, qr = qx >= twe, qt = qy < 0, qb = qy >= the;
+                        bm |= (ql && !qt && !qb) ? B_L : (qr && !qt && !qb) ? B_R
+                            : (qt && !ql && !qr) ? B_T : (qb && !ql && !qr) ? B_B
+                            : (ql && qt) ? B_TL : (qr && qt) ? B_TR : (ql && qb) ? B_BL : B_BR;
+                    }
+                }
+            }
         }
     }
     if (bm) atomicOr(&S.border, bm);
