@@ -194,3 +194,14 @@ def test_pass_budget_does_not_change_results():
                 flows.append(f)
     for f in flows[1:]:
         assert torch.equal(flows[0], f)
+    # the FP64 transform: budgets per phase, its finisher doing most of the
+    # work when the budget is 1 pass
+    ws64 = epic.workspace_bytes(sc.H, sc.W, sc.N, sc.K, precision=1)
+    flows64 = []
+    for passes, calls in ((1, 1), (3, 1), (0, 3)):
+        with epic.Context(0, ws64, passes=passes, precision=1) as ctx:
+            for _ in range(calls):
+                flows64.append(ctx.interp(c, m, sc.K, sc.a, sc.mode).clone())
+                torch.cuda.synchronize()
+    for f in flows64[1:]:
+        assert torch.equal(flows64[0], f)
