@@ -40,9 +40,11 @@ STAGE_BYTES_PER_PX = {"geodesic": 12.0, "graph_emit": 12.0, "assign": 12.0}
 KNN_BYTES_PER_MATCH = 6 * 8 + 8 + 4 + 16 + 24
 
 
-def stage_bytes(stage, HW, N, E):
+def stage_bytes(stage, HW, N, E, precision=0):
     if stage in STAGE_BYTES_PER_PX:
-        return STAGE_BYTES_PER_PX[stage] * HW
+        # FP64 everywhere: D is 8 bytes and L a separate 4 bytes
+        extra = 4.0 if precision == 1 and stage in ("geodesic", "graph_emit") else 0.0
+        return (STAGE_BYTES_PER_PX[stage] + extra) * HW
     if stage == "knn_fit":
         return (2 * E * 8 + N * (8 + 4 + 16 + 24))
     if stage == "csr_scatter":
@@ -222,6 +224,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tile", default="32x16", help="geodesic tile WxH")
+    ap.add_argument("--precision", type=int, default=0, choices=[0, 1],
+                    help="headline leg: 0 = FP32 path (default), 1 = FP64 everywhere")
     ap.add_argument("--passes", type=int, default=0,
                     help="geodesic passes per call (0 = automatic budget)")
     ap.add_argument("--no-batched", action="store_true")
@@ -259,8 +263,8 @@ def main():
     matches = torch.from_numpy(sc.matches).to(dev)
     flow = torch.empty((sc.H, sc.W, 2), dtype=torch.float32, device=dev)
     tile = tuple(int(v) for v in args.tile.split("x"))
-    ctx = epic.Context(0, epic.workspace_bytes(sc.H, sc.W, sc.N, sc.K), tile=tile,
-                       passes=args.passes)
+    ctx = epic.Context(0, epic.workspace_bytes(sc.H, sc.W, sc.N, sc.K, precision=args.precision), tile=tile,
+                       passes=args.passes, precision=args.precision)
     stream = torch.cuda.current_stream()
 
     log(f"bench: {sc.name} warmup {args.warmup}")
@@ -309,11 +313,12 @@ def main():
     log("bench: stage ms " + ", ".join(f"{k}={v:.4f}" for k, v in stages.items()))
     dom = max(stages, key=lambda k: stages[k])
     dom_ms = stages[dom]
-    nbytes = stage_bytes(dom, HW, sc.N, E)
+    nbytes = stage_bytes(dom, HW, sc.N, E, args.precision)
     achieved = nbytes / (dom_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 6),
-                "traffic": measured_traffic(dom), "kernel": dom, "kernel_ms": round(dom_ms, 5),
+                "traffic": measured_traffic(dom) if args.precision == 0 else None,
+                "kernel": dom, "kernel_ms": round(dom_ms, 5),
                 "algorithmic_bytes": nbytes}
 
     # parity spot check of the timed output against the oracle
@@ -353,7 +358,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f64" if args.precision == 1 else "f32",
         "data": "synthetic",
         "config": {"workload": sc.name, "H": sc.H, "W": sc.W, "N": sc.N, "K": sc.K,
                    "a": sc.a, "mode": "LA", "mean_epe_vs_oracle_px": float(epe.mean()),
