@@ -61,9 +61,12 @@ typedef enum {
     EPIC_ERR_NO_MATCHES = -3,  /* no match lies in the image (flow is filled with NaN) */
     EPIC_ERR_HIP = -4,         /* a HIP runtime call failed                          */
     EPIC_ERR_BUDGET = -5,      /* request exceeds the memory budget it was given     */
-    EPIC_ERR_CAPACITY = -6,    /* a fixed-capacity device structure overflowed (the
-                                  match-graph hash, or, on the FP32 path, a match
-                                  whose cell touches more than 65535 others)       */
+    EPIC_ERR_CAPACITY = -6,    /* a fixed-capacity device structure overflowed: the
+                                  match-graph hash; on the FP32 path, a match
+                                  whose cell touches more than 65535 others; or a
+                                  match whose graph search visited more nodes than
+                                  the largest K-NN table holds (2048 entries for
+                                  K <= 256; that match's model is then zero)      */
     EPIC_ERR_CONVERGENCE = -7, /* the geodesic transform hit its iteration bound     */
     EPIC_ERR_COST = -8         /* debug_validate found a cost value that is not
                                   finite and > 0 (the flow is filled with NaN)     */

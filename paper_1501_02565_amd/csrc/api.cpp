@@ -620,7 +620,11 @@ int epic_get_stats(epic_ctx* ctx, int pair, epic_stats* out) {
         return EPIC_ERR_HIP;
     if (hipMemcpy(&gerr, ctx->g_error, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) return EPIC_ERR_HIP;
     out->status = cnt[C_STATUS];
-    if (gerr && out->status == 0) out->status = EPIC_ERR_CONVERGENCE;
+    // found after the CSR scan wrote the status: a K-NN visited set that
+    // outgrew even the retry's table (that match's model is zero), or the
+    // transform finisher's pass bound
+    if ((cnt[C_OVERFLOW] & 2) && out->status == 0) out->status = EPIC_ERR_CAPACITY;
+    if ((gerr & 1) && out->status == 0) out->status = EPIC_ERR_CONVERGENCE;
     out->n_used = cnt[C_USED];
     out->n_outside = cnt[C_OUTSIDE];
     out->n_duplicate = cnt[C_DUPLICATE];

@@ -44,6 +44,7 @@ enum Counter {
     C_OVERFLOW = 8,    // bit 0 graph hash, bit 1 Dijkstra visited table
     C_TILE_VISITS = 9,
     C_BADCOST = 10,    // cost values not finite and > 0 (checked on request)
+    C_GEOERR = 11,     // a transform visit of this pair hit its round bound
     C_NCOUNTERS = 16
 };
 
@@ -130,6 +131,41 @@ __device__ __forceinline__ float2 gload(const float2* p) {
 __device__ __forceinline__ void gstore(uint4* p, uint4 v) { *(EPIC_GLOBAL gu32x4*)p = gu32x4{v.x, v.y, v.z, v.w}; }
 __device__ __forceinline__ void gstore(float2* p, float2 v) { *(EPIC_GLOBAL gf32x2*)p = gf32x2{v.x, v.y}; }
 
+// Relaxed atomic accesses for transform state that other threads read or
+// write at the same moment.  The transform's correctness argument only
+// needs each 64-bit (D, label) key to be read and written whole (a reader
+// sees the old or the new key, never a mix: a torn key could pair a new
+// distance with an old label and order below the optimum).  Relaxed atomics
+// state exactly that and nothing more (no ordering, no fences):
+//   lds_*     keys and flags in LDS shared by the waves of one workgroup
+//             (plain ds_read_b64 / ds_write_b64);
+//   dev_*     keys in global memory that workgroups of the same launch read
+//             as halo while their owner writes them (agent scope).
+template <typename T>
+__device__ __forceinline__ T lds_ld(const T* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+template <typename T>
+__device__ __forceinline__ void lds_st(T* p, T v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+template <typename T>
+__device__ __forceinline__ T dev_ld(const T* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ void dev_st(T* p, T v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// One step of the discretised geodesic of Eq. (3) in FP32, and a relaxation
+// across it, each operation rounded on its own (no fused multiply-add), so
+// that every place that prices a step gets the same bits.
+__device__ __forceinline__ float step_f32(float len, float cp, float cq) {
+    return __fmul_rn(len, __fmul_rn(0.5f, __fadd_rn(cp, cq)));
+}
+__device__ __forceinline__ float relax_f32(float d, float w) { return __fadd_rn(d, w); }
+
 // Nearest-match label of pixel i (packed in the key, or in the label array
 // of the FP64 path).
 __device__ __forceinline__ u32 label_at(const PairDev& P, long long i) {
@@ -141,7 +177,8 @@ struct RunDev {
     u32* dirty[2];          // per tile, by pass parity: tile needs a visit
     int* any;               // per pass: some tile border changed (kMaxPasses)
     int* any2;              // the same for the label phase of the FP64 path
-    int* error;             // global error word
+    int* error;             // global error word: bit 0 = the transform finisher hit
+                            //   its pass bound (per-pair errors live in the counters)
     int* passes_used;       // host-visible, 2 ints: passes the last transform needed
                             //   (FP64 path: distance phase, label phase); may be null
     int* ovf_list;          // K-NN sources to redo with a larger table

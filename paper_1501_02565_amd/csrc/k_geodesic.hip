@@ -14,9 +14,12 @@
 //     its halo into LDS, relaxed to a local fixpoint (or for a capped number
 //     of rounds, after which it marks itself dirty), written back, and the
 //     neighbours behind every changed border are marked dirty for the next
-//     pass.  Passes communicate only through memory across launches, so
-//     plain cached loads and stores are coherent; no workgroup waits for
-//     another.  A pass in which no border changed ends the transform: every
+//     pass.  Within a launch, a tile's halo may be read while its owner
+//     writes it: those keys are read and written with relaxed atomics at
+//     agent scope, so a reader gets the old or the new key whole (either
+//     is a valid upper bound, and any change it misses marks it dirty for
+//     the next pass).  Passes see each other's writes across launches; no
+//     workgroup waits for another.  A pass in which no border changed ends the transform: every
 //     later pass exits at once.
 //   * In-tile relaxation is Gauss-Seidel over lines of pixels owned by one
 //     thread, alternating between rows and columns and between sweep
@@ -92,7 +95,9 @@ struct TileLds {
 // another round: a round in which no pixel improved leaves every pixel at
 // the minimum over its neighbours, which is the fixpoint.  A wavefront whose
 // runs saw no change within one row since the previous round started skips
-// its sweeps (per-row change rounds, written with plain stores).
+// its sweeps (per-row change rounds in LDS).  Keys and flags that several
+// waves touch at once are read and written with relaxed atomics, which on
+// gfx950 are the plain 64-bit LDS accesses: a key is never seen half-written.
 //
 // A key (D bits, label) with D >= 0 read as an IEEE double is a non-negative
 // value below the NaN range whose order is the unsigned order of the key
@@ -144,7 +149,10 @@ __device__ __forceinline__ int visit_tile(const PairDev& P, int tx, int ty,
         lc[it] = 0.0f;
         if (i < NL && gx >= 0 && gy >= 0 && gx < W && gy < H) {
             const long long gi = (long long)gy * W + gx;
-            lk[it] = gmem(P.keys)[gi];
+            // the tile's own pixels are written only by this visit; the
+            // margin and halo belong to neighbours that may be writing them
+            const bool own = gx >= x0 && gy >= y0 && gx < x0 + twe && gy < y0 + the;
+            lk[it] = own ? gmem(P.keys)[gi] : dev_ld(P.keys + gi);
             lc[it] = gmem(P.cost)[gi];
         }
     }
@@ -174,11 +182,15 @@ __device__ __forceinline__ int visit_tile(const PairDev& P, int tx, int ty,
 #pragma unroll
         for (int k = 0; k < CONN; ++k) {
             const float len = (k < 4) ? 1.0f : 1.41421356237309515f;
-            wh[j][k] = len * (0.5f * (cph + S.cost[ch + DY[k] * LW + DX[k]]));
-            wv[j][k] = len * (0.5f * (cpv + S.cost[cv + DY[k] * LW + DX[k]]));
+            wh[j][k] = step_f32(len, cph, S.cost[ch + DY[k] * LW + DX[k]]);
+            wv[j][k] = step_f32(len, cpv, S.cost[cv + DY[k] * LW + DX[k]]);
         }
-        orig[j] = S.key[ch];
+        orig[j] = lds_ld(&S.key[ch]);
     }
+    // every thread has its pixels' values as loaded before any sweep writes
+    // (a value improved by another wave before it was read here would look
+    // unchanged at write-back and never reach global memory)
+    __syncthreads();
     const int round_cap = 4 * NL + 8;
     bool unconverged = false;
     for (int round = 0;; ++round) {
@@ -196,14 +208,14 @@ __device__ __forceinline__ int visit_tile(const PairDev& P, int tx, int ty,
 #pragma unroll
             for (int a = 0; a < 3; ++a)
 #pragma unroll
-                for (int b = 0; b < 3; ++b) win[a][b] = S.key[c + (a - 1) * SA + (b - 1) * SB];
+                for (int b = 0; b < 3; ++b) win[a][b] = lds_ld(&S.key[c + (a - 1) * SA + (b - 1) * SB]);
 #pragma unroll
             for (int jj = 0; jj < PPT; ++jj) {
                 const int j = FWD ? jj : PPT - 1 - jj;
                 u64 nxt[3] = {0, 0, 0};
                 if (jj + 1 < PPT) {
 #pragma unroll
-                    for (int b = 0; b < 3; ++b) nxt[b] = S.key[c + 2 * SA + (b - 1) * SB];
+                    for (int b = 0; b < 3; ++b) nxt[b] = lds_ld(&S.key[c + 2 * SA + (b - 1) * SB]);
                 }
                 const int lx = ROWS ? hx + j : vx, ly = ROWS ? hy : vy + j;
                 const u64 now = win[1][1];
@@ -224,7 +236,7 @@ __device__ __forceinline__ int visit_tile(const PairDev& P, int tx, int ty,
                         if (k < 0 || k >= CONN) continue;
                         const u64 q = win[a + 1][b + 1];
                         const float w = ROWS ? wh[j][k] : wv[j][k];
-                        const double cd = __longlong_as_double((long long)make_key(key_dist(q) + w, key_label(q)));
+                        const double cd = __longlong_as_double((long long)make_key(relax_f32(key_dist(q), w), key_label(q)));
                         if (a == -1 && b == 0 && jj > 0) behind = cd; else cand[nc++] = cd;
                     }
                 }
@@ -233,8 +245,8 @@ __device__ __forceinline__ int visit_tile(const PairDev& P, int tx, int ty,
                 u64 bk = (u64)__double_as_longlong(best);
                 if (lx < vx0 || lx >= vx1 || ly < vy0 || ly >= vy1) bk = now;   // outside the image
                 if (bk < now) {
-                    S.key[c] = bk;
-                    S.rowchg[ly + 1] = round;
+                    lds_st(&S.key[c], bk);
+                    lds_st(&S.rowchg[ly + 1], round);
                     changed = 1;
                 }
 #pragma unroll
@@ -254,10 +266,10 @@ __device__ __forceinline__ int visit_tile(const PairDev& P, int tx, int ty,
         // then none of its pixels can improve
         bool act_h = round == 0, act_v = round == 0;
         if (round != 0) {
-            act_h = max(max(S.rowchg[hy], S.rowchg[hy + 1]), S.rowchg[hy + 2]) >= round - 1;
-            int m = S.rowchg[vy];
+            act_h = max(max(lds_ld(&S.rowchg[hy]), lds_ld(&S.rowchg[hy + 1])), lds_ld(&S.rowchg[hy + 2])) >= round - 1;
+            int m = lds_ld(&S.rowchg[vy]);
 #pragma unroll
-            for (int j = 1; j < PPT + 2; ++j) m = max(m, S.rowchg[vy + j]);
+            for (int j = 1; j < PPT + 2; ++j) m = max(m, lds_ld(&S.rowchg[vy + j]));
             act_v = m >= round - 1;
         }
         const bool wave_h = __builtin_amdgcn_ballot_w64(act_h) != 0ull;
@@ -268,16 +280,16 @@ __device__ __forceinline__ int visit_tile(const PairDev& P, int tx, int ty,
         if (wave_v) sweep(F{}, F{});
         // flag this round's changes per wavefront (the flag of the next
         // round was last read two rounds ago) and meet
-        if (tid == 0) S.flag[(round + 1) % 3] = 0;
-        if (__builtin_amdgcn_ballot_w64(changed != 0) != 0ull && (tid & 63) == 0) S.flag[round % 3] = 1;
+        if (tid == 0) lds_st(&S.flag[(round + 1) % 3], 0);
+        if (__builtin_amdgcn_ballot_w64(changed != 0) != 0ull && (tid & 63) == 0) lds_st(&S.flag[round % 3], 1);
         __syncthreads();
-        if (S.flag[round % 3] == 0) break;
+        if (lds_ld(&S.flag[round % 3]) == 0) break;
         if (round + 1 >= soft_cap) {       // stop early; the next pass continues
             unconverged = true;
             break;
         }
         if (round > round_cap) {
-            if (tid == 0) atomicOr(error, 2);
+            if (tid == 0) atomicOr(error, 1);     // this pair's round bound
             break;
         }
     }
@@ -289,7 +301,7 @@ __device__ __forceinline__ int visit_tile(const PairDev& P, int tx, int ty,
         const int lx = hx + j - MX, ly = hy - MY;          // tile coordinates
         const u64 k = S.key[(hy + 1) * LW + hx + j + 1];
         if (lx >= 0 && ly >= 0 && lx < twe && ly < the && k != orig[j]) {
-            gmem(P.keys)[(long long)(y0 + ly) * W + x0 + lx] = k;
+            dev_st(P.keys + (long long)(y0 + ly) * W + x0 + lx, k);
             const bool l = lx == 0, r = lx == twe - 1, t = ly == 0, b = ly == the - 1;
             if (MX != 0 || MY != 0) {
                 // first pass: the neighbours' values are not known yet
@@ -308,7 +320,8 @@ __device__ __forceinline__ int visit_tile(const PairDev& P, int tx, int ty,
                     if (!out) continue;
                     const int qi = ci + DY[kk] * LW + DX[kk];
                     const float len = (kk < 4) ? 1.0f : 1.41421356237309515f;
-                    const u64 cand = make_key(dp + len * (0.5f * (cp + S.cost[qi])), key_label(k));
+                    // priced exactly as the neighbour's sweep would price it
+                    const u64 cand = make_key(relax_f32(dp, step_f32(len, cp, S.cost[qi])), key_label(k));
                     if (cand < S.key[qi]) {
                         const bool ql = qx < 0, qr = qx >= twe, qt = qy < 0, qb = qy >= the;
                         bm |= (ql && !qt && !qb) ? B_L : (qr && !qt && !qb) ? B_R
@@ -377,7 +390,7 @@ __global__ __launch_bounds__(NT) void k_geo_pass(const PairDev* __restrict__ pai
     const int tx = lt % P.tiles_x, ty = lt / P.tiles_x;
     __syncthreads();
     if (threadIdx.x == 0) dirty[tile] = 0u;                  // reused two passes later
-    const int border = visit_tile<TW, TH, 0, 0, CONN, NT>(P, tx, ty, S, run.error, kPassRounds);
+    const int border = visit_tile<TW, TH, 0, 0, CONN, NT>(P, tx, ty, S, P.counters + C_GEOERR, kPassRounds);
     if (threadIdx.x == 0) {
         atomicAdd(&P.counters[C_TILE_VISITS], 1);
         if (border) {
@@ -401,7 +414,7 @@ __global__ __launch_bounds__(NT) void k_geo_first(const PairDev* __restrict__ pa
     const int lt = tile - P.tile_base;
     const int tx = lt % P.tiles_x, ty = lt / P.tiles_x;
     if (threadIdx.x == 0) run.dirty[0][tile] = 0u;           // reused by pass 2
-    const int border = visit_tile<TW, TH, MX, MY, CONN, NT>(P, tx, ty, S, run.error, kFirstRounds);
+    const int border = visit_tile<TW, TH, MX, MY, CONN, NT>(P, tx, ty, S, P.counters + C_GEOERR, kFirstRounds);
     if (threadIdx.x == 0) {
         atomicAdd(&P.counters[C_TILE_VISITS], 1);
         if (border) {
@@ -438,7 +451,7 @@ __global__ __launch_bounds__(NT) void k_geo_finish(const PairDev* __restrict__ p
             const int tx = lt % P.tiles_x, ty = lt / P.tiles_x;
             __syncthreads();
             if (threadIdx.x == 0) dirty[tile] = 0u;
-            const int border = visit_tile<TW, TH, 0, 0, CONN, NT>(P, tx, ty, S, run.error);
+            const int border = visit_tile<TW, TH, 0, 0, CONN, NT>(P, tx, ty, S, P.counters + C_GEOERR);
             if (threadIdx.x == 0) {
                 atomicAdd(&P.counters[C_TILE_VISITS], 1);
                 if (border) {

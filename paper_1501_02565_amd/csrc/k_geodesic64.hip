@@ -85,8 +85,13 @@ __device__ __forceinline__ int visit64(const PairDev& P, int tx, int ty, Lds64<T
         lc[it] = 0.0f;
         if (i < NL && gx >= 0 && gy >= 0 && gx < W && gy < H) {
             const long long gi = (long long)gy * W + gx;
-            ld[it] = gmem(P.keys)[gi];
-            if (PHASE == 1) ll[it] = gmem(P.labels)[gi];
+            // the tile's own pixels are written only by this visit; the
+            // margin and halo belong to neighbours that may be writing them
+            // (relaxed atomics: read whole, old or new)
+            const bool own = gx >= x0 && gy >= y0 && gx < x0 + twe && gy < y0 + the;
+            if (PHASE == 0) ld[it] = own ? gmem(P.keys)[gi] : dev_ld(P.keys + gi);
+            else ld[it] = gmem(P.keys)[gi];          // distances are final in the label phase
+            if (PHASE == 1) ll[it] = own ? gmem(P.labels)[gi] : dev_ld(P.labels + gi);
             lc[it] = gmem(P.cost)[gi];
         }
     }
@@ -116,8 +121,12 @@ __device__ __forceinline__ int visit64(const PairDev& P, int tx, int ty, Lds64<T
             wh[j][k] = step64(S.cost[ch], S.cost[ch + DY[k] * LW + DX[k]], k);
             wv[j][k] = step64(S.cost[cv], S.cost[cv + DY[k] * LW + DX[k]], k);
         }
-        orig[j] = PHASE == 0 ? S.dist[ch] : (u64)S.lab[ch];
+        orig[j] = PHASE == 0 ? lds_ld(&S.dist[ch]) : (u64)lds_ld(&S.lab[ch]);
     }
+    // every thread has its pixels' values as loaded before any sweep writes
+    // (a value improved by another wave before it was read here would look
+    // unchanged at write-back and never reach global memory)
+    __syncthreads();
     const int round_cap = 4 * NL + 8;
     bool unconverged = false;
     for (int round = 0;; ++round) {
@@ -131,33 +140,34 @@ __device__ __forceinline__ int visit64(const PairDev& P, int tx, int ty, Lds64<T
                 if (lx < vx0 || lx >= vx1 || ly < vy0 || ly >= vy1) continue;   // outside the image
                 const int ci = (ly + 1) * LW + lx + 1;
                 if (PHASE == 0) {
-                    const double now = dbits(S.dist[ci]);
+                    const double now = dbits(lds_ld(&S.dist[ci]));
                     double best = now;
 #pragma unroll
                     for (int k = 0; k < CONN; ++k) {
-                        const double cand =
-                            __dadd_rn(dbits(S.dist[ci + DY[k] * LW + DX[k]]), ROWS ? wh[j][k] : wv[j][k]);
+                        const double cand = __dadd_rn(dbits(lds_ld(&S.dist[ci + DY[k] * LW + DX[k]])),
+                                                      ROWS ? wh[j][k] : wv[j][k]);
                         best = cand < best ? cand : best;
                     }
                     if (best < now) {
-                        S.dist[ci] = bitsd(best);
-                        S.rowchg[ly + 1] = round;
+                        lds_st(&S.dist[ci], bitsd(best));
+                        lds_st(&S.rowchg[ly + 1], round);
                         changed = 1;
                     }
                 } else {
+                    // distances are fixed in this phase (no writer)
                     const double dp = dbits(S.dist[ci]);
-                    const u32 now = S.lab[ci];
+                    const u32 now = lds_ld(&S.lab[ci]);
                     u32 best = now;
 #pragma unroll
                     for (int k = 0; k < CONN; ++k) {
                         const int q = ci + DY[k] * LW + DX[k];
                         const bool tight = __dadd_rn(dbits(S.dist[q]), ROWS ? wh[j][k] : wv[j][k]) == dp;
-                        const u32 lq = S.lab[q];
+                        const u32 lq = lds_ld(&S.lab[q]);
                         best = (tight && lq < best) ? lq : best;
                     }
                     if (best < now) {
-                        S.lab[ci] = best;
-                        S.rowchg[ly + 1] = round;
+                        lds_st(&S.lab[ci], best);
+                        lds_st(&S.rowchg[ly + 1], round);
                         changed = 1;
                     }
                 }
@@ -166,15 +176,15 @@ __device__ __forceinline__ int visit64(const PairDev& P, int tx, int ty, Lds64<T
         // rounds of four sweeps (rows and columns, both directions) with one
         // barrier; a wavefront skips its sweeps when no pixel within one row
         // of its runs changed since the previous round started; racing
-        // plain stores only cost further rounds (every value written is a
-        // valid distance or label, all pixels are relaxed until a round
-        // changes nothing)
+        // stores (relaxed atomics: never torn) only cost further rounds
+        // (every value written is a valid distance or label, all pixels are
+        // relaxed until a round changes nothing)
         bool act_h = round == 0, act_v = round == 0;
         if (round != 0) {
-            act_h = max(max(S.rowchg[hy], S.rowchg[hy + 1]), S.rowchg[hy + 2]) >= round - 1;
-            int mrow = S.rowchg[vy];
+            act_h = max(max(lds_ld(&S.rowchg[hy]), lds_ld(&S.rowchg[hy + 1])), lds_ld(&S.rowchg[hy + 2])) >= round - 1;
+            int mrow = lds_ld(&S.rowchg[vy]);
 #pragma unroll
-            for (int j = 1; j < PPT + 2; ++j) mrow = max(mrow, S.rowchg[vy + j]);
+            for (int j = 1; j < PPT + 2; ++j) mrow = max(mrow, lds_ld(&S.rowchg[vy + j]));
             act_v = mrow >= round - 1;
         }
         const bool wave_h = __builtin_amdgcn_ballot_w64(act_h) != 0ull;
@@ -185,16 +195,16 @@ __device__ __forceinline__ int visit64(const PairDev& P, int tx, int ty, Lds64<T
         if (wave_v) sweep(F{}, T{});
         if (wave_h) sweep(T{}, F{});
         if (wave_v) sweep(F{}, F{});
-        if (tid == 0) S.flag[(round + 1) % 3] = 0;
-        if (__builtin_amdgcn_ballot_w64(changed != 0) != 0ull && (tid & 63) == 0) S.flag[round % 3] = 1;
+        if (tid == 0) lds_st(&S.flag[(round + 1) % 3], 0);
+        if (__builtin_amdgcn_ballot_w64(changed != 0) != 0ull && (tid & 63) == 0) lds_st(&S.flag[round % 3], 1);
         __syncthreads();
-        if (S.flag[round % 3] == 0) break;
+        if (lds_ld(&S.flag[round % 3]) == 0) break;
         if (round + 1 >= soft_cap) {       // stop early; the next pass continues
             unconverged = true;
             break;
         }
         if (round > round_cap) {
-            if (tid == 0) atomicOr(error, 2);
+            if (tid == 0) atomicOr(error, 1);     // this pair's round bound
             break;
         }
     }
@@ -208,7 +218,7 @@ __device__ __forceinline__ int visit64(const PairDev& P, int tx, int ty, Lds64<T
         const u64 v = PHASE == 0 ? S.dist[ci] : (u64)S.lab[ci];
         if (lx >= 0 && ly >= 0 && lx < twe && ly < the && v != orig[j]) {
             const long long gi = (long long)(y0 + ly) * W + x0 + lx;
-            if (PHASE == 0) P.keys[gi] = v; else P.labels[gi] = (u32)v;
+            if (PHASE == 0) dev_st(P.keys + gi, v); else dev_st(P.labels + gi, (u32)v);
             const bool l = lx == 0, r = lx == twe - 1, t = ly == 0, b = ly == the - 1;
             if (MX != 0 || MY != 0 || PHASE == 1) {
                 // first pass (the neighbours' values are not known yet) and
@@ -287,7 +297,7 @@ __global__ __launch_bounds__(256) void k_geo64_pass(const PairDev* __restrict__ 
     const int tx = lt % P.tiles_x, ty = lt / P.tiles_x;
     __syncthreads();
     if (threadIdx.x == 0) dirty[tile] = 0u;
-    const int border = visit64<CONN, PHASE>(P, tx, ty, S, run.error, kPass64Rounds);
+    const int border = visit64<CONN, PHASE>(P, tx, ty, S, P.counters + C_GEOERR, kPass64Rounds);
     if (threadIdx.x == 0) {
         atomicAdd(&P.counters[C_TILE_VISITS], 1);
         if (border) {
@@ -317,7 +327,7 @@ __global__ __launch_bounds__(kFirst64Threads) void k_geo64_first(const PairDev* 
     const int tx = lt % P.tiles_x, ty = lt / P.tiles_x;
     if (threadIdx.x == 0) run.dirty[0][tile] = 0u;       // this pass visits every tile
     const int border = visit64<CONN, PHASE, kFirst64Margin, kFirst64Margin, kFirst64Threads>(
-        P, tx, ty, S, run.error, kFirst64Rounds);
+        P, tx, ty, S, P.counters + C_GEOERR, kFirst64Rounds);
     if (threadIdx.x == 0) {
         atomicAdd(&P.counters[C_TILE_VISITS], 1);
         if (border) {
@@ -352,7 +362,7 @@ __global__ __launch_bounds__(256) void k_geo64_finish(const PairDev* __restrict_
             const int tx = lt % P.tiles_x, ty = lt / P.tiles_x;
             __syncthreads();
             if (threadIdx.x == 0) dirty[tile] = 0u;
-            const int border = visit64<CONN, PHASE>(P, tx, ty, S, run.error);
+            const int border = visit64<CONN, PHASE>(P, tx, ty, S, P.counters + C_GEOERR);
             if (threadIdx.x == 0) {
                 atomicAdd(&P.counters[C_TILE_VISITS], 1);
                 if (border) {

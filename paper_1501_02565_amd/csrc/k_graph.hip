@@ -147,9 +147,10 @@ __global__ __launch_bounds__(EMIT_NT) void k_graph_emit(const PairDev* __restric
                     const double step = k < 2 ? half : __dmul_rn(1.4142135623730951, half);
                     wb = (V)bitsd(__dadd_rn(__dadd_rn(dbits(kp), step), dbits(kq)));
                 } else {
+                    // (D(p) + step) + D(q), each operation rounded on its own
                     const float len = (k < 2) ? 1.0f : 1.41421356237309515f;
-                    const float w = len * (0.5f * (cp + cqa[k]));
-                    wb = (V)__float_as_uint((key_dist(kp) + w) + key_dist(kq));
+                    const float w = step_f32(len, cp, cqa[k]);
+                    wb = (V)__float_as_uint(__fadd_rn(relax_f32(key_dist(kp), w), key_dist(kq)));
                 }
                 const u32 m = min(lp, lq), n = max(lp, lq);
                 const u64 hk = ((u64)m << 32) | n;
@@ -247,7 +248,7 @@ __global__ __launch_bounds__(1024) void k_csr_scan(const PairDev* __restrict__ p
         for (int w = 0; w < 16; ++w) any_big |= s_big[w];
         if (any_big && P.minin64 == nullptr) P.counters[C_OVERFLOW] |= 1;   // a degree above 65535
         if (P.counters[C_OVERFLOW]) status = -6;                       // EPIC_ERR_CAPACITY
-        if (*run.error) status = -7;                                   // EPIC_ERR_CONVERGENCE
+        if ((*run.error & 1) || P.counters[C_GEOERR]) status = -7;     // EPIC_ERR_CONVERGENCE
         if (P.counters[C_BADCOST]) {                                   // EPIC_ERR_COST: not seeded
             status = -8;
             P.counters[C_DUPLICATE] = 0;

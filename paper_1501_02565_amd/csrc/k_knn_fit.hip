@@ -38,8 +38,9 @@
 // lanes through LDS only need to keep the compiler from reordering them.
 //
 // A source whose visited set outgrows the small LDS table is put on an
-// overflow list and redone by a second launch with a table four times
-// larger; only if that overflows too is the pair's status set.
+// overflow list and redone by a second launch with a larger table; if that
+// overflows too, the match's model is zero and the pair's counters record
+// it (epic_get_stats then reports EPIC_ERR_CAPACITY for the pair).
 #include <type_traits>
 
 #include "epic_dev.h"

@@ -5,9 +5,27 @@ Tolerances (stated once, used by every parity test):
   * labels L: at most 0.1% of pixels may differ, and every differing pixel
     must be a near-tie -- the oracle's distance from the GPU's match to the
     pixel is within 1e-5 (relative) of the oracle's minimum;
-  * graph weights and K-NN distances: relative 1e-5 (edges and neighbours
-    that differ must be explained by label near-ties / distance near-ties);
-  * dense flow: mean endpoint difference to the oracle flow <= 1e-3 px.
+  * graph: the same edge set with weights within 1e-5 relative, except edges
+    with an endpoint whose cell holds a label near-tie (their weight is a
+    minimum over that cell's boundary, which the tie may move);
+  * K-NN lists: the same members with distances within 1e-5 relative,
+    except lists whose differing members all tie with the K-th distance
+    (within 1e-4 relative: FP32 sums of ~100 hops against FP64) or lists
+    that contain an endpoint of an excused edge (a shortest path through an
+    edge passes through its nearer endpoint, which is then in the list);
+  * per-match models of every list that matched: the model's prediction at
+    the K neighbours' positions differs from the oracle's by at most
+        S_m * (FIT_REL * max(1, kappa_m) + 2 a max_n |d_gpu - d_ref|)
+    where S_m = |u_m| + max_n |u_n - u_m| is the displacement scale the fit
+    combines, kappa_m the condition number of the neighbours' weighted
+    position covariance (the FP32 path solves only kappa <= 1e3 itself) and
+    the last term the weight change exp(-a d) implied by the FP32 graph
+    distances (each within 1e-5 relative, checked above);
+  * dense flow: mean endpoint difference to the oracle flow <= 1e-3 px, and
+    at most MAX_EPE = 1e-2 px at every pixel whose label agrees and whose
+    cell's list and model were not excused above.
+Nothing else is excused: no fraction of lists, edges or pixels may differ
+for an unexplained reason.
 """
 from __future__ import annotations
 
@@ -18,6 +36,9 @@ from oracle import epic_ref
 REL = 1e-5
 LABEL_FRAC = 1e-3
 EPE_MEAN = 1e-3
+MAX_EPE = 1e-2
+KNN_TIE_REL = 1e-4
+FIT_REL = 1e-5
 
 
 def gpu_stages(ctx, sc, K=None, a=None, mode=None):
@@ -39,82 +60,133 @@ def ref_stages(sc, K=None, a=None, mode=None, conn=8, wpow=2):
 
 
 def check_labels(sc, g, r, conn=8, frac=LABEL_FRAC):
-    """D within REL where labels agree; disagreements are rare near-ties."""
+    """D within REL where labels agree; disagreements are rare near-ties.
+    Returns the mask of pixels whose labels differ (all proven near-ties)."""
     Dg, Lg = g["D"].astype(np.float64), g["L"]
     Dr, Lr = r["D"], r["L"]
     same = Lg == Lr
     np.testing.assert_allclose(Dg[same], Dr[same], rtol=REL, atol=1e-30)
-    diff = np.argwhere(~same)
-    assert len(diff) <= frac * Lg.size, f"{len(diff)} label differences"
-    if len(diff):
-        H, W = sc.cost.shape
-        for lab in np.unique(Lg[~same]):
+    diff = ~same
+    assert diff.sum() <= frac * Lg.size, f"{int(diff.sum())} label differences"
+    if diff.any():
+        for lab in np.unique(Lg[diff]):
             src = int(r["seed_pix"][lab])
             assert src >= 0
             Ds = epic_ref.geodesic_from(sc.cost, src, conn)
-            pts = (Lg == lab) & ~same
+            pts = (Lg == lab) & diff
             np.testing.assert_allclose(Ds[pts], Dr[pts], rtol=REL)
             np.testing.assert_allclose(Dg[pts], Dr[pts], rtol=REL)
-    return int((~same).sum())
+    return diff
 
 
-def check_graph(g, r, n_label_diff):
+def check_graph(g, r, diff):
+    """Edge sets and weights; returns the set of nodes whose incident edges
+    may differ (labels on either side of a label near-tie)."""
+    tied = set(np.unique(g["L"][diff]).tolist()) | set(np.unique(r["L"][diff]).tolist())
     ge = {(int(m), int(n)): float(w) for m, n, w in zip(g["em"], g["en"], g["ew"])}
     re_ = {(int(m), int(n)): float(w) for m, n, w in zip(r["em"], r["en"], r["ew"])}
-    common = ge.keys() & re_.keys()
     sym = (ge.keys() - re_.keys()) | (re_.keys() - ge.keys())
-    if n_label_diff == 0:
-        assert not sym, f"edge sets differ: {sorted(sym)[:10]}"
-    else:
-        assert len(sym) <= max(4, 0.005 * len(re_)), len(sym)
-    bad = [e for e in common if abs(ge[e] - re_[e]) > REL * re_[e]]
-    if n_label_diff == 0:
-        assert not bad, f"edge weights differ: {[(e, ge[e], re_[e]) for e in bad[:5]]}"
-    else:
-        assert len(bad) <= max(4, 0.005 * len(common)), len(bad)
-    return len(sym), len(bad)
+    bad = [e for e in ge.keys() & re_.keys() if abs(ge[e] - re_[e]) > REL * re_[e]]
+    unexplained = [e for e in list(sym) + bad if e[0] not in tied and e[1] not in tied]
+    assert not unexplained, f"graph differs away from label ties: {sorted(unexplained)[:10]}"
+    excused = set()
+    for m, n in list(sym) + bad:
+        excused.update((m, n))
+    return excused
 
 
-def check_knn(g, r, K, tol_frac=0.0):
-    """Neighbour lists: the same set with distances within REL, except where
-    the K-th distance is a near-tie or the graph differs (tol_frac)."""
+def check_knn(g, r, K, excused_nodes=frozenset()):
+    """Neighbour lists: the same set with distances within REL, except a
+    K-th-distance near-tie or a list touching an excused edge.  Returns the
+    sources whose lists were excused."""
     gi, gd = g["knn_idx"][:, :K], g["knn_d"][:, :K].astype(np.float64)
     ri, rd = r["knn_idx"][:, :K], r["knn_d"][:, :K]
-    N = ri.shape[0]
-    mismatched = 0
-    for s in range(N):
+    excused = set()
+    unexplained = []
+    for s in range(ri.shape[0]):
         if ri[s, 0] < 0:
             assert gi[s, 0] == -1
             continue
         if set(gi[s].tolist()) == set(ri[s].tolist()) and \
                 np.allclose(gd[s], rd[s], rtol=REL, atol=1e-30):
             continue
-        # a near-tie at the K-th neighbour swaps members of equal distance
+        members = set(gi[s].tolist()) | set(ri[s].tolist())
+        if members & excused_nodes:
+            excused.add(s)
+            continue
+        # a near-tie at the K-th neighbour swaps members of equal distance;
+        # the members both lists share must agree in distance
         kth = rd[s][rd[s] < np.inf].max()
         only = set(gi[s].tolist()) ^ set(ri[s].tolist())
-        dmap = dict(zip(ri[s].tolist(), rd[s].tolist()))
-        dmap.update({k: v for k, v in zip(gi[s].tolist(), gd[s].tolist()) if k not in dmap})
-        if all(abs(dmap[n] - kth) <= 10 * REL * kth for n in only):
+        dr = dict(zip(ri[s].tolist(), rd[s].tolist()))
+        dg = dict(zip(gi[s].tolist(), gd[s].tolist()))
+        shared_ok = all(abs(dg[n] - dr[n]) <= REL * dr[n] for n in dr.keys() & dg.keys())
+        dmap = {**dg, **dr}
+        if shared_ok and all(abs(dmap[n] - kth) <= KNN_TIE_REL * kth for n in only):
+            excused.add(s)
             continue
-        mismatched += 1
-    assert mismatched <= tol_frac * N, f"{mismatched} K-NN lists differ"
-    return mismatched
+        unexplained.append(s)
+    assert not unexplained, f"{len(unexplained)} K-NN lists differ: {unexplained[:10]}"
+    return excused
 
 
-def check_flow(g, r, epe_mean=EPE_MEAN):
+def _cov_kappa(pos, w):
+    """Condition number of the weighted covariance of neighbour positions."""
+    c = pos - (w[:, None] * pos).sum(0) / w.sum()
+    cov = (w[:, None, None] * c[:, :, None] * c[:, None, :]).sum(0) / w.sum()
+    ev = np.linalg.eigvalsh(cov)
+    return float(ev[1] / ev[0]) if ev[0] > 0 else np.inf
+
+
+def check_params(sc, g, r, K, a, mode, wpow, skip):
+    """Per-match models against the oracle's for every source whose list
+    matched (see the module docstring for the bound).  Returns the largest
+    ratio of error to bound seen."""
+    m = sc.matches.astype(np.float64)
+    pos, disp = m[:, :2], m[:, 2:] - m[:, :2]
+    Pg, Pr = g["params"].astype(np.float64), r["params"]
+    ri, rd, gd = r["knn_idx"][:, :K], r["knn_d"][:, :K], g["knn_d"][:, :K].astype(np.float64)
+    worst, bad = 0.0, []
+    for s in range(ri.shape[0]):
+        if ri[s, 0] < 0 or s in skip:
+            continue
+        nb = ri[s][ri[s] >= 0]
+        dp = pos[nb] - pos[s]
+        dB = (Pg[s, :4] - Pr[s, :4]).reshape(2, 2)
+        err = np.abs(dp @ dB.T + (Pg[s, 4:] - Pr[s, 4:])).max()
+        S = np.abs(disp[s]).max() + np.abs(disp[nb] - disp[s]).max()
+        kappa = 1.0
+        if mode == 1 and r["status"][s] == 0:
+            k = np.exp(-a * rd[s][: len(nb)])
+            kappa = min(_cov_kappa(pos[nb], k if wpow == 1 else k * k), 1e3)
+        dd = np.abs(gd[s][: len(nb)] - rd[s][: len(nb)]).max()
+        tol = S * (FIT_REL * max(1.0, kappa) + 2.0 * a * dd) + 1e-6
+        worst = max(worst, err / tol)
+        if err > tol:
+            bad.append((s, err, tol))
+    assert not bad, f"{len(bad)} models differ: {bad[:5]}"
+    return worst
+
+
+def check_flow(g, r, epe_mean=EPE_MEAN, excused_pixels=None):
     fg = g["flow"].astype(np.float64)
     fr = r["flow"]
     if np.isnan(fr).all():
         assert np.isnan(fg).all()
-        return 0.0
+        return 0.0, 0.0
     epe = np.linalg.norm(fg - fr, axis=2)
     assert np.isfinite(epe).all()
     assert epe.mean() <= epe_mean, f"mean EPE {epe.mean():.3e}"
-    return float(epe.mean())
+    keep = np.ones(epe.shape, bool) if excused_pixels is None else ~excused_pixels
+    mx = float(epe[keep].max()) if keep.any() else 0.0
+    assert mx <= MAX_EPE, f"max EPE {mx:.3e} at a pixel with no excused label or list"
+    return float(epe.mean()), mx
 
 
-def full_check(ctx, sc, K=None, a=None, mode=None, conn=8, wpow=2, knn_tol=0.0):
+def full_check(ctx, sc, K=None, a=None, mode=None, conn=8, wpow=2):
     K = sc.K if K is None else K
+    a = sc.a if a is None else a
+    mode = sc.mode if mode is None else mode
     g = gpu_stages(ctx, sc, K, a, mode)
     r = ref_stages(sc, K, a, mode, conn, wpow)
     st = g["stats"]
@@ -126,9 +198,12 @@ def full_check(ctx, sc, K=None, a=None, mode=None, conn=8, wpow=2, knn_tol=0.0):
         assert np.isnan(g["flow"]).all()
         return dict(label_diff=0, epe=0.0)
     assert st["status"] == 0, st
-    nd = check_labels(sc, g, r, conn)
-    check_graph(g, r, nd)
+    diff = check_labels(sc, g, r, conn)
+    enodes = check_graph(g, r, diff)
     Keff = r["K"]
-    check_knn(g, r, Keff, tol_frac=knn_tol if nd == 0 else max(knn_tol, 0.01))
-    epe = check_flow(g, r)
-    return dict(label_diff=nd, epe=epe, stats=st)
+    kex = check_knn(g, r, Keff, enodes)
+    fit_ratio = check_params(sc, g, r, Keff, a, mode, wpow, kex)
+    excused_px = diff | np.isin(g["L"], list(kex))
+    epe, epe_max = check_flow(g, r, excused_pixels=excused_px)
+    return dict(label_diff=int(diff.sum()), excused_edges_nodes=len(enodes), excused_lists=len(kex),
+                fit_err_over_bound=round(fit_ratio, 4), epe=epe, epe_max=epe_max, stats=st)

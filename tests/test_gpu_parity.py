@@ -43,7 +43,7 @@ def test_config_scenes(ctx, i, mode):
     1242x375 road scene (NW and LA)."""
     sc = config_scene(i, mode=mode)
     _announce(f"{sc.name} mode={mode}")
-    res = parity.full_check(ctx, sc, knn_tol=0.001)
+    res = parity.full_check(ctx, sc)
     print(res, flush=True)
 
 
@@ -53,7 +53,7 @@ def test_largest_served_size(ctx, K):
     40000 matches, every stage against the oracle."""
     sc = serve_scene(dict(H=1080, W=2048, N=40000, K=K, seed=7001 + K))
     _announce(sc.name)
-    res = parity.full_check(ctx, sc, knn_tol=0.001)
+    res = parity.full_check(ctx, sc)
     print(res, flush=True)
 
 
@@ -123,8 +123,12 @@ def test_global_affine_recovered(ctx):
     t_cost = torch.from_numpy(sc.cost).cuda()
     flow = ctx.interp(t_cost, torch.from_numpy(m).cuda(), 32, 1.0, 1).cpu().numpy()
     ys, xs = np.mgrid[0:H, 0:W]
-    np.testing.assert_allclose(flow[..., 0], (A[0, 0] - 1) * xs + A[0, 1] * ys + t[0], atol=2e-3)
-    np.testing.assert_allclose(flow[..., 1], A[1, 0] * xs + (A[1, 1] - 1) * ys + t[1], atol=2e-3)
+    # FP32 rounding: centred sums of 32 terms (relative ~2e-6) move B by
+    # ~1e-7 and c by ~1e-6 px, i.e. ~1e-5 px at 30 px from the match
+    err = np.maximum(np.abs(flow[..., 0] - ((A[0, 0] - 1) * xs + A[0, 1] * ys + t[0])),
+                     np.abs(flow[..., 1] - (A[1, 0] * xs + (A[1, 1] - 1) * ys + t[1])))
+    print(f"global affine: max error {err.max():.2e} px", flush=True)
+    assert err.max() <= 1e-4
 
 
 def test_label_invariance_under_cost_scaling(ctx):
@@ -205,3 +209,24 @@ def test_pass_budget_does_not_change_results():
                 torch.cuda.synchronize()
     for f in flows64[1:]:
         assert torch.equal(flows64[0], f)
+
+
+def test_pass_budget_bitwise_on_large_scene():
+    """On the 1024 x 436 scene: 2 passes (the finisher does the rest), 5, 12
+    and the automatic budget over repeated calls give bitwise identical D,
+    L and flow -- the transform reaches the same fixpoint whatever the
+    schedule."""
+    import torch
+    import paper_1501_02565_amd as epic
+    sc = config_scene(2)
+    _announce(f"{sc.name} pass budgets")
+    ws = epic.workspace_bytes(sc.H, sc.W, sc.N, sc.K)
+    outs = []
+    for passes, calls in ((2, 1), (5, 1), (12, 1), (0, 4)):
+        with epic.Context(0, ws, passes=passes) as c:
+            for _ in range(calls):
+                g = parity.gpu_stages(c, sc)
+            outs.append(g)
+    for g in outs[1:]:
+        for k in ("D", "L", "flow"):
+            np.testing.assert_array_equal(outs[0][k], g[k])

@@ -114,3 +114,36 @@ def test_route_everything_to_fp64_agrees():
     assert g["stats"]["n_fp64_fits"] == g["stats"]["n_used"]
     r = parity.ref_stages(sc)
     parity.check_flow(g, r)
+
+
+def _line_scene(delta):
+    """Ten matches on one pixel row and one a sub-pixel distance `delta`
+    off it, every match a neighbour of every other (K = N) with equal weights
+    (a = 0): each neighbourhood has the same covariance eigenvalue ratio."""
+    sc = random_case(16, 64, 11, seed=41, K=11)
+    m = np.zeros((11, 4), np.float32)
+    m[:10, 0] = 2 + 5 * np.arange(10)
+    m[:10, 1] = 8
+    m[10, 0], m[10, 1] = 24.6, 8 + delta
+    p = m[:, :2].astype(np.float64)
+    m[:, 2:] = p + p @ np.array([[0.02, -0.01], [0.015, 0.03]]).T + np.array([1.5, -2.0])
+    sc.matches, sc.K, sc.a = m, 11, 0.0
+    pos = m[:, :2].astype(np.float64) - m[:, :2].astype(np.float64).mean(0)
+    ev = np.linalg.eigvalsh(pos.T @ pos / len(pos))
+    return sc, ev[0] / ev[1]
+
+
+@pytest.mark.parametrize("delta,degenerate", [(5e-3, False), (5e-4, True)])
+def test_degeneracy_boundary_through_fp64_route(ctx32, delta, degenerate):
+    """Near-collinear neighbourhoods on both sides of the degeneracy
+    threshold (eigenvalue ratio 1e-9): ~1e-8 is solved as LA, ~1e-10 falls
+    back to NW.  Both are far below the FP32 routing threshold, so the
+    decision is taken in the FP64 re-accumulation, as in the oracle."""
+    sc, ratio = _line_scene(delta)
+    print(f"[case] line + 1, ratio {ratio:.2e}", flush=True)
+    assert (ratio < 1e-9) == degenerate and 0.03 < abs(np.log10(ratio / 1e-9)) and ratio < 1e-7
+    res = parity.full_check(ctx32, sc)
+    st = res["stats"]
+    r = parity.ref_stages(sc)
+    assert st["n_fp64_fits"] == 11
+    assert st["n_degenerate"] == int((r["status"] == 2).sum()) == (11 if degenerate else 0)

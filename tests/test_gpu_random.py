@@ -45,7 +45,7 @@ def test_random_sweep():
             sc = random_case(c["H"], c["W"], c["N"], seed=c["seed"], K=c["K"], mode=c["mode"],
                              outside=min(c["outside"], c["N"] - 1), duplicates=min(c["dup"], c["N"] // 3))
             if c["prec"] == 0:
-                parity.full_check(ctx, sc, conn=c["conn"], wpow=c["wpow"], knn_tol=0.001)
+                parity.full_check(ctx, sc, conn=c["conn"], wpow=c["wpow"])
                 continue
             g = parity.gpu_stages(ctx, sc)
             r = parity.ref_stages(sc, conn=c["conn"], wpow=c["wpow"])

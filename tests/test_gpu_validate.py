@@ -88,3 +88,27 @@ def test_validation_in_a_batch():
             cost, matches, K, a, mode = probs[i]
             ref = plain.interp(cost, matches, K=K, a=a, mode=mode).cpu().numpy()
             np.testing.assert_array_equal(flows[i], ref)
+
+
+def test_knn_table_overflow_is_reported():
+    """A match whose cell touches more than the largest K-NN table holds
+    (a cheap row shared by one match, 2 x 2200 matches along it): every
+    search reaches it and overflows.  The pair reports EPIC_ERR_CAPACITY
+    instead of a silently zero model."""
+    import torch
+    import paper_1501_02565_amd as epic
+    H, W = 3, 2200
+    cost = np.ones((H, W), np.float32)
+    cost[1, :] = 1e-4
+    m = np.zeros((2 * W + 1, 4), np.float32)
+    m[0, :2] = (0, 1)                               # the hub: all of row 1 is its cell
+    m[1:W + 1, 0], m[1:W + 1, 1] = np.arange(W), 0
+    m[W + 1:, 0], m[W + 1:, 1] = np.arange(W), 2
+    m[:, 2:] = m[:, :2] + 1.0
+    print(f"[case] hub {H}x{W}, {len(m)} matches, K=100", flush=True)
+    with epic.Context(0, epic.workspace_bytes(H, W, len(m), 100)) as c:
+        flow = c.interp(torch.from_numpy(cost).cuda(), torch.from_numpy(m).cuda(), 100, 1.0, 1)
+        st = c.stats(0)
+    print(st, flush=True)
+    assert st["status"] == epic.ERR_CAPACITY
+    assert np.isfinite(flow.cpu().numpy()).all()
