@@ -74,23 +74,100 @@ def measured_traffic(stage):
     return None
 
 
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(sc, seconds):
     """The FP64 oracle on the host cores, on the same scene, repeated for a
-    bounded time."""
+    bounded time: once with all its OpenMP threads (the reported value) and
+    once on one core (the paper's setting)."""
     from oracle import epic_ref
     epic_ref.lib()
     cores = epic_ref.max_threads()
-    reps, t0 = 0, time.perf_counter()
-    while True:
-        epic_ref.interp(sc.cost, sc.matches, sc.K, sc.a, sc.mode)
-        reps += 1
-        el = time.perf_counter() - t0
-        if (el >= seconds and reps >= 2) or reps >= 200:
-            break
-    mpix = reps * sc.H * sc.W / el / 1e6
-    return {"value": round(mpix, 4), "unit": "Mpix/s", "cores": cores, "kind": "oracle",
+
+    def timed(threads, budget):
+        epic_ref.set_threads(threads)
+        reps, t0 = 0, time.perf_counter()
+        while True:
+            epic_ref.interp(sc.cost, sc.matches, sc.K, sc.a, sc.mode)
+            reps += 1
+            el = time.perf_counter() - t0
+            if (el >= budget and reps >= 2) or reps >= 200:
+                break
+        return reps, el
+
+    reps, el = timed(cores, seconds)
+    reps1, el1 = timed(1, seconds)
+    epic_ref.set_threads(cores)
+    px = sc.H * sc.W
+    return {"value": round(reps * px / el / 1e6, 4), "unit": "Mpix/s", "cores": cores, "kind": "oracle",
             "sample": f"{reps} full interpolations of the {sc.W}x{sc.H} scene "
-                      f"({sc.N} matches, K={sc.K}) in {el:.1f} s"}
+                      f"({sc.N} matches, K={sc.K}) in {el:.1f} s on {cores} threads",
+            "single_core": {"value": round(reps1 * px / el1 / 1e6, 4), "unit": "Mpix/s", "cores": 1,
+                            "ms_per_call": round(el1 / reps1 * 1e3, 1),
+                            "sample": f"{reps1} full interpolations in {el1:.1f} s on 1 thread"},
+            "cpu_model": cpu_model(), "nproc": os.cpu_count()}
+
+
+def copy_bandwidth(torch, nbytes=256 << 20, reps=20):
+    """A plain device-to-device copy of `nbytes`, timed with HIP events:
+    the bandwidth HBM actually gives a streaming kernel on this GPU."""
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    return {"bytes_per_copy": 2 * nbytes, "ms": round(ms, 4), "gbs": round(2 * nbytes / (ms * 1e-3) / 1e9, 1)}
+
+
+def error_vs_oracle(ctx, sc, np, torch):
+    """Every result's error against the FP64 oracle: relative D error where
+    labels agree, label disagreement, endpoint error of the flow."""
+    from oracle import epic_ref
+    dev = torch.device("cuda:0")
+    g = ctx.debug_stages(torch.from_numpy(sc.cost).to(dev), torch.from_numpy(sc.matches).to(dev),
+                         sc.K, sc.a, sc.mode)
+    r = epic_ref.stages(sc.cost, sc.matches, sc.K, sc.a, sc.mode)
+    D, L, f = g["D"].cpu().numpy().astype(np.float64), g["L"].cpu().numpy(), g["flow"].cpu().numpy()
+    same = L == r["L"]
+    drel = np.abs(D[same] - r["D"][same]) / np.maximum(r["D"][same], 1e-30)
+    epe = np.linalg.norm(f.astype(np.float64) - r["flow"], axis=2)
+    return {"max_rel_D_err": float(drel.max()), "mean_rel_D_err": float(drel.mean()),
+            "label_disagreement_pct": float(100.0 * (~same).mean()),
+            "mean_epe_px": float(epe.mean()), "max_epe_px": float(epe.max())}
+
+
+def latency(ctx, sc, torch, mode, reps=20, warm=3):
+    """Median wall latency of one call (enqueue to completion) on the plain
+    single-pair path."""
+    dev = torch.device("cuda:0")
+    c = torch.from_numpy(sc.cost).to(dev)
+    m = torch.from_numpy(sc.matches).to(dev)
+    out = torch.empty((sc.H, sc.W, 2), dtype=torch.float32, device=dev)
+    ts = []
+    for i in range(warm + reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.interp(c, m, sc.K, sc.a, mode, out=out)
+        torch.cuda.synchronize()
+        if i >= warm:
+            ts.append(time.perf_counter() - t0)
+    ms = sorted(ts)[len(ts) // 2] * 1e3
+    return {"workload": sc.name, "mode": "LA" if mode == 1 else "NW", "K": sc.K, "a": sc.a,
+            "p50_ms": round(ms, 4), "mpix_s": round(sc.H * sc.W / ms / 1e3, 1)}
 
 
 def batched_form(args, np, torch, epic):
@@ -150,8 +227,11 @@ def batched_form(args, np, torch, epic):
     for i in (0, 21, 42, 63):
         ref = epic_ref.interp(scs[i].cost, scs[i].matches, scs[i].K, scs[i].a, scs[i].mode)[0]
         epes.append(float(np.linalg.norm(flows[i].astype(np.float64) - ref, axis=2).mean()))
-    out = {"workload": f"batch of 64 mixed pairs, {px / 1e6:.2f} Mpx, {sum(sc.N for sc in scs)} matches",
+    nm = sum(sc.N for sc in scs)
+    path_gbs = (36.0 * px + 150.0 * nm) / (ms_batch * 1e-3) / 1e9
+    out = {"workload": f"batch of 64 mixed pairs, {px / 1e6:.2f} Mpx, {nm} matches",
            "mpix_s": round(px / ms_batch / 1e3, 2), "ms_per_batch": round(ms_batch, 4),
+           "path_roofline": {"achieved": round(path_gbs, 2), "frac": round(path_gbs / HBM_PEAK_GBS, 6)},
            "plain_mpix_s": None if args.no_plain else round(px / ms_plain / 1e3, 2),
            "plain_ms": None if args.no_plain else round(ms_plain, 4),
            "speedup_vs_plain": None if args.no_plain else round(ms_plain / ms_batch, 3),
@@ -161,37 +241,28 @@ def batched_form(args, np, torch, epic):
     return out
 
 
-def served_form(args, np, torch, epic, precision):
-    """Poisson stream (200 req/s) of mixed-size pairs through the continuous
-    batching server; latency = completion - arrival."""
-    from paper_1501_02565_amd.serve import GpuExecutor, Request, Server, percentile_ms
-    from scenes import serve_scene, serve_stream
-    stream = serve_stream(args.served_requests)
-    pool = {}
-    reqs = []
-    def pinned(a):
-        # request inputs arrive in page-locked host memory (a DMA-able receive
-        # buffer), so their upload runs on the slot's stream
-        t = torch.empty(a.shape, dtype=torch.float32, pin_memory=True)
-        t.numpy()[...] = a
-        return t
-    for i, r in enumerate(stream):
-        key = (r["H"], r["W"], r["K"])
-        if key not in pool:
-            sc = serve_scene(r)
-            pool[key] = (sc, pinned(sc.cost), pinned(sc.matches))
-        sc, pc, pm = pool[key]
-        reqs.append(Request(i, r["arrival"], sc.H, sc.W, sc.N, sc.K, sc.a, sc.mode, pc.numpy(), pm.numpy()))
+def served_form(args, np, torch, epic, precision, reqs_in, samples):
+    """Poisson stream (mean 5 ms between arrivals) of mixed-size pairs, each
+    with its own match count, through the continuous-batching server;
+    latency = completion - arrival.  Then the same requests all queued at
+    once (the server saturated): pixels over that wall time is the served
+    capacity.  `samples` (request ids) keep their flows for the oracle."""
+    from paper_1501_02565_amd.serve import GpuExecutor, Server, percentile_ms
+
+    def fresh(r, arrival):
+        return dataclasses.replace(r, arrival=arrival, admitted=None, done=None, status="waiting",
+                                   batch=-1, flow=None)
     ex = GpuExecutor(slots=2, slot_workspace=args.served_budget // 2, precision=precision)
     # the loop polls without sleeping and wakes 0.3 ms before each arrival
     srv = Server(ex, args.served_budget, max_batch=64, idle_s=0.0, wake_early_s=3e-4)
     # warm up every kernel variant once
-    srv_w = Server(ex, args.served_budget, max_batch=64)
-    srv_w.run([dataclasses.replace(reqs[0], rid=-1, arrival=0.0)])
+    Server(ex, args.served_budget, max_batch=64).run([fresh(reqs_in[0], 0.0)])
+    reqs = [fresh(r, r.arrival) for r in reqs_in]
     t0 = time.perf_counter()
     done = srv.run(reqs)
     wall = time.perf_counter() - t0
     ok = [r for r in done if r.status == "done"]
+    assert all(r.stats["status"] == 0 for r in ok), [r.stats for r in ok if r.stats["status"]][:3]
     # each result alone equals its result in the mix
     ident, max_epe = 0, 0.0
     sample = ok[:: max(1, len(ok) // 16)][:16]
@@ -202,17 +273,80 @@ def served_form(args, np, torch, epic, precision):
         mixed = r.flow.cpu().numpy()
         ident += int(np.array_equal(alone, mixed))
         max_epe = max(max_epe, float(np.linalg.norm(alone.astype(np.float64) - mixed, axis=2).mean()))
-    ex.close()
+    kept = {r.rid: r.flow.cpu().numpy() for r in ok if r.rid in samples}
     px = sum(r.pixels for r in ok)
+    # saturation: every request waiting at t = 0
+    srv_sat = Server(ex, args.served_budget, max_batch=64, idle_s=0.0)
+    sat = [fresh(r, 0.0) for r in reqs_in]
+    t0 = time.perf_counter()
+    srv_sat.run(sat)
+    wall_sat = time.perf_counter() - t0
+    ex.close()
+    span = max(r.arrival for r in reqs_in)
     out = {"precision": "fp64-everywhere" if precision else "fp32",
            "requests": len(done), "served": len(ok), "rejected": len(done) - len(ok),
            "p50_ms": round(percentile_ms([r.latency for r in ok], 50), 3),
            "p99_ms": round(percentile_ms([r.latency for r in ok], 99), 3),
-           "mpix_s": round(px / wall / 1e6, 2), "wall_s": round(wall, 3), "batches": srv.batches,
-           "overlapped_batches": srv.overlap_events,
+           "capacity_mpix_s": round(sum(r.pixels for r in sat) / wall_sat / 1e6, 2),
+           "capacity_wall_s": round(wall_sat, 3), "capacity_batches": srv_sat.batches,
+           "offered_load_mpix_s": round(px / span / 1e6, 2), "wall_s": round(wall, 3),
+           "batches": srv.batches, "overlapped_batches": srv.overlap_events,
            "alone_vs_mix": {"checked": len(sample), "bitwise_identical": ident,
                             "max_mean_epe_px": max_epe}}
     log(f"bench: served {out}")
+    return out, kept
+
+
+def served_pair(args, np, torch, epic):
+    """Both served paths (FP32 and FP64-everywhere) on one stream, with each
+    path's error against the oracle on 16 sampled requests."""
+    from oracle import epic_ref
+    from paper_1501_02565_amd.serve import Request
+    from scenes import serve_bases, serve_stream
+    t0 = time.perf_counter()
+    stream = serve_stream(args.served_requests)
+    bases = serve_bases()
+    pinned_cost = {}
+
+    def pinned(a):
+        # request inputs arrive in page-locked host memory (a DMA-able receive
+        # buffer), so their upload runs on the slot's stream
+        t = torch.empty(a.shape, dtype=torch.float32, pin_memory=True)
+        t.numpy()[...] = a
+        return t
+    reqs, scenes = [], {}
+    for i, r in enumerate(stream):
+        key = (r["H"], r["W"])
+        if key not in pinned_cost:
+            pinned_cost[key] = pinned(bases[key].cost)
+        sc = bases[key].request(r)
+        pm = pinned(sc.matches)
+        reqs.append(Request(i, r["arrival"], sc.H, sc.W, sc.N, sc.K, sc.a, sc.mode,
+                            pinned_cost[key].numpy(), pm.numpy()))
+        scenes[i] = sc
+    log(f"bench: {len(reqs)} served requests drawn in {time.perf_counter() - t0:.1f} s "
+        f"(N {min(r.N for r in reqs)}..{max(r.N for r in reqs)})")
+    samples = set(range(0, len(reqs), max(1, len(reqs) // 16)))
+    out, flows = {}, {}
+    for name, prec in (("fp32", 0), ("fp64", 1)):
+        out[name], flows[name] = served_form(args, np, torch, epic, prec, reqs, samples)
+    t0 = time.perf_counter()
+    epes = {"fp32": [], "fp64": []}
+    for rid in sorted(samples):
+        sc = scenes[rid]
+        ref = epic_ref.interp(sc.cost, sc.matches, sc.K, sc.a, sc.mode)[0]
+        for name in epes:
+            if rid in flows[name]:
+                e = np.linalg.norm(flows[name][rid].astype(np.float64) - ref, axis=2)
+                epes[name].append((float(e.mean()), float(e.max())))
+    for name in epes:
+        v = epes[name]
+        out[name]["error_vs_oracle"] = {"sampled": len(v),
+                                        "mean_epe_px": float(np.mean([a for a, _ in v])) if v else None,
+                                        "worst_mean_epe_px": max(a for a, _ in v) if v else None,
+                                        "max_epe_px": max(b for _, b in v) if v else None}
+    log(f"bench: served oracle check of {len(samples)} requests in {time.perf_counter() - t0:.1f} s: "
+        + ", ".join(f"{k} {out[k]['error_vs_oracle']}" for k in epes))
     return out
 
 
@@ -221,7 +355,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--cpu-seconds", type=float, default=8.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tile", default="32x16", help="geodesic tile WxH")
     ap.add_argument("--precision", type=int, default=0, choices=[0, 1],
@@ -321,25 +455,32 @@ def main():
                 "kernel": dom, "kernel_ms": round(dom_ms, 5),
                 "algorithmic_bytes": nbytes}
 
-    # parity spot check of the timed output against the oracle
-    from oracle import epic_ref
-    ref, rc, _ = epic_ref.interp(sc.cost, sc.matches, sc.K, sc.a, sc.mode)
-    epe = np.linalg.norm(flow.cpu().numpy().astype(np.float64) - ref, axis=2)
-    log(f"bench: mean EPE vs oracle {epe.mean():.3e} px (max {epe.max():.3e})")
+    # the path as a whole against the HBM roofline: 36 B per pixel plus
+    # ~150 B per match of algorithmic traffic per step
+    path_bytes = 36.0 * HW + 150.0 * sc.N
+    path_gbs = path_bytes / (ms_step * 1e-3) / 1e9
+    roofline["path"] = {"algorithmic_bytes": path_bytes, "achieved": round(path_gbs, 2),
+                        "frac": round(path_gbs / HBM_PEAK_GBS, 6)}
 
+    # error of the timed result against the oracle (every stage)
+    err = error_vs_oracle(ctx, sc, np, torch)
+    log(f"bench: error vs oracle {err}")
     ctx.close()
+
+    # latency of the other single-pair workloads (NW and LA on the road scene)
+    lat = []
+    with epic.Context(0, epic.workspace_bytes(436, 1242, 10000, 100)) as c2:
+        for i, mode in ((1, 1), (3, 1), (3, 0)):
+            s_i = config_scene(i, mode=mode)
+            lat.append(latency(c2, s_i, torch, mode))
+    log(f"bench: latency {lat}")
+    copy = copy_bandwidth(torch)
+    roofline["copy_kernel_gbs"] = copy["gbs"]
+    log(f"bench: device copy {copy}")
     if args.calibrate_copy:
-        src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
         log("bench: calibration copy of 256 MiB done")
     batched = None if args.no_batched else batched_form(args, np, torch, epic)
-    served = None
-    if not args.no_served:
-        served = {"fp32": served_form(args, np, torch, epic, 0),
-                  "fp64": served_form(args, np, torch, epic, 1)}
+    served = None if args.no_served else served_pair(args, np, torch, epic)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -361,9 +502,10 @@ def main():
         "dtype": "f64" if args.precision == 1 else "f32",
         "data": "synthetic",
         "config": {"workload": sc.name, "H": sc.H, "W": sc.W, "N": sc.N, "K": sc.K,
-                   "a": sc.a, "mode": "LA", "mean_epe_vs_oracle_px": float(epe.mean()),
+                   "a": sc.a, "mode": "LA", "error_vs_oracle": err,
                    "stage_ms": {k: round(v, 5) for k, v in stages.items()},
-                   "graph_replay_ms_per_step": round(graph_ms, 5)},
+                   "graph_replay_ms_per_step": round(graph_ms, 5),
+                   "latency_other_configs": lat},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "batched": batched,

@@ -28,6 +28,8 @@ __all__ = [
     "random_case",
     "batch_scenes",
     "serve_stream",
+    "serve_bases",
+    "ServeBase",
     "CONFIG_PARAMS",
 ]
 
@@ -338,6 +340,52 @@ def serve_stream(n_requests=2000, seed=5000, mean_gap_s=0.005):
         reqs.append(dict(arrival=float(t[i]), H=H, W=W, N=n, K=K,
                          seed=seed + 1 + i))
     return reqs
+
+
+class ServeBase:
+    """One image of the served stream's size class: 4 layers (t ~ U[-32, 32])
+    with their cost map, motion and saliency field.  Requests of this size
+    draw their own matches from it (``ServeBase.request``)."""
+
+    def __init__(self, H, W, seed):
+        rng = np.random.default_rng(seed)
+        layer = np.zeros((H, W), np.int32)
+        params = [(rng.uniform(-0.05, 0.05, (2, 2)), rng.uniform(-32, 32, 2), ((W - 1) / 2, (H - 1) / 2))]
+        for li in range(1, 4):
+            poly, ctr = _star_polygon(rng, H, W)
+            layer[_fill_polygon(poly, H, W)] = li
+            params.append((rng.uniform(-0.05, 0.05, (2, 2)), rng.uniform(-32, 32, 2), ctr))
+        self.H, self.W = H, W
+        self.cost = _cost_from_layers(rng, layer)
+        self.flow = _motion(layer, params)
+        self.saliency = ndimage.gaussian_filter(rng.standard_normal((H, W)), 8.0)
+
+    def request(self, req) -> Scene:
+        """The request's own match set: grid at the stride its N needs, the
+        10% lowest-saliency points dropped, subsampled to exactly N, 5%
+        outliers with U[-32, 32] px displacements, all from its own seed."""
+        H, W, n = self.H, self.W, req["N"]
+        rng = np.random.default_rng(req["seed"])
+        gx, gy = _grid(H, W, _stride_for(H, W, n, 0.1))
+        keep = np.sort(np.argsort(self.saliency[gy, gx], kind="stable")[int(round(0.1 * len(gx))):])
+        gx, gy = gx[keep], gy[keep]
+        if len(gx) > n:
+            sel = np.sort(rng.choice(len(gx), n, replace=False))
+            gx, gy = gx[sel], gy[sel]
+        u = self.flow[gy, gx].copy()
+        n_out = int(round(0.05 * len(gx)))
+        if n_out:
+            idx = rng.choice(len(gx), n_out, replace=False)
+            u[idx] = rng.uniform(-32.0, 32.0, (n_out, 2))
+        m = np.empty((len(gx), 4), np.float32)
+        m[:, 0], m[:, 1] = gx, gy
+        m[:, 2], m[:, 3] = gx + u[:, 0], gy + u[:, 1]
+        return Scene(self.cost, m, req["K"], 1.0, 1, f"serve_{W}x{H}_n{len(gx)}_k{req['K']}")
+
+
+def serve_bases(seed=5000):
+    """One ServeBase per size of the served stream."""
+    return {(H, W): ServeBase(H, W, seed + 100000 + i) for i, (H, W) in enumerate(SERVE_SIZES)}
 
 
 def serve_scene(req) -> Scene:
