@@ -558,3 +558,49 @@ int epic_ref_interp(const float* C, int H, int W, const float* matches, int N,
     free(ki); free(kd); free(P); free(st);
     return 0;
 }
+
+/* ------------------------------------------------------------------ */
+/* consistency check of the matches (Sec. 5.1, "Pruning of matches")    */
+/* ------------------------------------------------------------------ */
+/* The interpolation is run once with the NW estimator (same K and a);
+ * a match is kept when its own displacement u_m differs from that first
+ * estimate at its pixel by at most prune_px (Euclidean norm).  At the
+ * pixel of match m the NW field is the model of cell m, whose value there
+ * is c_m.  Matches that are not placed on a pixel (outside the image, or
+ * sharing a pixel with a lower index) are not kept.  kept[] receives the
+ * original indices of the kept matches in increasing order; the count is
+ * returned. */
+int epic_ref_prune(const float* C, int H, int W, const float* matches, int N,
+                   int K, double a, int conn, double prune_px, int* kept)
+{
+    long HW = (long)H * W;
+    int* seed = (int*)malloc(sizeof(int) * (size_t)(N > 0 ? N : 1));
+    int outside = 0, dup = 0;
+    int used = epic_ref_seeds(H, W, matches, N, seed, &outside, &dup);
+    if (used == 0) { free(seed); return 0; }
+    double* D = (double*)malloc(sizeof(double) * HW);
+    int* L = (int*)malloc(sizeof(int) * HW);
+    epic_ref_voronoi(C, H, W, seed, N, conn, D, L);
+    long cap = 4 * HW + 1;
+    int* em = (int*)malloc(sizeof(int) * cap);
+    int* en = (int*)malloc(sizeof(int) * cap);
+    double* ew = (double*)malloc(sizeof(double) * cap);
+    long E = epic_ref_graph(C, H, W, D, L, conn, em, en, ew, cap);
+    int Kc = K < used ? K : used;
+    int* ki = (int*)malloc(sizeof(int) * (size_t)N * Kc);
+    double* kd = (double*)malloc(sizeof(double) * (size_t)N * Kc);
+    epic_ref_knn(N, seed, E, em, en, ew, Kc, ki, kd);
+    double* P = (double*)malloc(sizeof(double) * (size_t)N * 6);
+    int* st = (int*)malloc(sizeof(int) * (size_t)N);
+    epic_ref_fit(matches, N, seed, ki, kd, Kc, a, 0, 2, 0.0, P, st);
+    int nk = 0;
+    for (int m = 0; m < N; ++m) {
+        if (seed[m] < 0) continue;
+        double du = ((double)matches[4L * m + 2] - matches[4L * m + 0]) - P[6L * m + 4];
+        double dv = ((double)matches[4L * m + 3] - matches[4L * m + 1]) - P[6L * m + 5];
+        if (sqrt(du * du + dv * dv) <= prune_px) kept[nk++] = m;
+    }
+    free(seed); free(D); free(L); free(em); free(en); free(ew);
+    free(ki); free(kd); free(P); free(st);
+    return nk;
+}

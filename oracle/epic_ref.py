@@ -66,6 +66,8 @@ def lib():
         L.epic_ref_interp.argtypes = [P, i32, i32, P, i32, i32, f64, i32, i32,
                                       i32, f64, P, P]
         L.epic_ref_interp.restype = i32
+        L.epic_ref_prune.argtypes = [P, i32, i32, P, i32, i32, f64, i32, f64, P]
+        L.epic_ref_prune.restype = i32
         L.epic_ref_set_threads.argtypes = [i32]
         L.epic_ref_set_threads.restype = None
         L.epic_ref_max_threads.argtypes = []
@@ -221,3 +223,29 @@ def stages(cost, matches, K, a, mode, conn=8, wpow=2, deg_tau=DEG_TAU):
     out.update(D=D, L=L, em=em, en=en, ew=ew, K=Kc, knn_idx=ki, knn_d=kd,
                params=P, status=st, flow=flow)
     return out
+
+
+def prune(cost, matches, K, a, prune_px, conn=8):
+    """Consistency check of the matches (Sec. 5.1, "Pruning of matches"):
+    one NW interpolation, then the matches whose displacement differs from
+    that estimate at their own pixel by more than prune_px are removed.
+    Returns the original indices of the kept matches (increasing)."""
+    c = _f32(cost)
+    H, W = c.shape
+    m = _f32(matches).reshape(-1, 4)
+    kept = np.empty(max(m.shape[0], 1), np.int32)
+    n = lib().epic_ref_prune(_p(c), H, W, _p(m), m.shape[0], int(K), float(a),
+                             conn, float(prune_px), _p(kept))
+    return kept[:n].copy()
+
+
+def interp_pruned(cost, matches, K, a, mode, prune_px, conn=8, wpow=2, deg_tau=DEG_TAU):
+    """The interpolation of the matches that pass the consistency check
+    (Sec. 5.1).  Returns (flow, status, stats, kept indices)."""
+    kept = prune(cost, matches, K, a, prune_px, conn)
+    m = _f32(matches).reshape(-1, 4)[kept]
+    if len(kept) == 0:
+        H, W = np.shape(cost)
+        return np.full((H, W, 2), np.nan), -3, {}, kept
+    flow, rc, st = interp(cost, m, K, a, mode, conn, wpow, deg_tau)
+    return flow, rc, st, kept

@@ -517,3 +517,53 @@ def test_property_knn_bruteforce(seed, K):
         dist = dict(zip(idx.tolist(), d.tolist()))
         dist.update(zip(s["knn_idx"][src].tolist(), s["knn_d"][src].tolist()))
         assert all(math.isclose(dist[n], d[-1], rel_tol=1e-12) for n in only), (src, only)
+
+
+# ------------------------------------------------------- match pruning --
+
+def _grid_translation(outlier_at=None, outlier_u=(30.0, 30.0)):
+    """11 x 11 matches 5 px apart on a 60 x 60 image of constant cost 0.01,
+    all moving by (3, -2) except one planted outlier."""
+    g = 5 + 5 * np.arange(11)
+    ys, xs = np.meshgrid(g, g, indexing="ij")
+    m = np.zeros((121, 4), np.float32)
+    m[:, 0], m[:, 1] = xs.ravel(), ys.ravel()
+    u = np.tile([3.0, -2.0], (121, 1))
+    if outlier_at is not None:
+        u[outlier_at] = outlier_u
+    m[:, 2:] = m[:, :2] + u
+    return np.full((60, 60), 0.01, np.float32), m
+
+
+def test_prune_drops_a_planted_outlier(ref):
+    """Sec. 5.1: with graph distances of ~0.05 per grid step (weights near
+    1), the outlier's NW estimate is dominated by its 31 consistent
+    neighbours (about (4, -0.9), 40 px from its own displacement), while
+    each neighbour's estimate moves by at most ~1/27 of the outlier's
+    deviation (< 2 px): exactly the outlier goes."""
+    cost, m = _grid_translation(outlier_at=60)
+    kept = ref.prune(cost, m, 32, 1.0, 5.0)
+    assert kept.tolist() == [i for i in range(121) if i != 60]
+    # with no outlier nothing goes, even at a threshold of 1e-9 px: the NW
+    # estimate of a constant field is that constant, to rounding
+    cost, m = _grid_translation()
+    assert ref.prune(cost, m, 32, 1.0, 5.0).tolist() == list(range(121))
+    assert len(ref.prune(cost, m, 32, 1.0, 1e-9)) == 121
+
+
+def test_prune_compares_with_the_nw_field_at_the_match_pixel(ref):
+    """The decision is |u_m - F_NW(pixel of m)| <= threshold, F_NW being the
+    dense NW interpolation; matches outside the image or on a pixel held
+    by a lower index are never kept."""
+    sc = random_case(70, 90, 140, seed=9, K=20, outside=4, duplicates=5)
+    f, rc, _ = ref.interp(sc.cost, sc.matches, 20, sc.a, 0)
+    sp, _, _ = ref.seeds(sc.H, sc.W, sc.matches)
+    for thr in (0.5, 2.0, 5.0):
+        kept = ref.prune(sc.cost, sc.matches, 20, sc.a, thr)
+        want = []
+        for i in np.nonzero(sp >= 0)[0]:
+            y, x = divmod(int(sp[i]), sc.W)
+            u = sc.matches[i, 2:].astype(np.float64) - sc.matches[i, :2]
+            if np.linalg.norm(u - f[y, x]) <= thr:
+                want.append(int(i))
+        assert kept.tolist() == want
