@@ -170,6 +170,36 @@ def latency(ctx, sc, torch, mode, reps=20, warm=3):
             "p50_ms": round(ms, 4), "mpix_s": round(sc.H * sc.W / ms / 1e3, 1)}
 
 
+def pruned_leg(args, np, torch, epic, sc, steps=50):
+    """The headline call with the consistency check of the matches (Sec.
+    5.1, threshold 5 px): an NW pass, the compaction of the kept matches,
+    then the interpolation of those; its error against the oracle's pruned
+    interpolation."""
+    from oracle import epic_ref
+    dev = torch.device("cuda:0")
+    c = torch.from_numpy(sc.cost).to(dev)
+    m = torch.from_numpy(sc.matches).to(dev)
+    out = torch.empty((sc.H, sc.W, 2), dtype=torch.float32, device=dev)
+    with epic.Context(0, epic.workspace_bytes(sc.H, sc.W, sc.N, sc.K), prune_px=5.0) as ctx:
+        for _ in range(5):
+            ctx.interp(c, m, sc.K, sc.a, sc.mode, out=out)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            ctx.interp(c, m, sc.K, sc.a, sc.mode, out=out)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) / steps * 1e3
+        st = ctx.stats(0)
+    ref, rc, _, kept = epic_ref.interp_pruned(sc.cost, sc.matches, sc.K, sc.a, sc.mode, 5.0)
+    epe = np.linalg.norm(out.cpu().numpy().astype(np.float64) - ref, axis=2)
+    res = {"workload": sc.name + "_pruned5px", "ms_per_step": round(ms, 5),
+           "mpix_s": round(sc.H * sc.W / ms / 1e3, 1), "kept": st["n_used"], "pruned": st["n_pruned"],
+           "oracle_kept": int(len(kept)), "mean_epe_vs_oracle_px": float(epe.mean()),
+           "max_epe_vs_oracle_px": float(epe.max())}
+    log(f"bench: pruned {res}")
+    return res
+
+
 def batched_form(args, np, torch, epic):
     """The 64-pair mixed-size batch: one fused launch sequence per batch,
     captured as a HIP graph with the autotuned configuration, against the
@@ -474,6 +504,8 @@ def main():
             s_i = config_scene(i, mode=mode)
             lat.append(latency(c2, s_i, torch, mode))
     log(f"bench: latency {lat}")
+    # the consistency check of the matches (Sec. 5.1) before the same call
+    pruned = pruned_leg(args, np, torch, epic, sc)
     copy = copy_bandwidth(torch)
     roofline["copy_kernel_gbs"] = copy["gbs"]
     log(f"bench: device copy {copy}")
@@ -510,6 +542,7 @@ def main():
         "cpu_baseline": cpu,
         "batched": batched,
         "served": served,
+        "pruned": pruned,
     }
     print(json.dumps(out), flush=True)
 

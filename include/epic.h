@@ -114,6 +114,15 @@ typedef struct epic_options {
                                EPIC_ERR_COST and n_bad_cost in epic_stats and
                                its flow is filled with NaN; the other pairs of
                                a batch are unaffected                          */
+    float prune_px;         /* consistency check of the matches (Sec. 5.1,
+                               "Pruning of matches"): 0 (default) = off; > 0:
+                               every call first interpolates with NW (same K
+                               and a), removes the matches whose displacement
+                               differs from that estimate at their own pixel
+                               by more than prune_px pixels (the paper uses
+                               5), then interpolates the kept matches with the
+                               requested estimator.  Twice the work of a call
+                               without it; stats report n_pruned           */
 } epic_options;
 
 typedef struct epic_ctx epic_ctx;
@@ -192,6 +201,10 @@ typedef struct epic_stats {
     int tile_visits;       /* tiles processed by the geodesic transform     */
     int n_bad_cost;        /* cost values not finite and > 0 (counted only
                               with debug_validate)                          */
+    int n_pruned;          /* placed matches removed by the consistency check
+                              (prune_px > 0); the other counts then refer to
+                              the kept matches, except n_outside and
+                              n_duplicate, which count the original ones    */
 } epic_stats;
 int epic_get_stats(epic_ctx* ctx, int pair, epic_stats* out);
 
@@ -214,6 +227,20 @@ int epic_debug_stages(epic_ctx* ctx, const float* cost, int H, int W,
                       float* edge_w, int max_edges, int* n_edges,
                       int* knn_idx, float* knn_d, float* params, float* flow,
                       void* stream);
+
+/* The consistency check of the matches alone (Sec. 5.1, "Pruning of
+ * matches"): one NW interpolation (K, a as given) and the test
+ * |u_m - F_NW(p_m)| <= prune_px at every placed match, where u_m is the
+ * match's displacement and F_NW(p_m) the NW field at its pixel.
+ *   kept     device, N int32: the original indices of the kept matches in
+ *            increasing order (entries beyond the count are unspecified)
+ *   n_kept   device int32: their count
+ * Matches outside the image or on a pixel held by a lower index are never
+ * kept.  prune_px must be finite and > 0 (EPIC_ERR_ARG otherwise); other
+ * arguments as in epic_interp.  Asynchronous on `stream`. */
+int epic_prune(epic_ctx* ctx, const float* cost, int H, int W,
+               const float* matches, int N, int K, float a, float prune_px,
+               int* kept, int* n_kept, void* stream);
 
 /* Stage timing (instrumentation).  While enabled, every call records HIP
  * events between its stages on the call's stream (a ring of the last 64

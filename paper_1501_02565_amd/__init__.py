@@ -59,13 +59,17 @@ class Context:
     (0 = default; 128 or 256 with 32 x 16 tiles); like ``passes`` it only
     changes the speed.
     ``debug_validate`` makes every call check the cost map on the device
-    (finite and > 0); a pair that fails reports ERR_COST in its stats."""
+    (finite and > 0); a pair that fails reports ERR_COST in its stats.
+    ``prune_px`` > 0 runs the consistency check of the matches (Sec. 5.1)
+    before every interpolation: matches further than prune_px from a first
+    NW estimate at their pixel are removed (the paper uses 5)."""
 
     def __init__(self, device: int = 0, workspace: int | None = None, *,
                  connectivity: int = 8, la_weight_power: int = 2,
                  precision: int = 0, fp64_route: float = 1e-3,
                  degenerate_tau: float = 1e-9, tile: tuple[int, int] = (32, 16),
-                 passes: int = 0, geo_threads: int = 0, debug_validate: bool = False):
+                 passes: int = 0, geo_threads: int = 0, debug_validate: bool = False,
+                 prune_px: float = 0.0):
         torch = _torch()
         L = _lib.load()
         self.device = int(device)
@@ -74,7 +78,8 @@ class Context:
         self.workspace = int(workspace)
         self.options = _lib.Options(connectivity, la_weight_power, precision,
                                     fp64_route, degenerate_tau, tile[0], tile[1],
-                                    passes, int(geo_threads), int(bool(debug_validate)))
+                                    passes, int(geo_threads), int(bool(debug_validate)),
+                                    float(prune_px))
         torch.cuda.init()
         with torch.cuda.device(self.device):
             self._ctx = L.epic_create(self.device, self.workspace,
@@ -195,6 +200,24 @@ class Context:
         E = min(int(ne.item()), max_edges)
         return dict(D=D, L=L, em=em[:E], en=en[:E], ew=ew[:E], knn_idx=ki,
                     knn_d=kd, params=P, flow=flow, stats=st)
+
+    def prune(self, cost, matches, K: int, a: float, prune_px: float = 5.0, stream=None):
+        """The consistency check alone (synchronises): original indices of
+        the matches whose displacement is within prune_px of the NW
+        estimate at their pixel, as an int32 CUDA tensor."""
+        torch = _torch()
+        _check_tensor(cost, "cost", torch.float32)
+        _check_tensor(matches, "matches", torch.float32, (4,))
+        H, W = cost.shape
+        N = matches.shape[0]
+        kept = torch.empty(N, dtype=torch.int32, device=cost.device)
+        nk = torch.zeros(1, dtype=torch.int32, device=cost.device)
+        rc = _lib.load().epic_prune(self._ctx, cost.data_ptr(), H, W, matches.data_ptr(), N, int(K),
+                                    float(a), float(prune_px), kept.data_ptr(), nk.data_ptr(),
+                                    _stream_handle(stream))
+        if rc != OK:
+            raise EpicError(rc, "epic_prune")
+        return kept[: int(nk.item())]
 
     def profile(self, enable: bool = True) -> None:
         """Turns per-stage HIP-event timing of every call on or off."""

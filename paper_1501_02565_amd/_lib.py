@@ -20,7 +20,7 @@ SYMBOLS = ["epic_create", "epic_destroy", "epic_workspace_bytes", "epic_interp",
            "epic_interp_batch", "epic_get_stats", "epic_debug_stages",
            "epic_strerror", "epic_last_error", "epic_validate", "epic_profile",
            "epic_stage_times", "epic_stage_name", "epic_graph_capture",
-           "epic_graph_launch", "epic_graph_destroy"]
+           "epic_graph_launch", "epic_graph_destroy", "epic_prune"]
 
 
 class Options(ctypes.Structure):
@@ -33,7 +33,8 @@ class Options(ctypes.Structure):
                 ("tile_h", ctypes.c_int),
                 ("geo_passes", ctypes.c_int),
                 ("geo_threads", ctypes.c_int),
-                ("debug_validate", ctypes.c_int)]
+                ("debug_validate", ctypes.c_int),
+                ("prune_px", ctypes.c_float)]
 
 
 class Request(ctypes.Structure):
@@ -50,7 +51,7 @@ class Stats(ctypes.Structure):
                 ("n_outside", ctypes.c_int), ("n_duplicate", ctypes.c_int),
                 ("n_edges", ctypes.c_int), ("n_degenerate", ctypes.c_int),
                 ("n_fp64_fits", ctypes.c_int), ("tile_visits", ctypes.c_int),
-                ("n_bad_cost", ctypes.c_int)]
+                ("n_bad_cost", ctypes.c_int), ("n_pruned", ctypes.c_int)]
 
 
 _lib = None
@@ -87,6 +88,8 @@ def load():
     L.epic_debug_stages.argtypes = [P, P, i32, i32, P, i32, i32, f32, i32,
                                     P, P, P, P, P, i32, P, P, P, P, P, P]
     L.epic_debug_stages.restype = i32
+    L.epic_prune.argtypes = [P, P, i32, i32, P, i32, i32, f32, f32, P, P, P]
+    L.epic_prune.restype = i32
     L.epic_strerror.argtypes = [i32]
     L.epic_strerror.restype = ctypes.c_char_p
     L.epic_last_error.argtypes = []

@@ -76,6 +76,8 @@ size_t pair_bytes(int H, int W, int N, int precision) {
     b += align_up(4 * (size_t)N);     // K-NN overflow list share
     b += align_up(24 * (size_t)N);    // params
     b += align_up(4 * C_NCOUNTERS);
+    b += align_up(16 * (size_t)N);    // kept matches (consistency check)
+    b += align_up(4 * (size_t)N);     // their original indices
     return b;
 }
 
@@ -113,6 +115,7 @@ struct epic_ctx {
     bool prof_ok[kProfRing]{};
     int prof_next = 0;
     int prof_count = 0;
+    bool last_pruned = false;           // the last call ran the consistency check
 };
 
 extern "C" {
@@ -175,6 +178,7 @@ epic_ctx* epic_create(int device, size_t workspace_bytes, const epic_options* op
     o.geo_passes = 0;
     o.geo_threads = 0;
     o.debug_validate = 0;
+    o.prune_px = 0.0f;
     if (opts) {
         o = *opts;
         if (o.connectivity != 4) o.connectivity = 8;
@@ -189,6 +193,7 @@ epic_ctx* epic_create(int device, size_t workspace_bytes, const epic_options* op
         if (o.geo_passes > kMaxPasses - 1) o.geo_passes = kMaxPasses - 1;
         if (o.debug_validate != 1) o.debug_validate = 0;
         if (!(o.tile_h == 16 && (o.geo_threads == 128 || o.geo_threads == 256))) o.geo_threads = 0;
+        if (!(o.prune_px > 0.0f)) o.prune_px = 0.0f;     // off (also for NaN)
     }
     c->auto_passes = o.geo_passes == 0;
     c->passes = c->auto_passes ? kAutoPassesStart : o.geo_passes;
@@ -247,6 +252,12 @@ struct DebugOut {
     int* knn_idx = nullptr;
     float* knn_d = nullptr;
     float* params = nullptr;
+    // consistency check only (epic_prune): stop after it, write the kept
+    // original indices and their count
+    bool prune_only = false;
+    float prune_px = 0.0f;
+    int* kept = nullptr;
+    int* n_kept = nullptr;
 };
 
 // Where a call's descriptor table lives: the context's upload ring (default)
@@ -352,6 +363,8 @@ int run_pairs(epic_ctx* c, const epic_request* reqs, int n, hipStream_t stream, 
         P.adj = reinterpret_cast<uint4*>(take(16 * cap));
         P.params = reinterpret_cast<float*>(take(24 * (size_t)r.N));
         P.counters = reinterpret_cast<int*>(take(4 * C_NCOUNTERS));
+        P.matches_kept = reinterpret_cast<float*>(take(16 * (size_t)r.N));
+        P.kept_idx = reinterpret_cast<int*>(take(4 * (size_t)r.N));
         if (c->opt.precision == 1) {
             P.labels = reinterpret_cast<u32*>(take(4 * (size_t)HW));
             P.hval64 = reinterpret_cast<u64*>(take(8 * cap));
@@ -370,6 +383,8 @@ int run_pairs(epic_ctx* c, const epic_request* reqs, int n, hipStream_t stream, 
             P.dbg_ew = dbg->ew;
             P.dbg_max_edges = dbg->max_edges;
             P.dbg_n_edges = dbg->n_edges;
+            P.dbg_kept = dbg->kept;
+            P.dbg_n_kept = dbg->n_kept;
         }
     }
     if ((size_t)(cur - c->ws) > c->ws_bytes) return EPIC_ERR_WORKSPACE;
@@ -405,7 +420,7 @@ int run_pairs(epic_ctx* c, const epic_request* reqs, int n, hipStream_t stream, 
     }
 
     hipEvent_t* ev = nullptr;
-    if (c->prof && !tgt) {
+    if (c->prof && !tgt && !(dbg && dbg->prune_only)) {
         const int r = c->prof_next;
         c->prof_next = (c->prof_next + 1) % kProfRing;
         ev = c->prof_ev[r];
@@ -421,13 +436,6 @@ int run_pairs(epic_ctx* c, const epic_request* reqs, int n, hipStream_t stream, 
     auto mark = [&](int stage) {
         if (ev && e == hipSuccess) e = hipEventRecord(ev[stage + 1], stream);
     };
-    if (e == hipSuccess) e = launch_clear(dd, run, init_blocks, inline_desc ? hd : nullptr, n, stream);
-    mark(0);
-    // a pair whose cost map fails the check is not seeded (it then takes the
-    // path of a pair without usable matches)
-    if (e == hipSuccess && c->opt.debug_validate) e = launch_check_cost(dd, run, pix_blocks, stream);
-    if (e == hipSuccess) e = launch_seed(dd, run, seed_blocks, stream);
-    mark(1);
     // Automatic budget: the largest number of passes the recently finished
     // transforms needed (read when each call is issued; the value may come
     // from an older call while the last one is still running), plus one when
@@ -453,22 +461,51 @@ int run_pairs(epic_ctx* c, const epic_request* reqs, int n, hipStream_t stream, 
         const int floor_ = (c->opt.precision == 1 && hi != lo) ? kAutoPassesStart : kAutoPassesMin;
         return std::min(kMaxPasses - 1, std::max(floor_, hi + (hi == lo ? 0 : 1)));
     };
-    if (e == hipSuccess)
-        e = c->opt.precision == 1 ? launch_geodesic64(dd, run, budget(0), budget(1), stream)
-                                  : launch_geodesic(dd, run, tl.tw, tl.th, c->opt.geo_threads, budget(0), stream);
-    mark(2);
-    if (e == hipSuccess) e = launch_graph_emit(dd, run, emit_blocks, stream);
-    mark(3);
-    if (e == hipSuccess) e = launch_csr_scan(dd, run, stream);
-    mark(4);
-    if (e == hipSuccess) e = launch_csr_scatter(dd, run, slot_blocks, stream);
-    mark(5);
-    if (e == hipSuccess) e = launch_knn_fit(dd, run, src_blocks, kmax, stream);
-    mark(6);
+    // With the consistency check (Sec. 5.1) the sequence runs twice: first
+    // with NW fits and no assignment, then k_prune compacts the kept matches
+    // and points each pair's descriptor at them, and the second pass
+    // interpolates those.  Stage timing marks the second pass (its "clear"
+    // stage then spans the whole first pass).
+    const float prune_px = dbg && dbg->prune_only ? dbg->prune_px : c->opt.prune_px;
+    const bool two_pass = prune_px > 0.0f;
     bool any_flow = false;
     for (int i = 0; i < n; ++i) any_flow |= reqs[i].flow != nullptr;
-    if (e == hipSuccess && any_flow) e = launch_assign(dd, run, pix_blocks, stream);
-    mark(7);
+    for (int pass = two_pass ? 0 : 1; pass < 2 && e == hipSuccess; ++pass) {
+        const bool first = pass == 0;
+        const bool last = pass == 1;
+        run.force_nw = first ? 1 : 0;
+        run.keep_prune_counters = two_pass && last ? 1 : 0;
+        // the descriptor table travels inline only with the first launch of
+        // the call (the second pass reads the table k_prune rewrote)
+        const bool inl = inline_desc && (first || !two_pass);
+        if (e == hipSuccess) e = launch_clear(dd, run, init_blocks, inl ? hd : nullptr, inl ? n : 0, stream);
+        if (last) mark(0);
+        // a pair whose cost map fails the check is not seeded (it then takes
+        // the path of a pair without usable matches)
+        if (e == hipSuccess && c->opt.debug_validate) e = launch_check_cost(dd, run, pix_blocks, stream);
+        if (e == hipSuccess) e = launch_seed(dd, run, seed_blocks, stream);
+        if (last) mark(1);
+        if (e == hipSuccess)
+            e = c->opt.precision == 1 ? launch_geodesic64(dd, run, budget(0), budget(1), stream)
+                                      : launch_geodesic(dd, run, tl.tw, tl.th, c->opt.geo_threads, budget(0), stream);
+        if (last) mark(2);
+        if (e == hipSuccess) e = launch_graph_emit(dd, run, emit_blocks, stream);
+        if (last) mark(3);
+        if (e == hipSuccess) e = launch_csr_scan(dd, run, stream);
+        if (last) mark(4);
+        if (e == hipSuccess) e = launch_csr_scatter(dd, run, slot_blocks, stream);
+        if (last) mark(5);
+        if (e == hipSuccess) e = launch_knn_fit(dd, run, src_blocks, kmax, stream);
+        if (last) mark(6);
+        if (first) {
+            if (e == hipSuccess) e = launch_prune(dd, run, prune_px, stream);
+            if (dbg && dbg->prune_only) break;
+            continue;
+        }
+        if (e == hipSuccess && any_flow) e = launch_assign(dd, run, pix_blocks, stream);
+        mark(7);
+    }
+    c->last_pruned = two_pass && !(dbg && dbg->prune_only);
     if (e == hipSuccess && dbg && (dbg->D || dbg->L)) e = launch_unpack(dd, run, pix_blocks, dbg->D, dbg->L, stream);
     if (e == hipSuccess && dbg && dbg->params)
         e = hipMemcpyAsync(dbg->params, hd[0].params, 24 * (size_t)reqs[0].N, hipMemcpyDeviceToDevice, stream);
@@ -513,6 +550,19 @@ int epic_debug_stages(epic_ctx* ctx, const float* cost, int H, int W, const floa
     d.knn_d = knn_d;
     d.params = params;
     epic_request r{cost, H, W, matches, N, K, a, mode, flow};
+    return run_pairs(ctx, &r, 1, (hipStream_t)stream, &d);
+}
+
+int epic_prune(epic_ctx* ctx, const float* cost, int H, int W, const float* matches, int N, int K, float a,
+               float prune_px, int* kept, int* n_kept, void* stream) {
+    if (!ctx || !kept || !n_kept || !(prune_px > 0.0f) || !std::isfinite(prune_px)) return EPIC_ERR_ARG;
+    DebugOut d;
+    d.prune_only = true;
+    d.prune_px = prune_px;
+    d.kept = kept;
+    d.n_kept = n_kept;
+    epic_request r{cost, H, W, matches, N, K, a, EPIC_NW, nullptr};
+    // no flow: the debug path validates the request against its cost pointer
     return run_pairs(ctx, &r, 1, (hipStream_t)stream, &d);
 }
 
@@ -620,14 +670,17 @@ int epic_get_stats(epic_ctx* ctx, int pair, epic_stats* out) {
         return EPIC_ERR_HIP;
     if (hipMemcpy(&gerr, ctx->g_error, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) return EPIC_ERR_HIP;
     out->status = cnt[C_STATUS];
+    if (ctx->last_pruned && out->status == 0) out->status = cnt[C_STATUS0];
     // found after the CSR scan wrote the status: a K-NN visited set that
     // outgrew even the retry's table (that match's model is zero), or the
     // transform finisher's pass bound
     if ((cnt[C_OVERFLOW] & 2) && out->status == 0) out->status = EPIC_ERR_CAPACITY;
     if ((gerr & 1) && out->status == 0) out->status = EPIC_ERR_CONVERGENCE;
     out->n_used = cnt[C_USED];
-    out->n_outside = cnt[C_OUTSIDE];
-    out->n_duplicate = cnt[C_DUPLICATE];
+    // with the consistency check, drops are those of the original matches
+    out->n_outside = ctx->last_pruned ? cnt[C_OUTSIDE0] : cnt[C_OUTSIDE];
+    out->n_duplicate = ctx->last_pruned ? cnt[C_DUP0] : cnt[C_DUPLICATE];
+    out->n_pruned = ctx->last_pruned ? cnt[C_PRUNED] : 0;
     out->n_edges = cnt[C_EDGES];
     out->n_degenerate = cnt[C_DEGENERATE];
     out->n_fp64_fits = cnt[C_FP64];

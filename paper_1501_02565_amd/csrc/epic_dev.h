@@ -45,6 +45,12 @@ enum Counter {
     C_TILE_VISITS = 9,
     C_BADCOST = 10,    // cost values not finite and > 0 (checked on request)
     C_GEOERR = 11,     // a transform visit of this pair hit its round bound
+    // kept across the two passes of a call with the consistency check (the
+    // second pass clears only the counters before C_PRUNED)
+    C_PRUNED = 12,     // placed matches removed by the consistency check
+    C_OUTSIDE0 = 13,   // the first pass's outside / duplicate counts and status
+    C_DUP0 = 14,
+    C_STATUS0 = 15,
     C_NCOUNTERS = 16
 };
 
@@ -92,6 +98,10 @@ struct PairDev {
     double* adjw64;         // hash_cap: CSR edge weights
     u64* nbmin64;           // hash_cap: double bits of the neighbour's lightest edge
     double* params64;       // N*6
+    // consistency check of the matches (Sec. 5.1): the kept matches,
+    // compacted in index order, and their original indices
+    float* matches_kept;    // N*4
+    int* kept_idx;          // N
     // optional stage dumps (NULL = off)
     int* dbg_knn_idx;       // N*K
     float* dbg_knn_d;       // N*K
@@ -100,6 +110,8 @@ struct PairDev {
     float* dbg_ew;
     int dbg_max_edges;
     int* dbg_n_edges;       // device int
+    int* dbg_kept;          // N: original indices of the kept matches
+    int* dbg_n_kept;        // device int
 };
 
 // Global-memory view of a pointer.  Pointers read out of a PairDev (which
@@ -130,6 +142,9 @@ __device__ __forceinline__ float2 gload(const float2* p) {
 }
 __device__ __forceinline__ void gstore(uint4* p, uint4 v) { *(EPIC_GLOBAL gu32x4*)p = gu32x4{v.x, v.y, v.z, v.w}; }
 __device__ __forceinline__ void gstore(float2* p, float2 v) { *(EPIC_GLOBAL gf32x2*)p = gf32x2{v.x, v.y}; }
+__device__ __forceinline__ void gstore(float4* p, float4 v) {
+    *(EPIC_GLOBAL gf32x4*)p = gf32x4{v.x, v.y, v.z, v.w};
+}
 
 // Relaxed atomic accesses for transform state that other threads read or
 // write at the same moment.  The transform's correctness argument only
@@ -191,6 +206,9 @@ struct RunDev {
     int precision;          // 0 or 1
     float fp64_route;
     double deg_tau;
+    int force_nw;           // 1: fit NW whatever the pair's mode (the first pass of
+                            //   the consistency check)
+    int keep_prune_counters;   // 1: the clear keeps counters C_PRUNED.. (second pass)
 };
 
 constexpr int kMaxPasses = 64;   // passes launched per call, at most
@@ -237,6 +255,7 @@ hipError_t launch_csr_scatter(const PairDev* d_pairs, const RunDev& run, int tot
 hipError_t launch_knn_fit(const PairDev* d_pairs, const RunDev& run, int total_blocks, int kmax,
                           hipStream_t s);
 hipError_t launch_assign(const PairDev* d_pairs, const RunDev& run, int total_blocks, hipStream_t s);
+hipError_t launch_prune(PairDev* d_pairs, const RunDev& run, float prune_px, hipStream_t s);
 hipError_t launch_unpack(const PairDev* d_pairs, const RunDev& run, int total_blocks, float* D, int* L,
                          hipStream_t s);
 

@@ -574,7 +574,7 @@ __device__ __forceinline__ bool knn_fit_one(const PairDev& P, const RunDev& run,
         const float itk = __builtin_amdgcn_rcpf(tk);
         out[4] = um + tu * itk;
         out[5] = vm + tv * itk;
-        if (P.mode == 1) {
+        if (P.mode == 1 && !run.force_nw) {
             sw = wave::sum(sw);
             sx = wave::sum(sx);
             sy = wave::sum(sy);
@@ -639,7 +639,7 @@ __device__ __forceinline__ bool knn_fit_one(const PairDev& P, const RunDev& run,
         Tk = wave::sum(Tk); Tu = wave::sum(Tu); Tv = wave::sum(Tv);
         double o[6] = {0, 0, 0, 0, umd + Tu / Tk, vmd + Tv / Tk};
         bool degenerate = false;
-        if (P.mode == 1) {
+        if (P.mode == 1 && !run.force_nw) {
             Sw = wave::sum(Sw); Sx = wave::sum(Sx); Sy = wave::sum(Sy);
             const double mx = Sx / Sw, my = Sy / Sw;
             double sxx = 0, sxy = 0, syy = 0, sxu = 0, syu = 0, sxv = 0, syv = 0, su = 0, sv = 0;
@@ -677,7 +677,7 @@ __device__ __forceinline__ bool knn_fit_one(const PairDev& P, const RunDev& run,
             gmem(P.params64)[6LL * s + lane] = v;
         }
         if (lane == 0) {
-            if (P.mode == 1) atomicAdd(&P.counters[C_FP64], 1);
+            if (P.mode == 1 && !run.force_nw) atomicAdd(&P.counters[C_FP64], 1);
             if (degenerate) atomicAdd(&P.counters[C_DEGENERATE], 1);
         }
     }
@@ -718,6 +718,7 @@ __global__ __launch_bounds__(64) void k_knn_fit(const PairDev* __restrict__ pair
     const int p = find_pair(run.npairs, (int)blockIdx.x, [&](int i) { return pairs[i].src_block_base; });
     const PairDev& P = pairs[p];
     const int s = (int)blockIdx.x - P.src_block_base;
+    if (s >= P.N) return;          // after the consistency check: a match that was removed
     if (!knn_active(P, s)) {
         knn_fit_inactive(P, s);
         return;

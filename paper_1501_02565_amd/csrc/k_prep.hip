@@ -52,7 +52,7 @@ __global__ __launch_bounds__(256) void k_clear(PairDev* __restrict__ pairs, RunD
         run.dirty[0][P.tile_base + i] = 0u;
         run.dirty[1][P.tile_base + i] = 0u;
     }
-    if (i0 < C_NCOUNTERS) P.counters[i0] = 0;
+    if (i0 < (run.keep_prune_counters ? (long long)C_PRUNED : (long long)C_NCOUNTERS)) P.counters[i0] = 0;
     if (i0 == 0 && P.dbg_n_edges) *P.dbg_n_edges = 0;
     if (p == 0 && i0 < kMaxPasses) {
         run.any[i0] = 0;

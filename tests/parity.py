@@ -207,3 +207,55 @@ def full_check(ctx, sc, K=None, a=None, mode=None, conn=8, wpow=2):
     epe, epe_max = check_flow(g, r, excused_pixels=excused_px)
     return dict(label_diff=int(diff.sum()), excused_edges_nodes=len(enodes), excused_lists=len(kex),
                 fit_err_over_bound=round(fit_ratio, 4), epe=epe, epe_max=epe_max, stats=st)
+
+
+def prune_check(ctx, sc, prune_px, K=None, a=None, margin=1e-3):
+    """The GPU's kept set against the oracle's (Sec. 5.1): identical except
+    matches whose distance to their NW estimate lies within `margin` px of
+    the threshold (the GPU decides from FP32 models).  Returns (kept_gpu,
+    kept_ref, number of near-threshold matches)."""
+    import torch
+    K = sc.K if K is None else K
+    a = sc.a if a is None else a
+    dev = torch.device("cuda:0")
+    kg = ctx.prune(torch.from_numpy(sc.cost).to(dev), torch.from_numpy(sc.matches).to(dev), K, a,
+                   prune_px).cpu().numpy()
+    kr = epic_ref.prune(sc.cost, sc.matches, K, a, prune_px)
+    nw = epic_ref.stages(sc.cost, sc.matches, K, a, 0)
+    u = sc.matches[:, 2:].astype(np.float64) - sc.matches[:, :2]
+    dist = np.linalg.norm(u - nw["params"][:, 4:], axis=1) if "params" in nw else np.zeros(len(u))
+    near = set(np.nonzero(np.abs(dist - prune_px) <= margin)[0].tolist())
+    assert np.all(np.diff(kg) > 0), "kept indices must increase"
+    diff = set(kg.tolist()) ^ set(kr.tolist())
+    assert diff <= near, f"kept sets differ away from the threshold: {sorted(diff - near)[:10]}"
+    return kg, kr, len(near)
+
+
+def full_check_pruned(ctx_pruned, sc, prune_px, K=None, a=None, mode=None, conn=8, wpow=2):
+    """Every stage of the second pass of a call with the consistency check
+    against the oracle run on the kept matches (in index order)."""
+    import dataclasses
+    K = sc.K if K is None else K
+    a = sc.a if a is None else a
+    mode = sc.mode if mode is None else mode
+    kept = epic_ref.prune(sc.cost, sc.matches, K, a, prune_px, conn)
+    g = gpu_stages(ctx_pruned, sc, K, a, mode)
+    n = len(kept)
+    st = g["stats"]
+    assert st["n_pruned"] == int((epic_ref.seeds(sc.H, sc.W, sc.matches)[0] >= 0).sum()) - n, st
+    for k in ("knn_idx", "knn_d", "params"):
+        g[k] = g[k][:n]
+    sk = dataclasses.replace(sc, matches=np.ascontiguousarray(sc.matches[kept]))
+    r = ref_stages(sk, K, a, mode, conn, wpow)
+    assert st["n_used"] == r["used"] == n
+    if n == 0:
+        assert st["status"] == -3 and np.isnan(g["flow"]).all()
+        return dict(kept=0)
+    assert st["status"] == 0, st
+    diff = check_labels(sk, g, r, conn)
+    enodes = check_graph(g, r, diff)
+    kex = check_knn(g, r, r["K"], enodes)
+    fit_ratio = check_params(sk, g, r, r["K"], a, mode, wpow, kex)
+    epe, epe_max = check_flow(g, r, excused_pixels=diff | np.isin(g["L"], list(kex)))
+    return dict(kept=n, pruned=st["n_pruned"], label_diff=int(diff.sum()), excused_lists=len(kex),
+                fit_err_over_bound=round(fit_ratio, 4), epe=epe, epe_max=epe_max)
