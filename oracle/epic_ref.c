@@ -604,3 +604,31 @@ int epic_ref_prune(const float* C, int H, int W, const float* matches, int N,
     free(ki); free(kd); free(P); free(st);
     return nk;
 }
+
+/* ------------------------------------------------------------------ */
+/* cost map from the image gradient (Table 2, contour row: the norm of  */
+/* the image gradient; the same norm sets the smoothness weight, Sec. 4) */
+/* ------------------------------------------------------------------ */
+/* C(p) = sqrt(sum over channels of gx^2 + gy^2) + eps, with central
+ * differences gx = (I(x+1) - I(x-1)) / 2, gy = (I(y+1) - I(y-1)) / 2 and
+ * the border pixel repeated outside the image.  image: H*W*ch float,
+ * channels interleaved. */
+void epic_ref_grad_cost(const float* image, int H, int W, int ch, double eps, double* cost)
+{
+    #pragma omp parallel for schedule(static)
+    for (int y = 0; y < H; ++y) {
+        int yu = y > 0 ? y - 1 : 0, yd = y < H - 1 ? y + 1 : H - 1;
+        for (int x = 0; x < W; ++x) {
+            int xl = x > 0 ? x - 1 : 0, xr = x < W - 1 ? x + 1 : W - 1;
+            double s = 0.0;
+            for (int c = 0; c < ch; ++c) {
+                double gx = ((double)image[((long)y * W + xr) * ch + c] -
+                             (double)image[((long)y * W + xl) * ch + c]) / 2.0;
+                double gy = ((double)image[((long)yd * W + x) * ch + c] -
+                             (double)image[((long)yu * W + x) * ch + c]) / 2.0;
+                s += gx * gx + gy * gy;
+            }
+            cost[(long)y * W + x] = sqrt(s) + eps;
+        }
+    }
+}

@@ -68,6 +68,8 @@ def lib():
         L.epic_ref_interp.restype = i32
         L.epic_ref_prune.argtypes = [P, i32, i32, P, i32, i32, f64, i32, f64, P]
         L.epic_ref_prune.restype = i32
+        L.epic_ref_grad_cost.argtypes = [P, i32, i32, i32, f64, P]
+        L.epic_ref_grad_cost.restype = None
         L.epic_ref_set_threads.argtypes = [i32]
         L.epic_ref_set_threads.restype = None
         L.epic_ref_max_threads.argtypes = []
@@ -249,3 +251,26 @@ def interp_pruned(cost, matches, K, a, mode, prune_px, conn=8, wpow=2, deg_tau=D
         return np.full((H, W, 2), np.nan), -3, {}, kept
     flow, rc, st = interp(cost, m, K, a, mode, conn, wpow, deg_tau)
     return flow, rc, st, kept
+
+
+# --------------------------------------------------------------------------
+# cost map from the image gradient (Table 2, contour row "norm of the image
+# gradient"; the same gradient norm sets the smoothness weight of Sec. 4)
+# --------------------------------------------------------------------------
+GRAD_EPS = 1e-3
+
+
+def grad_norm_cost(image, eps=GRAD_EPS):
+    """C(p) = ||grad I(p)||_2 + eps in float64.  image: (H, W) or (H, W, ch).
+    The gradient is taken by central differences, (I(x+1) - I(x-1)) / 2 and
+    (I(y+1) - I(y-1)) / 2, with the border pixel repeated outside the image;
+    the norm runs over both directions and all channels.  eps keeps the
+    cost positive where the image is flat."""
+    I = _f32(image)
+    if I.ndim == 2:
+        I = I[:, :, None]
+    I = np.ascontiguousarray(I)
+    H, W, ch = I.shape
+    out = np.empty((H, W), np.float64)
+    lib().epic_ref_grad_cost(_p(I), H, W, ch, float(eps), _p(out))
+    return out

@@ -45,6 +45,7 @@ class Scene:
     mode: int                 # 0 = NW, 1 = LA
     name: str = ""
     gt_flow: np.ndarray | None = None   # (H, W, 2) float32, generator's motion
+    image: np.ndarray | None = None     # (H, W, 3) float32 in [0, 1] (on request)
 
     @property
     def H(self) -> int:
@@ -106,6 +107,23 @@ def _cost_from_layers(rng, layer, sigma=1.0, noise=0.05, floor=1e-3):
     return c.astype(np.float32)
 
 
+def _layer_image(layer, seed):
+    """An RGB image of the layer map (for the cost-from-gradient path): each
+    layer a random base colour in [0.15, 0.85]^3 with a smooth texture
+    (sigma-2 blurred normal noise, amplitude 0.08) and a little pixel noise,
+    clipped to [0, 1].  Its own generator, so drawing it leaves the rest of
+    the scene unchanged."""
+    rng = np.random.default_rng(seed + 7919)
+    H, W = layer.shape
+    n = int(layer.max()) + 1
+    base = rng.uniform(0.15, 0.85, (n, 3))
+    img = base[layer]
+    for c in range(3):
+        img[:, :, c] += 0.08 * ndimage.gaussian_filter(rng.standard_normal((H, W)), 2.0)
+    img += rng.uniform(0.0, 0.01, img.shape)
+    return np.clip(img, 0.0, 1.0).astype(np.float32)
+
+
 def _motion(layer, params):
     H, W = layer.shape
     ys, xs = np.mgrid[0:H, 0:W].astype(np.float64)
@@ -160,7 +178,7 @@ def _finish_matches(rng, gx, gy, flow, n_target, drop_frac, outlier_frac,
 def layered_scene(H, W, n_layers, t_range, n_matches, stride, *, seed,
                   occl_frac=0.0, drop_frac=0.0, outlier_frac=0.0,
                   outlier_r=20.0, offset=None, K=100, a=1.0, mode=1,
-                  name="layered"):
+                  name="layered", with_image=False):
     """Background plus random star-shaped polygon layers, painted in order.
 
     Each layer moves by its own affine field u(p) = B (p - centre) + t with
@@ -186,7 +204,8 @@ def layered_scene(H, W, n_layers, t_range, n_matches, stride, *, seed,
         gx, gy = gx[keep], gy[keep]
     m = _finish_matches(rng, gx, gy, flow, n_matches, drop_frac, outlier_frac,
                         outlier_r, H, W)
-    return Scene(cost, m, K, a, mode, name, flow.astype(np.float32))
+    img = _layer_image(layer, seed) if with_image else None
+    return Scene(cost, m, K, a, mode, name, flow.astype(np.float32), img)
 
 
 def road_scene(H=375, W=1242, n_matches=10000, *, seed, horizon=150, K=100,
@@ -235,7 +254,7 @@ CONFIG_PARAMS = {
 }
 
 
-def config_scene(i: int, mode: int | None = None) -> Scene:
+def config_scene(i: int, mode: int | None = None, with_image: bool = False) -> Scene:
     """The single-pair workloads: 1 = 128x96 small scene, 2 = 1024x436
     large-displacement scene, 3 = 1242x375 road scene (NW or LA)."""
     if i == 3:
@@ -246,7 +265,7 @@ def config_scene(i: int, mode: int | None = None) -> Scene:
         p["mode"] = mode
     H, W = p.pop("H"), p.pop("W")
     name = {1: "layered_128x96_n300_k32", 2: "layered_1024x436_n8000_k100"}[i]
-    return layered_scene(H, W, name=name, **p)
+    return layered_scene(H, W, name=name, with_image=with_image, **p)
 
 
 def random_case(H, W, N, *, seed, K=8, a=1.0, mode=1, subpixel=True,
@@ -305,7 +324,7 @@ def _stride_for(H, W, n, drop=0.0):
     return s
 
 
-def batch_scenes(n_pairs=64, seed0=4000, K=100, a=1.0, mode=1):
+def batch_scenes(n_pairs=64, seed0=4000, K=100, a=1.0, mode=1, with_image=False):
     """Mixed-size batch: each pair uniform over 4 sizes, 500..15000 matches,
     3-6 layers with t ~ U[-32, 32], per-pair seeds seed0 + i."""
     out = []
@@ -318,7 +337,7 @@ def batch_scenes(n_pairs=64, seed0=4000, K=100, a=1.0, mode=1):
         out.append(layered_scene(H, W, nl, 32.0, n, s, seed=seed0 + i,
                                  drop_frac=0.1, outlier_frac=0.05,
                                  outlier_r=32.0, K=K, a=a, mode=mode,
-                                 name=f"batch{i}_{W}x{H}_n{n}"))
+                                 name=f"batch{i}_{W}x{H}_n{n}", with_image=with_image))
     return out
 
 

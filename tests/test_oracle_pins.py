@@ -567,3 +567,41 @@ def test_prune_compares_with_the_nw_field_at_the_match_pixel(ref):
             if np.linalg.norm(u - f[y, x]) <= thr:
                 want.append(int(i))
         assert kept.tolist() == want
+
+
+# --------------------------------------------- cost from image gradient --
+
+def test_grad_cost_closed_forms(ref):
+    """A linear ramp I = alpha x + beta y in every channel has gradient
+    (alpha, beta) inside the image (exact for central differences) and half
+    of the normal component on a border (one-sided over the repeated border
+    pixel); a flat image costs eps; a unit step costs 1/2 on both sides of
+    the edge and nothing elsewhere."""
+    H, W, ch = 7, 9, 3
+    ys, xs = np.mgrid[0:H, 0:W].astype(np.float64)
+    al, be = 0.25, -0.125
+    ramp = np.repeat((al * xs + be * ys)[:, :, None], ch, 2).astype(np.float32)
+    C = ref.grad_norm_cost(ramp, eps=0.0)
+    np.testing.assert_allclose(C[1:-1, 1:-1], math.sqrt(ch * (al ** 2 + be ** 2)), rtol=1e-12)
+    np.testing.assert_allclose(C[1:-1, 0], math.sqrt(ch * ((al / 2) ** 2 + be ** 2)), rtol=1e-12)
+    np.testing.assert_allclose(C[0, 1:-1], math.sqrt(ch * (al ** 2 + (be / 2) ** 2)), rtol=1e-12)
+    np.testing.assert_allclose(C[0, 0], math.sqrt(ch * ((al / 2) ** 2 + (be / 2) ** 2)), rtol=1e-12)
+    np.testing.assert_array_equal(ref.grad_norm_cost(np.full((5, 6), 0.7, np.float32)), 1e-3)
+    step = np.zeros((4, 10), np.float32)
+    step[:, 5:] = 1.0
+    C = ref.grad_norm_cost(step, eps=0.0)
+    want = np.zeros((4, 10))
+    want[:, 4:6] = 0.5
+    np.testing.assert_array_equal(C, want)
+
+
+def test_grad_cost_scales_and_matches_numpy_gradient(ref):
+    """Scaling the image scales the cost above eps; the interior equals the
+    norm of numpy.gradient (second-order central differences)."""
+    rng = np.random.default_rng(3)
+    img = rng.uniform(0, 1, (12, 15, 3)).astype(np.float32)
+    C = ref.grad_norm_cost(img, eps=0.0)
+    np.testing.assert_allclose(ref.grad_norm_cost(img * np.float32(4), eps=0.0), 4 * C, rtol=1e-12)
+    gy, gx = np.gradient(img.astype(np.float64), axis=(0, 1))
+    want = np.sqrt((gx ** 2 + gy ** 2).sum(2))
+    np.testing.assert_allclose(C[1:-1, 1:-1], want[1:-1, 1:-1], rtol=1e-12)
