@@ -200,6 +200,34 @@ def pruned_leg(args, np, torch, epic, sc, steps=50):
     return res
 
 
+def image_cost_leg(np, torch, epic, reps=20):
+    """The cost maps of the 64-pair batch's RGB images from their gradient
+    (Table 2, norm-of-gradient row): an HBM-bound stencil, 12 B read and
+    4 B written per pixel, timed with HIP events on the current stream."""
+    from scenes import batch_scenes
+    scs = batch_scenes(64, with_image=True)
+    imgs = [torch.from_numpy(s.image).cuda() for s in scs]
+    outs = [torch.empty((s.H, s.W), dtype=torch.float32, device="cuda") for s in scs]
+    plan = epic.ImageCostPlan(imgs, outs)      # descriptors marshalled once
+    for _ in range(3):
+        plan.run()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        plan.run()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    px = sum(s.H * s.W for s in scs)
+    nbytes = 16.0 * px
+    gbs = nbytes / (ms * 1e-3) / 1e9
+    res = {"workload": f"gradient cost of 64 RGB images, {px / 1e6:.2f} Mpx", "ms": round(ms, 4),
+           "launches": 1, "algorithmic_bytes": nbytes, "achieved_gbs": round(gbs, 1),
+           "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4), "mpix_s": round(px / ms / 1e3, 1)}
+    log(f"bench: image cost {res}")
+    return res
+
+
 def batched_form(args, np, torch, epic):
     """The 64-pair mixed-size batch: one fused launch sequence per batch,
     captured as a HIP graph with the autotuned configuration, against the
@@ -508,6 +536,8 @@ def main():
     pruned = pruned_leg(args, np, torch, epic, sc)
     copy = copy_bandwidth(torch)
     roofline["copy_kernel_gbs"] = copy["gbs"]
+    imcost = image_cost_leg(np, torch, epic)
+    imcost["frac_of_copy"] = round(imcost["achieved_gbs"] / copy["gbs"], 4)
     log(f"bench: device copy {copy}")
     if args.calibrate_copy:
         log("bench: calibration copy of 256 MiB done")
@@ -543,6 +573,7 @@ def main():
         "batched": batched,
         "served": served,
         "pruned": pruned,
+        "image_cost": imcost,
     }
     print(json.dumps(out), flush=True)
 

@@ -242,6 +242,36 @@ int epic_prune(epic_ctx* ctx, const float* cost, int H, int W,
                const float* matches, int N, int K, float a, float prune_px,
                int* kept, int* n_kept, void* stream);
 
+/* Cost maps from images (Table 2, the norm-of-gradient contour row: the
+ * cost is the norm of the image gradient; Sec. 4 uses the same norm):
+ *   C(p) = sqrt(sum over channels of gx^2 + gy^2) + eps
+ * with central differences gx = (I(x+1) - I(x-1)) / 2, gy = (I(y+1) -
+ * I(y-1)) / 2 and the border pixel repeated outside the image; FP32, each
+ * operation rounded on its own.  eps (finite, > 0) keeps C > 0 on flat
+ * regions, as the transform requires.
+ *   image    device, H*W*channels float32, channels (1 to 4) interleaved
+ *   cost     device, H*W float32 output (caller-owned; may be passed to
+ *            epic_interp as its cost map)
+ * `imgs` is a host array of n descriptors; images with equal channel
+ * counts share launches (up to 64 per launch).  Needs no context and no
+ * workspace.  Host-side validation returns EPIC_ERR_ARG (null or
+ * misaligned pointers, sizes, channels, eps); asynchronous on `stream`. */
+typedef struct epic_image {
+    const float* image;
+    int H, W, channels;
+    float* cost;
+} epic_image;
+int epic_image_cost(const epic_image* imgs, int n, float eps, void* stream);
+
+/* epic_interp with an image in place of the cost map: the cost of
+ * epic_image_cost (image H*W*channels float32 on the device) is computed
+ * into the context's workspace, then the pair is interpolated as by
+ * epic_interp.  The workspace must hold epic_workspace_bytes(...) plus
+ * 4*H*W + 512 bytes (EPIC_ERR_WORKSPACE otherwise). */
+int epic_interp_image(epic_ctx* ctx, const float* image, int H, int W, int channels, float eps,
+                      const float* matches, int N, int K, float a, int mode, float* flow,
+                      void* stream);
+
 /* Stage timing (instrumentation).  While enabled, every call records HIP
  * events between its stages on the call's stream (a ring of the last 64
  * calls).  epic_stage_times synchronises those calls and writes, for each

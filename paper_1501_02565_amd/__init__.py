@@ -17,7 +17,9 @@ from . import _lib
 from ._lib import (LA, NW, OK, EpicError, ERR_ARG, ERR_BUDGET, ERR_CAPACITY,  # noqa: F401
                    ERR_CONVERGENCE, ERR_COST, ERR_HIP, ERR_NO_MATCHES, ERR_WORKSPACE)
 
-__all__ = ["Context", "workspace_bytes", "LA", "NW", "EpicError"]
+__all__ = ["Context", "workspace_bytes", "image_cost", "ImageCostPlan", "LA", "NW", "EpicError"]
+
+GRAD_EPS = 1e-3      # default floor of the gradient cost
 
 
 def _torch():
@@ -29,6 +31,43 @@ def workspace_bytes(H: int, W: int, N: int, K: int, mode: int = LA,
                     precision: int = 0) -> int:
     """Device workspace one call of this size needs (host-only query)."""
     return int(_lib.load().epic_workspace_bytes(H, W, N, K, mode, precision))
+
+
+class ImageCostPlan:
+    """Descriptors of a fixed set of images and cost buffers, marshalled once
+    (for repeated calls: run() is then a single C call)."""
+
+    def __init__(self, images, outs=None, eps: float = GRAD_EPS):
+        torch = _torch()
+        self.images = list(images)
+        self.eps = float(eps)
+        self.descs = (_lib.Image * len(self.images))()
+        self.costs = []
+        for i, im in enumerate(self.images):
+            _check_tensor(im, "image", torch.float32)
+            H, W = im.shape[:2]
+            ch = 1 if im.dim() == 2 else int(im.shape[2])
+            c = outs[i] if outs is not None else torch.empty((H, W), dtype=torch.float32, device=im.device)
+            _check_tensor(c, "cost", torch.float32)
+            self.costs.append(c)
+            self.descs[i] = _lib.Image(im.data_ptr(), H, W, ch, c.data_ptr())
+
+    def run(self, stream=None):
+        rc = _lib.load().epic_image_cost(self.descs, len(self.images), self.eps, _stream_handle(stream))
+        if rc != OK:
+            raise EpicError(rc, "epic_image_cost")
+        return self.costs
+
+
+def image_cost(images, eps: float = GRAD_EPS, outs=None, stream=None):
+    """Cost maps from images (Table 2, norm of the image gradient): for each
+    float32 CUDA tensor of shape (H, W) or (H, W, channels <= 4), C =
+    ||grad I|| + eps as an (H, W) float32 tensor.  One launch per run of up
+    to 64 images with equal channel counts."""
+    torch = _torch()
+    single = isinstance(images, torch.Tensor)
+    costs = ImageCostPlan([images] if single else images, outs, eps).run(stream)
+    return costs[0] if single else costs
 
 
 def _stream_handle(stream):
@@ -124,6 +163,25 @@ class Context:
                                      _stream_handle(stream))
         if rc != OK:
             raise EpicError(rc, "epic_interp")
+        return out
+
+    def interp_image(self, image, matches, K: int, a: float, mode: int = LA, eps: float = GRAD_EPS,
+                     out=None, stream=None):
+        """As interp, with an image (H, W[, channels]) in place of the cost
+        map: the cost is its gradient norm plus eps, computed on the GPU."""
+        torch = _torch()
+        _check_tensor(image, "image", torch.float32)
+        _check_tensor(matches, "matches", torch.float32, (4,))
+        H, W = image.shape[:2]
+        ch = 1 if image.dim() == 2 else int(image.shape[2])
+        if out is None:
+            out = torch.empty((H, W, 2), dtype=torch.float32, device=image.device)
+        _check_tensor(out, "out", torch.float32, (H, W, 2))
+        rc = _lib.load().epic_interp_image(self._ctx, image.data_ptr(), H, W, ch, float(eps),
+                                           matches.data_ptr(), matches.shape[0], int(K), float(a),
+                                           int(mode), out.data_ptr(), _stream_handle(stream))
+        if rc != OK:
+            raise EpicError(rc, "epic_interp_image")
         return out
 
     def interp_batch(self, problems, outs=None, stream=None):

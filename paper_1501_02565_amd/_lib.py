@@ -20,7 +20,8 @@ SYMBOLS = ["epic_create", "epic_destroy", "epic_workspace_bytes", "epic_interp",
            "epic_interp_batch", "epic_get_stats", "epic_debug_stages",
            "epic_strerror", "epic_last_error", "epic_validate", "epic_profile",
            "epic_stage_times", "epic_stage_name", "epic_graph_capture",
-           "epic_graph_launch", "epic_graph_destroy", "epic_prune"]
+           "epic_graph_launch", "epic_graph_destroy", "epic_prune", "epic_image_cost",
+           "epic_interp_image"]
 
 
 class Options(ctypes.Structure):
@@ -44,6 +45,12 @@ class Request(ctypes.Structure):
                 ("N", ctypes.c_int), ("K", ctypes.c_int),
                 ("a", ctypes.c_float), ("mode", ctypes.c_int),
                 ("flow", ctypes.c_void_p)]
+
+
+class Image(ctypes.Structure):
+    _fields_ = [("image", ctypes.c_void_p),
+                ("H", ctypes.c_int), ("W", ctypes.c_int), ("channels", ctypes.c_int),
+                ("cost", ctypes.c_void_p)]
 
 
 class Stats(ctypes.Structure):
@@ -90,6 +97,10 @@ def load():
     L.epic_debug_stages.restype = i32
     L.epic_prune.argtypes = [P, P, i32, i32, P, i32, i32, f32, f32, P, P, P]
     L.epic_prune.restype = i32
+    L.epic_image_cost.argtypes = [ctypes.POINTER(Image), i32, f32, P]
+    L.epic_image_cost.restype = i32
+    L.epic_interp_image.argtypes = [P, P, i32, i32, i32, f32, P, i32, i32, f32, i32, P, P]
+    L.epic_interp_image.restype = i32
     L.epic_strerror.argtypes = [i32]
     L.epic_strerror.restype = ctypes.c_char_p
     L.epic_last_error.argtypes = []

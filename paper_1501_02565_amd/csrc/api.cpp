@@ -106,9 +106,12 @@ struct epic_ctx {
     int* g_error = nullptr;
     int passes = 16;                    // geodesic passes launched per call (fixed budget)
     bool auto_passes = true;            // budget from the passes the last call needed
-    int* h_passes_used = nullptr;       // pinned, 2 ints, written by the transform's finisher(s)
-    int used_hist[2][kAutoPassesHistory]{};  // needs seen at the last calls, per FP64 phase (0: none yet)
-    int used_next[2]{};
+    // pinned, 4 ints written by the transform's finisher(s): slots 0-1 the
+    // transform of a call (FP64: its two phases), 2-3 the first transform
+    // of a call with the consistency check, whose seeds differ
+    int* h_passes_used = nullptr;
+    int used_hist[4][kAutoPassesHistory]{};  // needs seen at the last calls, per slot (0: none yet)
+    int used_next[4]{};
     // stage timing
     bool prof = false;
     hipEvent_t prof_ev[kProfRing][kStages + 1]{};
@@ -212,9 +215,9 @@ epic_ctx* epic_create(int device, size_t workspace_bytes, const epic_options* op
     for (int i = 0; i < kRing; ++i)
         if (hipEventCreateWithFlags(&c->ring_ev[i], hipEventDisableTiming) != hipSuccess)
             return fail("event creation failed");
-    if (hipHostMalloc((void**)&c->h_passes_used, 2 * sizeof(int), hipHostMallocDefault) != hipSuccess)
+    if (hipHostMalloc((void**)&c->h_passes_used, 4 * sizeof(int), hipHostMallocDefault) != hipSuccess)
         return fail("pinned counter allocation failed");
-    c->h_passes_used[0] = c->h_passes_used[1] = 0;
+    for (int i = 0; i < 4; ++i) c->h_passes_used[i] = 0;
     c->g_error = reinterpret_cast<int*>(c->ws);
     c->g_any = reinterpret_cast<int*>(c->ws) + 256;         // kMaxPasses ints
     return c;
@@ -268,7 +271,7 @@ struct DescTarget {
 };
 
 int run_pairs(epic_ctx* c, const epic_request* reqs, int n, hipStream_t stream, const DebugOut* dbg,
-              const DescTarget* tgt = nullptr) {
+              const DescTarget* tgt = nullptr, size_t reserve_tail = 0) {
     if (!c || !reqs || n < 1 || n > kMaxPairs) return EPIC_ERR_ARG;
     for (int i = 0; i < n; ++i) {
         const epic_request& r = reqs[i];
@@ -283,7 +286,7 @@ int run_pairs(epic_ctx* c, const epic_request* reqs, int n, hipStream_t stream, 
     for (int i = 0; i < n; ++i) total_tiles += tiles_of(reqs[i].H, reqs[i].W, tl);
     need += 2 * align_up(4 * total_tiles);
     for (int i = 0; i < n; ++i) need += pair_bytes(reqs[i].H, reqs[i].W, reqs[i].N, c->opt.precision);
-    if (need > c->ws_bytes) return EPIC_ERR_WORKSPACE;
+    if (need + reserve_tail > c->ws_bytes) return EPIC_ERR_WORKSPACE;
     if (hipSetDevice(c->device) != hipSuccess) return EPIC_ERR_HIP;
 
     int slot = -1;
@@ -475,6 +478,10 @@ int run_pairs(epic_ctx* c, const epic_request* reqs, int n, hipStream_t stream, 
         const bool last = pass == 1;
         run.force_nw = first ? 1 : 0;
         run.keep_prune_counters = two_pass && last ? 1 : 0;
+        run.prune_px = first ? prune_px : 0.0f;
+        // each transform of the call keeps its own pass history
+        const int slot0 = first ? 2 : 0;
+        run.passes_used = c->h_passes_used + slot0;
         // the descriptor table travels inline only with the first launch of
         // the call (the second pass reads the table k_prune rewrote)
         const bool inl = inline_desc && (first || !two_pass);
@@ -486,8 +493,9 @@ int run_pairs(epic_ctx* c, const epic_request* reqs, int n, hipStream_t stream, 
         if (e == hipSuccess) e = launch_seed(dd, run, seed_blocks, stream);
         if (last) mark(1);
         if (e == hipSuccess)
-            e = c->opt.precision == 1 ? launch_geodesic64(dd, run, budget(0), budget(1), stream)
-                                      : launch_geodesic(dd, run, tl.tw, tl.th, c->opt.geo_threads, budget(0), stream);
+            e = c->opt.precision == 1 ? launch_geodesic64(dd, run, budget(slot0), budget(slot0 + 1), stream)
+                                      : launch_geodesic(dd, run, tl.tw, tl.th, c->opt.geo_threads, budget(slot0),
+                                                        stream);
         if (last) mark(2);
         if (e == hipSuccess) e = launch_graph_emit(dd, run, emit_blocks, stream);
         if (last) mark(3);
@@ -498,7 +506,7 @@ int run_pairs(epic_ctx* c, const epic_request* reqs, int n, hipStream_t stream, 
         if (e == hipSuccess) e = launch_knn_fit(dd, run, src_blocks, kmax, stream);
         if (last) mark(6);
         if (first) {
-            if (e == hipSuccess) e = launch_prune(dd, run, prune_px, stream);
+            if (e == hipSuccess) e = launch_prune(dd, run, stream);
             if (dbg && dbg->prune_only) break;
             continue;
         }
@@ -564,6 +572,59 @@ int epic_prune(epic_ctx* ctx, const float* cost, int H, int W, const float* matc
     epic_request r{cost, H, W, matches, N, K, a, EPIC_NW, nullptr};
     // no flow: the debug path validates the request against its cost pointer
     return run_pairs(ctx, &r, 1, (hipStream_t)stream, &d);
+}
+
+int epic_image_cost(const epic_image* imgs, int n, float eps, void* stream) {
+    if (!imgs || n < 1 || !std::isfinite(eps) || !(eps > 0.0f)) return EPIC_ERR_ARG;
+    for (int i = 0; i < n; ++i) {
+        const epic_image& m = imgs[i];
+        if (!m.image || !m.cost || ((uintptr_t)m.image & 3) || ((uintptr_t)m.cost & 3)) return EPIC_ERR_ARG;
+        if (m.H < 1 || m.W < 1 || (long long)m.H * m.W >= (1LL << 31) || m.channels < 1 || m.channels > 4)
+            return EPIC_ERR_ARG;
+    }
+    // one launch per run of up to kImagesPerLaunch images with the same
+    // channel count
+    for (int i = 0; i < n;) {
+        ImageCostArgs args{};
+        args.eps = eps;
+        const int ch = imgs[i].channels;
+        int blocks = 0;
+        while (i < n && args.n < kImagesPerLaunch && imgs[i].channels == ch) {
+            ImageDesc& d = args.img[args.n++];
+            d.image = imgs[i].image;
+            d.cost = imgs[i].cost;
+            d.H = imgs[i].H;
+            d.W = imgs[i].W;
+            d.block_base = blocks;
+            blocks += image_cost_blocks(d.H, d.W);
+            ++i;
+        }
+        if (launch_image_cost(args, ch, blocks, (hipStream_t)stream) != hipSuccess) return EPIC_ERR_HIP;
+    }
+    return EPIC_OK;
+}
+
+int epic_interp_image(epic_ctx* ctx, const float* image, int H, int W, int channels, float eps,
+                      const float* matches, int N, int K, float a, int mode, float* flow, void* stream) {
+    if (!ctx) return EPIC_ERR_ARG;
+    if (!image || channels < 1 || channels > 4 || !std::isfinite(eps) || !(eps > 0.0f)) return EPIC_ERR_ARG;
+    if (H < 1 || W < 1 || (long long)H * W >= (1LL << 31)) return EPIC_ERR_ARG;
+    // the cost map lives at the end of the workspace, after what the call needs
+    const size_t tail = align_up(4 * (size_t)H * W);
+    if (tail > ctx->ws_bytes) return EPIC_ERR_WORKSPACE;
+    float* cost = reinterpret_cast<float*>(ctx->ws + ((ctx->ws_bytes - tail) & ~(kAlign - 1)));
+    const int v = epic_validate(cost, H, W, matches, N, K, a, mode, flow);
+    if (v != EPIC_OK) return v;
+    // check the workspace before anything is enqueued
+    epic_request r{cost, H, W, matches, N, K, a, mode, flow};
+    const size_t need = kFixed + 2 * align_up(4 * tiles_of(H, W, Tiling{ctx->opt.tile_w, ctx->opt.tile_h})) +
+                        pair_bytes(H, W, N, ctx->opt.precision);
+    if (need + tail + kAlign > ctx->ws_bytes) return EPIC_ERR_WORKSPACE;
+    if (hipSetDevice(ctx->device) != hipSuccess) return EPIC_ERR_HIP;
+    epic_image im{image, H, W, channels, cost};
+    const int rc = epic_image_cost(&im, 1, eps, stream);
+    if (rc != EPIC_OK) return rc;
+    return run_pairs(ctx, &r, 1, (hipStream_t)stream, nullptr, nullptr, tail + kAlign);
 }
 
 struct epic_graph {

@@ -82,7 +82,9 @@ struct PairDev {
     u64* hkey;              // hash_cap: (m << 32 | n), m < n
     u32* hval;              // hash_cap: float bits of the edge weight
     u32* deg;               // N
-    u32* fill;              // N
+    u32* fill;              // N (CSR fill counts; in the first pass of the
+                            //   consistency check the K-NN then stores each match's
+                            //   keep flag there, the counts being used up)
     u32* row_ptr;           // N + 1
     u32* minin;             // N: float bits of the lightest incident edge
     uint4* adj;             // hash_cap: CSR edges (neighbour id, weight bits,
@@ -209,6 +211,8 @@ struct RunDev {
     int force_nw;           // 1: fit NW whatever the pair's mode (the first pass of
                             //   the consistency check)
     int keep_prune_counters;   // 1: the clear keeps counters C_PRUNED.. (second pass)
+    float prune_px;         // > 0 in the first pass of the consistency check: the
+                            //   K-NN + fit writes each match's keep flag into fill[]
 };
 
 constexpr int kMaxPasses = 64;   // passes launched per call, at most
@@ -255,7 +259,25 @@ hipError_t launch_csr_scatter(const PairDev* d_pairs, const RunDev& run, int tot
 hipError_t launch_knn_fit(const PairDev* d_pairs, const RunDev& run, int total_blocks, int kmax,
                           hipStream_t s);
 hipError_t launch_assign(const PairDev* d_pairs, const RunDev& run, int total_blocks, hipStream_t s);
-hipError_t launch_prune(PairDev* d_pairs, const RunDev& run, float prune_px, hipStream_t s);
+hipError_t launch_prune(PairDev* d_pairs, const RunDev& run, hipStream_t s);
+
+// Cost map from the image gradient: up to kImagesPerLaunch images per launch,
+// described in the kernel arguments.
+struct ImageDesc {
+    const float* image;     // H*W*channels, interleaved
+    float* cost;            // H*W
+    int H, W;
+    int block_base;         // first block of this image's strips
+    int pad;
+};
+constexpr int kImagesPerLaunch = 64;
+struct ImageCostArgs {
+    ImageDesc img[kImagesPerLaunch];
+    int n;
+    float eps;
+};
+int image_cost_blocks(int H, int W);
+hipError_t launch_image_cost(const ImageCostArgs& args, int channels, int total_blocks, hipStream_t s);
 hipError_t launch_unpack(const PairDev* d_pairs, const RunDev& run, int total_blocks, float* D, int* L,
                          hipStream_t s);
 

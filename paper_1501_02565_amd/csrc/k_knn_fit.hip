@@ -687,6 +687,13 @@ __device__ __forceinline__ bool knn_fit_one(const PairDev& P, const RunDev& run,
         for (int i = 1; i < 6; ++i) v = lane == i ? out[i] : v;
         prm[lane] = v;
     }
+    if (run.prune_px > 0.0f && lane == 0) {
+        // consistency check (first, NW pass): the NW field at this match's
+        // pixel is its own model's constant, out[4], out[5]
+        const double du = ((double)me.z - (double)me.x) - (double)out[4];
+        const double dv = ((double)me.w - (double)me.y) - (double)out[5];
+        P.fill[s] = sqrt(du * du + dv * dv) <= (double)run.prune_px ? 1u : 0u;
+    }
     return true;
 }
 
@@ -694,6 +701,7 @@ __device__ __forceinline__ bool knn_fit_one(const PairDev& P, const RunDev& run,
 __device__ __forceinline__ void knn_fit_inactive(const PairDev& P, int s) {
     const int lane = threadIdx.x;
     if (lane < 6) P.params[6LL * s + lane] = 0.0f;
+    if (lane == 0) P.fill[s] = 0u;        // never kept by the consistency check
     if (P.dbg_knn_idx)
         for (int j = lane; j < P.K; j += 64) {
             P.dbg_knn_idx[(long long)s * P.K + j] = -1;

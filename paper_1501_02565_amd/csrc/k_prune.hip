@@ -6,13 +6,14 @@
 //
 // At the pixel of match m the NW field is the model of cell m, whose value
 // there is its constant c_m, so the test only needs the per-match models of
-// the first pass: keep m when m was placed on its pixel and
+// the first pass: m is kept when it was placed on its pixel and
 // |u_m - c_m| <= threshold (Euclidean norm, evaluated in double from the
-// FP32 model).  The kept matches are compacted in index order (so ties keep
-// breaking towards the lower original index) and the pair's descriptor is
-// pointed at them: the second pass of every kernel then sees N' matches.
-// The first pass's drop counts and status are saved in counters the second
-// pass keeps.
+// FP32 model).  The K-NN + fit kernel of the first pass takes that decision
+// right after the fit and leaves a flag per match; k_prune compacts the
+// kept matches in index order (so ties keep breaking towards the lower
+// original index) and points the pair's descriptor at them: the second
+// pass of every kernel then sees N' matches.  The first pass's drop counts
+// and status are saved in counters the second pass keeps.
 #include "epic_dev.h"
 #include "wave.h"
 
@@ -22,7 +23,7 @@ namespace epic {
 // chunk of matches, counts its kept ones, and the counts are scanned
 // (wavefront DPP scans, then across the 16 wavefronts) to place each kept
 // match.
-__global__ __launch_bounds__(1024) void k_prune(PairDev* __restrict__ pairs, RunDev run, float prune_px) {
+__global__ __launch_bounds__(1024) void k_prune(PairDev* __restrict__ pairs, RunDev run) {
     PairDev& P = pairs[blockIdx.x];
     __shared__ int s_wave[16];
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
@@ -30,14 +31,9 @@ __global__ __launch_bounds__(1024) void k_prune(PairDev* __restrict__ pairs, Run
     const int chunk = (N + 1023) / 1024;
     const int b = min(N, tid * chunk), e = min(N, b + chunk);
     const float4* rows = reinterpret_cast<const float4*>(P.matches);
-    auto keep = [&](int m) -> bool {
-        const int sp = P.seed_pix[m];
-        if (sp < 0 || label_at(P, sp) != (u32)m) return false;     // not placed on its pixel
-        const float4 r = gload(rows + m);
-        const double du = ((double)r.z - (double)r.x) - (double)P.params[6LL * m + 4];
-        const double dv = ((double)r.w - (double)r.y) - (double)P.params[6LL * m + 5];
-        return sqrt(du * du + dv * dv) <= (double)prune_px;
-    };
+    // keep flags left by the first pass's K-NN + fit (0 for matches that
+    // were not placed on their pixel)
+    auto keep = [&](int m) -> bool { return P.fill[m] != 0u; };
     int cnt = 0;
     for (int m = b; m < e; ++m) cnt += keep(m) ? 1 : 0;
     const int incl = wave::incl_scan(cnt);
@@ -69,8 +65,8 @@ __global__ __launch_bounds__(1024) void k_prune(PairDev* __restrict__ pairs, Run
     }
 }
 
-hipError_t launch_prune(PairDev* d_pairs, const RunDev& run, float prune_px, hipStream_t s) {
-    hipLaunchKernelGGL(k_prune, dim3(run.npairs), dim3(1024), 0, s, d_pairs, run, prune_px);
+hipError_t launch_prune(PairDev* d_pairs, const RunDev& run, hipStream_t s) {
+    hipLaunchKernelGGL(k_prune, dim3(run.npairs), dim3(1024), 0, s, d_pairs, run);
     return hipGetLastError();
 }
 

@@ -140,3 +140,20 @@ def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
     monkeypatch.setattr(_lib, "_lib", None)
     with pytest.raises(RuntimeError, match="missing"):
         _lib.load()
+
+
+def test_image_cost_rejects_bad_arguments(lib):
+    from paper_1501_02565_amd import _lib
+    good = _lib.Image(0x1000, 10, 20, 3, 0x2000)
+    arr = (_lib.Image * 1)(good)
+    bad_eps = [0.0, -1.0, float("nan"), float("inf")]
+    for e in bad_eps:
+        assert lib.epic_image_cost(arr, 1, e, None) == -1
+    for fields in [dict(image=None), dict(cost=None), dict(H=0), dict(W=0), dict(channels=0),
+                   dict(channels=5), dict(image=0x1002), dict(H=65536, W=32768)]:
+        d = dict(image=0x1000, H=10, W=20, channels=3, cost=0x2000)
+        d.update(fields)
+        a = (_lib.Image * 1)(_lib.Image(d["image"], d["H"], d["W"], d["channels"], d["cost"]))
+        assert lib.epic_image_cost(a, 1, 1e-3, None) == -1, fields
+    assert lib.epic_image_cost(arr, 0, 1e-3, None) == -1
+    assert lib.epic_interp_image(None, P, 10, 20, 3, 1e-3, P, 5, 3, 1.0, 1, P, None) == -1

@@ -78,7 +78,10 @@ def test_batch_with_pruning_equals_alone(ctx_pruned):
         alone = ctx_pruned.interp(*p).cpu().numpy()
         st1 = ctx_pruned.stats(0)
         assert np.array_equal(alone, f, equal_nan=True)
-        assert st == st1
+        # every count but the transform's tile visits (which depend on the
+        # schedule, not the result) is the same alone and in the batch
+        assert {k: v for k, v in st.items() if k != "tile_visits"} == \
+            {k: v for k, v in st1.items() if k != "tile_visits"}
         ref, rc, _, kept = epic_ref.interp_pruned(sc.cost, sc.matches, sc.K, sc.a, sc.mode, 5.0)
         assert st["n_used"] == len(kept)
         if rc == 0:
