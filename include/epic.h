@@ -272,6 +272,23 @@ int epic_interp_image(epic_ctx* ctx, const float* image, int H, int W, int chann
                       const float* matches, int N, int K, float a, int mode, float* flow,
                       void* stream);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): epic_interp without a
+ * context.  Its workspace is a 64 MiB device array inside the library, one
+ * copy per GPU, held until the process ends; the call allocates nothing (no
+ * hipMalloc, no pinned memory, no events) and runs on the current HIP
+ * device with the default options (FP32, 8-connected, LA weights k^2) and a
+ * fixed pass budget (results equal epic_interp's).  Arguments as in
+ * epic_interp.  Sizes whose workspace (epic_workspace_bytes with precision
+ * 0) exceeds 64 MiB -- e.g. beyond 2048 x 1080 pixels with 40000 matches --
+ * return EPIC_ERR_WORKSPACE before anything runs.  Every call on one GPU
+ * shares that GPU's array and leaves its contents behind (each call clears
+ * what it needs first): calls that overlap on one GPU race, so order them
+ * on one stream (or with events), from one host thread at a time.  There
+ * are no per-call statistics; a pair without a usable match gets NaN flow. */
+int epic_interp_noalloc(const float* cost, int H, int W, const float* matches, int N, int K,
+                        float a, int mode, float* flow, void* stream);
+
 /* Stage timing (instrumentation).  While enabled, every call records HIP
  * events between its stages on the call's stream (a ring of the last 64
  * calls).  epic_stage_times synchronises those calls and writes, for each

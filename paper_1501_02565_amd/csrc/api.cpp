@@ -6,6 +6,7 @@
 // Every stage is one launch for all pairs of a call.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -101,7 +102,7 @@ struct epic_ctx {
     // last call
     hipStream_t last_stream = nullptr;
     int last_npairs = 0;
-    std::vector<int*> last_counters;
+    int* last_counters[kMaxPairs]{};    // per pair of the last call (fixed: calls allocate nothing)
     int* g_any = nullptr;
     int* g_error = nullptr;
     int passes = 16;                    // geodesic passes launched per call (fixed budget)
@@ -317,7 +318,7 @@ int run_pairs(epic_ctx* c, const epic_request* reqs, int n, hipStream_t stream, 
     int tile_base = 0, pix_blocks = 0, seed_blocks = 0, src_blocks = 0, slot_blocks = 0, init_blocks = 0;
     int emit_blocks = 0;
     int kmax = 1;
-    c->last_counters.assign(n, nullptr);
+    for (int i = 0; i < n; ++i) c->last_counters[i] = nullptr;
     for (int i = 0; i < n; ++i) {
         const epic_request& r = reqs[i];
         PairDev& P = hd[i];
@@ -481,7 +482,7 @@ int run_pairs(epic_ctx* c, const epic_request* reqs, int n, hipStream_t stream, 
         run.prune_px = first ? prune_px : 0.0f;
         // each transform of the call keeps its own pass history
         const int slot0 = first ? 2 : 0;
-        run.passes_used = c->h_passes_used + slot0;
+        run.passes_used = c->h_passes_used ? c->h_passes_used + slot0 : nullptr;
         // the descriptor table travels inline only with the first launch of
         // the call (the second pass reads the table k_prune rewrote)
         const bool inl = inline_desc && (first || !two_pass);
@@ -670,7 +671,7 @@ epic_graph* epic_graph_capture(epic_ctx* ctx, const epic_request* reqs, int n) {
         epic_graph_destroy(g);
         return nullptr;
     }
-    g->counters = ctx->last_counters;
+    g->counters.assign(ctx->last_counters, ctx->last_counters + n);
     return g;
 }
 
@@ -679,7 +680,7 @@ int epic_graph_launch(epic_graph* g, void* stream) {
     epic_ctx* c = g->ctx;
     if (hipSetDevice(c->device) != hipSuccess) return EPIC_ERR_HIP;
     if (hipGraphLaunch(g->exec, (hipStream_t)stream) != hipSuccess) return EPIC_ERR_HIP;
-    c->last_counters = g->counters;
+    std::copy(g->counters.begin(), g->counters.end(), c->last_counters);
     c->last_npairs = g->n;
     c->last_stream = (hipStream_t)stream;
     return EPIC_OK;
@@ -751,3 +752,68 @@ int epic_get_stats(epic_ctx* ctx, int pair, epic_stats* out) {
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Allocation-free entry point.  Its workspace is a device array of the
+// library, one copy per GPU for the life of the process; its host state is a
+// static context per device; descriptors travel in the first kernel's
+// arguments; the pass budget is fixed (the transform's finisher completes
+// any remainder, so results are those of epic_interp).
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr size_t kScratchBytes = 64ull << 20;     // 64 MiB per GPU
+constexpr int kNoAllocPasses = 8;
+constexpr int kMaxDevices = 64;
+
+__device__ __align__(256) char scratch[kScratchBytes];
+
+struct NoAllocState {
+    std::once_flag once;
+    int init_status = EPIC_ERR_HIP;
+    char* ptr = nullptr;          // this device's copy of `scratch`
+    epic_ctx ctx;                 // host state (no pinned memory, no events)
+};
+NoAllocState g_noalloc[kMaxDevices];
+
+}  // namespace
+
+extern "C" int epic_interp_noalloc(const float* cost, int H, int W, const float* matches, int N, int K,
+                                   float a, int mode, float* flow, void* stream) {
+    const int v = epic_validate(cost, H, W, matches, N, K, a, mode, flow);
+    if (v != EPIC_OK) return v;
+    // sizes beyond the array are refused before any device call
+    if (epic_workspace_bytes(H, W, N, K, mode, 0) > kScratchBytes) return EPIC_ERR_WORKSPACE;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return EPIC_ERR_HIP;
+    NoAllocState& st = g_noalloc[dev];
+    std::call_once(st.once, [&] {
+        // the array's name is a host-side stand-in: its device address comes
+        // from the runtime, once per device, with that device current
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return;
+        st.ptr = static_cast<char*>(p);
+        epic_ctx& c = st.ctx;
+        c.device = dev;
+        c.opt.connectivity = 8;
+        c.opt.la_weight_power = 2;
+        c.opt.precision = 0;
+        c.opt.fp64_route = 1e-3f;
+        c.opt.degenerate_tau = 1e-9;
+        c.opt.tile_w = 32;
+        c.opt.tile_h = 16;
+        c.opt.geo_passes = kNoAllocPasses;
+        c.auto_passes = false;
+        c.passes = kNoAllocPasses;
+        c.ws = st.ptr;
+        c.ws_bytes = kScratchBytes;
+        c.g_error = reinterpret_cast<int*>(st.ptr);
+        c.g_any = reinterpret_cast<int*>(st.ptr) + 256;
+        st.init_status = EPIC_OK;
+    });
+    if (st.init_status != EPIC_OK) return st.init_status;
+    PairDev host_desc[1];
+    DescTarget tgt{host_desc, reinterpret_cast<PairDev*>(st.ptr + 4096)};
+    epic_request r{cost, H, W, matches, N, K, a, mode, flow};
+    return run_pairs(&st.ctx, &r, 1, (hipStream_t)stream, nullptr, &tgt);
+}
