@@ -632,3 +632,111 @@ void epic_ref_grad_cost(const float* image, int H, int W, int ch, double eps, do
         }
     }
 }
+
+/* ------------------------------------------------------------------ */
+/* exact per-pixel geodesic interpolation (Table 2, "Geodesic (exact)") */
+/* ------------------------------------------------------------------ */
+typedef struct { double d; int m; } dm_pair;
+
+static int dm_cmp(const void* a, const void* b)
+{
+    const dm_pair* x = (const dm_pair*)a;
+    const dm_pair* y = (const dm_pair*)b;
+    if (x->d < y->d) return -1;
+    if (x->d > y->d) return 1;
+    return (x->m > y->m) - (x->m < y->m);
+}
+
+/* The variant without the approximation of Sec. 3.4: every pixel p gets its
+ * own K nearest matches under the discretised geodesic distance of Eq. (3)
+ * itself, D_G(p, p_m) -- one Dijkstra from p over the pixel graph --
+ * ordered by (distance, index), weights exp(-a D_G), and its own NW
+ * (Eq. 1) or LA (Eq. 2) estimate, evaluated at p (the displacement at p of
+ * the affine map fitted about p).  Matches are placed, dropped and
+ * deduplicated as in epic_ref_seeds; K is clamped to the placed matches;
+ * the near-collinear LA test and its NW fallback are those of epic_ref_fit.
+ * pix[0..npix): the pixels (y*W + x) to evaluate; flow, knn_idx, knn_d
+ * receive npix rows (knn outputs may be NULL).  Returns 0, or -3 when no
+ * match lies in the image (flow NaN). */
+int epic_ref_exact(const float* C, int H, int W, const float* matches, int N,
+                   int K, double a, int mode, int conn, int wpow, double deg_tau,
+                   const long* pix, long npix, double* flow, int* knn_idx, double* knn_d)
+{
+    long HW = (long)H * W;
+    int* seed = (int*)malloc(sizeof(int) * (size_t)(N > 0 ? N : 1));
+    int outside = 0, dup = 0;
+    int used = epic_ref_seeds(H, W, matches, N, seed, &outside, &dup);
+    if (used == 0) {
+        for (long i = 0; i < 2 * npix; ++i) flow[i] = NAN;
+        free(seed);
+        return -3;
+    }
+    int Kc = K < used ? K : used;
+    #pragma omp parallel
+    {
+        double* D = (double*)malloc(sizeof(double) * HW);
+        dm_pair* cand = (dm_pair*)malloc(sizeof(dm_pair) * (size_t)used);
+        double* px = (double*)malloc(sizeof(double) * (size_t)Kc);
+        double* py = (double*)malloc(sizeof(double) * (size_t)Kc);
+        double* pu = (double*)malloc(sizeof(double) * (size_t)Kc);
+        double* pv = (double*)malloc(sizeof(double) * (size_t)Kc);
+        double* kw = (double*)malloc(sizeof(double) * (size_t)Kc);
+        double* lw = (double*)malloc(sizeof(double) * (size_t)Kc);
+        double* A = (double*)malloc(sizeof(double) * (size_t)Kc * 3);
+        double* b = (double*)malloc(sizeof(double) * (size_t)Kc * 2);
+        #pragma omp for schedule(dynamic, 1)
+        for (long t = 0; t < npix; ++t) {
+            long p = pix[t];
+            double xp = (double)(p % W), yp = (double)(p / W);
+            epic_ref_geodesic_from(C, H, W, (int)p, conn, D);
+            int nc = 0;
+            for (int m = 0; m < N; ++m)
+                if (seed[m] >= 0) { cand[nc].d = D[seed[m]]; cand[nc].m = m; ++nc; }
+            qsort(cand, (size_t)nc, sizeof(dm_pair), dm_cmp);
+            for (int j = 0; j < Kc; ++j) {
+                const float* r = matches + 4L * cand[j].m;
+                px[j] = r[0]; py[j] = r[1];
+                pu[j] = (double)r[2] - (double)r[0];
+                pv[j] = (double)r[3] - (double)r[1];
+                kw[j] = exp(-a * cand[j].d);
+                lw[j] = wpow == 1 ? kw[j] : kw[j] * kw[j];
+                if (knn_idx) knn_idx[t * K + j] = cand[j].m;
+                if (knn_d) knn_d[t * K + j] = cand[j].d;
+            }
+            for (int j = Kc; j < K; ++j) {
+                if (knn_idx) knn_idx[t * K + j] = -1;
+                if (knn_d) knn_d[t * K + j] = REF_INF;
+            }
+            /* Nadaraya-Watson, Eq. (1), on displacements */
+            double sk = 0, su = 0, sv = 0;
+            for (int j = 0; j < Kc; ++j) { sk += kw[j]; su += kw[j] * pu[j]; sv += kw[j] * pv[j]; }
+            double fu = su / sk, fv = sv / sk;
+            if (mode == 1) {
+                /* LA, Eq. (2), about the pixel itself: rows k [x - x_p, y - y_p, 1] */
+                int degenerate = Kc < 3;
+                if (!degenerate) {
+                    double l1, l2;
+                    cov_eigs(px, py, lw, Kc, &l1, &l2);
+                    degenerate = !(l1 > 0.0) || l2 <= deg_tau * l1;
+                }
+                if (!degenerate) {
+                    for (int j = 0; j < Kc; ++j) {
+                        double s = sqrt(lw[j]);
+                        A[j * 3 + 0] = s * (px[j] - xp);
+                        A[j * 3 + 1] = s * (py[j] - yp);
+                        A[j * 3 + 2] = s;
+                        b[j * 2 + 0] = s * pu[j];
+                        b[j * 2 + 1] = s * pv[j];
+                    }
+                    double xu[3], xv[3];
+                    if (qr_lstsq3(A, b, Kc, xu, xv) == 0) { fu = xu[2]; fv = xv[2]; }
+                }
+            }
+            flow[2 * t + 0] = fu;
+            flow[2 * t + 1] = fv;
+        }
+        free(D); free(cand); free(px); free(py); free(pu); free(pv); free(kw); free(lw); free(A); free(b);
+    }
+    free(seed);
+    return 0;
+}

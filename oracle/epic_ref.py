@@ -70,6 +70,9 @@ def lib():
         L.epic_ref_prune.restype = i32
         L.epic_ref_grad_cost.argtypes = [P, i32, i32, i32, f64, P]
         L.epic_ref_grad_cost.restype = None
+        L.epic_ref_exact.argtypes = [P, i32, i32, P, i32, i32, f64, i32, i32, i32, f64, P, i64,
+                                     P, P, P]
+        L.epic_ref_exact.restype = i32
         L.epic_ref_set_threads.argtypes = [i32]
         L.epic_ref_set_threads.restype = None
         L.epic_ref_max_threads.argtypes = []
@@ -274,3 +277,22 @@ def grad_norm_cost(image, eps=GRAD_EPS):
     out = np.empty((H, W), np.float64)
     lib().epic_ref_grad_cost(_p(I), H, W, ch, float(eps), _p(out))
     return out
+
+
+def exact(cost, matches, K, a, mode, pixels=None, conn=8, wpow=2, deg_tau=DEG_TAU):
+    """The exact per-pixel geodesic interpolation (Table 2, "Geodesic
+    (exact)"): every pixel's own K nearest matches under the geodesic
+    distance of Eq. (3) (one Dijkstra from the pixel), its own NW or LA fit
+    evaluated at the pixel.  pixels: flat indices y*W + x (default: all).
+    Returns (flow (npix, 2), knn_idx (npix, K), knn_d (npix, K), status)."""
+    c = _f32(cost)
+    H, W = c.shape
+    m = _f32(matches).reshape(-1, 4)
+    pix = np.arange(H * W, dtype=np.int64) if pixels is None else np.ascontiguousarray(pixels, np.int64)
+    n = len(pix)
+    flow = np.empty((max(n, 1), 2), np.float64)
+    ki = np.empty((max(n, 1), K), np.int32)
+    kd = np.empty((max(n, 1), K), np.float64)
+    rc = lib().epic_ref_exact(_p(c), H, W, _p(m), m.shape[0], int(K), float(a), int(mode), conn, wpow,
+                              float(deg_tau), _p(pix), n, _p(flow), _p(ki), _p(kd))
+    return flow[:n], ki[:n], kd[:n], rc

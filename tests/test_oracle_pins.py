@@ -605,3 +605,79 @@ def test_grad_cost_scales_and_matches_numpy_gradient(ref):
     gy, gx = np.gradient(img.astype(np.float64), axis=(0, 1))
     want = np.sqrt((gx ** 2 + gy ** 2).sum(2))
     np.testing.assert_allclose(C[1:-1, 1:-1], want[1:-1, 1:-1], rtol=1e-12)
+
+
+# ------------------------------------- exact per-pixel interpolation --
+
+@pytest.mark.parametrize("mode,wpow", [(1, 2), (1, 1), (0, 2)])
+def test_exact_matches_brute_force(ref, mode, wpow):
+    """Table 2's exact variant from scratch: scipy distances from every
+    match, each pixel's K nearest by (distance, index), and numpy's
+    weighted mean or least squares at the pixel (Eq. 1, Eq. 2 with rows
+    scaled by k for power 2 and sqrt(k) for power 1)."""
+    cost, m = _rand_problem(21, H=13, W=16, N=10)
+    K, a = 5, 0.8
+    f, ki, kd, rc = ref.exact(cost, m, K, a, mode, wpow=wpow)
+    assert rc == 0
+    sp = indep.seed_pixels(*cost.shape, m)
+    Dall, ids = indep.all_source_distances(cost, sp)
+    H, W = cost.shape
+    pos = m[:, :2].astype(np.float64)
+    disp = m[:, 2:].astype(np.float64) - pos
+    for p in range(H * W):
+        d = Dall[:, p]
+        order = np.lexsort((ids, d))[:K]
+        nb, dn = ids[order], d[order]
+        np.testing.assert_array_equal(ki[p], nb)
+        np.testing.assert_allclose(kd[p], dn, rtol=1e-12)
+        k = np.exp(-a * dn)
+        if mode == 0:
+            want = indep.nw_fit(disp[nb], k)
+        else:
+            A, t = indep.la_fit_absolute(pos[nb] - [p % W, p // W], disp[nb], k if wpow == 2 else np.sqrt(k))
+            want = t
+        np.testing.assert_allclose(f[p], want, rtol=1e-9, atol=1e-9)
+
+
+def test_exact_k1_equals_the_approximation(ref):
+    """With K = 1 the nearest match is the geodesic Voronoi label, so the
+    exact and the approximated interpolation agree at every pixel (to the
+    rounding of k u / k: the one weight is exp(-a D) here and 1 there)."""
+    sc = random_case(30, 41, 25, seed=23, K=1)
+    for mode in (0, 1):
+        fe, ki, _, _ = ref.exact(sc.cost, sc.matches, 1, 1.0, mode)
+        st = ref.stages(sc.cost, sc.matches, 1, 1.0, mode)
+        np.testing.assert_array_equal(ki[:, 0], st["L"].ravel())
+        fa = st["flow"].reshape(-1, 2)
+        np.testing.assert_allclose(fe, fa, rtol=1e-15, atol=1e-14)
+
+
+def test_exact_closed_forms(ref):
+    """A single global affine motion is recovered at every pixel (LA, any
+    cost map); a constant translation by NW and LA; K = N with a = 0 gives
+    the global least-squares affine map and the global mean."""
+    rng = np.random.default_rng(24)
+    H, W, N = 20, 26, 30
+    cost = rng.uniform(0.01, 2.0, (H, W)).astype(np.float32)
+    A = np.array([[1.0625, -0.03125], [0.046875, 0.9375]])
+    t = np.array([2.25, -3.5])
+    m = _exact_affine_matches(rng, H, W, N, A, t)
+    ys, xs = np.mgrid[0:H, 0:W]
+    f = ref.exact(cost, m, 6, 1.0, 1)[0]
+    np.testing.assert_allclose(f[:, 0], ((A[0, 0] - 1) * xs + A[0, 1] * ys + t[0]).ravel(), atol=1e-9)
+    np.testing.assert_allclose(f[:, 1], (A[1, 0] * xs + (A[1, 1] - 1) * ys + t[1]).ravel(), atol=1e-9)
+    m2 = m.copy()
+    m2[:, 2:] = m2[:, :2] + np.array([3.25, -1.5], np.float32)
+    for mode in (0, 1):
+        f = ref.exact(cost, m2, 7, 0.5, mode)[0]
+        np.testing.assert_allclose(f, np.tile([3.25, -1.5], (H * W, 1)), atol=1e-9)
+    rnd = m.copy()
+    rnd[:, 2:] = rnd[:, :2] + rng.normal(0, 2, (N, 2)).astype(np.float32)
+    pos = rnd[:, :2].astype(np.float64)
+    disp = rnd[:, 2:].astype(np.float64) - pos
+    fn = ref.exact(cost, rnd, N, 0.0, 0)[0]
+    np.testing.assert_allclose(fn, np.tile(disp.mean(0), (H * W, 1)), atol=1e-9)
+    fl = ref.exact(cost, rnd, N, 0.0, 1)[0]
+    Ag, tg = indep.la_fit_absolute(pos, rnd[:, 2:].astype(np.float64), np.ones(N))
+    g = np.stack([xs.ravel(), ys.ravel()], 1) @ Ag.T + tg - np.stack([xs.ravel(), ys.ravel()], 1)
+    np.testing.assert_allclose(fl, g, atol=1e-8)
