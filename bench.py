@@ -228,6 +228,47 @@ def image_cost_leg(np, torch, epic, reps=20):
     return res
 
 
+def exact_leg(np, torch, epic, full_size=True):
+    """The exact per-pixel geodesic interpolation (Table 2, "Geodesic
+    (exact)"): its time, its error against the oracle (all pixels of the
+    small scene, 48 sampled pixels of the large one), and -- as Table 2
+    compares -- the average endpoint error of the approximated and the exact
+    flow against the scene's generating motion."""
+    from oracle import epic_ref
+    from scenes import config_scene
+    out = []
+    for i in ((1, 2) if full_size else (1,)):
+        sc = config_scene(i)
+        c = torch.from_numpy(sc.cost).cuda()
+        m = torch.from_numpy(sc.matches).cuda()
+        ws = 8 * sc.K * sc.H * sc.W + sc.N + 4096 + min(1024, sc.N) * epic.workspace_bytes(sc.H, sc.W, 1, 1) \
+            + (64 << 20)
+        with epic.Context(0, ws) as ctx:
+            ts = []
+            for rep in range(3 if i == 2 else 6):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                fe = ctx.interp_exact(c, m, sc.K, sc.a, sc.mode)
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t0)
+            fa = ctx.interp(c, m, sc.K, sc.a, sc.mode).cpu().numpy().astype(np.float64)
+        fe = fe.cpu().numpy().astype(np.float64)
+        ms = sorted(ts[1:])[len(ts[1:]) // 2] * 1e3
+        HW = sc.H * sc.W
+        pix = np.arange(HW) if i == 1 else np.linspace(0, HW - 1, 48).astype(np.int64)
+        rf = epic_ref.exact(sc.cost, sc.matches, sc.K, sc.a, sc.mode, pixels=pix)[0]
+        e = np.linalg.norm(fe.reshape(-1, 2)[pix] - rf, axis=1)
+        gt = sc.gt_flow.astype(np.float64)
+        res = {"workload": sc.name, "ms": round(ms, 3), "mpix_s": round(HW / ms / 1e3, 3),
+               "vs_oracle": {"pixels": int(len(pix)), "mean_epe_px": float(e.mean()), "max_epe_px": float(e.max())},
+               "aee_vs_generating_motion": {"approximated": float(np.linalg.norm(fa - gt, axis=2).mean()),
+                                            "exact": float(np.linalg.norm(fe - gt, axis=2).mean())},
+               "mean_diff_approx_exact_px": float(np.linalg.norm(fa - fe, axis=2).mean())}
+        log(f"bench: exact {res}")
+        out.append(res)
+    return out
+
+
 def batched_form(args, np, torch, epic):
     """The 64-pair mixed-size batch: one fused launch sequence per batch,
     captured as a HIP graph with the autotuned configuration, against the
@@ -427,6 +468,7 @@ def main():
     ap.add_argument("--no-plain", action="store_true",
                     help="batched form: skip the single-pair comparison loop")
     ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--no-exact", action="store_true", help="skip the exact per-pixel interpolation leg")
     ap.add_argument("--served-requests", type=int, default=2000)
     ap.add_argument("--served-budget", type=int, default=8 << 30)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -537,6 +579,7 @@ def main():
     copy = copy_bandwidth(torch)
     roofline["copy_kernel_gbs"] = copy["gbs"]
     imcost = image_cost_leg(np, torch, epic)
+    exact = None if args.no_exact else exact_leg(np, torch, epic)
     imcost["frac_of_copy"] = round(imcost["achieved_gbs"] / copy["gbs"], 4)
     log(f"bench: device copy {copy}")
     if args.calibrate_copy:
@@ -574,6 +617,7 @@ def main():
         "served": served,
         "pruned": pruned,
         "image_cost": imcost,
+        "exact": exact,
     }
     print(json.dumps(out), flush=True)
 

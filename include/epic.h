@@ -91,7 +91,7 @@ typedef struct epic_options {
     int   tile_w, tile_h;   /* geodesic-transform tile (0 = default 32 x 16;
                                supported: 32x16, 32x32, 32x64; tile_w is 32)   */
     int   geo_passes;       /* bulk-synchronous passes of the geodesic
-                               transform launched per call, at most 63;
+                               transform launched per call, at most 255;
                                0 (default) = automatic: the most passes
                                the last 8 finished calls needed, plus 1
                                when those needs differed (16 before the
@@ -271,6 +271,24 @@ int epic_image_cost(const epic_image* imgs, int n, float eps, void* stream);
 int epic_interp_image(epic_ctx* ctx, const float* image, int H, int W, int channels, float eps,
                       const float* matches, int N, int K, float a, int mode, float* flow,
                       void* stream);
+
+/* The exact per-pixel geodesic interpolation (Table 2, "Geodesic (exact)";
+ * the quality reference for the approximation of Sec. 3.4): every pixel p
+ * gets its own K nearest matches under the geodesic distance of Eq. (3)
+ * itself, D_G(p, p_m), ordered by (distance, index), with weights
+ * exp(-a D_G), and its own NW (Eq. 1) or LA (Eq. 2) estimate evaluated at
+ * p.  One single-source transform per match (in chunks of up to 1024 that
+ * fit the workspace), a per-pixel selection and a per-pixel fit; the
+ * near-collinear LA rule and FP64 routing are those of epic_interp.
+ * Arguments as in epic_interp, with K <= 128 and a context created with
+ * precision 0 (EPIC_ERR_ARG otherwise).  The workspace must hold 8*K*H*W +
+ * N + 512 bytes for the pixels' lists plus, per match of a chunk,
+ * epic_workspace_bytes(H, W, 1, 1, mode, 0) (EPIC_ERR_WORKSPACE when not
+ * even one fits); a chunk of 1024 at 1024 x 436 needs about 3.7 GB.  No
+ * per-call statistics (epic_get_stats refers to no pair afterwards).
+ * Asynchronous on `stream`. */
+int epic_interp_exact(epic_ctx* ctx, const float* cost, int H, int W, const float* matches, int N,
+                      int K, float a, int mode, float* flow, void* stream);
 
 /* For callers that cannot allocate (code under HIP graph capture, tight
  * serving loops, harnesses that forbid allocation): epic_interp without a

@@ -184,6 +184,26 @@ class Context:
             raise EpicError(rc, "epic_interp_image")
         return out
 
+    def interp_exact(self, cost, matches, K: int, a: float, mode: int = LA, out=None, stream=None):
+        """The exact per-pixel geodesic interpolation (Table 2, "Geodesic
+        (exact)"): each pixel's own K nearest matches under the geodesic
+        distance and its own fit.  Needs a workspace of about
+        8*K*H*W + N + 512 bytes plus, per match processed at once,
+        workspace_bytes(H, W, 1, 1)."""
+        torch = _torch()
+        _check_tensor(cost, "cost", torch.float32)
+        _check_tensor(matches, "matches", torch.float32, (4,))
+        H, W = cost.shape
+        if out is None:
+            out = torch.empty((H, W, 2), dtype=torch.float32, device=cost.device)
+        _check_tensor(out, "out", torch.float32, (H, W, 2))
+        rc = _lib.load().epic_interp_exact(self._ctx, cost.data_ptr(), H, W, matches.data_ptr(),
+                                           matches.shape[0], int(K), float(a), int(mode), out.data_ptr(),
+                                           _stream_handle(stream))
+        if rc != OK:
+            raise EpicError(rc, "epic_interp_exact")
+        return out
+
     def interp_batch(self, problems, outs=None, stream=None):
         """problems: list of (cost, matches, K, a, mode).  One fused launch
         sequence for all of them; returns the list of flows."""

@@ -21,7 +21,7 @@ SYMBOLS = ["epic_create", "epic_destroy", "epic_workspace_bytes", "epic_interp",
            "epic_strerror", "epic_last_error", "epic_validate", "epic_profile",
            "epic_stage_times", "epic_stage_name", "epic_graph_capture",
            "epic_graph_launch", "epic_graph_destroy", "epic_prune", "epic_image_cost",
-           "epic_interp_image", "epic_interp_noalloc"]
+           "epic_interp_image", "epic_interp_noalloc", "epic_interp_exact"]
 
 
 class Options(ctypes.Structure):
@@ -103,6 +103,8 @@ def load():
     L.epic_interp_image.restype = i32
     L.epic_interp_noalloc.argtypes = [P, i32, i32, P, i32, i32, f32, i32, P, P]
     L.epic_interp_noalloc.restype = i32
+    L.epic_interp_exact.argtypes = [P, P, i32, i32, P, i32, i32, f32, i32, P, P]
+    L.epic_interp_exact.restype = i32
     L.epic_strerror.argtypes = [i32]
     L.epic_strerror.restype = ctypes.c_char_p
     L.epic_last_error.argtypes = []

@@ -120,6 +120,7 @@ struct epic_ctx {
     int prof_next = 0;
     int prof_count = 0;
     bool last_pruned = false;           // the last call ran the consistency check
+    PairDev* last_desc = nullptr;       // device descriptor table of the last call
 };
 
 extern "C" {
@@ -262,6 +263,11 @@ struct DebugOut {
     float prune_px = 0.0f;
     int* kept = nullptr;
     int* n_kept = nullptr;
+    // partial sequences (the exact per-pixel interpolation): 1 = stop after
+    // the seeding, 2 = after the transform; geo_passes > 0 overrides the
+    // pass budget
+    int stop_after = 0;
+    int geo_passes = 0;
 };
 
 // Where a call's descriptor table lives: the context's upload ring (default)
@@ -424,7 +430,7 @@ int run_pairs(epic_ctx* c, const epic_request* reqs, int n, hipStream_t stream, 
     }
 
     hipEvent_t* ev = nullptr;
-    if (c->prof && !tgt && !(dbg && dbg->prune_only)) {
+    if (c->prof && !tgt && !(dbg && (dbg->prune_only || dbg->stop_after))) {
         const int r = c->prof_next;
         c->prof_next = (c->prof_next + 1) % kProfRing;
         ev = c->prof_ev[r];
@@ -493,11 +499,14 @@ int run_pairs(epic_ctx* c, const epic_request* reqs, int n, hipStream_t stream, 
         if (e == hipSuccess && c->opt.debug_validate) e = launch_check_cost(dd, run, pix_blocks, stream);
         if (e == hipSuccess) e = launch_seed(dd, run, seed_blocks, stream);
         if (last) mark(1);
+        if (dbg && dbg->stop_after == 1) break;
+        const int pb0 = dbg && dbg->geo_passes > 0 ? dbg->geo_passes : budget(slot0);
         if (e == hipSuccess)
-            e = c->opt.precision == 1 ? launch_geodesic64(dd, run, budget(slot0), budget(slot0 + 1), stream)
-                                      : launch_geodesic(dd, run, tl.tw, tl.th, c->opt.geo_threads, budget(slot0),
-                                                        stream);
+            e = c->opt.precision == 1
+                    ? launch_geodesic64(dd, run, pb0, dbg && dbg->geo_passes > 0 ? pb0 : budget(slot0 + 1), stream)
+                    : launch_geodesic(dd, run, tl.tw, tl.th, c->opt.geo_threads, pb0, stream);
         if (last) mark(2);
+        if (dbg && dbg->stop_after == 2) break;
         if (e == hipSuccess) e = launch_graph_emit(dd, run, emit_blocks, stream);
         if (last) mark(3);
         if (e == hipSuccess) e = launch_csr_scan(dd, run, stream);
@@ -515,6 +524,7 @@ int run_pairs(epic_ctx* c, const epic_request* reqs, int n, hipStream_t stream, 
         mark(7);
     }
     c->last_pruned = two_pass && !(dbg && dbg->prune_only);
+    c->last_desc = dd;
     if (e == hipSuccess && dbg && (dbg->D || dbg->L)) e = launch_unpack(dd, run, pix_blocks, dbg->D, dbg->L, stream);
     if (e == hipSuccess && dbg && dbg->params)
         e = hipMemcpyAsync(dbg->params, hd[0].params, 24 * (size_t)reqs[0].N, hipMemcpyDeviceToDevice, stream);
@@ -626,6 +636,68 @@ int epic_interp_image(epic_ctx* ctx, const float* image, int H, int W, int chann
     const int rc = epic_image_cost(&im, 1, eps, stream);
     if (rc != EPIC_OK) return rc;
     return run_pairs(ctx, &r, 1, (hipStream_t)stream, nullptr, nullptr, tail + kAlign);
+}
+
+int epic_interp_exact(epic_ctx* ctx, const float* cost, int H, int W, const float* matches, int N, int K,
+                      float a, int mode, float* flow, void* stream) {
+    const int v = epic_validate(cost, H, W, matches, N, K, a, mode, flow);
+    if (v != EPIC_OK) return v;
+    if (!ctx || K > 128) return EPIC_ERR_ARG;
+    if (ctx->opt.precision != 0) return EPIC_ERR_ARG;
+    const hipStream_t st = (hipStream_t)stream;
+    const long long HW = (long long)H * W;
+    // the pixels' lists and the owner flags live at the end of the workspace
+    const size_t lists_b = align_up(8 * (size_t)K * HW), owner_b = align_up((size_t)N);
+    const size_t tail = lists_b + owner_b + kAlign;
+    if (tail >= ctx->ws_bytes) return EPIC_ERR_WORKSPACE;
+    char* tail_p = ctx->ws + ((ctx->ws_bytes - lists_b - owner_b) & ~(kAlign - 1));
+    ExactArgs A{};
+    A.matches = matches;
+    A.N = N;
+    A.K = K;
+    A.H = H;
+    A.W = W;
+    A.HW = HW;
+    A.lists = reinterpret_cast<u64*>(tail_p);
+    A.owner = reinterpret_cast<unsigned char*>(tail_p + lists_b);
+    A.flow = flow;
+    A.a = a;
+    A.mode = mode;
+    A.wpow = ctx->opt.la_weight_power;
+    A.fp64_route = ctx->opt.fp64_route;
+    A.deg_tau = ctx->opt.degenerate_tau;
+    // 1. which matches hold their pixel (the seeding of the whole set)
+    DebugOut seed_only;
+    seed_only.stop_after = 1;
+    epic_request full{cost, H, W, matches, N, 1, a, mode, flow};
+    int rc = run_pairs(ctx, &full, 1, st, &seed_only, nullptr, tail);
+    if (rc != EPIC_OK) return rc;
+    if (launch_exact_owner(ctx->last_desc, A, st) != hipSuccess) return EPIC_ERR_HIP;
+    // 2. single-source transforms, one match per pair, in chunks that fit
+    const Tiling tl{ctx->opt.tile_w, ctx->opt.tile_h};
+    const size_t per = pair_bytes(H, W, 1, 0) + 2 * align_up(4 * tiles_of(H, W, tl)) + kAlign;
+    if (ctx->ws_bytes < kFixed + tail + per) return EPIC_ERR_WORKSPACE;
+    const int chunk = (int)std::min<size_t>(kMaxPairs, (ctx->ws_bytes - kFixed - tail) / per);
+    // generous budget: a single source's distances cross the whole image
+    const int tx = (W + tl.tw - 1) / tl.tw, ty = (H + tl.th - 1) / tl.th;
+    DebugOut transform_only;
+    transform_only.stop_after = 2;
+    transform_only.geo_passes = std::min(kMaxPasses - 1, 2 * (tx + ty) + 8);
+    std::vector<epic_request> reqs;
+    for (int s0 = 0; s0 < N; s0 += chunk) {
+        const int n = std::min(chunk, N - s0);
+        reqs.assign(n, epic_request{});
+        for (int j = 0; j < n; ++j)
+            reqs[j] = epic_request{cost, H, W, matches + 4LL * (s0 + j), 1, 1, a, mode, flow};
+        rc = run_pairs(ctx, reqs.data(), n, st, &transform_only, nullptr, tail);
+        if (rc != EPIC_OK) return rc;
+        // 3. fold the chunk into every pixel's K nearest
+        if (launch_exact_select(ctx->last_desc, n, s0, s0 == 0, A, st) != hipSuccess) return EPIC_ERR_HIP;
+    }
+    // 4. one fit per pixel
+    if (launch_exact_fit(A, st) != hipSuccess) return EPIC_ERR_HIP;
+    ctx->last_npairs = 0;          // no per-call statistics
+    return EPIC_OK;
 }
 
 struct epic_graph {

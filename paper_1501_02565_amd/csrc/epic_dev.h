@@ -215,7 +215,8 @@ struct RunDev {
                             //   K-NN + fit writes each match's keep flag into fill[]
 };
 
-constexpr int kMaxPasses = 64;   // passes launched per call, at most
+constexpr int kMaxPasses = 256;  // passes launched per call, at most (pass flags
+                                 //   live in the workspace's first 4 KiB)
 
 // Descriptor tables of up to kInlinePairs pairs travel in the first kernel's
 // arguments (which the launch copies anyway); that kernel writes them to the
@@ -277,6 +278,26 @@ struct ImageCostArgs {
     float eps;
 };
 int image_cost_blocks(int H, int W);
+
+// Exact per-pixel geodesic interpolation (every pixel's own K nearest
+// matches under the geodesic distance itself).
+struct ExactArgs {
+    const float* matches;   // N*4, the call's matches
+    int N, K, H, W;
+    long long HW;
+    u64* lists;             // K*HW: entry k of pixel p at k*HW + p, packed
+                            //   (distance bits << 32 | match), ascending; ~0 = none
+    unsigned char* owner;   // N: 1 when the match holds its pixel
+    float* flow;            // H*W*2
+    float a;
+    int mode, wpow;
+    float fp64_route;
+    double deg_tau;
+};
+hipError_t launch_exact_owner(const PairDev* full, const ExactArgs& A, hipStream_t s);
+hipError_t launch_exact_select(const PairDev* chunk, int nsrc, int src0, int first, const ExactArgs& A,
+                               hipStream_t s);
+hipError_t launch_exact_fit(const ExactArgs& A, hipStream_t s);
 hipError_t launch_image_cost(const ImageCostArgs& args, int channels, int total_blocks, hipStream_t s);
 hipError_t launch_unpack(const PairDev* d_pairs, const RunDev& run, int total_blocks, float* D, int* L,
                          hipStream_t s);

@@ -1,0 +1,135 @@
+// k_exact.hip -- the exact per-pixel geodesic interpolation (Table 2 of the
+// paper, the "Geodesic (exact)" row; Sec. 5.2 compares it with the
+// approximation of Sec. 3.4): every pixel p gets its own K nearest matches
+// under the geodesic distance of Eq. (3) itself, D_G(p, p_m), ordered by
+// (distance, index), with weights exp(-a D_G), and its own NW or LA
+// estimate evaluated at p -- no Voronoi cells, no match graph.
+//
+// The distances come from single-source transforms: each match is a pair of
+// its own in a batch (the same cost map, that one match) run through the
+// tiled transform of k_geodesic.hip, which gives D_m(p) at every pixel in
+// FP32.  Sources are processed in chunks that fit the workspace; after each
+// chunk, k_exact_select folds the chunk's distances into every pixel's
+// running list of the K smallest (distance, index) keys.  k_exact_owner
+// first marks the matches that hold their pixel (placed, lowest index), so
+// dropped and duplicate matches never enter a list.  k_exact_fit then fits
+// each pixel (fit.h) with the pixel as the anchor.
+#include "epic_dev.h"
+#include "fit.h"
+#include "wave.h"
+
+namespace epic {
+
+__global__ __launch_bounds__(256) void k_exact_owner(const PairDev* __restrict__ full, ExactArgs A) {
+    const int m = (int)(blockIdx.x * 256 + threadIdx.x);
+    if (m >= A.N) return;
+    const PairDev& P = full[0];
+    const int sp = P.seed_pix[m];
+    A.owner[m] = (sp >= 0 && key_label(P.keys[sp]) == (u32)m) ? 1 : 0;
+}
+
+// One wavefront per 64 consecutive pixels (a pixel per lane); each lane's
+// sorted list of at most K (<= 128) keys lives in LDS, entry k of lane l at
+// [k * 64 + l] (consecutive lanes, consecutive words; 64 KiB at K = 128).  Sources come in
+// increasing index order, so equal distances keep the lower index first.
+__global__ __launch_bounds__(64) void k_exact_select(const PairDev* __restrict__ chunk, int nsrc, int src0,
+                                                     int first, ExactArgs A) {
+    extern __shared__ u64 L[];
+    const int lane = threadIdx.x;
+    const long long p = (long long)blockIdx.x * 64 + lane;
+    const bool valid = p < A.HW;
+    const int K = A.K;
+    int cnt = 0;
+    for (int k = 0; k < K; ++k) {
+        const u64 v = (!first && valid) ? gmem(A.lists)[(long long)k * A.HW + p] : ~0ull;
+        L[k * 64 + lane] = v;
+        cnt += v != ~0ull ? 1 : 0;
+    }
+    // sources in groups of 8 with all their loads in flight together
+    constexpr int G = 8;
+    for (int j0 = 0; j0 < nsrc; j0 += G) {
+        float d[G];
+#pragma unroll
+        for (int u = 0; u < G; ++u) {
+            const int j = j0 + u;
+            const bool use = j < nsrc && A.owner[src0 + j] != 0;          // uniform
+            d[u] = (use && valid) ? key_dist(gmem(chunk[j].keys)[p]) : __int_as_float(0x7f800000);
+        }
+#pragma unroll
+        for (int u = 0; u < G; ++u) {
+            if (!(d[u] < __int_as_float(0x7f800000))) continue;
+            const u64 key = ((u64)__float_as_uint(d[u]) << 32) | (u32)(src0 + j0 + u);
+            if (cnt == K && !(key < L[(K - 1) * 64 + lane])) continue;
+            int i = cnt < K ? cnt : K - 1;
+            while (i > 0 && L[(i - 1) * 64 + lane] > key) {
+                L[i * 64 + lane] = L[(i - 1) * 64 + lane];
+                --i;
+            }
+            L[i * 64 + lane] = key;
+            if (cnt < K) ++cnt;
+        }
+    }
+    if (valid)
+        for (int k = 0; k < K; ++k) gmem(A.lists)[(long long)k * A.HW + p] = L[k * 64 + lane];
+}
+
+// One wavefront per pixel: its list, two entries per lane at most, the
+// neighbours' rows, and the fit about the pixel (displacements taken
+// relative to the nearest neighbour's).
+template <int KMAX>
+__global__ __launch_bounds__(64) void k_exact_fit(ExactArgs A) {
+    constexpr int RK = KMAX / 64;
+    const int lane = threadIdx.x;
+    const long long p = blockIdx.x;
+    const int K = A.K;
+    int node[RK];
+    float kd[RK];
+    int n = 0;
+#pragma unroll
+    for (int r = 0; r < RK; ++r) {
+        const int j = lane + 64 * r;
+        const u64 v = j < K ? gmem(A.lists)[(long long)j * A.HW + p] : ~0ull;
+        node[r] = v != ~0ull ? (int)(u32)v : -1;
+        kd[r] = v != ~0ull ? key_dist(v) : 0.0f;
+        n += __popcll(wave::ballot(node[r] >= 0));
+    }
+    float2 f;
+    if (n == 0) {
+        f.x = f.y = __int_as_float(0x7fc00000);          // no match in the image
+    } else {
+        const int n0 = __builtin_amdgcn_readfirstlane(node[0]);
+        float4 mrow[RK];
+#pragma unroll
+        for (int r = 0; r < RK; ++r) mrow[r] = gload(reinterpret_cast<const float4*>(A.matches) + (node[r] >= 0 ? node[r] : n0));
+        const float4 m0 = gload(reinterpret_cast<const float4*>(A.matches) + n0);
+        const float xp = (float)(int)(p % A.W), yp = (float)(int)(p / A.W);
+        const FitOut fo = fit_about<RK, false>(lane, n, kd, mrow, xp, yp, m0.z - m0.x, m0.w - m0.y,
+                                               (double)m0.z - (double)m0.x, (double)m0.w - (double)m0.y,
+                                               A.a, A.wpow, A.mode == 1, A.fp64_route, A.deg_tau);
+        f.x = fo.p[4];
+        f.y = fo.p[5];
+    }
+    if (lane == 0) gstore(reinterpret_cast<float2*>(A.flow) + p, f);
+}
+
+hipError_t launch_exact_owner(const PairDev* full, const ExactArgs& A, hipStream_t s) {
+    hipLaunchKernelGGL(k_exact_owner, dim3((A.N + 255) / 256), dim3(256), 0, s, full, A);
+    return hipGetLastError();
+}
+
+hipError_t launch_exact_select(const PairDev* chunk, int nsrc, int src0, int first, const ExactArgs& A,
+                               hipStream_t s) {
+    const size_t lds = (size_t)A.K * 64 * sizeof(u64);
+    hipLaunchKernelGGL(k_exact_select, dim3((unsigned)((A.HW + 63) / 64)), dim3(64), lds, s, chunk, nsrc, src0,
+                       first, A);
+    return hipGetLastError();
+}
+
+hipError_t launch_exact_fit(const ExactArgs& A, hipStream_t s) {
+    const dim3 g((unsigned)A.HW);
+    if (A.K <= 64) hipLaunchKernelGGL(k_exact_fit<64>, g, dim3(64), 0, s, A);
+    else hipLaunchKernelGGL(k_exact_fit<128>, g, dim3(64), 0, s, A);
+    return hipGetLastError();
+}
+
+}  // namespace epic

@@ -439,12 +439,24 @@ __global__ __launch_bounds__(NT) void k_geo_finish(const PairDev* __restrict__ p
         if (threadIdx.x == 0 && run.passes_used) *run.passes_used = changed + 1;
         return;
     }
+    __shared__ int s_list[NT];
+    __shared__ int s_cnt;
     for (int pass = pass0; pass < pass0 + 65536; ++pass) {
         if (threadIdx.x == 0) s_any = 0;
         __syncthreads();
         u32* dirty = run.dirty[pass & 1];
-        for (int tile = 0; tile < run.total_tiles; ++tile) {
-            if (dirty[tile] == 0u) continue;                 // uniform: same load in all threads
+        // the dirty flags of NT tiles at a time are read in parallel and the
+        // dirty tiles listed (a batch of a million tiles is mostly clean);
+        // tiles are visited in any order, the fixpoint being unique
+        for (int t0 = 0; t0 < run.total_tiles; t0 += NT) {
+            if (threadIdx.x == 0) s_cnt = 0;
+            __syncthreads();
+            const int tt = t0 + (int)threadIdx.x;
+            if (tt < run.total_tiles && dirty[tt] != 0u) s_list[atomicAdd(&s_cnt, 1)] = tt;
+            __syncthreads();
+            const int cnt = s_cnt;
+            for (int q = 0; q < cnt; ++q) {
+            const int tile = s_list[q];
             const int p = find_pair(run.npairs, tile, [&](int i) { return pairs[i].tile_base; });
             const PairDev& P = pairs[p];
             const int lt = tile - P.tile_base;
@@ -460,6 +472,8 @@ __global__ __launch_bounds__(NT) void k_geo_finish(const PairDev* __restrict__ p
                 }
             }
             __threadfence_block();
+            __syncthreads();
+            }
             __syncthreads();
         }
         __syncthreads();

@@ -350,12 +350,22 @@ __global__ __launch_bounds__(256) void k_geo64_finish(const PairDev* __restrict_
         if (threadIdx.x == 0 && run.passes_used) run.passes_used[PHASE] = changed + 1;
         return;
     }
+    __shared__ int s_list[256];
+    __shared__ int s_cnt;
     for (int pass = pass0; pass < pass0 + 65536; ++pass) {
         if (threadIdx.x == 0) s_any = 0;
         __syncthreads();
         u32* dirty = run.dirty[pass & 1];
-        for (int tile = 0; tile < run.total_tiles; ++tile) {
-            if (dirty[tile] == 0u) continue;
+        // dirty flags read 256 at a time in parallel, dirty tiles listed
+        for (int t0 = 0; t0 < run.total_tiles; t0 += 256) {
+            if (threadIdx.x == 0) s_cnt = 0;
+            __syncthreads();
+            const int tt = t0 + (int)threadIdx.x;
+            if (tt < run.total_tiles && dirty[tt] != 0u) s_list[atomicAdd(&s_cnt, 1)] = tt;
+            __syncthreads();
+            const int cnt = s_cnt;
+            for (int q = 0; q < cnt; ++q) {
+            const int tile = s_list[q];
             const int p = find_pair(run.npairs, tile, [&](int i) { return pairs[i].tile_base; });
             const PairDev& P = pairs[p];
             const int lt = tile - P.tile_base;
@@ -371,6 +381,8 @@ __global__ __launch_bounds__(256) void k_geo64_finish(const PairDev* __restrict_
                 }
             }
             __threadfence_block();
+            __syncthreads();
+            }
             __syncthreads();
         }
         __syncthreads();
