@@ -87,6 +87,8 @@ size_t tiles_of(int H, int W, Tiling t) {
 }
 
 constexpr size_t kFixed = 4096 + (size_t)kRing * kMaxPairs * sizeof(PairDev);
+// per-tile arrays of a call: two dirty-flag arrays and three dirty-tile lists
+constexpr size_t kTileArrays = 5;
 
 }  // namespace
 
@@ -160,7 +162,7 @@ size_t epic_workspace_bytes(int H, int W, int N, int K, int mode, int precision)
         return 0;
     // the smallest tiling gives the largest tile-state array and queue ring
     const size_t t = tiles_of(H, W, Tiling{32, 16});       // the smallest tile
-    return kFixed + 2 * align_up(4 * t) + pair_bytes(H, W, N, precision);
+    return kFixed + kTileArrays * align_up(4 * t) + pair_bytes(H, W, N, precision);
 }
 
 epic_ctx* epic_create(int device, size_t workspace_bytes, const epic_options* opts) {
@@ -291,7 +293,7 @@ int run_pairs(epic_ctx* c, const epic_request* reqs, int n, hipStream_t stream, 
     // ---- carve the workspace
     size_t total_tiles = 0, need = kFixed;
     for (int i = 0; i < n; ++i) total_tiles += tiles_of(reqs[i].H, reqs[i].W, tl);
-    need += 2 * align_up(4 * total_tiles);
+    need += kTileArrays * align_up(4 * total_tiles);
     for (int i = 0; i < n; ++i) need += pair_bytes(reqs[i].H, reqs[i].W, reqs[i].N, c->opt.precision);
     if (need + reserve_tail > c->ws_bytes) return EPIC_ERR_WORKSPACE;
     if (hipSetDevice(c->device) != hipSuccess) return EPIC_ERR_HIP;
@@ -318,6 +320,8 @@ int run_pairs(epic_ctx* c, const epic_request* reqs, int n, hipStream_t stream, 
     };
     u32* dirty0 = reinterpret_cast<u32*>(take(4 * total_tiles));
     u32* dirty1 = reinterpret_cast<u32*>(take(4 * total_tiles));
+    u32* wl[3];
+    for (int k = 0; k < 3; ++k) wl[k] = reinterpret_cast<u32*>(take(4 * total_tiles));
     long long total_n = 0;
     for (int i = 0; i < n; ++i) total_n += reqs[i].N;
     int* ovf_list = reinterpret_cast<int*>(take(4 * (size_t)total_n));
@@ -401,6 +405,8 @@ int run_pairs(epic_ctx* c, const epic_request* reqs, int n, hipStream_t stream, 
     if (dbg && dbg->knn_idx && !dbg->knn_d) return EPIC_ERR_ARG;
 
     RunDev run{};
+    for (int k = 0; k < 3; ++k) run.wl[k] = wl[k];
+    run.wl_cnt = c->g_error + 12;
     run.dirty[0] = dirty0;
     run.dirty[1] = dirty1;
     run.any = c->g_any;
@@ -628,7 +634,7 @@ int epic_interp_image(epic_ctx* ctx, const float* image, int H, int W, int chann
     if (v != EPIC_OK) return v;
     // check the workspace before anything is enqueued
     epic_request r{cost, H, W, matches, N, K, a, mode, flow};
-    const size_t need = kFixed + 2 * align_up(4 * tiles_of(H, W, Tiling{ctx->opt.tile_w, ctx->opt.tile_h})) +
+    const size_t need = kFixed + kTileArrays * align_up(4 * tiles_of(H, W, Tiling{ctx->opt.tile_w, ctx->opt.tile_h})) +
                         pair_bytes(H, W, N, ctx->opt.precision);
     if (need + tail + kAlign > ctx->ws_bytes) return EPIC_ERR_WORKSPACE;
     if (hipSetDevice(ctx->device) != hipSuccess) return EPIC_ERR_HIP;
@@ -675,7 +681,7 @@ int epic_interp_exact(epic_ctx* ctx, const float* cost, int H, int W, const floa
     if (launch_exact_owner(ctx->last_desc, A, st) != hipSuccess) return EPIC_ERR_HIP;
     // 2. single-source transforms, one match per pair, in chunks that fit
     const Tiling tl{ctx->opt.tile_w, ctx->opt.tile_h};
-    const size_t per = pair_bytes(H, W, 1, 0) + 2 * align_up(4 * tiles_of(H, W, tl)) + kAlign;
+    const size_t per = pair_bytes(H, W, 1, 0) + kTileArrays * align_up(4 * tiles_of(H, W, tl)) + kAlign;
     if (ctx->ws_bytes < kFixed + tail + per) return EPIC_ERR_WORKSPACE;
     const int chunk = (int)std::min<size_t>(kMaxPairs, (ctx->ws_bytes - kFixed - tail) / per);
     // generous budget: a single source's distances cross the whole image

@@ -192,6 +192,9 @@ __device__ __forceinline__ u32 label_at(const PairDev& P, long long i) {
 // Globals of one launch sequence (shared by all pairs of a batch).
 struct RunDev {
     u32* dirty[2];          // per tile, by pass parity: tile needs a visit
+    u32* wl[3];             // the dirty tiles of pass p, listed in wl[p % 3] (FP32
+                            //   transform): each tile once, appended when its flag is set
+    int* wl_cnt;            // 3 list lengths
     int* any;               // per pass: some tile border changed (kMaxPasses)
     int* any2;              // the same for the label phase of the FP64 path
     int* error;             // global error word: bit 0 = the transform finisher hit

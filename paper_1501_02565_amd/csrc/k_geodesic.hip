@@ -10,7 +10,8 @@
 // Algorithm: bulk-synchronous, tiled label-correcting relaxation.
 //   * The image is cut into TW x TH tiles.  A tile is dirty when a pixel of
 //     its 1-pixel halo (or a seed inside it) changed since its last visit.
-//   * One pass is one launch over all tiles.  A dirty tile is loaded with
+//   * One pass is one launch.  The first visits every tile; each later one
+//     walks the list of tiles marked dirty by the pass before.  A dirty tile is loaded with
 //     its halo into LDS, relaxed to a local fixpoint (or for a capped number
 //     of rounds, after which it marks itself dirty), written back, and the
 //     neighbours behind every changed border are marked dirty for the next
@@ -31,11 +32,12 @@
 //   * In the first pass (every tile busy) blocks are mapped to tiles so that
 //     each XCD (blocks are dealt to the 8 XCDs round-robin) works on a
 //     contiguous band of tile rows, keeping most halo traffic in one XCD's
-//     L2; the later passes map block b to tile b, which spreads their
-//     spatially clustered dirty tiles over all XCDs.
+//     L2; the later passes take their tiles in list order, which spreads
+//     the spatially clustered dirty tiles over all XCDs.
 //   * A fixed number of passes is launched.  If the last one still changed
 //     a border, a single-workgroup finisher continues the same passes until
 //     the fixpoint, so the result never depends on the pass budget.
+#include <algorithm>
 #include <type_traits>
 
 #include "epic_dev.h"
@@ -339,24 +341,40 @@ __device__ __forceinline__ int visit_tile(const PairDev& P, int tx, int ty,
     return border;
 }
 
-// Marks the tiles behind changed borders dirty for pass `next`.
-template <int CONN>
+// Marks the tiles behind changed borders dirty for pass `next`; called by
+// every thread of the workgroup with the (uniform) border mask.  With
+// LISTED, thread k < 9 takes direction k (its exchange and append round
+// trips overlap the others'), and a tile whose flag it sets is appended to
+// the pass's dirty-tile list (the exchange lets each tile enter once);
+// without, thread 0 stores the flags (passes that visit every flagged tile
+// by scanning).
+template <int CONN, bool LISTED>
 __device__ void mark_neighbours(const PairDev& P, const RunDev& run, int tx, int ty, int border, int next) {
-    EPIC_GLOBAL u32* dirty = gmem(run.dirty[next & 1]) + P.tile_base;
-    const int nx = P.tiles_x, ny = P.tiles_y;
-    auto mark = [&](int cx, int cy) {
-        if (cx >= 0 && cy >= 0 && cx < nx && cy < ny) dirty[cy * nx + cx] = 1u;
-    };
-    if (border & B_SELF) mark(tx, ty);
-    if (border & B_L) mark(tx - 1, ty);
-    if (border & B_R) mark(tx + 1, ty);
-    if (border & B_T) mark(tx, ty - 1);
-    if (border & B_B) mark(tx, ty + 1);
-    if (CONN == 8) {
-        if (border & B_TL) mark(tx - 1, ty - 1);
-        if (border & B_TR) mark(tx + 1, ty - 1);
-        if (border & B_BL) mark(tx - 1, ty + 1);
-        if (border & B_BR) mark(tx + 1, ty + 1);
+    constexpr int BIT[9] = {B_SELF, B_L, B_R, B_T, B_B, B_TL, B_TR, B_BL, B_BR};
+    constexpr int DXK[9] = {0, -1, 1, 0, 0, -1, 1, -1, 1};
+    constexpr int DYK[9] = {0, 0, 0, -1, 1, -1, -1, 1, 1};
+    constexpr int ND = CONN == 8 ? 9 : 5;
+    if (!LISTED) {
+        // plain stores, issued one after another by one thread (measured
+        // faster than spreading them over lanes)
+        if (threadIdx.x != 0) return;
+        EPIC_GLOBAL u32* dirty = gmem(run.dirty[next & 1]) + P.tile_base;
+#pragma unroll
+        for (int k = 0; k < ND; ++k) {
+            const int cx = tx + DXK[k], cy = ty + DYK[k];
+            if ((border & BIT[k]) && cx >= 0 && cy >= 0 && cx < P.tiles_x && cy < P.tiles_y)
+                dirty[cy * P.tiles_x + cx] = 1u;
+        }
+        return;
+    }
+    const int k = threadIdx.x;
+    if (k >= ND || !(border & BIT[k])) return;
+    const int cx = tx + DXK[k], cy = ty + DYK[k];
+    if (cx < 0 || cy < 0 || cx >= P.tiles_x || cy >= P.tiles_y) return;
+    const int t = cy * P.tiles_x + cx;
+    if (atomicExch(&run.dirty[next & 1][P.tile_base + t], 1u) == 0u) {
+        const int L = next % 3;
+        run.wl[L][atomicAdd(&run.wl_cnt[L], 1)] = (u32)(P.tile_base + t);
     }
 }
 
@@ -372,38 +390,49 @@ __device__ void mark_neighbours(const PairDev& P, const RunDev& run, int tx, int
 constexpr int kFirstRounds = 4;
 constexpr int kPassRounds = 5;
 
-// One pass over all tiles of all pairs.
-template <int TW, int TH, int CONN, int NT>
+// One pass.  LISTED: the grid walks the pass's list of dirty tiles (written
+// by the previous pass), so a launch costs what its dirty tiles cost however
+// many tiles the pairs of the call have; the list of pass p + 2 (read by
+// pass p - 1) is emptied here for pass p + 1 to fill, and list order (the
+// order of marking) spreads the spatially clustered dirty tiles over the
+// XCDs.  Otherwise block b takes tile b (consecutive tiles go to different
+// XCDs) and returns at once when its flag is clear: cheaper for a single
+// image, whose marks then are plain stores.
+template <int TW, int TH, int CONN, int NT, bool LISTED>
 __global__ __launch_bounds__(NT) void k_geo_pass(const PairDev* __restrict__ pairs, RunDev run, int pass) {
     __shared__ TileLds<TW, TH> S;
     if (pass > 0 && run.any[pass - 1] == 0) return;          // converged
-    // block b takes tile b: consecutive tiles go to different XCDs (blocks
-    // are dealt to the 8 XCDs in turn), so the dirty tiles of a later pass,
-    // which cluster in space, are spread over all of them
-    const int tile = (int)blockIdx.x;
-    if (tile >= run.total_tiles) return;
     u32* dirty = run.dirty[pass & 1];
-    if (dirty[tile] == 0u) return;
-    const int p = find_pair(run.npairs, tile, [&](int i) { return pairs[i].tile_base; });
-    const PairDev& P = pairs[p];
-    const int lt = tile - P.tile_base;
-    const int tx = lt % P.tiles_x, ty = lt / P.tiles_x;
-    __syncthreads();
-    if (threadIdx.x == 0) dirty[tile] = 0u;                  // reused two passes later
-    const int border = visit_tile<TW, TH, 0, 0, CONN, NT>(P, tx, ty, S, P.counters + C_GEOERR, kPassRounds);
-    if (threadIdx.x == 0) {
-        atomicAdd(&P.counters[C_TILE_VISITS], 1);
+    auto visit = [&](int tile) {
+        const int p = find_pair(run.npairs, tile, [&](int k) { return pairs[k].tile_base; });
+        const PairDev& P = pairs[p];
+        const int lt = tile - P.tile_base;
+        const int tx = lt % P.tiles_x, ty = lt / P.tiles_x;
+        __syncthreads();                                     // the previous tile's LDS is done
+        if (threadIdx.x == 0) dirty[tile] = 0u;              // reused two passes later
+        const int border = visit_tile<TW, TH, 0, 0, CONN, NT>(P, tx, ty, S, P.counters + C_GEOERR, kPassRounds);
+        if (threadIdx.x == 0) atomicAdd(&P.counters[C_TILE_VISITS], 1);
         if (border) {
-            mark_neighbours<CONN>(P, run, tx, ty, border, pass + 1);
-            run.any[pass] = 1;
+            mark_neighbours<CONN, LISTED>(P, run, tx, ty, border, pass + 1);
+            if (threadIdx.x == 0) run.any[pass] = 1;
         }
+    };
+    if constexpr (LISTED) {
+        const int cnt = run.wl_cnt[pass % 3];
+        if (blockIdx.x == 0 && threadIdx.x == 0) run.wl_cnt[(pass + 2) % 3] = 0;
+        const u32* list = run.wl[pass % 3];
+        for (int i = (int)blockIdx.x; i < cnt; i += (int)gridDim.x) visit((int)list[i]);
+    } else {
+        const int tile = (int)blockIdx.x;
+        if (tile >= run.total_tiles || dirty[tile] == 0u) return;
+        visit(tile);
     }
 }
 
 
 // The first pass: every tile, relaxed over the tile and a margin of MX
 // columns and MY rows around it (seeds from the start, written by k_seed).
-template <int TW, int TH, int MX, int MY, int CONN, int NT>
+template <int TW, int TH, int MX, int MY, int CONN, int NT, bool LISTED>
 __global__ __launch_bounds__(NT) void k_geo_first(const PairDev* __restrict__ pairs, RunDev run) {
     __shared__ TileLds<TW + 2 * MX, TH + 2 * MY> S;
     const int per_xcd = (run.total_tiles + 7) / 8;
@@ -415,12 +444,10 @@ __global__ __launch_bounds__(NT) void k_geo_first(const PairDev* __restrict__ pa
     const int tx = lt % P.tiles_x, ty = lt / P.tiles_x;
     if (threadIdx.x == 0) run.dirty[0][tile] = 0u;           // reused by pass 2
     const int border = visit_tile<TW, TH, MX, MY, CONN, NT>(P, tx, ty, S, P.counters + C_GEOERR, kFirstRounds);
-    if (threadIdx.x == 0) {
-        atomicAdd(&P.counters[C_TILE_VISITS], 1);
-        if (border) {
-            mark_neighbours<CONN>(P, run, tx, ty, border, 1);
-            run.any[0] = 1;
-        }
+    if (threadIdx.x == 0) atomicAdd(&P.counters[C_TILE_VISITS], 1);
+    if (border) {
+        mark_neighbours<CONN, LISTED>(P, run, tx, ty, border, 1);
+        if (threadIdx.x == 0) run.any[0] = 1;
     }
 }
 
@@ -464,12 +491,10 @@ __global__ __launch_bounds__(NT) void k_geo_finish(const PairDev* __restrict__ p
             __syncthreads();
             if (threadIdx.x == 0) dirty[tile] = 0u;
             const int border = visit_tile<TW, TH, 0, 0, CONN, NT>(P, tx, ty, S, P.counters + C_GEOERR);
-            if (threadIdx.x == 0) {
-                atomicAdd(&P.counters[C_TILE_VISITS], 1);
-                if (border) {
-                    mark_neighbours<CONN>(P, run, tx, ty, border, pass + 1);
-                    s_any = 1;
-                }
+            if (threadIdx.x == 0) atomicAdd(&P.counters[C_TILE_VISITS], 1);
+            if (border) {
+                mark_neighbours<CONN, false>(P, run, tx, ty, border, pass + 1);
+                if (threadIdx.x == 0) s_any = 1;
             }
             __threadfence_block();
             __syncthreads();
@@ -497,18 +522,32 @@ namespace {
 constexpr int first_margin(int th) { return th == 16 ? 2 : 4; }
 constexpr int first_threads(int th) { return th == 16 ? 180 : th == 32 ? 800 : 720; }
 
-template <int TW, int TH, int CONN, int NT>
-hipError_t launch_t(const PairDev* d_pairs, const RunDev& run, int passes, hipStream_t s) {
+// Calls with more tiles than kListTiles walk dirty-tile lists in their
+// later passes, with grids of at most kPassGrid blocks (a longer list is
+// walked in turns); smaller ones launch a block per tile.
+constexpr int kListTiles = 4096;
+constexpr int kPassGrid = 2048;
+
+template <int TW, int TH, int CONN, int NT, bool LISTED>
+hipError_t launch_l(const PairDev* d_pairs, const RunDev& run, int passes, hipStream_t s) {
     const int grid = 8 * ((run.total_tiles + 7) / 8);
+    const int pgrid = LISTED ? std::min(run.total_tiles, kPassGrid) : grid;
     constexpr int NT0 = first_threads(TH), M0 = first_margin(TH);
-    hipLaunchKernelGGL((k_geo_first<TW, TH, M0, M0, CONN, NT0>), dim3(grid), dim3(NT0), 0, s, d_pairs, run);
+    hipLaunchKernelGGL((k_geo_first<TW, TH, M0, M0, CONN, NT0, LISTED>), dim3(grid), dim3(NT0), 0, s, d_pairs,
+                       run);
     for (int p = 1; p < passes; ++p) {
-        hipLaunchKernelGGL((k_geo_pass<TW, TH, CONN, NT>), dim3(grid), dim3(NT), 0, s, d_pairs, run, p);
+        hipLaunchKernelGGL((k_geo_pass<TW, TH, CONN, NT, LISTED>), dim3(pgrid), dim3(NT), 0, s, d_pairs, run, p);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
     hipLaunchKernelGGL((k_geo_finish<TW, TH, CONN, NT>), dim3(1), dim3(NT), 0, s, d_pairs, run, passes);
     return hipGetLastError();
+}
+
+template <int TW, int TH, int CONN, int NT>
+hipError_t launch_t(const PairDev* d_pairs, const RunDev& run, int passes, hipStream_t s) {
+    return run.total_tiles > kListTiles ? launch_l<TW, TH, CONN, NT, true>(d_pairs, run, passes, s)
+                                        : launch_l<TW, TH, CONN, NT, false>(d_pairs, run, passes, s);
 }
 
 // Threads per tile: runs of 2 pixels (32 x 16), 8 (32 x 32, 32 x 64)

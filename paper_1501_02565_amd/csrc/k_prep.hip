@@ -62,6 +62,7 @@ __global__ __launch_bounds__(256) void k_clear(PairDev* __restrict__ pairs, RunD
         *run.error = 0;
         *run.ovf_count = 0;
     }
+    if (p == 0 && i0 < 3) run.wl_cnt[i0] = 0;
 }
 
 __global__ __launch_bounds__(256) void k_seed(const PairDev* __restrict__ pairs, RunDev run) {
