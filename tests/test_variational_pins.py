@@ -137,7 +137,7 @@ def test_iterate_is_a_stationary_point_of_the_energy():
     I1 = _texture(rng, H, W)
     I2 = _texture(rng, H, W)
     u0 = rng.normal(0, 0.5, (H, W, 2))
-    p = va.Params(fixed_point=80, sor=300)
+    p = va.Params(fixed_point=200, sor=200)
     _, du, dv = va.refine(I1, I2, u0, p, return_du=True)
     JC, JG, alpha = va.coefficients(I1, I2, u0, p)
     u0d = np.asarray(u0, np.float32).astype(np.float64)
