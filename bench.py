@@ -269,6 +269,67 @@ def exact_leg(np, torch, epic, full_size=True):
     return out
 
 
+def refine_leg(np, torch, epic, reps=10):
+    """The one-level variational refinement (Sec. 4) of the interpolated
+    field of each single-pair scene with an image pair: its time alone and
+    after the interpolation (both on one stream, HIP events), the average
+    endpoint error against the scene's generating motion before and after,
+    and its difference from the oracle (both refining the oracle's own
+    interpolation).  Roofline of the relaxation sweep kernel, which carries
+    the bytes: per pixel and sweep 8 B du/dv, 8 B u0, 28 B of the system
+    read and 8 B written (52 B; neighbours come from the caches)."""
+    from oracle import epic_ref
+    from oracle import variational as va
+    from scenes import config_scene
+    out = []
+    p = epic.refine_params()
+    for i in (1, 2):
+        sc = config_scene(i, with_pair=True)
+        t = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float32)).cuda()
+        c, m, I1, I2 = t(sc.cost), t(sc.matches), t(sc.image), t(sc.image2)
+        HW = sc.H * sc.W
+        ws = epic.workspace_bytes(sc.H, sc.W, sc.N, sc.K) + epic.refine_bytes(sc.H, sc.W, 3) + (1 << 20)
+        with epic.Context(0, ws) as ctx:
+            flow = ctx.interp(c, m, sc.K, sc.a, sc.mode)
+            ref_out = ctx.refine(I1, I2, flow)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            for _ in range(3):
+                ctx.refine(I1, I2, flow, out=ref_out)
+            e0.record()
+            for _ in range(reps):
+                ctx.refine(I1, I2, flow, out=ref_out)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            e0.record()
+            for _ in range(reps):
+                ctx.interp(c, m, sc.K, sc.a, sc.mode, out=flow)
+                ctx.refine(I1, I2, flow, out=ref_out)
+            e1.record()
+            torch.cuda.synchronize()
+            ms_both = e0.elapsed_time(e1) / reps
+            f0 = flow.cpu().numpy().astype(np.float64)
+            f1 = ref_out.cpu().numpy().astype(np.float64)
+            u0 = epic_ref.interp(sc.cost, sc.matches, sc.K, sc.a, sc.mode)[0].astype(np.float32)
+            g = ctx.refine(I1, I2, t(u0)).cpu().numpy().astype(np.float64)
+        r = va.refine(sc.image, sc.image2, u0)
+        d = np.linalg.norm(g - r, axis=2)
+        gt = sc.gt_flow.astype(np.float64)
+        sweeps = p.fixed_point * p.sor
+        nbytes = 52.0 * HW * sweeps
+        res = {"workload": sc.name + "_pair", "ms": round(ms, 4), "interp_plus_refine_ms": round(ms_both, 4),
+               "mpix_s": round(HW / ms / 1e3, 2), "fixed_point": p.fixed_point, "sor": p.sor,
+               "launches": 4 + p.fixed_point * (1 + 2 * p.sor),
+               "sweep_algorithmic_bytes": nbytes,
+               "sweep_bytes_per_ms_of_call_gbs": round(nbytes / (ms * 1e-3) / 1e9, 1),
+               "aee_vs_generating_motion": {"interpolated": float(np.linalg.norm(f0 - gt, axis=2).mean()),
+                                            "refined": float(np.linalg.norm(f1 - gt, axis=2).mean())},
+               "vs_oracle": {"mean_epe_px": float(d.mean()), "max_epe_px": float(d.max())}}
+        log(f"bench: refine {res}")
+        out.append(res)
+    return out
+
+
 def batched_form(args, np, torch, epic):
     """The 64-pair mixed-size batch: one fused launch sequence per batch,
     captured as a HIP graph with the autotuned configuration, against the
@@ -469,6 +530,7 @@ def main():
                     help="batched form: skip the single-pair comparison loop")
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--no-exact", action="store_true", help="skip the exact per-pixel interpolation leg")
+    ap.add_argument("--no-refine", action="store_true", help="skip the variational refinement leg")
     ap.add_argument("--served-requests", type=int, default=2000)
     ap.add_argument("--served-budget", type=int, default=8 << 30)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -580,6 +642,7 @@ def main():
     roofline["copy_kernel_gbs"] = copy["gbs"]
     imcost = image_cost_leg(np, torch, epic)
     exact = None if args.no_exact else exact_leg(np, torch, epic)
+    refine = None if args.no_refine else refine_leg(np, torch, epic)
     imcost["frac_of_copy"] = round(imcost["achieved_gbs"] / copy["gbs"], 4)
     log(f"bench: device copy {copy}")
     if args.calibrate_copy:
@@ -618,6 +681,7 @@ def main():
         "pruned": pruned,
         "image_cost": imcost,
         "exact": exact,
+        "refine": refine,
     }
     print(json.dumps(out), flush=True)
 

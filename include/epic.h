@@ -290,6 +290,59 @@ int epic_interp_image(epic_ctx* ctx, const float* image, int H, int W, int chann
 int epic_interp_exact(epic_ctx* ctx, const float* cost, int H, int W, const float* matches, int N,
                       int K, float a, int mode, float* flow, void* stream);
 
+/* One-level variational refinement of a dense flow field (Sec. 4: the
+ * interpolated field initialises an energy minimisation run at the full
+ * resolution only, without coarse-to-fine).  The energy (the data term is
+ * cited by the paper, not written out; this is the library's reading of
+ * it): with I2w = I2 warped by the input field u0 (bilinear, coordinates
+ * clamped), derivatives by central differences with the border pixel
+ * repeated, and per channel Iz = I2w - I1, Ixz/Iyz the gradient of I2w
+ * minus that of I1,
+ *   E(du) = sum_x  delta psi(sum_c (Iz + Ix du + Iy dv)^2 / (Ix^2 + Iy^2 + zeta^2))
+ *               + gamma psi(sum_c (Ixz + Ixx du + Ixy dv)^2 / (Ixx^2 + Ixy^2 + zeta^2)
+ *                                + (Iyz + Ixy du + Iyy dv)^2 / (Ixy^2 + Iyy^2 + zeta^2))
+ *         + sum over 4-neighbour edges (i, j)
+ *               lam (alpha_i + alpha_j) / 2 psi(|U_j - U_i|^2 + |V_j - V_i|^2)
+ * where psi(s^2) = sqrt(s^2 + eps^2), U = u0 + du, V = v0 + dv and the
+ * local smoothness weight alpha = exp(-kappa ||grad I1||) (kappa = 5 in the
+ * paper).  The data term is linearised once about u0; `fixed_point` times
+ * (5 in the paper) the weights psi' are evaluated at the current update and
+ * the linear Euler-Lagrange system is relaxed by `sor` red-black
+ * successive-over-relaxation sweeps (30 in the paper) with factor omega.
+ * The output is u0 + du.  FP32 throughout.
+ *   I1, I2     device, H*W*channels float32 (channels 1 to 4, interleaved)
+ *   flow_in    device, H*W*2 float32, the field to refine (e.g. the output
+ *              of epic_interp)
+ *   flow_out   device, H*W*2 float32 output; may be flow_in itself, must not
+ *              overlap it otherwise
+ *   params     host; NULL takes epic_refine_defaults
+ * Scratch: epic_refine_bytes(H, W, channels) bytes at the end of the
+ * context's workspace (88 + 4*channels bytes per pixel plus alignment),
+ * after the workspace's fixed 4096 + descriptor-ring head; EPIC_ERR_WORKSPACE
+ * when it does not fit.  The statistics of the last interpolation remain
+ * readable when the workspace also holds that call's part.  Host-side
+ * validation returns EPIC_ERR_ARG (null or misaligned pointers, sizes,
+ * non-finite or negative parameters, eps or zeta not > 0, omega outside
+ * (0, 2), fixed_point outside [0, 100], sor outside [0, 10000]).
+ * Asynchronous on `stream`; calls on one context must be ordered (one
+ * stream), as for epic_interp. */
+typedef struct epic_refine_params {
+    float lam;          /* smoothness weight, default 0.1 */
+    float delta;        /* colour-constancy weight, default 0.1 */
+    float gamma;        /* gradient-constancy weight, default 0.7 */
+    float kappa;        /* alpha = exp(-kappa ||grad I1||), default 5 */
+    float eps;          /* psi's regulariser, default 1e-3 */
+    float zeta;         /* normalisation floor, default 0.1 */
+    float omega;        /* over-relaxation factor, default 1.6 */
+    int fixed_point;    /* outer iterations, default 5 */
+    int sor;            /* sweeps per outer iteration, default 30 */
+} epic_refine_params;
+void epic_refine_defaults(epic_refine_params* p);
+size_t epic_refine_bytes(int H, int W, int channels);
+int epic_refine(epic_ctx* ctx, const float* I1, const float* I2, int H, int W, int channels,
+                const float* flow_in, float* flow_out, const epic_refine_params* params,
+                void* stream);
+
 /* For callers that cannot allocate (code under HIP graph capture, tight
  * serving loops, harnesses that forbid allocation): epic_interp without a
  * context.  Its workspace is a 64 MiB device array inside the library, one

@@ -38,7 +38,8 @@ smoothness term, g_ij = lam (alpha_i + alpha_j) / 2 psi'(...) -- and solves
    (A11 + sum_j g_ij) du_i + A12 dv_i = b1 + sum_j g_ij (U_j - u0_i)
    A12 du_i + (A22 + sum_j g_ij) dv_i = b2 + sum_j g_ij (V_j - v0_i)
 by 30 red-black SOR sweeps (red: x + y even, then black; du before dv at
-each pixel).  The result is u0 + du.
+each pixel); an equation whose diagonal is zero (no image gradient and no
+neighbour weight) leaves its unknown unchanged.  The result is u0 + du.
 """
 from __future__ import annotations
 
@@ -192,10 +193,15 @@ def sor_sweep(A11, A12, A22, b1, b2, gx, gy, u0, du, dv, p: Params, color):
     ys, xs = np.mgrid[0:H, 0:W]
     sel = ((xs + ys) & 1) == color
     sw, su, sv = _neighbour_sums(gx, gy, u0, du, dv)
-    nu = (b1 - A12 * dv + su) / (A11 + sw)
-    du_new = np.where(sel, (1 - p.omega) * du + p.omega * nu, du)
-    nv = (b2 - A12 * du_new + sv) / (A22 + sw)
-    dv_new = np.where(sel, (1 - p.omega) * dv + p.omega * nv, dv)
+    # a zero diagonal (no image gradient and no neighbour weight: a flat
+    # 1 x 1 image, or lam = 0 on a flat region) leaves the equation empty:
+    # that unknown keeps its value
+    du_u = sel & (A11 + sw > 0)
+    nu = (b1 - A12 * dv + su) / np.where(du_u, A11 + sw, 1.0)
+    du_new = np.where(du_u, (1 - p.omega) * du + p.omega * nu, du)
+    dv_u = sel & (A22 + sw > 0)
+    nv = (b2 - A12 * du_new + sv) / np.where(dv_u, A22 + sw, 1.0)
+    dv_new = np.where(dv_u, (1 - p.omega) * dv + p.omega * nv, dv)
     du[...] = du_new
     dv[...] = dv_new
 

@@ -70,6 +70,22 @@ def image_cost(images, eps: float = GRAD_EPS, outs=None, stream=None):
     return costs[0] if single else costs
 
 
+def refine_params(**overrides):
+    """epic_refine_params: the library defaults with `overrides` applied."""
+    p = _lib.RefineParams()
+    _lib.load().epic_refine_defaults(ctypes.byref(p))
+    for k, v in overrides.items():
+        if not any(k == f[0] for f in _lib.RefineParams._fields_):
+            raise TypeError(f"unknown refinement parameter {k!r}")
+        setattr(p, k, v)
+    return p
+
+
+def refine_bytes(H: int, W: int, channels: int = 3) -> int:
+    """Workspace bytes epic_refine takes at the end of the workspace."""
+    return int(_lib.load().epic_refine_bytes(H, W, channels))
+
+
 def _stream_handle(stream):
     torch = _torch()
     if stream is None:
@@ -202,6 +218,32 @@ class Context:
                                            _stream_handle(stream))
         if rc != OK:
             raise EpicError(rc, "epic_interp_exact")
+        return out
+
+    def refine(self, I1, I2, flow, out=None, stream=None, **params):
+        """One-level variational refinement (Sec. 4) of a dense field
+        `flow` (H, W, 2) between images I1 and I2 (H, W[, channels <= 4]),
+        all float32 CUDA tensors.  Keyword parameters override the defaults
+        (lam, delta, gamma, kappa, eps, zeta, omega, fixed_point, sor);
+        `out` may be `flow` itself.  Needs refine_bytes(H, W, channels)
+        bytes at the end of the workspace beyond its fixed head."""
+        torch = _torch()
+        _check_tensor(I1, "I1", torch.float32)
+        _check_tensor(I2, "I2", torch.float32)
+        if I1.shape != I2.shape:
+            raise ValueError("I1 and I2 must have the same shape")
+        H, W = I1.shape[:2]
+        ch = 1 if I1.dim() == 2 else int(I1.shape[2])
+        _check_tensor(flow, "flow", torch.float32, (H, W, 2))
+        if out is None:
+            out = torch.empty((H, W, 2), dtype=torch.float32, device=flow.device)
+        _check_tensor(out, "out", torch.float32, (H, W, 2))
+        p = refine_params(**params)
+        rc = _lib.load().epic_refine(self._ctx, I1.data_ptr(), I2.data_ptr(), H, W, ch,
+                                     flow.data_ptr(), out.data_ptr(), ctypes.byref(p),
+                                     _stream_handle(stream))
+        if rc != OK:
+            raise EpicError(rc, "epic_refine")
         return out
 
     def interp_batch(self, problems, outs=None, stream=None):

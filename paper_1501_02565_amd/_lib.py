@@ -21,7 +21,8 @@ SYMBOLS = ["epic_create", "epic_destroy", "epic_workspace_bytes", "epic_interp",
            "epic_strerror", "epic_last_error", "epic_validate", "epic_profile",
            "epic_stage_times", "epic_stage_name", "epic_graph_capture",
            "epic_graph_launch", "epic_graph_destroy", "epic_prune", "epic_image_cost",
-           "epic_interp_image", "epic_interp_noalloc", "epic_interp_exact"]
+           "epic_interp_image", "epic_interp_noalloc", "epic_interp_exact",
+           "epic_refine_defaults", "epic_refine_bytes", "epic_refine"]
 
 
 class Options(ctypes.Structure):
@@ -51,6 +52,14 @@ class Image(ctypes.Structure):
     _fields_ = [("image", ctypes.c_void_p),
                 ("H", ctypes.c_int), ("W", ctypes.c_int), ("channels", ctypes.c_int),
                 ("cost", ctypes.c_void_p)]
+
+
+class RefineParams(ctypes.Structure):
+    _fields_ = [("lam", ctypes.c_float), ("delta", ctypes.c_float),
+                ("gamma", ctypes.c_float), ("kappa", ctypes.c_float),
+                ("eps", ctypes.c_float), ("zeta", ctypes.c_float),
+                ("omega", ctypes.c_float), ("fixed_point", ctypes.c_int),
+                ("sor", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):
@@ -105,6 +114,12 @@ def load():
     L.epic_interp_noalloc.restype = i32
     L.epic_interp_exact.argtypes = [P, P, i32, i32, P, i32, i32, f32, i32, P, P]
     L.epic_interp_exact.restype = i32
+    L.epic_refine_defaults.argtypes = [ctypes.POINTER(RefineParams)]
+    L.epic_refine_defaults.restype = None
+    L.epic_refine_bytes.argtypes = [i32, i32, i32]
+    L.epic_refine_bytes.restype = sz
+    L.epic_refine.argtypes = [P, P, P, i32, i32, i32, P, P, ctypes.POINTER(RefineParams), P]
+    L.epic_refine.restype = i32
     L.epic_strerror.argtypes = [i32]
     L.epic_strerror.restype = ctypes.c_char_p
     L.epic_last_error.argtypes = []

@@ -123,6 +123,7 @@ struct epic_ctx {
     int prof_count = 0;
     bool last_pruned = false;           // the last call ran the consistency check
     PairDev* last_desc = nullptr;       // device descriptor table of the last call
+    size_t last_used = 0;               // workspace bytes the last call carved (from its start)
 };
 
 extern "C" {
@@ -325,6 +326,7 @@ int run_pairs(epic_ctx* c, const epic_request* reqs, int n, hipStream_t stream, 
     long long total_n = 0;
     for (int i = 0; i < n; ++i) total_n += reqs[i].N;
     int* ovf_list = reinterpret_cast<int*>(take(4 * (size_t)total_n));
+    c->last_used = need;
     int tile_base = 0, pix_blocks = 0, seed_blocks = 0, src_blocks = 0, slot_blocks = 0, init_blocks = 0;
     int emit_blocks = 0;
     int kmax = 1;
@@ -703,6 +705,81 @@ int epic_interp_exact(epic_ctx* ctx, const float* cost, int H, int W, const floa
     // 4. one fit per pixel
     if (launch_exact_fit(A, st) != hipSuccess) return EPIC_ERR_HIP;
     ctx->last_npairs = 0;          // no per-call statistics
+    return EPIC_OK;
+}
+
+void epic_refine_defaults(epic_refine_params* p) {
+    if (!p) return;
+    p->lam = 0.1f;
+    p->delta = 0.1f;
+    p->gamma = 0.7f;
+    p->kappa = 5.0f;
+    p->eps = 1e-3f;
+    p->zeta = 0.1f;
+    p->omega = 1.6f;
+    p->fixed_point = 5;
+    p->sor = 30;
+}
+
+size_t epic_refine_bytes(int H, int W, int channels) {
+    if (H < 1 || W < 1 || channels < 1 || channels > 4) return 0;
+    const size_t HW = (size_t)H * W;
+    return align_up(4 * HW * channels) + kVarPlanes * align_up(4 * HW) + kAlign;
+}
+
+int epic_refine(epic_ctx* ctx, const float* I1, const float* I2, int H, int W, int channels,
+                const float* flow_in, float* flow_out, const epic_refine_params* params, void* stream) {
+    if (!ctx || !I1 || !I2 || !flow_in || !flow_out) return EPIC_ERR_ARG;
+    if (H < 1 || W < 1 || (long long)H * W >= (1LL << 31) || channels < 1 || channels > 4) return EPIC_ERR_ARG;
+    for (const void* q : {(const void*)I1, (const void*)I2, (const void*)flow_in, (const void*)flow_out})
+        if ((uintptr_t)q & 3) return EPIC_ERR_ARG;
+    const long long HW = (long long)H * W;
+    // the output may be the input itself, but not a shifted view of it
+    const char *fi = (const char*)flow_in, *fo = (const char*)flow_out;
+    if (fi != fo && fo < fi + 8 * HW && fi < fo + 8 * HW) return EPIC_ERR_ARG;
+    epic_refine_params p;
+    if (params) p = *params; else epic_refine_defaults(&p);
+    const float fs[] = {p.lam, p.delta, p.gamma, p.kappa, p.eps, p.zeta, p.omega};
+    for (float f : fs)
+        if (!std::isfinite(f) || f < 0.0f) return EPIC_ERR_ARG;
+    if (!(p.eps > 0.0f) || !(p.zeta > 0.0f) || !(p.omega > 0.0f) || !(p.omega < 2.0f)) return EPIC_ERR_ARG;
+    if (p.fixed_point < 0 || p.fixed_point > 100 || p.sor < 0 || p.sor > 10000) return EPIC_ERR_ARG;
+    // the refinement's planes sit at the end of the workspace, behind the
+    // descriptor ring; the last interpolation's statistics stay readable
+    // when its part of the workspace lies before them
+    const size_t need = epic_refine_bytes(H, W, channels);
+    if (kFixed + need > ctx->ws_bytes) return EPIC_ERR_WORKSPACE;
+    if (hipSetDevice(ctx->device) != hipSuccess) return EPIC_ERR_HIP;
+    const size_t start = (ctx->ws_bytes - need + kAlign - 1) & ~(kAlign - 1);
+    char* w = ctx->ws + start;
+    VarArgs A{};
+    A.I1 = I1;
+    A.I2 = I2;
+    A.u0 = flow_in;
+    A.flow = flow_out;
+    A.I2w = reinterpret_cast<float*>(w);
+    w += align_up(4 * (size_t)HW * channels);
+    float* planes[kVarPlanes];
+    for (int k = 0; k < kVarPlanes; ++k, w += align_up(4 * (size_t)HW)) planes[k] = reinterpret_cast<float*>(w);
+    A.coef = planes[0];            // 13 consecutive planes
+    A.sys = planes[13];            // 7
+    A.du = planes[20];
+    A.dv = planes[21];
+    A.H = H;
+    A.W = W;
+    A.C = channels;
+    A.HW = HW;
+    A.lam = p.lam;
+    A.delta = p.delta;
+    A.gamma = p.gamma;
+    A.kappa = p.kappa;
+    A.eps = p.eps;
+    A.zeta = p.zeta;
+    A.omega = p.omega;
+    A.fixed_point = p.fixed_point;
+    A.sor = p.sor;
+    if (start < ctx->last_used) ctx->last_npairs = 0;
+    if (launch_variational(A, (hipStream_t)stream) != hipSuccess) return EPIC_ERR_HIP;
     return EPIC_OK;
 }
 

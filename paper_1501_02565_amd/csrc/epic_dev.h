@@ -302,6 +302,25 @@ hipError_t launch_exact_select(const PairDev* chunk, int nsrc, int src0, int fir
                                hipStream_t s);
 hipError_t launch_exact_fit(const ExactArgs& A, hipStream_t s);
 hipError_t launch_image_cost(const ImageCostArgs& args, int channels, int total_blocks, hipStream_t s);
+
+// One-level variational refinement of a flow field (Sec. 4).
+struct VarArgs {
+    const float* I1;        // H*W*C, interleaved
+    const float* I2;        // H*W*C
+    const float* u0;        // H*W*2, the field to refine
+    float* flow;            // H*W*2 output (may equal u0)
+    float* I2w;             // H*W*C scratch: I2 warped by u0
+    float* coef;            // 13 planes of H*W: JC (6), JG (6), alpha
+    float* sys;             // 7 planes of H*W: A11 A12 A22 b1 b2, g right, g down
+    float* du;              // H*W
+    float* dv;              // H*W
+    int H, W, C;
+    long long HW;
+    float lam, delta, gamma, kappa, eps, zeta, omega;
+    int fixed_point, sor;
+};
+constexpr int kVarPlanes = 13 + 7 + 2;   // float planes of H*W besides I2w
+hipError_t launch_variational(const VarArgs& A, hipStream_t s);
 hipError_t launch_unpack(const PairDev* d_pairs, const RunDev& run, int total_blocks, float* D, int* L,
                          hipStream_t s);
 

@@ -46,6 +46,7 @@ class Scene:
     name: str = ""
     gt_flow: np.ndarray | None = None   # (H, W, 2) float32, generator's motion
     image: np.ndarray | None = None     # (H, W, 3) float32 in [0, 1] (on request)
+    image2: np.ndarray | None = None    # (H, W, 3) the second frame (on request)
 
     @property
     def H(self) -> int:
@@ -107,19 +108,63 @@ def _cost_from_layers(rng, layer, sigma=1.0, noise=0.05, floor=1e-3):
     return c.astype(np.float32)
 
 
-def _layer_image(layer, seed):
-    """An RGB image of the layer map (for the cost-from-gradient path): each
-    layer a random base colour in [0.15, 0.85]^3 with a smooth texture
-    (sigma-2 blurred normal noise, amplitude 0.08) and a little pixel noise,
-    clipped to [0, 1].  Its own generator, so drawing it leaves the rest of
-    the scene unchanged."""
+def _layer_texture(H, W, n, seed):
+    """The per-layer colours and the shared texture fields of the scene's
+    images: each layer a random base colour in [0.15, 0.85]^3, plus per
+    channel a smooth texture (sigma-2 blurred normal noise, amplitude 0.08).
+    Its own generator, so drawing it leaves the rest of the scene
+    unchanged; returns the generator for the pixel noise."""
     rng = np.random.default_rng(seed + 7919)
-    H, W = layer.shape
-    n = int(layer.max()) + 1
     base = rng.uniform(0.15, 0.85, (n, 3))
+    tex = [0.08 * ndimage.gaussian_filter(rng.standard_normal((H, W)), 2.0) for _ in range(3)]
+    return base, tex, rng
+
+
+def _layer_image(layer, seed):
+    """An RGB image of the layer map (for the cost-from-gradient path): the
+    layer's base colour plus the texture at the pixel and a little pixel
+    noise (U[0, 0.01]), clipped to [0, 1]."""
+    H, W = layer.shape
+    base, tex, rng = _layer_texture(H, W, int(layer.max()) + 1, seed)
     img = base[layer]
     for c in range(3):
-        img[:, :, c] += 0.08 * ndimage.gaussian_filter(rng.standard_normal((H, W)), 2.0)
+        img[:, :, c] += tex[c]
+    img += rng.uniform(0.0, 0.01, img.shape)
+    return np.clip(img, 0.0, 1.0).astype(np.float32)
+
+
+def _second_image(masks, params, seed, H, W):
+    """The second frame of a layered scene: every layer moved by its affine
+    motion, painted in the same order as the first frame (later layers on
+    top).  A pixel y of the second frame shows layer l when the point
+    p = c + (I + B)^-1 (y - c - t) that moves onto it lies inside the
+    layer's polygon (the background covers everything); it takes the layer's
+    colour plus the texture sampled at p (bilinear, the texture carried
+    along with the layer) and fresh pixel noise.  So I2(p + u(p)) matches
+    I1(p) wherever p stays visible."""
+    n = len(masks)
+    base, tex, rng = _layer_texture(H, W, n, seed)
+    rng.uniform(0.0, 0.01, (H, W, 3))          # the first frame's pixel noise
+    ys, xs = np.mgrid[0:H, 0:W].astype(np.float64)
+    top = np.zeros((H, W), np.int64)
+    src = np.zeros((2, H, W))
+    for li, (B, t, ctr) in enumerate(params):
+        M = np.linalg.inv(np.eye(2) + B)
+        rx, ry = xs - ctr[0] - t[0], ys - ctr[1] - t[1]
+        px = ctr[0] + M[0, 0] * rx + M[0, 1] * ry
+        py = ctr[1] + M[1, 0] * rx + M[1, 1] * ry
+        if li == 0:
+            cover = np.ones((H, W), bool)
+        else:
+            ix, iy = np.rint(px).astype(np.int64), np.rint(py).astype(np.int64)
+            inside = (ix >= 0) & (ix < W) & (iy >= 0) & (iy < H)
+            cover = np.zeros((H, W), bool)
+            cover[inside] = masks[li][iy[inside], ix[inside]]
+        top[cover] = li
+        src[0][cover], src[1][cover] = py[cover], px[cover]
+    img = base[top]
+    for c in range(3):
+        img[:, :, c] += ndimage.map_coordinates(tex[c], src, order=1, mode="nearest")
     img += rng.uniform(0.0, 0.01, img.shape)
     return np.clip(img, 0.0, 1.0).astype(np.float32)
 
@@ -178,7 +223,7 @@ def _finish_matches(rng, gx, gy, flow, n_target, drop_frac, outlier_frac,
 def layered_scene(H, W, n_layers, t_range, n_matches, stride, *, seed,
                   occl_frac=0.0, drop_frac=0.0, outlier_frac=0.0,
                   outlier_r=20.0, offset=None, K=100, a=1.0, mode=1,
-                  name="layered", with_image=False):
+                  name="layered", with_image=False, with_pair=False):
     """Background plus random star-shaped polygon layers, painted in order.
 
     Each layer moves by its own affine field u(p) = B (p - centre) + t with
@@ -188,9 +233,11 @@ def layered_scene(H, W, n_layers, t_range, n_matches, stride, *, seed,
     layer = np.zeros((H, W), np.int32)
     params = [(rng.uniform(-0.05, 0.05, (2, 2)),
                rng.uniform(-t_range, t_range, 2), ((W - 1) / 2, (H - 1) / 2))]
+    masks = [None]
     for li in range(1, n_layers):
         poly, ctr = _star_polygon(rng, H, W)
-        layer[_fill_polygon(poly, H, W)] = li
+        masks.append(_fill_polygon(poly, H, W))
+        layer[masks[-1]] = li
         params.append((rng.uniform(-0.05, 0.05, (2, 2)),
                        rng.uniform(-t_range, t_range, 2), ctr))
     cost = _cost_from_layers(rng, layer)
@@ -204,8 +251,9 @@ def layered_scene(H, W, n_layers, t_range, n_matches, stride, *, seed,
         gx, gy = gx[keep], gy[keep]
     m = _finish_matches(rng, gx, gy, flow, n_matches, drop_frac, outlier_frac,
                         outlier_r, H, W)
-    img = _layer_image(layer, seed) if with_image else None
-    return Scene(cost, m, K, a, mode, name, flow.astype(np.float32), img)
+    img = _layer_image(layer, seed) if (with_image or with_pair) else None
+    img2 = _second_image(masks, params, seed, H, W) if with_pair else None
+    return Scene(cost, m, K, a, mode, name, flow.astype(np.float32), img, img2)
 
 
 def road_scene(H=375, W=1242, n_matches=10000, *, seed, horizon=150, K=100,
@@ -254,7 +302,8 @@ CONFIG_PARAMS = {
 }
 
 
-def config_scene(i: int, mode: int | None = None, with_image: bool = False) -> Scene:
+def config_scene(i: int, mode: int | None = None, with_image: bool = False,
+                 with_pair: bool = False) -> Scene:
     """The single-pair workloads: 1 = 128x96 small scene, 2 = 1024x436
     large-displacement scene, 3 = 1242x375 road scene (NW or LA)."""
     if i == 3:
@@ -265,7 +314,7 @@ def config_scene(i: int, mode: int | None = None, with_image: bool = False) -> S
         p["mode"] = mode
     H, W = p.pop("H"), p.pop("W")
     name = {1: "layered_128x96_n300_k32", 2: "layered_1024x436_n8000_k100"}[i]
-    return layered_scene(H, W, name=name, with_image=with_image, **p)
+    return layered_scene(H, W, name=name, with_image=with_image, with_pair=with_pair, **p)
 
 
 def random_case(H, W, N, *, seed, K=8, a=1.0, mode=1, subpixel=True,

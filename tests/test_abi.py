@@ -107,7 +107,8 @@ def _struct_fields(name):
 def test_binding_structs_follow_the_header():
     from paper_1501_02565_amd import _lib
     for cname, cls in (("epic_options", _lib.Options), ("epic_stats", _lib.Stats),
-                       ("epic_request", _lib.Request)):
+                       ("epic_request", _lib.Request), ("epic_image", _lib.Image),
+                       ("epic_refine_params", _lib.RefineParams)):
         assert _struct_fields(cname) == [f for f, _ in cls._fields_], cname
 
 
@@ -157,3 +158,23 @@ def test_image_cost_rejects_bad_arguments(lib):
         assert lib.epic_image_cost(a, 1, 1e-3, None) == -1, fields
     assert lib.epic_image_cost(arr, 0, 1e-3, None) == -1
     assert lib.epic_interp_image(None, P, 10, 20, 3, 1e-3, P, 5, 3, 1.0, 1, P, None) == -1
+
+
+def test_refine_defaults_and_bytes(lib):
+    """The library's refinement defaults are the paper's (kappa 5, 5 outer
+    iterations of 30 sweeps) and the oracle's; the scratch size is 88 + 4 C
+    bytes per pixel plus alignment; a null context is refused."""
+    import dataclasses
+    from paper_1501_02565_amd import _lib
+    from oracle import variational as va
+    p = _lib.RefineParams()
+    lib.epic_refine_defaults(ctypes.byref(p))
+    for f in dataclasses.fields(va.Params):
+        assert getattr(p, f.name) == pytest.approx(getattr(va.Params(), f.name), rel=1e-7), f.name
+    assert (p.kappa, p.fixed_point, p.sor) == (5.0, 5, 30)
+    for H, W, C in ((436, 1024, 3), (1, 1, 1), (97, 131, 4)):
+        b = lib.epic_refine_bytes(H, W, C)
+        assert 0 <= b - (88 + 4 * C) * H * W <= 23 * 256 + 256
+    assert lib.epic_refine_bytes(0, 5, 3) == 0 and lib.epic_refine_bytes(5, 5, 5) == 0
+    P = 0x1000
+    assert lib.epic_refine(None, P, P, 10, 20, 3, P, P, None, None) == -1

@@ -155,3 +155,21 @@ def test_iterate_is_a_stationary_point_of_the_energy():
     g0 = max(abs(grad_at(z, z, y, x, c)) for y, x, c in pts)
     g1 = max(abs(grad_at(du, dv, y, x, c)) for y, x, c in pts)
     assert g0 > 1e-3 and g1 <= 1e-4 * g0, (g0, g1)
+
+
+def test_empty_equations_keep_the_initial_flow():
+    """An equation with a zero diagonal says nothing about its unknown: a
+    1 x 1 image (no gradient, no neighbour) and a flat image with lam = 0
+    return the initial field unchanged, without NaN."""
+    rng = np.random.default_rng(11)
+    I1 = rng.uniform(0, 1, (1, 1, 3))
+    u0 = np.array([[[1.5, -2.0]]])
+    out = va.refine(I1, I1 + 0.1, u0)
+    assert np.array_equal(out, u0.astype(np.float32).astype(np.float64))
+    flat = np.full((6, 9), 0.4)
+    u0 = rng.normal(0, 1, (6, 9, 2))
+    out = va.refine(flat, flat + 0.2, u0, va.Params(lam=0.0))
+    assert np.array_equal(out, u0.astype(np.float32).astype(np.float64))
+    # with lam > 0 the flat image's field is smoothed, and stays finite
+    out = va.refine(flat, flat + 0.2, u0)
+    assert np.isfinite(out).all() and np.std(out[..., 0]) < np.std(u0[..., 0])
