@@ -317,7 +317,7 @@ int epic_interp_exact(epic_ctx* ctx, const float* cost, int H, int W, const floa
  *              overlap it otherwise
  *   params     host; NULL takes epic_refine_defaults
  * Scratch: epic_refine_bytes(H, W, channels) bytes at the end of the
- * context's workspace (88 + 4*channels bytes per pixel plus alignment),
+ * context's workspace (104 + 4*channels bytes per pixel plus alignment),
  * after the workspace's fixed 4096 + descriptor-ring head; EPIC_ERR_WORKSPACE
  * when it does not fit.  The statistics of the last interpolation remain
  * readable when the workspace also holds that call's part.  Host-side

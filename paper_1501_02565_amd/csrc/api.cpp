@@ -762,9 +762,11 @@ int epic_refine(epic_ctx* ctx, const float* I1, const float* I2, int H, int W, i
     float* planes[kVarPlanes];
     for (int k = 0; k < kVarPlanes; ++k, w += align_up(4 * (size_t)HW)) planes[k] = reinterpret_cast<float*>(w);
     A.coef = planes[0];            // 13 consecutive planes
-    A.sys = planes[13];            // 7
-    A.du = planes[20];
-    A.dv = planes[21];
+    A.sys = planes[13];            // 9
+    A.du[0] = planes[22];
+    A.du[1] = planes[23];
+    A.dv[0] = planes[24];
+    A.dv[1] = planes[25];
     A.H = H;
     A.W = W;
     A.C = channels;

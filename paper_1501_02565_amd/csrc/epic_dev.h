@@ -311,15 +311,15 @@ struct VarArgs {
     float* flow;            // H*W*2 output (may equal u0)
     float* I2w;             // H*W*C scratch: I2 warped by u0
     float* coef;            // 13 planes of H*W: JC (6), JG (6), alpha
-    float* sys;             // 7 planes of H*W: A11 A12 A22 b1 b2, g right, g down
-    float* du;              // H*W
-    float* dv;              // H*W
+    float* sys;             // 9 planes of H*W: a fixed-point step's per-pixel update
+    float* du[2];           // H*W each, a ping-pong pair
+    float* dv[2];
     int H, W, C;
     long long HW;
     float lam, delta, gamma, kappa, eps, zeta, omega;
     int fixed_point, sor;
 };
-constexpr int kVarPlanes = 13 + 7 + 2;   // float planes of H*W besides I2w
+constexpr int kVarPlanes = 13 + 9 + 4;   // float planes of H*W besides I2w
 hipError_t launch_variational(const VarArgs& A, hipStream_t s);
 hipError_t launch_unpack(const PairDev* d_pairs, const RunDev& run, int total_blocks, float* D, int* L,
                          hipStream_t s);
