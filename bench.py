@@ -275,9 +275,10 @@ def refine_leg(np, torch, epic, reps=10):
     after the interpolation (both on one stream, HIP events), the average
     endpoint error against the scene's generating motion before and after,
     and its difference from the oracle (both refining the oracle's own
-    interpolation).  Roofline of the relaxation sweep kernel, which carries
-    the bytes: per pixel and sweep 8 B du/dv, 8 B u0, 28 B of the system
-    read and 8 B written (52 B; neighbours come from the caches)."""
+    interpolation).  The sweeps run blocked in time, 12 half-sweeps per
+    launch of the sweep kernel; its algorithmic bytes per launch are, per
+    pixel, 36 B of the fixed-point step's system and 8 B of (du, dv) read
+    and 8 B written (52 B)."""
     from oracle import epic_ref
     from oracle import variational as va
     from scenes import config_scene
@@ -315,13 +316,11 @@ def refine_leg(np, torch, epic, reps=10):
         r = va.refine(sc.image, sc.image2, u0)
         d = np.linalg.norm(g - r, axis=2)
         gt = sc.gt_flow.astype(np.float64)
-        sweeps = p.fixed_point * p.sor
-        nbytes = 52.0 * HW * sweeps
+        sweep_launches = p.fixed_point * -(-2 * p.sor // 12)
         res = {"workload": sc.name + "_pair", "ms": round(ms, 4), "interp_plus_refine_ms": round(ms_both, 4),
                "mpix_s": round(HW / ms / 1e3, 2), "fixed_point": p.fixed_point, "sor": p.sor,
-               "launches": 4 + p.fixed_point * (1 + 2 * p.sor),
-               "sweep_algorithmic_bytes": nbytes,
-               "sweep_bytes_per_ms_of_call_gbs": round(nbytes / (ms * 1e-3) / 1e9, 1),
+               "launches": 4 + p.fixed_point + sweep_launches, "sweep_launches": sweep_launches,
+               "sweep_algorithmic_bytes_per_launch": 52.0 * HW,
                "aee_vs_generating_motion": {"interpolated": float(np.linalg.norm(f0 - gt, axis=2).mean()),
                                             "refined": float(np.linalg.norm(f1 - gt, axis=2).mean())},
                "vs_oracle": {"mean_epe_px": float(d.mean()), "max_epe_px": float(d.max())}}
@@ -535,6 +534,8 @@ def main():
     ap.add_argument("--served-budget", type=int, default=8 << 30)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (HBM counter calibration)")
+    ap.add_argument("--only-headline", action="store_true",
+                    help="only the single-pair measurement and the device copy (profiling runs)")
     ap.add_argument("--only-batched", action="store_true",
                     help="skip the single-pair measurement (profiling the batched form)")
     args = ap.parse_args()
@@ -629,32 +630,36 @@ def main():
     log(f"bench: error vs oracle {err}")
     ctx.close()
 
-    # latency of the other single-pair workloads (NW and LA on the road scene)
-    lat = []
-    with epic.Context(0, epic.workspace_bytes(436, 1242, 10000, 100)) as c2:
-        for i, mode in ((1, 1), (3, 1), (3, 0)):
-            s_i = config_scene(i, mode=mode)
-            lat.append(latency(c2, s_i, torch, mode))
-    log(f"bench: latency {lat}")
-    # the consistency check of the matches (Sec. 5.1) before the same call
-    pruned = pruned_leg(args, np, torch, epic, sc)
-    copy = copy_bandwidth(torch)
-    roofline["copy_kernel_gbs"] = copy["gbs"]
-    imcost = image_cost_leg(np, torch, epic)
-    exact = None if args.no_exact else exact_leg(np, torch, epic)
-    refine = None if args.no_refine else refine_leg(np, torch, epic)
-    imcost["frac_of_copy"] = round(imcost["achieved_gbs"] / copy["gbs"], 4)
-    log(f"bench: device copy {copy}")
-    if args.calibrate_copy:
-        log("bench: calibration copy of 256 MiB done")
-    batched = None if args.no_batched else batched_form(args, np, torch, epic)
-    served = None if args.no_served else served_pair(args, np, torch, epic)
-
-    cpu = None
-    if not args.no_cpu_baseline:
-        log("bench: timing the oracle on the host")
-        cpu = cpu_baseline(sc, args.cpu_seconds)
-        log(f"bench: oracle {cpu}")
+    lat = pruned = imcost = exact = refine = batched = served = cpu = None
+    if args.only_headline:
+        copy = copy_bandwidth(torch)
+        roofline["copy_kernel_gbs"] = copy["gbs"]
+        log(f"bench: device copy {copy}")
+    else:
+        # latency of the other single-pair workloads (NW and LA on the road scene)
+        lat = []
+        with epic.Context(0, epic.workspace_bytes(436, 1242, 10000, 100)) as c2:
+            for i, mode in ((1, 1), (3, 1), (3, 0)):
+                s_i = config_scene(i, mode=mode)
+                lat.append(latency(c2, s_i, torch, mode))
+        log(f"bench: latency {lat}")
+        # the consistency check of the matches (Sec. 5.1) before the same call
+        pruned = pruned_leg(args, np, torch, epic, sc)
+        copy = copy_bandwidth(torch)
+        roofline["copy_kernel_gbs"] = copy["gbs"]
+        imcost = image_cost_leg(np, torch, epic)
+        exact = None if args.no_exact else exact_leg(np, torch, epic)
+        refine = None if args.no_refine else refine_leg(np, torch, epic)
+        imcost["frac_of_copy"] = round(imcost["achieved_gbs"] / copy["gbs"], 4)
+        log(f"bench: device copy {copy}")
+        if args.calibrate_copy:
+            log("bench: calibration copy of 256 MiB done")
+        batched = None if args.no_batched else batched_form(args, np, torch, epic)
+        served = None if args.no_served else served_pair(args, np, torch, epic)
+        if not args.no_cpu_baseline:
+            log("bench: timing the oracle on the host")
+            cpu = cpu_baseline(sc, args.cpu_seconds)
+            log(f"bench: oracle {cpu}")
 
     out = {
         "metric": "interpolated Mpix/s (1024x436, 8k matches, K=100); served p50/p99 latency",
