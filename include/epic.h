@@ -68,8 +68,10 @@ typedef enum {
                                   the largest K-NN table holds (2048 entries for
                                   K <= 256; that match's model is then zero)      */
     EPIC_ERR_CONVERGENCE = -7, /* the geodesic transform hit its iteration bound     */
-    EPIC_ERR_COST = -8         /* debug_validate found a cost value that is not
+    EPIC_ERR_COST = -8,        /* debug_validate found a cost value that is not
                                   finite and > 0 (the flow is filled with NaN)     */
+    EPIC_ERR_INVARIANT = -9    /* debug_validate found a violated invariant of the
+                                  transform or the match graph (n_invariant)       */
 } epic_status;
 
 /* Options; NULL selects the defaults shown. */
@@ -113,7 +115,22 @@ typedef struct epic_options {
                                map fails is not interpolated: it reports
                                EPIC_ERR_COST and n_bad_cost in epic_stats and
                                its flow is filled with NaN; the other pairs of
-                               a batch are unaffected                          */
+                               a batch are unaffected.  It also checks the
+                               intermediate state on the device: after the
+                               transform, that every pixel has a defined label,
+                               that seeds hold D = 0 and their own (lowest)
+                               index, and that no neighbour offers a pixel a
+                               better (D, label) than it holds in the
+                               transform's arithmetic (the fixpoint of Eq. (3)
+                               on the pixel graph); after the graph build, that
+                               the adjacency is symmetric with equal weights
+                               and consistent row pointers.  Violations are
+                               counted in n_invariant and reported as
+                               EPIC_ERR_INVARIANT; results are unchanged.
+                               2: as 1, after first raising pixel 0's distance
+                               of every pair by one (a planted violation that
+                               tests the checks; results are then not
+                               meaningful)                                     */
     float prune_px;         /* consistency check of the matches (Sec. 5.1,
                                "Pruning of matches"): 0 (default) = off; > 0:
                                every call first interpolates with NW (same K
@@ -205,6 +222,7 @@ typedef struct epic_stats {
                               (prune_px > 0); the other counts then refer to
                               the kept matches, except n_outside and
                               n_duplicate, which count the original ones    */
+    int n_invariant;       /* violated device invariants (debug_validate)  */
 } epic_stats;
 int epic_get_stats(epic_ctx* ctx, int pair, epic_stats* out);
 

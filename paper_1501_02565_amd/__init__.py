@@ -15,7 +15,7 @@ import ctypes
 
 from . import _lib
 from ._lib import (LA, NW, OK, EpicError, ERR_ARG, ERR_BUDGET, ERR_CAPACITY,  # noqa: F401
-                   ERR_CONVERGENCE, ERR_COST, ERR_HIP, ERR_NO_MATCHES, ERR_WORKSPACE)
+                   ERR_CONVERGENCE, ERR_COST, ERR_HIP, ERR_INVARIANT, ERR_NO_MATCHES, ERR_WORKSPACE)
 
 __all__ = ["Context", "workspace_bytes", "image_cost", "ImageCostPlan", "LA", "NW", "EpicError"]
 
@@ -114,7 +114,10 @@ class Context:
     (0 = default; 128 or 256 with 32 x 16 tiles); like ``passes`` it only
     changes the speed.
     ``debug_validate`` makes every call check the cost map on the device
-    (finite and > 0); a pair that fails reports ERR_COST in its stats.
+    (finite and > 0; a pair that fails reports ERR_COST in its stats) and
+    the invariants of its transform and match graph (violations:
+    n_invariant, ERR_INVARIANT); 2 plants a violation first (a self-test of
+    the checks).
     ``prune_px`` > 0 runs the consistency check of the matches (Sec. 5.1)
     before every interpolation: matches further than prune_px from a first
     NW estimate at their pixel are removed (the paper uses 5)."""
@@ -123,7 +126,7 @@ class Context:
                  connectivity: int = 8, la_weight_power: int = 2,
                  precision: int = 0, fp64_route: float = 1e-3,
                  degenerate_tau: float = 1e-9, tile: tuple[int, int] = (32, 16),
-                 passes: int = 0, geo_threads: int = 0, debug_validate: bool = False,
+                 passes: int = 0, geo_threads: int = 0, debug_validate: int = 0,
                  prune_px: float = 0.0):
         torch = _torch()
         L = _lib.load()
@@ -133,7 +136,7 @@ class Context:
         self.workspace = int(workspace)
         self.options = _lib.Options(connectivity, la_weight_power, precision,
                                     fp64_route, degenerate_tau, tile[0], tile[1],
-                                    passes, int(geo_threads), int(bool(debug_validate)),
+                                    passes, int(geo_threads), int(debug_validate),
                                     float(prune_px))
         torch.cuda.init()
         with torch.cuda.device(self.device):

@@ -13,7 +13,7 @@ LIB_PATH = os.path.join(HERE, "libepic.so")
 
 # epic_status
 OK, ERR_ARG, ERR_WORKSPACE, ERR_NO_MATCHES, ERR_HIP, ERR_BUDGET, ERR_CAPACITY, \
-    ERR_CONVERGENCE, ERR_COST = 0, -1, -2, -3, -4, -5, -6, -7, -8
+    ERR_CONVERGENCE, ERR_COST, ERR_INVARIANT = 0, -1, -2, -3, -4, -5, -6, -7, -8, -9
 NW, LA = 0, 1
 
 SYMBOLS = ["epic_create", "epic_destroy", "epic_workspace_bytes", "epic_interp",
@@ -67,7 +67,8 @@ class Stats(ctypes.Structure):
                 ("n_outside", ctypes.c_int), ("n_duplicate", ctypes.c_int),
                 ("n_edges", ctypes.c_int), ("n_degenerate", ctypes.c_int),
                 ("n_fp64_fits", ctypes.c_int), ("tile_visits", ctypes.c_int),
-                ("n_bad_cost", ctypes.c_int), ("n_pruned", ctypes.c_int)]
+                ("n_bad_cost", ctypes.c_int), ("n_pruned", ctypes.c_int),
+                ("n_invariant", ctypes.c_int)]
 
 
 _lib = None

@@ -10,7 +10,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libepic.so")
 SOURCES = ["k_prep.hip", "k_geodesic.hip", "k_geodesic64.hip", "k_graph.hip",
-           "k_knn_fit.hip", "k_assign.hip", "k_prune.hip", "k_image_cost.hip", "k_exact.hip", "k_variational.hip",
+           "k_knn_fit.hip", "k_assign.hip", "k_prune.hip", "k_image_cost.hip", "k_exact.hip", "k_variational.hip", "k_invariants.hip",
            "api.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

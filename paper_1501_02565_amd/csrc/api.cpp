@@ -139,6 +139,7 @@ const char* epic_strerror(int s) {
         case EPIC_ERR_CAPACITY: return "fixed-capacity device structure overflowed";
         case EPIC_ERR_CONVERGENCE: return "geodesic transform did not converge within its bound";
         case EPIC_ERR_COST: return "cost map holds a value that is not finite and > 0";
+        case EPIC_ERR_INVARIANT: return "a debug_validate check of the transform or the graph failed";
         default: return "unknown status";
     }
 }
@@ -199,7 +200,7 @@ epic_ctx* epic_create(int device, size_t workspace_bytes, const epic_options* op
         o.tile_h = t.th;
         if (o.geo_passes < 0) o.geo_passes = 0;
         if (o.geo_passes > kMaxPasses - 1) o.geo_passes = kMaxPasses - 1;
-        if (o.debug_validate != 1) o.debug_validate = 0;
+        if (o.debug_validate != 1 && o.debug_validate != 2) o.debug_validate = 0;
         if (!(o.tile_h == 16 && (o.geo_threads == 128 || o.geo_threads == 256))) o.geo_threads = 0;
         if (!(o.prune_px > 0.0f)) o.prune_px = 0.0f;     // off (also for NaN)
     }
@@ -515,11 +516,14 @@ int run_pairs(epic_ctx* c, const epic_request* reqs, int n, hipStream_t stream, 
                     : launch_geodesic(dd, run, tl.tw, tl.th, c->opt.geo_threads, pb0, stream);
         if (last) mark(2);
         if (dbg && dbg->stop_after == 2) break;
+        if (e == hipSuccess && c->opt.debug_validate)
+            e = launch_check_transform(dd, run, pix_blocks, c->opt.debug_validate == 2, stream);
         if (e == hipSuccess) e = launch_graph_emit(dd, run, emit_blocks, stream);
         if (last) mark(3);
         if (e == hipSuccess) e = launch_csr_scan(dd, run, stream);
         if (last) mark(4);
         if (e == hipSuccess) e = launch_csr_scatter(dd, run, slot_blocks, stream);
+        if (e == hipSuccess && c->opt.debug_validate) e = launch_check_graph(dd, run, slot_blocks, stream);
         if (last) mark(5);
         if (e == hipSuccess) e = launch_knn_fit(dd, run, src_blocks, kmax, stream);
         if (last) mark(6);
@@ -895,6 +899,7 @@ int epic_get_stats(epic_ctx* ctx, int pair, epic_stats* out) {
     // transform finisher's pass bound
     if ((cnt[C_OVERFLOW] & 2) && out->status == 0) out->status = EPIC_ERR_CAPACITY;
     if ((gerr & 1) && out->status == 0) out->status = EPIC_ERR_CONVERGENCE;
+    if (cnt[C_INVARIANT] && out->status == 0) out->status = EPIC_ERR_INVARIANT;
     out->n_used = cnt[C_USED];
     // with the consistency check, drops are those of the original matches
     out->n_outside = ctx->last_pruned ? cnt[C_OUTSIDE0] : cnt[C_OUTSIDE];
@@ -905,6 +910,7 @@ int epic_get_stats(epic_ctx* ctx, int pair, epic_stats* out) {
     out->n_fp64_fits = cnt[C_FP64];
     out->tile_visits = cnt[C_TILE_VISITS];
     out->n_bad_cost = cnt[C_BADCOST];
+    out->n_invariant = cnt[C_INVARIANT];
     return EPIC_OK;
 }
 

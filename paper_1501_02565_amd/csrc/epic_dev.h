@@ -51,7 +51,8 @@ enum Counter {
     C_OUTSIDE0 = 13,   // the first pass's outside / duplicate counts and status
     C_DUP0 = 14,
     C_STATUS0 = 15,
-    C_NCOUNTERS = 16
+    C_INVARIANT = 16,  // debug_validate: violated invariants of the transform and graph
+    C_NCOUNTERS = 17
 };
 
 // Everything a kernel needs about one image pair.  Kernels of a batch launch
@@ -176,12 +177,31 @@ __device__ __forceinline__ void dev_st(T* p, T v) {
 }
 
 // One step of the discretised geodesic of Eq. (3) in FP32, and a relaxation
-// across it, each operation rounded on its own (no fused multiply-add), so
-// that every place that prices a step gets the same bits.
+// across it, each operation rounded on its own, so that every place that
+// prices a step gets the same bits.  HIP's __fmul_rn / __fadd_rn are plain
+// operators that the compiler may fuse into a multiply-add once inlined
+// (relax_f32(d, step_f32(...)) in one expression would become an FMA in one
+// kernel and a multiply and an add in another); the pragma keeps these
+// operations unfused wherever they are inlined.
 __device__ __forceinline__ float step_f32(float len, float cp, float cq) {
-    return __fmul_rn(len, __fmul_rn(0.5f, __fadd_rn(cp, cq)));
+#pragma clang fp contract(off)
+    return len * (0.5f * (cp + cq));
 }
-__device__ __forceinline__ float relax_f32(float d, float w) { return __fadd_rn(d, w); }
+__device__ __forceinline__ float relax_f32(float d, float w) {
+#pragma clang fp contract(off)
+    return d + w;
+}
+// The same step in FP64 (the FP64-everywhere transform): neighbour k < 4 is
+// axial, k >= 4 diagonal; relax_f64 adds it.
+__device__ __forceinline__ double step_f64(float cp, float cq, int k) {
+#pragma clang fp contract(off)
+    const double half = 0.5 * ((double)cp + (double)cq);
+    return k < 4 ? half : 1.4142135623730951 * half;
+}
+__device__ __forceinline__ double relax_f64(double d, double w) {
+#pragma clang fp contract(off)
+    return d + w;
+}
 
 // Nearest-match label of pixel i (packed in the key, or in the label array
 // of the FP64 path).
@@ -302,6 +322,9 @@ hipError_t launch_exact_select(const PairDev* chunk, int nsrc, int src0, int fir
                                hipStream_t s);
 hipError_t launch_exact_fit(const ExactArgs& A, hipStream_t s);
 hipError_t launch_image_cost(const ImageCostArgs& args, int channels, int total_blocks, hipStream_t s);
+hipError_t launch_check_transform(const PairDev* d_pairs, const RunDev& run, int pix_blocks, int plant,
+                                  hipStream_t s);
+hipError_t launch_check_graph(const PairDev* d_pairs, const RunDev& run, int slot_blocks, hipStream_t s);
 
 // One-level variational refinement of a flow field (Sec. 4).
 struct VarArgs {

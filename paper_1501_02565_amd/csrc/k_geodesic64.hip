@@ -43,10 +43,6 @@ struct Lds64 {
     int border;
 };
 
-__device__ __forceinline__ double step64(float cp, float cq, int k) {
-    const double half = __dmul_rn(0.5, __dadd_rn((double)cp, (double)cq));
-    return k < 4 ? half : __dmul_rn(1.4142135623730951, half);
-}
 
 // PHASE 0: distances; PHASE 1: labels.  The region relaxed is the tile
 // widened by MX columns and MY rows on each side (0 in the normal passes;
@@ -118,8 +114,8 @@ __device__ __forceinline__ int visit64(const PairDev& P, int tx, int ty, Lds64<T
         const int ch = (hy + 1) * LW + hx + j + 1, cv = (vy + j + 1) * LW + vx + 1;
 #pragma unroll
         for (int k = 0; k < CONN; ++k) {
-            wh[j][k] = step64(S.cost[ch], S.cost[ch + DY[k] * LW + DX[k]], k);
-            wv[j][k] = step64(S.cost[cv], S.cost[cv + DY[k] * LW + DX[k]], k);
+            wh[j][k] = step_f64(S.cost[ch], S.cost[ch + DY[k] * LW + DX[k]], k);
+            wv[j][k] = step_f64(S.cost[cv], S.cost[cv + DY[k] * LW + DX[k]], k);
         }
         orig[j] = PHASE == 0 ? lds_ld(&S.dist[ch]) : (u64)lds_ld(&S.lab[ch]);
     }
@@ -144,7 +140,7 @@ __device__ __forceinline__ int visit64(const PairDev& P, int tx, int ty, Lds64<T
                     double best = now;
 #pragma unroll
                     for (int k = 0; k < CONN; ++k) {
-                        const double cand = __dadd_rn(dbits(lds_ld(&S.dist[ci + DY[k] * LW + DX[k]])),
+                        const double cand = relax_f64(dbits(lds_ld(&S.dist[ci + DY[k] * LW + DX[k]])),
                                                       ROWS ? wh[j][k] : wv[j][k]);
                         best = cand < best ? cand : best;
                     }
@@ -161,7 +157,7 @@ __device__ __forceinline__ int visit64(const PairDev& P, int tx, int ty, Lds64<T
 #pragma unroll
                     for (int k = 0; k < CONN; ++k) {
                         const int q = ci + DY[k] * LW + DX[k];
-                        const bool tight = __dadd_rn(dbits(S.dist[q]), ROWS ? wh[j][k] : wv[j][k]) == dp;
+                        const bool tight = relax_f64(dbits(S.dist[q]), ROWS ? wh[j][k] : wv[j][k]) == dp;
                         const u32 lq = lds_ld(&S.lab[q]);
                         best = (tight && lq < best) ? lq : best;
                     }
@@ -235,8 +231,8 @@ __device__ __forceinline__ int visit64(const PairDev& P, int tx, int ty, Lds64<T
                     const bool out = qx < 0 || qy < 0 || qx >= twe || qy >= the;
                     if (!out) continue;
                     const int qi = ci + DY[kk] * LW + DX[kk];
-                    const double w = step64(S.cost[ci], S.cost[qi], kk);
-                    if (__dadd_rn(dbits(v), w) < dbits(S.dist[qi])) {
+                    const double w = step_f64(S.cost[ci], S.cost[qi], kk);
+                    if (relax_f64(dbits(v), w) < dbits(S.dist[qi])) {
                         const bool ql = qx < 0, qr = qx >= twe, qt = qy < 0, qb = qy >= the;
                         bm |= (ql && !qt && !qb) ? B_L : (qr && !qt && !qb) ? B_R
                             : (qt && !ql && !qr) ? B_T : (qb && !ql && !qr) ? B_B

@@ -141,16 +141,15 @@ __global__ __launch_bounds__(EMIT_NT) void k_graph_emit(const PairDev* __restric
                 const u32 lq = F64 ? lqa[k] : key_label(kq);
                 if (lq == lp || lq == NO_LABEL) continue;
                 V wb;
+                // (D(p) + step) + D(q), each operation rounded on its own (the
+                // helpers are never fused into multiply-adds)
                 if (F64) {
-                    // (D(p) + step) + D(q), each operation rounded (no fused multiply-add)
-                    const double half = __dmul_rn(0.5, __dadd_rn((double)cp, (double)cqa[k]));
-                    const double step = k < 2 ? half : __dmul_rn(1.4142135623730951, half);
-                    wb = (V)bitsd(__dadd_rn(__dadd_rn(dbits(kp), step), dbits(kq)));
+                    const double step = step_f64(cp, cqa[k], k < 2 ? 0 : 4);
+                    wb = (V)bitsd(relax_f64(relax_f64(dbits(kp), step), dbits(kq)));
                 } else {
-                    // (D(p) + step) + D(q), each operation rounded on its own
                     const float len = (k < 2) ? 1.0f : 1.41421356237309515f;
                     const float w = step_f32(len, cp, cqa[k]);
-                    wb = (V)__float_as_uint(__fadd_rn(relax_f32(key_dist(kp), w), key_dist(kq)));
+                    wb = (V)__float_as_uint(relax_f32(relax_f32(key_dist(kp), w), key_dist(kq)));
                 }
                 const u32 m = min(lp, lq), n = max(lp, lq);
                 const u64 hk = ((u64)m << 32) | n;

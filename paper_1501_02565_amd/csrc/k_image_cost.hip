@@ -35,6 +35,8 @@ __device__ __forceinline__ void load_px(const float* img, long long i, float (&v
 
 template <int CH>
 __global__ __launch_bounds__(kTileW * kTileH) void k_image_cost(ImageCostArgs args) {
+    // one rounding per operation (no fused multiply-adds)
+#pragma clang fp contract(off)
     // the image whose tiles this block belongs to: a binary search over the
     // ascending block bases (a block's whole work is a few loads, so a
     // linear walk over up to 32 images would take as long as the loads)
@@ -56,11 +58,11 @@ __global__ __launch_bounds__(kTileW * kTileH) void k_image_cost(ImageCostArgs ar
     float s = 0.0f;
 #pragma unroll
     for (int c = 0; c < CH; ++c) {
-        const float gx = __fmul_rn(0.5f, __fsub_rn(r[c], l[c]));
-        const float gy = __fmul_rn(0.5f, __fsub_rn(d[c], u[c]));
-        s = __fadd_rn(s, __fadd_rn(__fmul_rn(gx, gx), __fmul_rn(gy, gy)));
+        const float gx = 0.5f * (r[c] - l[c]);
+        const float gy = 0.5f * (d[c] - u[c]);
+        s = s + (gx * gx + gy * gy);
     }
-    gmem(D.cost)[(long long)y * W + x] = __fadd_rn(__fsqrt_rn(s), args.eps);
+    gmem(D.cost)[(long long)y * W + x] = __fsqrt_rn(s) + args.eps;
 }
 
 int image_cost_blocks(int H, int W) {

@@ -112,3 +112,54 @@ def test_knn_table_overflow_is_reported():
     print(st, flush=True)
     assert st["status"] == epic.ERR_CAPACITY
     assert np.isfinite(flow.cpu().numpy()).all()
+
+
+@pytest.mark.parametrize("precision,conn", [(0, 8), (0, 4), (1, 8)])
+def test_invariants_hold_and_change_nothing(precision, conn):
+    """With debug_validate the device checks the transform's fixpoint, the
+    seeds, the labels and the graph's symmetry: none is violated on scenes
+    with sub-pixel, outside and shared matches, a batch and the consistency
+    check, and the flow is bitwise that of a context without the checks."""
+    import torch
+    import paper_1501_02565_amd as epic
+    from scenes import config_scene
+    cases = [random_case(70, 90, 140, seed=9, K=20, outside=4, duplicates=5),
+             random_case(33, 257, 300, seed=12, K=8), config_scene(1)]
+    kw = dict(precision=precision, connectivity=conn)
+    with epic.Context(0, **kw) as plain, epic.Context(0, debug_validate=1, **kw) as chk:
+        for sc in cases:
+            _announce(f"{sc.name} precision={precision} conn={conn}")
+            cost, matches = _dev(sc)
+            ref = plain.interp(cost, matches, sc.K, sc.a, sc.mode).cpu().numpy()
+            out = chk.interp(cost, matches, sc.K, sc.a, sc.mode).cpu().numpy()
+            st = chk.stats(0)
+            assert st["status"] == 0 and st["n_invariant"] == 0, st
+            np.testing.assert_array_equal(out, ref)
+        _announce(f"batch of 3 precision={precision} conn={conn}")
+        probs = [(*_dev(sc), sc.K, sc.a, sc.mode) for sc in cases]
+        flows = [f.cpu().numpy() for f in chk.interp_batch(probs)]
+        for i, (cost, matches, K, a, mode) in enumerate(probs):
+            assert chk.stats(i)["n_invariant"] == 0, chk.stats(i)
+            np.testing.assert_array_equal(flows[i], plain.interp(cost, matches, K, a, mode).cpu().numpy())
+    with epic.Context(0, debug_validate=1, prune_px=5.0, **kw) as chk:
+        sc = cases[0]
+        _announce(f"{sc.name} with the consistency check precision={precision}")
+        cost, matches = _dev(sc)
+        chk.interp(cost, matches, sc.K, sc.a, sc.mode)
+        st = chk.stats(0)
+        assert st["status"] == 0 and st["n_invariant"] == 0, st
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_planted_violation_is_reported(precision):
+    """debug_validate = 2 raises pixel 0's distance before the checks (a
+    planted violation of the fixpoint): the pair reports ERR_INVARIANT."""
+    import paper_1501_02565_amd as epic
+    sc = random_case(70, 90, 140, seed=9, K=20)
+    cost, matches = _dev(sc)
+    _announce(f"{sc.name} planted violation precision={precision}")
+    with epic.Context(0, precision=precision, debug_validate=2) as chk:
+        chk.interp(cost, matches, sc.K, sc.a, sc.mode)
+        st = chk.stats(0)
+    print(st, flush=True)
+    assert st["status"] == epic.ERR_INVARIANT and st["n_invariant"] >= 1, st
