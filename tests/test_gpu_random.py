@@ -4,7 +4,8 @@ register and LDS sorts), NW or LA, 4- or 8-connectivity, the LA weight
 power, FP32 or FP64-everywhere, and some matches outside the image or on
 shared pixels; every stage of the HIP path is checked against the oracle
 (FP32 with the parity tolerances, FP64 bit-exact for D, L and the K-NN
-lists).  Needs an MI355X."""
+lists), and the device's own invariant checks (debug_validate: transform
+fixpoint, seeds, labels, graph symmetry) report nothing.  Needs an MI355X."""
 from __future__ import annotations
 
 import numpy as np
@@ -39,15 +40,17 @@ def test_random_sweep():
             if key not in ctxs:
                 ctxs[key] = epic.Context(0, 2 * epic.workspace_bytes(400, 400, 4000, 256, 1, c["prec"]),
                                          connectivity=c["conn"], la_weight_power=c["wpow"],
-                                         precision=c["prec"])
+                                         precision=c["prec"], debug_validate=1)
             ctx = ctxs[key]
             print(f"[case] {c}", flush=True)
             sc = random_case(c["H"], c["W"], c["N"], seed=c["seed"], K=c["K"], mode=c["mode"],
                              outside=min(c["outside"], c["N"] - 1), duplicates=min(c["dup"], c["N"] // 3))
             if c["prec"] == 0:
                 parity.full_check(ctx, sc, conn=c["conn"], wpow=c["wpow"])
+                assert ctx.stats(0)["n_invariant"] == 0, ctx.stats(0)
                 continue
             g = parity.gpu_stages(ctx, sc)
+            assert ctx.stats(0)["n_invariant"] == 0, ctx.stats(0)
             r = parity.ref_stages(sc, conn=c["conn"], wpow=c["wpow"])
             np.testing.assert_array_equal(g["D"], r["D"])
             np.testing.assert_array_equal(g["L"], r["L"])
