@@ -61,9 +61,13 @@ def measured_traffic(stage):
     summary, or None when the kernel source changed since it was taken."""
     import hashlib
     prof = os.path.join(ROOT, "profiles", "epic_1024x436_n8000_k100_hbm_counters.txt")
-    src = os.path.join(ROOT, "paper_1501_02565_amd", "csrc", "k_geodesic.hip")
+    csrc = os.path.join(ROOT, "paper_1501_02565_amd", "csrc")
     try:
-        cur = hashlib.sha1(open(src, "rb").read()).hexdigest()[:12]
+        # the kernel's source and the device header it includes
+        h = hashlib.sha1()
+        for f in ("k_geodesic.hip", "epic_dev.h"):
+            h.update(open(os.path.join(csrc, f), "rb").read())
+        cur = h.hexdigest()[:12]
         for line in open(prof):
             if line.startswith("TRAFFIC " + stage + " "):
                 kv = dict(t.split("=") for t in line.split()[2:])
