@@ -608,10 +608,12 @@ def main():
     for _ in range(nprof):
         ctx.interp(cost, matches, sc.K, sc.a, sc.mode, out=flow)
     stages = ctx.stage_times(nprof)
+    pass_visits = ctx.pass_visits()        # of the last profiled call
     ctx.profile(False)
     E = st["n_edges"]
     log(f"bench: stats {st}")
     log("bench: stage ms " + ", ".join(f"{k}={v:.4f}" for k, v in stages.items()))
+    log(f"bench: transform tile visits per pass {pass_visits}")
     dom = max(stages, key=lambda k: stages[k])
     dom_ms = stages[dom]
     nbytes = stage_bytes(dom, HW, sc.N, E, args.precision)
@@ -682,6 +684,8 @@ def main():
                    "a": sc.a, "mode": "LA", "error_vs_oracle": err,
                    "stage_ms": {k: round(v, 5) for k, v in stages.items()},
                    "graph_replay_ms_per_step": round(graph_ms, 5),
+                   "transform_tiles": -(-sc.W // tile[0]) * -(-sc.H // tile[1]),
+                   "transform_visits_per_pass": pass_visits,
                    "latency_other_configs": lat},
         "roofline": roofline,
         "cpu_baseline": cpu,

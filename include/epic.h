@@ -392,6 +392,15 @@ int epic_stage_times(epic_ctx* ctx, float* ms, int n_stages, int calls);
 /* Name of stage i of epic_stage_times ("" when out of range). */
 const char* epic_stage_name(int i);
 
+/* Tile visits per pass of the last call's geodesic transform (pass 0 the
+ * first pass over every tile, then the dirty-tile passes, the finisher's
+ * passes after them), summed over the call's pairs.  Counted only for FP32
+ * calls made while profiling is enabled (epic_profile); otherwise all zero.
+ * Synchronises the last call's stream, writes min(n, 256) counts and
+ * returns the number of passes that visited a tile (or a negative
+ * epic_status). */
+int epic_pass_visits(epic_ctx* ctx, int* visits, int n);
+
 /* Human-readable text of an epic_status. */
 const char* epic_strerror(int status);
 

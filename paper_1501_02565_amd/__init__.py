@@ -358,6 +358,15 @@ class Context:
             raise EpicError(n, "epic_stage_times")
         return {L.epic_stage_name(i).decode(): float(buf[i]) for i in range(n)}
 
+    def pass_visits(self) -> list:
+        """Tile visits per pass of the last call's transform (FP32 calls made
+        while profiling; empty otherwise)."""
+        buf = (ctypes.c_int * 256)()
+        n = _lib.load().epic_pass_visits(self._ctx, buf, 256)
+        if n < 0:
+            raise EpicError(n, "epic_pass_visits")
+        return list(buf[:n])
+
     def stats(self, pair: int = 0) -> dict:
         """Device counters of the last call (synchronises its stream)."""
         s = _lib.Stats()

@@ -22,7 +22,7 @@ SYMBOLS = ["epic_create", "epic_destroy", "epic_workspace_bytes", "epic_interp",
            "epic_stage_times", "epic_stage_name", "epic_graph_capture",
            "epic_graph_launch", "epic_graph_destroy", "epic_prune", "epic_image_cost",
            "epic_interp_image", "epic_interp_noalloc", "epic_interp_exact",
-           "epic_refine_defaults", "epic_refine_bytes", "epic_refine"]
+           "epic_refine_defaults", "epic_refine_bytes", "epic_refine", "epic_pass_visits"]
 
 
 class Options(ctypes.Structure):
@@ -115,6 +115,8 @@ def load():
     L.epic_interp_noalloc.restype = i32
     L.epic_interp_exact.argtypes = [P, P, i32, i32, P, i32, i32, f32, i32, P, P]
     L.epic_interp_exact.restype = i32
+    L.epic_pass_visits.argtypes = [P, ctypes.POINTER(ctypes.c_int), i32]
+    L.epic_pass_visits.restype = i32
     L.epic_refine_defaults.argtypes = [ctypes.POINTER(RefineParams)]
     L.epic_refine_defaults.restype = None
     L.epic_refine_bytes.argtypes = [i32, i32, i32]

@@ -124,6 +124,7 @@ struct epic_ctx {
     bool last_pruned = false;           // the last call ran the consistency check
     PairDev* last_desc = nullptr;       // device descriptor table of the last call
     size_t last_used = 0;               // workspace bytes the last call carved (from its start)
+    bool last_pass_visits = false;      // the last call counted its transform's visits per pass
 };
 
 extern "C" {
@@ -414,6 +415,8 @@ int run_pairs(epic_ctx* c, const epic_request* reqs, int n, hipStream_t stream, 
     run.dirty[1] = dirty1;
     run.any = c->g_any;
     run.any2 = c->g_any + kMaxPasses;
+    run.pass_visits = c->prof && c->opt.precision == 0 ? c->g_any + 2 * kMaxPasses : nullptr;
+    c->last_pass_visits = run.pass_visits != nullptr;
     run.error = c->g_error;
     run.passes_used = c->h_passes_used;
     run.ovf_list = ovf_list;
@@ -882,6 +885,21 @@ int epic_stage_times(epic_ctx* ctx, float* ms, int n_stages, int calls) {
 }
 
 const char* epic_stage_name(int i) { return (i >= 0 && i < kStages) ? kStageNames[i] : ""; }
+
+int epic_pass_visits(epic_ctx* ctx, int* visits, int n) {
+    if (!ctx || !visits || n < 1) return EPIC_ERR_ARG;
+    const int m = std::min(n, kMaxPasses);
+    for (int i = 0; i < m; ++i) visits[i] = 0;
+    if (!ctx->last_pass_visits) return 0;
+    if (hipSetDevice(ctx->device) != hipSuccess) return EPIC_ERR_HIP;
+    if (hipStreamSynchronize(ctx->last_stream) != hipSuccess) return EPIC_ERR_HIP;
+    if (hipMemcpy(visits, ctx->g_any + 2 * kMaxPasses, sizeof(int) * m, hipMemcpyDeviceToHost) != hipSuccess)
+        return EPIC_ERR_HIP;
+    int used = 0;
+    for (int i = 0; i < m; ++i)
+        if (visits[i] > 0) used = i + 1;
+    return used;
+}
 
 int epic_get_stats(epic_ctx* ctx, int pair, epic_stats* out) {
     if (!ctx || !out || pair < 0 || pair >= ctx->last_npairs) return EPIC_ERR_ARG;

@@ -217,6 +217,8 @@ struct RunDev {
     int* wl_cnt;            // 3 list lengths
     int* any;               // per pass: some tile border changed (kMaxPasses)
     int* any2;              // the same for the label phase of the FP64 path
+    int* pass_visits;       // per pass: tile visits of the FP32 transform (counted
+                            //   only while profiling; null otherwise)
     int* error;             // global error word: bit 0 = the transform finisher hit
                             //   its pass bound (per-pair errors live in the counters)
     int* passes_used;       // host-visible, 2 ints: passes the last transform needed

@@ -412,6 +412,7 @@ __global__ __launch_bounds__(NT) void k_geo_pass(const PairDev* __restrict__ pai
         if (threadIdx.x == 0) dirty[tile] = 0u;              // reused two passes later
         const int border = visit_tile<TW, TH, 0, 0, CONN, NT>(P, tx, ty, S, P.counters + C_GEOERR, kPassRounds);
         if (threadIdx.x == 0) atomicAdd(&P.counters[C_TILE_VISITS], 1);
+        if (threadIdx.x == 0 && run.pass_visits) atomicAdd(&run.pass_visits[pass], 1);
         if (border) {
             mark_neighbours<CONN, LISTED>(P, run, tx, ty, border, pass + 1);
             if (threadIdx.x == 0) run.any[pass] = 1;
@@ -445,6 +446,7 @@ __global__ __launch_bounds__(NT) void k_geo_first(const PairDev* __restrict__ pa
     if (threadIdx.x == 0) run.dirty[0][tile] = 0u;           // reused by pass 2
     const int border = visit_tile<TW, TH, MX, MY, CONN, NT>(P, tx, ty, S, P.counters + C_GEOERR, kFirstRounds);
     if (threadIdx.x == 0) atomicAdd(&P.counters[C_TILE_VISITS], 1);
+    if (threadIdx.x == 0 && run.pass_visits) atomicAdd(&run.pass_visits[0], 1);
     if (border) {
         mark_neighbours<CONN, LISTED>(P, run, tx, ty, border, 1);
         if (threadIdx.x == 0) run.any[0] = 1;
@@ -492,6 +494,7 @@ __global__ __launch_bounds__(NT) void k_geo_finish(const PairDev* __restrict__ p
             if (threadIdx.x == 0) dirty[tile] = 0u;
             const int border = visit_tile<TW, TH, 0, 0, CONN, NT>(P, tx, ty, S, P.counters + C_GEOERR);
             if (threadIdx.x == 0) atomicAdd(&P.counters[C_TILE_VISITS], 1);
+            if (threadIdx.x == 0 && run.pass_visits) atomicAdd(&run.pass_visits[min(pass, kMaxPasses - 1)], 1);
             if (border) {
                 mark_neighbours<CONN, false>(P, run, tx, ty, border, pass + 1);
                 if (threadIdx.x == 0) s_any = 1;

@@ -57,6 +57,7 @@ __global__ __launch_bounds__(256) void k_clear(PairDev* __restrict__ pairs, RunD
     if (p == 0 && i0 < kMaxPasses) {
         run.any[i0] = 0;
         run.any2[i0] = 0;
+        if (run.pass_visits) run.pass_visits[i0] = 0;
     }
     if (p == 0 && i0 == 0) {
         *run.error = 0;

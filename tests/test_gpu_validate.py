@@ -163,3 +163,24 @@ def test_planted_violation_is_reported(precision):
         st = chk.stats(0)
     print(st, flush=True)
     assert st["status"] == epic.ERR_INVARIANT and st["n_invariant"] >= 1, st
+
+
+def test_pass_visits_are_counted_while_profiling():
+    """epic_pass_visits: the first pass visits every tile, the counts add up
+    to the call's tile visits, and nothing is counted without profiling."""
+    import paper_1501_02565_amd as epic
+    from scenes import config_scene
+    sc = config_scene(1)
+    cost, matches = _dev(sc)
+    _announce(f"{sc.name} pass visits")
+    with epic.Context(0) as ctx:
+        ctx.interp(cost, matches, sc.K, sc.a, sc.mode)
+        assert ctx.pass_visits() == []
+        ctx.profile(True)
+        ctx.interp(cost, matches, sc.K, sc.a, sc.mode)
+        v = ctx.pass_visits()
+        st = ctx.stats(0)
+        ctx.profile(False)
+    tiles = -(-sc.W // 32) * -(-sc.H // 16)
+    print(v, st["tile_visits"], tiles, flush=True)
+    assert v[0] == tiles and sum(v) == st["tile_visits"] and all(x > 0 for x in v)
