@@ -40,6 +40,14 @@ smoothness term, g_ij = lam (alpha_i + alpha_j) / 2 psi'(...) -- and solves
 by 30 red-black SOR sweeps (red: x + y even, then black; du before dv at
 each pixel); an equation whose diagonal is zero (no image gradient and no
 neighbour weight) leaves its unknown unchanged.  The result is u0 + du.
+
+Pinning: the tests pin this code to the mathematics of the energy above
+(closed forms of the warp and derivatives, the SOR solve against a direct
+sparse solve, stationarity of the linearised energy at the converged
+iterate, the exact field staying put).  The paper itself fixes only
+alpha, kappa and the iteration counts: the data term's form and the
+weights delta, gamma, lam, zeta, eps and omega are this reading, so for
+the data term parity with the paper's method is partly unpinned.
 """
 from __future__ import annotations
 
