@@ -295,16 +295,23 @@ int epic_interp_image(epic_ctx* ctx, const float* image, int H, int W, int chann
  * gets its own K nearest matches under the geodesic distance of Eq. (3)
  * itself, D_G(p, p_m), ordered by (distance, index), with weights
  * exp(-a D_G), and its own NW (Eq. 1) or LA (Eq. 2) estimate evaluated at
- * p.  One single-source transform per match (in chunks of up to 1024 that
- * fit the workspace), a per-pixel selection and a per-pixel fit; the
- * near-collinear LA rule and FP64 routing are those of epic_interp.
+ * p.  The approximated interpolation runs first: its distances (each the
+ * length of a path of the pixel graph) bound, at every pixel, the distance
+ * of the K-th nearest match; then one single-source transform per match (in
+ * chunks of up to 1024 that fit the workspace) keeps only distances within
+ * those bounds, a per-pixel selection folds each chunk into the pixels' K
+ * nearest, and a per-pixel fit ends it; the near-collinear LA rule and FP64
+ * routing are those of epic_interp.  The bound only skips work: the result
+ * is the same as with full-image transforms.
  * Arguments as in epic_interp, with K <= 128 and a context created with
- * precision 0 (EPIC_ERR_ARG otherwise).  The workspace must hold 8*K*H*W +
- * N + 512 bytes for the pixels' lists plus, per match of a chunk,
- * epic_workspace_bytes(H, W, 1, 1, mode, 0) (EPIC_ERR_WORKSPACE when not
- * even one fits); a chunk of 1024 at 1024 x 436 needs about 3.7 GB.  No
- * per-call statistics (epic_get_stats refers to no pair afterwards).
- * Asynchronous on `stream`. */
+ * precision 0 (EPIC_ERR_ARG otherwise).  The workspace must hold
+ * 8*K*H*W + 4*H*W + N + 8*N*K bytes (plus 2 KB of alignment) at its end
+ * for the pixels' lists, the bounds and the approximated lists, besides
+ * epic_workspace_bytes(H, W, N, K, mode, 0) for the approximated pass and,
+ * per match of a chunk, epic_workspace_bytes(H, W, 1, 1, mode, 0)
+ * (EPIC_ERR_WORKSPACE when not even one fits); a chunk of 1024 at
+ * 1024 x 436 needs about 3.7 GB.  No per-call statistics (epic_get_stats
+ * refers to no pair afterwards).  Asynchronous on `stream`. */
 int epic_interp_exact(epic_ctx* ctx, const float* cost, int H, int W, const float* matches, int N,
                       int K, float a, int mode, float* flow, void* stream);
 

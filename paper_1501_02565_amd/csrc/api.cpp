@@ -273,6 +273,9 @@ struct DebugOut {
     // pass budget
     int stop_after = 0;
     int geo_passes = 0;
+    // the exact interpolation's single-source transforms: per-pixel bound
+    // on the distances worth keeping (32 x 16 tiles)
+    const float* ubound = nullptr;
 };
 
 // Where a call's descriptor table lives: the context's upload ring (default)
@@ -292,7 +295,8 @@ int run_pairs(epic_ctx* c, const epic_request* reqs, int n, hipStream_t stream, 
         if (v != EPIC_OK) return v;
     }
     // the FP64 transform runs on 32 x 16 tiles
-    const Tiling tl = c->opt.precision == 1 ? Tiling{32, 16} : Tiling{c->opt.tile_w, c->opt.tile_h};
+    const bool bounded = dbg && dbg->ubound;
+    const Tiling tl = c->opt.precision == 1 || bounded ? Tiling{32, 16} : Tiling{c->opt.tile_w, c->opt.tile_h};
     // ---- carve the workspace
     size_t total_tiles = 0, need = kFixed;
     for (int i = 0; i < n; ++i) total_tiles += tiles_of(reqs[i].H, reqs[i].W, tl);
@@ -392,6 +396,7 @@ int run_pairs(epic_ctx* c, const epic_request* reqs, int n, hipStream_t stream, 
             P.params64 = reinterpret_cast<double*>(take(48 * (size_t)r.N));
         }
         c->last_counters[i] = P.counters;
+        if (bounded) P.ubound = dbg->ubound;
         if (dbg && i == 0) {
             P.dbg_knn_idx = dbg->knn_idx;
             P.dbg_knn_d = dbg->knn_d;
@@ -424,6 +429,7 @@ int run_pairs(epic_ctx* c, const epic_request* reqs, int n, hipStream_t stream, 
     run.total_tiles = tile_base;
     run.npairs = n;
     run.conn = c->opt.connectivity;
+    run.bounded = bounded ? 1 : 0;
     run.tile_w = tl.tw;
     run.tile_h = tl.th;
     run.la_wpow = c->opt.la_weight_power;
@@ -661,11 +667,13 @@ int epic_interp_exact(epic_ctx* ctx, const float* cost, int H, int W, const floa
     if (ctx->opt.precision != 0) return EPIC_ERR_ARG;
     const hipStream_t st = (hipStream_t)stream;
     const long long HW = (long long)H * W;
-    // the pixels' lists and the owner flags live at the end of the workspace
+    // at the end of the workspace: the pixels' lists, the owner flags, the
+    // per-pixel distance bounds and the approximate K-NN lists they come from
     const size_t lists_b = align_up(8 * (size_t)K * HW), owner_b = align_up((size_t)N);
-    const size_t tail = lists_b + owner_b + kAlign;
+    const size_t ub_b = align_up(4 * (size_t)HW), knn_b = align_up(4 * (size_t)N * K);
+    const size_t tail = lists_b + owner_b + ub_b + 2 * knn_b + kAlign;
     if (tail >= ctx->ws_bytes) return EPIC_ERR_WORKSPACE;
-    char* tail_p = ctx->ws + ((ctx->ws_bytes - lists_b - owner_b) & ~(kAlign - 1));
+    char* tail_p = ctx->ws + ((ctx->ws_bytes - (tail - kAlign)) & ~(kAlign - 1));
     ExactArgs A{};
     A.matches = matches;
     A.N = N;
@@ -675,29 +683,40 @@ int epic_interp_exact(epic_ctx* ctx, const float* cost, int H, int W, const floa
     A.HW = HW;
     A.lists = reinterpret_cast<u64*>(tail_p);
     A.owner = reinterpret_cast<unsigned char*>(tail_p + lists_b);
+    A.ubound = reinterpret_cast<float*>(tail_p + lists_b + owner_b);
+    A.knn_idx = reinterpret_cast<int*>(tail_p + lists_b + owner_b + ub_b);
+    A.knn_d = reinterpret_cast<float*>(tail_p + lists_b + owner_b + ub_b + knn_b);
     A.flow = flow;
     A.a = a;
     A.mode = mode;
     A.wpow = ctx->opt.la_weight_power;
     A.fp64_route = ctx->opt.fp64_route;
     A.deg_tau = ctx->opt.degenerate_tau;
-    // 1. which matches hold their pixel (the seeding of the whole set)
-    DebugOut seed_only;
-    seed_only.stop_after = 1;
-    epic_request full{cost, H, W, matches, N, 1, a, mode, flow};
-    int rc = run_pairs(ctx, &full, 1, st, &seed_only, nullptr, tail);
+    // 1. the approximated interpolation (Sec. 3.4) of the whole set: which
+    //    matches hold their pixel, and each match's K nearest in the graph,
+    //    whose K-th distance plus D(p) bounds the distance of every pixel's
+    //    K-th nearest match (each approximated distance is the length of a
+    //    path of the pixel graph)
+    DebugOut approx;
+    approx.knn_idx = A.knn_idx;
+    approx.knn_d = A.knn_d;
+    epic_request full{cost, H, W, matches, N, K, a, mode, flow};
+    int rc = run_pairs(ctx, &full, 1, st, &approx, nullptr, tail);
     if (rc != EPIC_OK) return rc;
     if (launch_exact_owner(ctx->last_desc, A, st) != hipSuccess) return EPIC_ERR_HIP;
-    // 2. single-source transforms, one match per pair, in chunks that fit
-    const Tiling tl{ctx->opt.tile_w, ctx->opt.tile_h};
+    if (launch_exact_bound(ctx->last_desc, A, st) != hipSuccess) return EPIC_ERR_HIP;
+    // 2. single-source transforms bounded by those distances, one match per
+    //    pair, in chunks that fit
+    const Tiling tl{32, 16};
     const size_t per = pair_bytes(H, W, 1, 0) + kTileArrays * align_up(4 * tiles_of(H, W, tl)) + kAlign;
     if (ctx->ws_bytes < kFixed + tail + per) return EPIC_ERR_WORKSPACE;
     const int chunk = (int)std::min<size_t>(kMaxPairs, (ctx->ws_bytes - kFixed - tail) / per);
-    // generous budget: a single source's distances cross the whole image
+    // generous budget: a single source's distances may cross the whole image
     const int tx = (W + tl.tw - 1) / tl.tw, ty = (H + tl.th - 1) / tl.th;
     DebugOut transform_only;
     transform_only.stop_after = 2;
     transform_only.geo_passes = std::min(kMaxPasses - 1, 2 * (tx + ty) + 8);
+    transform_only.ubound = A.ubound;
     std::vector<epic_request> reqs;
     for (int s0 = 0; s0 < N; s0 += chunk) {
         const int n = std::min(chunk, N - s0);

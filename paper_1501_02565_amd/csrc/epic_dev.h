@@ -103,6 +103,9 @@ struct PairDev {
     double* params64;       // N*6
     // consistency check of the matches (Sec. 5.1): the kept matches,
     // compacted in index order, and their original indices
+    // exact interpolation: per-pixel bound on the distances worth keeping in
+    // a single-source transform (null: none)
+    const float* ubound;    // H*W
     float* matches_kept;    // N*4
     int* kept_idx;          // N
     // optional stage dumps (NULL = off)
@@ -233,6 +236,7 @@ struct RunDev {
     int precision;          // 0 or 1
     float fp64_route;
     double deg_tau;
+    int bounded;            // 1: the transform keeps only distances within P.ubound
     int force_nw;           // 1: fit NW whatever the pair's mode (the first pass of
                             //   the consistency check)
     int keep_prune_counters;   // 1: the clear keeps counters C_PRUNED.. (second pass)
@@ -313,6 +317,9 @@ struct ExactArgs {
     u64* lists;             // K*HW: entry k of pixel p at k*HW + p, packed
                             //   (distance bits << 32 | match), ascending; ~0 = none
     unsigned char* owner;   // N: 1 when the match holds its pixel
+    float* ubound;          // H*W: bound on the distance of the pixel's K-th nearest match
+    int* knn_idx;           // N*K: the approximated K-NN lists the bound comes from
+    float* knn_d;           // N*K
     float* flow;            // H*W*2
     float a;
     int mode, wpow;
@@ -323,6 +330,7 @@ hipError_t launch_exact_owner(const PairDev* full, const ExactArgs& A, hipStream
 hipError_t launch_exact_select(const PairDev* chunk, int nsrc, int src0, int first, const ExactArgs& A,
                                hipStream_t s);
 hipError_t launch_exact_fit(const ExactArgs& A, hipStream_t s);
+hipError_t launch_exact_bound(const PairDev* full, const ExactArgs& A, hipStream_t s);
 hipError_t launch_image_cost(const ImageCostArgs& args, int channels, int total_blocks, hipStream_t s);
 hipError_t launch_check_transform(const PairDev* d_pairs, const RunDev& run, int pix_blocks, int plant,
                                   hipStream_t s);

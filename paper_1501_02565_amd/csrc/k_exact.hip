@@ -20,6 +20,28 @@
 
 namespace epic {
 
+// Per pixel p, an upper bound of the distance of its K-th nearest match:
+// D(p) + the K-th graph distance from p's cell's match (the approximation
+// of Eq. (4) is the length of a path of the pixel graph for each of those K
+// matches, so K matches lie within it).  Widened by 1e-3 relative (and
+// 1e-6) so that rounding in either sum never makes it too small; infinite
+// (no bound) when the cell has fewer than K neighbours in its list or the
+// approximated pass reported a problem.
+__global__ __launch_bounds__(256) void k_exact_bound(const PairDev* __restrict__ full, ExactArgs A) {
+    const long long p = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (p >= A.HW) return;
+    const PairDev& P = full[0];
+    float u = __int_as_float(0x7f800000);
+    const bool ok = P.counters[C_STATUS] == 0 && (P.counters[C_OVERFLOW] & 2) == 0;
+    const u64 k = P.keys[p];
+    const u32 L = key_label(k);
+    if (ok && L < (u32)P.N) {
+        const long long j = (long long)L * A.K + (A.K - 1);
+        if (A.knn_idx[j] >= 0) u = (key_dist(k) + A.knn_d[j]) * 1.001f + 1e-6f;
+    }
+    A.ubound[p] = u;
+}
+
 __global__ __launch_bounds__(256) void k_exact_owner(const PairDev* __restrict__ full, ExactArgs A) {
     const int m = (int)(blockIdx.x * 256 + threadIdx.x);
     if (m >= A.N) return;
@@ -122,6 +144,11 @@ hipError_t launch_exact_select(const PairDev* chunk, int nsrc, int src0, int fir
     const size_t lds = (size_t)A.K * 64 * sizeof(u64);
     hipLaunchKernelGGL(k_exact_select, dim3((unsigned)((A.HW + 63) / 64)), dim3(64), lds, s, chunk, nsrc, src0,
                        first, A);
+    return hipGetLastError();
+}
+
+hipError_t launch_exact_bound(const PairDev* full, const ExactArgs& A, hipStream_t s) {
+    hipLaunchKernelGGL(k_exact_bound, dim3((unsigned)((A.HW + 255) / 256)), dim3(256), 0, s, full, A);
     return hipGetLastError();
 }
 

@@ -79,6 +79,21 @@ struct TileLds {
     int border;
 };
 
+// The same with a per-pixel bound on the distances worth keeping (the exact
+// interpolation's single-source transforms).
+template <int TW, int TH>
+struct TileLdsB : TileLds<TW, TH> {
+    float ub[TileLds<TW, TH>::NL];
+};
+template <int TW, int TH, bool BOUND>
+using TileLdsT = typename std::conditional<BOUND, TileLdsB<TW, TH>, TileLds<TW, TH>>::type;
+
+template <class L>
+__device__ __forceinline__ float bound_at(const L& S, int i) {
+    if constexpr (std::is_same<L, TileLdsB<L::LW - 2, L::LH - 2>>::value) return S.ub[i];
+    else return INFINITY;
+}
+
 // Visits one tile: load with halo, relax to a local fixpoint, write back.
 // Returns (to every thread) the mask of borders with a changed pixel.
 //
@@ -117,9 +132,16 @@ constexpr int nb_index(int dx, int dy) {
 // The first pass uses a margin so that seeds just outside a tile already
 // shape its distances, which saves most of the passes that would otherwise
 // carry them in one tile at a time.
-template <int TW, int TH, int MX, int MY, int CONN, int NT>
+//
+// BOUND: a key whose distance exceeds the pixel's bound (P.ubound) is not
+// taken, so a transform only spreads where its distances can still matter.
+// A value above the bound at some pixel is above it at every pixel the path
+// continues to (the bound is an upper bound of the distance to the K-th
+// nearest match, which grows by at most a step per step), so pruning never
+// hides a distance below a bound.
+template <int TW, int TH, int MX, int MY, int CONN, int NT, bool BOUND = false>
 __device__ __forceinline__ int visit_tile(const PairDev& P, int tx, int ty,
-                                          TileLds<TW + 2 * MX, TH + 2 * MY>& S, int* error,
+                                          TileLdsT<TW + 2 * MX, TH + 2 * MY, BOUND>& S, int* error,
                                           int soft_cap = 1 << 30) {
     constexpr int RW = TW + 2 * MX, RH = TH + 2 * MY;     // region relaxed
     constexpr int PPT = RW * RH / NT;
@@ -142,6 +164,7 @@ __device__ __forceinline__ int visit_tile(const PairDev& P, int tx, int ty,
     constexpr int LI = (NL + NT - 1) / NT;
     u64 lk[LI];
     float lc[LI];
+    float lu[BOUND ? LI : 1];
 #pragma unroll
     for (int it = 0; it < LI; ++it) {
         const int i = tid + it * NT;
@@ -149,6 +172,7 @@ __device__ __forceinline__ int visit_tile(const PairDev& P, int tx, int ty,
         const int gx = rx0 + lxx - 1, gy = ry0 + ly - 1;
         lk[it] = KEY_INF;
         lc[it] = 0.0f;
+        if constexpr (BOUND) lu[it] = 0.0f;
         if (i < NL && gx >= 0 && gy >= 0 && gx < W && gy < H) {
             const long long gi = (long long)gy * W + gx;
             // the tile's own pixels are written only by this visit; the
@@ -156,6 +180,7 @@ __device__ __forceinline__ int visit_tile(const PairDev& P, int tx, int ty,
             const bool own = gx >= x0 && gy >= y0 && gx < x0 + twe && gy < y0 + the;
             lk[it] = own ? gmem(P.keys)[gi] : dev_ld(P.keys + gi);
             lc[it] = gmem(P.cost)[gi];
+            if constexpr (BOUND) lu[it] = gmem(P.ubound)[gi];
         }
     }
 #pragma unroll
@@ -164,6 +189,7 @@ __device__ __forceinline__ int visit_tile(const PairDev& P, int tx, int ty,
         if (i < NL) {
             S.key[i] = lk[it];
             S.cost[i] = lc[it];
+            if constexpr (BOUND) S.ub[i] = lu[it];
         }
     }
     if (tid < 3) S.flag[tid] = 0;
@@ -246,6 +272,9 @@ __device__ __forceinline__ int visit_tile(const PairDev& P, int tx, int ty,
                 if (jj > 0) best = min_f64(best, behind);
                 u64 bk = (u64)__double_as_longlong(best);
                 if (lx < vx0 || lx >= vx1 || ly < vy0 || ly >= vy1) bk = now;   // outside the image
+                if constexpr (BOUND) {
+                    if (key_dist(bk) > S.ub[c]) bk = now;                    // beyond the bound
+                }
                 if (bk < now) {
                     lds_st(&S.key[c], bk);
                     lds_st(&S.rowchg[ly + 1], round);
@@ -324,7 +353,7 @@ __device__ __forceinline__ int visit_tile(const PairDev& P, int tx, int ty,
                     const float len = (kk < 4) ? 1.0f : 1.41421356237309515f;
                     // priced exactly as the neighbour's sweep would price it
                     const u64 cand = make_key(relax_f32(dp, step_f32(len, cp, S.cost[qi])), key_label(k));
-                    if (cand < S.key[qi]) {
+                    if (cand < S.key[qi] && (!BOUND || key_dist(cand) <= bound_at(S, qi))) {
                         const bool ql = qx < 0, qr = qx >= twe, qt = qy < 0, qb = qy >= the;
                         bm |= (ql && !qt && !qb) ? B_L : (qr && !qt && !qb) ? B_R
                             : (qt && !ql && !qr) ? B_T : (qb && !ql && !qr) ? B_B
@@ -398,9 +427,9 @@ constexpr int kPassRounds = 5;
 // XCDs.  Otherwise block b takes tile b (consecutive tiles go to different
 // XCDs) and returns at once when its flag is clear: cheaper for a single
 // image, whose marks then are plain stores.
-template <int TW, int TH, int CONN, int NT, bool LISTED>
+template <int TW, int TH, int CONN, int NT, bool LISTED, bool BOUND = false>
 __global__ __launch_bounds__(NT) void k_geo_pass(const PairDev* __restrict__ pairs, RunDev run, int pass) {
-    __shared__ TileLds<TW, TH> S;
+    __shared__ TileLdsT<TW, TH, BOUND> S;
     if (pass > 0 && run.any[pass - 1] == 0) return;          // converged
     u32* dirty = run.dirty[pass & 1];
     auto visit = [&](int tile) {
@@ -410,7 +439,8 @@ __global__ __launch_bounds__(NT) void k_geo_pass(const PairDev* __restrict__ pai
         const int tx = lt % P.tiles_x, ty = lt / P.tiles_x;
         __syncthreads();                                     // the previous tile's LDS is done
         if (threadIdx.x == 0) dirty[tile] = 0u;              // reused two passes later
-        const int border = visit_tile<TW, TH, 0, 0, CONN, NT>(P, tx, ty, S, P.counters + C_GEOERR, kPassRounds);
+        const int border = visit_tile<TW, TH, 0, 0, CONN, NT, BOUND>(P, tx, ty, S, P.counters + C_GEOERR,
+                                                                     kPassRounds);
         if (threadIdx.x == 0) atomicAdd(&P.counters[C_TILE_VISITS], 1);
         if (threadIdx.x == 0 && run.pass_visits) atomicAdd(&run.pass_visits[pass], 1);
         if (border) {
@@ -433,9 +463,9 @@ __global__ __launch_bounds__(NT) void k_geo_pass(const PairDev* __restrict__ pai
 
 // The first pass: every tile, relaxed over the tile and a margin of MX
 // columns and MY rows around it (seeds from the start, written by k_seed).
-template <int TW, int TH, int MX, int MY, int CONN, int NT, bool LISTED>
+template <int TW, int TH, int MX, int MY, int CONN, int NT, bool LISTED, bool BOUND = false>
 __global__ __launch_bounds__(NT) void k_geo_first(const PairDev* __restrict__ pairs, RunDev run) {
-    __shared__ TileLds<TW + 2 * MX, TH + 2 * MY> S;
+    __shared__ TileLdsT<TW + 2 * MX, TH + 2 * MY, BOUND> S;
     const int per_xcd = (run.total_tiles + 7) / 8;
     const int tile = (int)(blockIdx.x % 8) * per_xcd + (int)(blockIdx.x / 8);
     if (tile >= run.total_tiles) return;
@@ -444,7 +474,8 @@ __global__ __launch_bounds__(NT) void k_geo_first(const PairDev* __restrict__ pa
     const int lt = tile - P.tile_base;
     const int tx = lt % P.tiles_x, ty = lt / P.tiles_x;
     if (threadIdx.x == 0) run.dirty[0][tile] = 0u;           // reused by pass 2
-    const int border = visit_tile<TW, TH, MX, MY, CONN, NT>(P, tx, ty, S, P.counters + C_GEOERR, kFirstRounds);
+    const int border = visit_tile<TW, TH, MX, MY, CONN, NT, BOUND>(P, tx, ty, S, P.counters + C_GEOERR,
+                                                                   kFirstRounds);
     if (threadIdx.x == 0) atomicAdd(&P.counters[C_TILE_VISITS], 1);
     if (threadIdx.x == 0 && run.pass_visits) atomicAdd(&run.pass_visits[0], 1);
     if (border) {
@@ -455,9 +486,9 @@ __global__ __launch_bounds__(NT) void k_geo_first(const PairDev* __restrict__ pa
 
 // Continues the passes in one workgroup until no border changes (only runs
 // when the launched passes did not reach the fixpoint).
-template <int TW, int TH, int CONN, int NT>
+template <int TW, int TH, int CONN, int NT, bool BOUND = false>
 __global__ __launch_bounds__(NT) void k_geo_finish(const PairDev* __restrict__ pairs, RunDev run, int pass0) {
-    __shared__ TileLds<TW, TH> S;
+    __shared__ TileLdsT<TW, TH, BOUND> S;
     __shared__ int s_any;
     // passes that changed something so far (they form a prefix): the
     // transform needs one more than that, which is reported for the
@@ -492,7 +523,7 @@ __global__ __launch_bounds__(NT) void k_geo_finish(const PairDev* __restrict__ p
             const int tx = lt % P.tiles_x, ty = lt / P.tiles_x;
             __syncthreads();
             if (threadIdx.x == 0) dirty[tile] = 0u;
-            const int border = visit_tile<TW, TH, 0, 0, CONN, NT>(P, tx, ty, S, P.counters + C_GEOERR);
+            const int border = visit_tile<TW, TH, 0, 0, CONN, NT, BOUND>(P, tx, ty, S, P.counters + C_GEOERR);
             if (threadIdx.x == 0) atomicAdd(&P.counters[C_TILE_VISITS], 1);
             if (threadIdx.x == 0 && run.pass_visits) atomicAdd(&run.pass_visits[min(pass, kMaxPasses - 1)], 1);
             if (border) {
@@ -531,19 +562,20 @@ constexpr int first_threads(int th) { return th == 16 ? 180 : th == 32 ? 800 : 7
 constexpr int kListTiles = 4096;
 constexpr int kPassGrid = 2048;
 
-template <int TW, int TH, int CONN, int NT, bool LISTED>
+template <int TW, int TH, int CONN, int NT, bool LISTED, bool BOUND = false>
 hipError_t launch_l(const PairDev* d_pairs, const RunDev& run, int passes, hipStream_t s) {
     const int grid = 8 * ((run.total_tiles + 7) / 8);
     const int pgrid = LISTED ? std::min(run.total_tiles, kPassGrid) : grid;
     constexpr int NT0 = first_threads(TH), M0 = first_margin(TH);
-    hipLaunchKernelGGL((k_geo_first<TW, TH, M0, M0, CONN, NT0, LISTED>), dim3(grid), dim3(NT0), 0, s, d_pairs,
-                       run);
+    hipLaunchKernelGGL((k_geo_first<TW, TH, M0, M0, CONN, NT0, LISTED, BOUND>), dim3(grid), dim3(NT0), 0, s,
+                       d_pairs, run);
     for (int p = 1; p < passes; ++p) {
-        hipLaunchKernelGGL((k_geo_pass<TW, TH, CONN, NT, LISTED>), dim3(pgrid), dim3(NT), 0, s, d_pairs, run, p);
+        hipLaunchKernelGGL((k_geo_pass<TW, TH, CONN, NT, LISTED, BOUND>), dim3(pgrid), dim3(NT), 0, s, d_pairs, run,
+                           p);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL((k_geo_finish<TW, TH, CONN, NT>), dim3(1), dim3(NT), 0, s, d_pairs, run, passes);
+    hipLaunchKernelGGL((k_geo_finish<TW, TH, CONN, NT, BOUND>), dim3(1), dim3(NT), 0, s, d_pairs, run, passes);
     return hipGetLastError();
 }
 
@@ -553,6 +585,13 @@ hipError_t launch_t(const PairDev* d_pairs, const RunDev& run, int passes, hipSt
                                         : launch_l<TW, TH, CONN, NT, false>(d_pairs, run, passes, s);
 }
 
+// Bounded transforms (32 x 16 tiles, default threads).
+template <int CONN>
+hipError_t launch_bounded(const PairDev* d_pairs, const RunDev& run, int passes, hipStream_t s) {
+    return run.total_tiles > kListTiles ? launch_l<32, 16, CONN, 256, true, true>(d_pairs, run, passes, s)
+                                        : launch_l<32, 16, CONN, 256, false, true>(d_pairs, run, passes, s);
+}
+
 // Threads per tile: runs of 2 pixels (32 x 16), 8 (32 x 32, 32 x 64)
 constexpr int kThreads16 = 256, kThreads32 = 128, kThreads64 = 256;
 }  // namespace
@@ -560,6 +599,10 @@ constexpr int kThreads16 = 256, kThreads32 = 128, kThreads64 = 256;
 hipError_t launch_geodesic(const PairDev* d_pairs, const RunDev& run, int tile_w, int tile_h, int threads,
                            int passes, hipStream_t s) {
     const bool c8 = run.conn != 4;
+    if (run.bounded) {
+        if (tile_w != 32 || tile_h != 16) return hipErrorInvalidValue;
+        return c8 ? launch_bounded<8>(d_pairs, run, passes, s) : launch_bounded<4>(d_pairs, run, passes, s);
+    }
     if (tile_h == 16 && threads == 128)      // runs of 4 pixels in the later passes
         return c8 ? launch_t<32, 16, 8, 128>(d_pairs, run, passes, s)
                   : launch_t<32, 16, 4, 128>(d_pairs, run, passes, s);

@@ -62,10 +62,17 @@ def test_exact_in_chunks_equals_one_chunk():
     import paper_1501_02565_amd as epic
     sc = random_case(50, 64, 90, seed=85, K=12)
     cost, m = torch.from_numpy(sc.cost).cuda(), torch.from_numpy(sc.matches).cuda()
-    one = 8 * 12 * sc.H * sc.W + sc.N + 4096 + 2 * (1 << 20)
-    per = epic.workspace_bytes(sc.H, sc.W, 1, 1)
+    HW = sc.H * sc.W
+    # the lists, bounds and approximated lists at the workspace's end, the
+    # approximated pass, then room for about 20 single-source transforms at
+    # a time (a pair's bytes: a one-match workspace less the fixed head,
+    # which is what a 1 x 1 workspace nearly is)
+    tail = 8 * sc.K * HW + 4 * HW + sc.N + 8 * sc.N * sc.K + 8192
+    per = epic.workspace_bytes(sc.H, sc.W, 1, 1) - epic.workspace_bytes(1, 1, 1, 1) + 4096
+    small = max(epic.workspace_bytes(sc.H, sc.W, sc.N, sc.K), epic.workspace_bytes(1, 1, 1, 1) + 20 * per) + tail
+    assert 20 * per < sc.N * per                       # several chunks
     outs = []
-    for ws in (256 << 20, one + 7 * per):
+    for ws in (256 << 20, small):
         with epic.Context(0, ws) as c:
             outs.append(c.interp_exact(cost, m, sc.K, sc.a, sc.mode).cpu().numpy())
     assert np.array_equal(outs[0], outs[1])
