@@ -276,6 +276,7 @@ struct DebugOut {
     // the exact interpolation's single-source transforms: per-pixel bound
     // on the distances worth keeping (32 x 16 tiles)
     const float* ubound = nullptr;
+    const int4* clear_boxes = nullptr;   // per pair: what its keys' clearing must reset
 };
 
 // Where a call's descriptor table lives: the context's upload ring (default)
@@ -372,6 +373,9 @@ int run_pairs(epic_ctx* c, const epic_request* reqs, int n, hipStream_t stream, 
         slot_blocks += P.hash_cap / SLOT_BLOCK;
         P.init_block_base = init_blocks;
         P.init_blocks = (int)std::min<long long>(1024, std::max<long long>(1, (std::max<long long>(HW, P.hash_cap) + 1023) / 1024));
+        // bounded single-source runs come 1024 to a call: a few blocks per
+        // pair (each striding over its pair) keep the grid small
+        if (bounded) P.init_blocks = std::min(P.init_blocks, 16);
         init_blocks += P.init_blocks;
         const size_t cap = (size_t)P.hash_cap;
         P.keys = reinterpret_cast<u64*>(take(8 * (size_t)HW));
@@ -396,7 +400,10 @@ int run_pairs(epic_ctx* c, const epic_request* reqs, int n, hipStream_t stream, 
             P.params64 = reinterpret_cast<double*>(take(48 * (size_t)r.N));
         }
         c->last_counters[i] = P.counters;
-        if (bounded) P.ubound = dbg->ubound;
+        if (bounded) {
+            P.ubound = dbg->ubound;
+            if (dbg->clear_boxes) P.clear_box = dbg->clear_boxes + i;
+        }
         if (dbg && i == 0) {
             P.dbg_knn_idx = dbg->knn_idx;
             P.dbg_knn_d = dbg->knn_d;
@@ -671,7 +678,8 @@ int epic_interp_exact(epic_ctx* ctx, const float* cost, int H, int W, const floa
     // per-pixel distance bounds and the approximate K-NN lists they come from
     const size_t lists_b = align_up(8 * (size_t)K * HW), owner_b = align_up((size_t)N);
     const size_t ub_b = align_up(4 * (size_t)HW), knn_b = align_up(4 * (size_t)N * K);
-    const size_t tail = lists_b + owner_b + ub_b + 2 * knn_b + kAlign;
+    const size_t box_b = align_up(16 * (size_t)kExactChunk);
+    const size_t tail = lists_b + owner_b + ub_b + 2 * knn_b + 2 * box_b + kAlign;
     if (tail >= ctx->ws_bytes) return EPIC_ERR_WORKSPACE;
     char* tail_p = ctx->ws + ((ctx->ws_bytes - (tail - kAlign)) & ~(kAlign - 1));
     ExactArgs A{};
@@ -686,6 +694,8 @@ int epic_interp_exact(epic_ctx* ctx, const float* cost, int H, int W, const floa
     A.ubound = reinterpret_cast<float*>(tail_p + lists_b + owner_b);
     A.knn_idx = reinterpret_cast<int*>(tail_p + lists_b + owner_b + ub_b);
     A.knn_d = reinterpret_cast<float*>(tail_p + lists_b + owner_b + ub_b + knn_b);
+    A.boxes = reinterpret_cast<int4*>(tail_p + lists_b + owner_b + ub_b + 2 * knn_b);
+    A.clear_boxes = reinterpret_cast<int4*>(tail_p + lists_b + owner_b + ub_b + 2 * knn_b + box_b);
     A.flow = flow;
     A.a = a;
     A.mode = mode;
@@ -710,7 +720,7 @@ int epic_interp_exact(epic_ctx* ctx, const float* cost, int H, int W, const floa
     const Tiling tl{32, 16};
     const size_t per = pair_bytes(H, W, 1, 0) + kTileArrays * align_up(4 * tiles_of(H, W, tl)) + kAlign;
     if (ctx->ws_bytes < kFixed + tail + per) return EPIC_ERR_WORKSPACE;
-    const int chunk = (int)std::min<size_t>(kMaxPairs, (ctx->ws_bytes - kFixed - tail) / per);
+    const int chunk = (int)std::min<size_t>(std::min(kMaxPairs, kExactChunk), (ctx->ws_bytes - kFixed - tail) / per);
     // generous budget: a single source's distances may cross the whole image
     const int tx = (W + tl.tw - 1) / tl.tw, ty = (H + tl.th - 1) / tl.th;
     DebugOut transform_only;
@@ -718,8 +728,13 @@ int epic_interp_exact(epic_ctx* ctx, const float* cost, int H, int W, const floa
     transform_only.geo_passes = std::min(kMaxPasses - 1, 2 * (tx + ty) + 8);
     transform_only.ubound = A.ubound;
     std::vector<epic_request> reqs;
+    int prev_n = 0;
     for (int s0 = 0; s0 < N; s0 += chunk) {
         const int n = std::min(chunk, N - s0);
+        // a chunk of the previous one's size reuses its workspace layout, so
+        // only the boxes those transforms reached need clearing
+        transform_only.clear_boxes = n == prev_n ? A.clear_boxes : nullptr;
+        prev_n = n;
         reqs.assign(n, epic_request{});
         for (int j = 0; j < n; ++j)
             reqs[j] = epic_request{cost, H, W, matches + 4LL * (s0 + j), 1, 1, a, mode, flow};
@@ -727,6 +742,14 @@ int epic_interp_exact(epic_ctx* ctx, const float* cost, int H, int W, const floa
         if (rc != EPIC_OK) return rc;
         // 3. fold the chunk into every pixel's K nearest
         if (launch_exact_select(ctx->last_desc, n, s0, s0 == 0, A, st) != hipSuccess) return EPIC_ERR_HIP;
+        if (s0 == 0 && chunk < N && ctx->h_passes_used) {
+            // the later chunks launch the passes the first one needed, and a
+            // few more (their sources are alike; the finisher completes any
+            // transform that needs more, so the budget never changes results)
+            if (hipStreamSynchronize(st) != hipSuccess) return EPIC_ERR_HIP;
+            const int used = reinterpret_cast<volatile int*>(ctx->h_passes_used)[0];
+            if (used > 0) transform_only.geo_passes = std::min(transform_only.geo_passes, used + used / 2 + 4);
+        }
     }
     // 4. one fit per pixel
     if (launch_exact_fit(A, st) != hipSuccess) return EPIC_ERR_HIP;

@@ -52,7 +52,13 @@ enum Counter {
     C_DUP0 = 14,
     C_STATUS0 = 15,
     C_INVARIANT = 16,  // debug_validate: violated invariants of the transform and graph
-    C_NCOUNTERS = 17
+    // bounded transforms: the tiles a pair's distances reached, as a box
+    // (0 = none): (1 << 24) - least tile x / y, 1 + greatest tile x / y
+    C_BX0 = 17,
+    C_BY0 = 18,
+    C_BX1 = 19,
+    C_BY1 = 20,
+    C_NCOUNTERS = 21
 };
 
 // Everything a kernel needs about one image pair.  Kernels of a batch launch
@@ -106,6 +112,9 @@ struct PairDev {
     // exact interpolation: per-pixel bound on the distances worth keeping in
     // a single-source transform (null: none)
     const float* ubound;    // H*W
+    // bounded runs: the only pixels whose keys the clearing must reset (the
+    // box the pair that last used this workspace reached; null = all)
+    const int4* clear_box;
     float* matches_kept;    // N*4
     int* kept_idx;          // N
     // optional stage dumps (NULL = off)
@@ -320,6 +329,9 @@ struct ExactArgs {
     float* ubound;          // H*W: bound on the distance of the pixel's K-th nearest match
     int* knn_idx;           // N*K: the approximated K-NN lists the bound comes from
     float* knn_d;           // N*K
+    int4* boxes;            // per source of a chunk: the pixel box its transform reached
+                            //   (empty for sources that hold no pixel)
+    int4* clear_boxes;      // the same for every source (what the next chunk must clear)
     float* flow;            // H*W*2
     float a;
     int mode, wpow;
@@ -331,6 +343,7 @@ hipError_t launch_exact_select(const PairDev* chunk, int nsrc, int src0, int fir
                                hipStream_t s);
 hipError_t launch_exact_fit(const ExactArgs& A, hipStream_t s);
 hipError_t launch_exact_bound(const PairDev* full, const ExactArgs& A, hipStream_t s);
+constexpr int kExactChunk = 1024;   // sources per chunk of the exact interpolation, at most
 hipError_t launch_image_cost(const ImageCostArgs& args, int channels, int total_blocks, hipStream_t s);
 hipError_t launch_check_transform(const PairDev* d_pairs, const RunDev& run, int pix_blocks, int plant,
                                   hipStream_t s);

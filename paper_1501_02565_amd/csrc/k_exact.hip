@@ -50,15 +50,39 @@ __global__ __launch_bounds__(256) void k_exact_owner(const PairDev* __restrict__
     A.owner[m] = (sp >= 0 && key_label(P.keys[sp]) == (u32)m) ? 1 : 0;
 }
 
+// The pixel box each source of a chunk reached (its bounded transform
+// recorded the tiles): for the selection (sources that hold no pixel count
+// as reaching nothing) and for the next chunk's clearing of the same
+// workspace; empty boxes have x0 > x1.
+__global__ __launch_bounds__(256) void k_exact_boxes(const PairDev* __restrict__ chunk, int nsrc, int src0,
+                                                     ExactArgs A) {
+    const int j = (int)(blockIdx.x * 256 + threadIdx.x);
+    if (j >= nsrc) return;
+    const int* c = chunk[j].counters;
+    int4 b = make_int4(0x7fffffff, 0, -1, -1);
+    if (c[C_BX1] > 0) {
+        b.x = ((1 << 24) - c[C_BX0]) * 32;
+        b.y = ((1 << 24) - c[C_BY0]) * 16;
+        b.z = min((c[C_BX1] - 1) * 32 + 31, A.W - 1);
+        b.w = min((c[C_BY1] - 1) * 16 + 15, A.H - 1);
+    }
+    A.clear_boxes[j] = b;
+    if (A.owner[src0 + j] == 0) b = make_int4(0x7fffffff, 0, -1, -1);
+    A.boxes[j] = b;
+}
+
 // One wavefront per 64 consecutive pixels (a pixel per lane); each lane's
 // sorted list of at most K (<= 128) keys lives in LDS, entry k of lane l at
-// [k * 64 + l] (consecutive lanes, consecutive words; 64 KiB at K = 128).  Sources come in
+// [k * 64 + l] (consecutive lanes, consecutive words; 64 KiB at K = 128).
+// The wavefront first lists the chunk's sources whose box meets its pixels
+// (in index order), then reads only their distances; sources come in
 // increasing index order, so equal distances keep the lower index first.
 __global__ __launch_bounds__(64) void k_exact_select(const PairDev* __restrict__ chunk, int nsrc, int src0,
                                                      int first, ExactArgs A) {
     extern __shared__ u64 L[];
+    unsigned short* hits = reinterpret_cast<unsigned short*>(L + (size_t)A.K * 64);   // up to kExactChunk
     const int lane = threadIdx.x;
-    const long long p = (long long)blockIdx.x * 64 + lane;
+    const long long p0 = (long long)blockIdx.x * 64, p = p0 + lane;
     const bool valid = p < A.HW;
     const int K = A.K;
     int cnt = 0;
@@ -67,20 +91,38 @@ __global__ __launch_bounds__(64) void k_exact_select(const PairDev* __restrict__
         L[k * 64 + lane] = v;
         cnt += v != ~0ull ? 1 : 0;
     }
-    // sources in groups of 8 with all their loads in flight together
+    // the wavefront's pixels: rows ya..yb, columns xa..xb (all of them when
+    // the run wraps a row)
+    const long long pe = min(p0 + 63, A.HW - 1);
+    const int ya = (int)(p0 / A.W), yb = (int)(pe / A.W);
+    const int xa = ya == yb ? (int)(p0 % A.W) : 0, xb = ya == yb ? (int)(pe % A.W) : A.W - 1;
+    int nh = 0;
+    for (int j0 = 0; j0 < nsrc; j0 += 64) {
+        const int j = j0 + lane;
+        bool hit = false;
+        if (j < nsrc) {
+            const int4 b = A.boxes[j];
+            hit = b.x <= xb && b.z >= xa && b.y <= yb && b.w >= ya;
+        }
+        const u64 m = wave::ballot(hit);
+        if (hit) hits[nh + wave::lanes_below(m)] = (unsigned short)j;
+        nh += __popcll(m);
+    }
+    __syncthreads();
+    // the listed sources in groups of 8 with all their loads in flight together
     constexpr int G = 8;
-    for (int j0 = 0; j0 < nsrc; j0 += G) {
+    for (int h0 = 0; h0 < nh; h0 += G) {
         float d[G];
+        int jj[G];
 #pragma unroll
         for (int u = 0; u < G; ++u) {
-            const int j = j0 + u;
-            const bool use = j < nsrc && A.owner[src0 + j] != 0;          // uniform
-            d[u] = (use && valid) ? key_dist(gmem(chunk[j].keys)[p]) : __int_as_float(0x7f800000);
+            jj[u] = h0 + u < nh ? hits[h0 + u] : -1;                        // uniform
+            d[u] = (jj[u] >= 0 && valid) ? key_dist(gmem(chunk[jj[u]].keys)[p]) : __int_as_float(0x7f800000);
         }
 #pragma unroll
         for (int u = 0; u < G; ++u) {
             if (!(d[u] < __int_as_float(0x7f800000))) continue;
-            const u64 key = ((u64)__float_as_uint(d[u]) << 32) | (u32)(src0 + j0 + u);
+            const u64 key = ((u64)__float_as_uint(d[u]) << 32) | (u32)(src0 + jj[u]);
             if (cnt == K && !(key < L[(K - 1) * 64 + lane])) continue;
             int i = cnt < K ? cnt : K - 1;
             while (i > 0 && L[(i - 1) * 64 + lane] > key) {
@@ -141,7 +183,9 @@ hipError_t launch_exact_owner(const PairDev* full, const ExactArgs& A, hipStream
 
 hipError_t launch_exact_select(const PairDev* chunk, int nsrc, int src0, int first, const ExactArgs& A,
                                hipStream_t s) {
-    const size_t lds = (size_t)A.K * 64 * sizeof(u64);
+    if (nsrc > kExactChunk) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_exact_boxes, dim3((unsigned)((nsrc + 255) / 256)), dim3(256), 0, s, chunk, nsrc, src0, A);
+    const size_t lds = (size_t)A.K * 64 * sizeof(u64) + (size_t)kExactChunk * sizeof(unsigned short);
     hipLaunchKernelGGL(k_exact_select, dim3((unsigned)((A.HW + 63) / 64)), dim3(64), lds, s, chunk, nsrc, src0,
                        first, A);
     return hipGetLastError();

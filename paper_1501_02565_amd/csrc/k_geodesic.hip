@@ -67,7 +67,8 @@ __device__ __forceinline__ double tree_min(double (&c)[N], int n) {
     return c[0];
 }
 
-enum : int { B_L = 1, B_R = 2, B_T = 4, B_B = 8, B_TL = 16, B_TR = 32, B_BL = 64, B_BR = 128, B_SELF = 256 };
+enum : int { B_L = 1, B_R = 2, B_T = 4, B_B = 8, B_TL = 16, B_TR = 32, B_BL = 64, B_BR = 128, B_SELF = 256,
+             B_REACHED = 512 };
 
 template <int TW, int TH>
 struct TileLds {
@@ -331,6 +332,10 @@ __device__ __forceinline__ int visit_tile(const PairDev& P, int tx, int ty,
     for (int j = 0; j < PPT; ++j) {
         const int lx = hx + j - MX, ly = hy - MY;          // tile coordinates
         const u64 k = S.key[(hy + 1) * LW + hx + j + 1];
+        if constexpr (BOUND) {
+            if (lx >= 0 && ly >= 0 && lx < twe && ly < the && key_dist(k) < __int_as_float(0x7f800000))
+                bm |= B_REACHED;
+        }
         if (lx >= 0 && ly >= 0 && lx < twe && ly < the && k != orig[j]) {
             dev_st(P.keys + (long long)(y0 + ly) * W + x0 + lx, k);
             const bool l = lx == 0, r = lx == twe - 1, t = ly == 0, b = ly == the - 1;
@@ -365,8 +370,18 @@ __device__ __forceinline__ int visit_tile(const PairDev& P, int tx, int ty,
     }
     if (bm) atomicOr(&S.border, bm);
     __syncthreads();
-    const int border = S.border | (unconverged ? B_SELF : 0);
+    int border = S.border | (unconverged ? B_SELF : 0);
     __syncthreads();
+    if constexpr (BOUND) {
+        // the box of tiles this pair's distances reached
+        if ((border & B_REACHED) && tid == 0) {
+            atomicMax(&P.counters[C_BX0], (1 << 24) - tx);
+            atomicMax(&P.counters[C_BY0], (1 << 24) - ty);
+            atomicMax(&P.counters[C_BX1], 1 + tx);
+            atomicMax(&P.counters[C_BY1], 1 + ty);
+        }
+        border &= ~B_REACHED;
+    }
     return border;
 }
 
@@ -463,24 +478,51 @@ __global__ __launch_bounds__(NT) void k_geo_pass(const PairDev* __restrict__ pai
 
 // The first pass: every tile, relaxed over the tile and a margin of MX
 // columns and MY rows around it (seeds from the start, written by k_seed).
+// Bounded (single-source) transforms launch one block per pair instead,
+// which visits the tiles holding the pair's seeds; the others are reached
+// through the marks of later passes.
 template <int TW, int TH, int MX, int MY, int CONN, int NT, bool LISTED, bool BOUND = false>
 __global__ __launch_bounds__(NT) void k_geo_first(const PairDev* __restrict__ pairs, RunDev run) {
     __shared__ TileLdsT<TW + 2 * MX, TH + 2 * MY, BOUND> S;
-    const int per_xcd = (run.total_tiles + 7) / 8;
-    const int tile = (int)(blockIdx.x % 8) * per_xcd + (int)(blockIdx.x / 8);
-    if (tile >= run.total_tiles) return;
-    const int p = find_pair(run.npairs, tile, [&](int i) { return pairs[i].tile_base; });
-    const PairDev& P = pairs[p];
-    const int lt = tile - P.tile_base;
-    const int tx = lt % P.tiles_x, ty = lt / P.tiles_x;
-    if (threadIdx.x == 0) run.dirty[0][tile] = 0u;           // reused by pass 2
-    const int border = visit_tile<TW, TH, MX, MY, CONN, NT, BOUND>(P, tx, ty, S, P.counters + C_GEOERR,
-                                                                   kFirstRounds);
-    if (threadIdx.x == 0) atomicAdd(&P.counters[C_TILE_VISITS], 1);
-    if (threadIdx.x == 0 && run.pass_visits) atomicAdd(&run.pass_visits[0], 1);
-    if (border) {
-        mark_neighbours<CONN, LISTED>(P, run, tx, ty, border, 1);
-        if (threadIdx.x == 0) run.any[0] = 1;
+    if constexpr (BOUND) {
+        const PairDev& P = pairs[blockIdx.x];
+        for (int m = 0; m < P.N; ++m) {
+            const int sp = P.seed_pix[m];
+            if (sp < 0) continue;
+            const int tile = P.tile_base + (sp / P.W / TH) * P.tiles_x + (sp % P.W) / TW;
+            __syncthreads();                                     // the previous visit is done
+            if (run.dirty[0][tile] == 0u) continue;              // (uniform) visited already
+            __syncthreads();                                     // every thread has read the flag
+            const int lt = tile - P.tile_base;
+            const int tx = lt % P.tiles_x, ty = lt / P.tiles_x;
+            if (threadIdx.x == 0) run.dirty[0][tile] = 0u;
+            const int border = visit_tile<TW, TH, MX, MY, CONN, NT, BOUND>(P, tx, ty, S, P.counters + C_GEOERR,
+                                                                           kFirstRounds);
+            if (threadIdx.x == 0) atomicAdd(&P.counters[C_TILE_VISITS], 1);
+            if (threadIdx.x == 0 && run.pass_visits) atomicAdd(&run.pass_visits[0], 1);
+            if (border) {
+                mark_neighbours<CONN, LISTED>(P, run, tx, ty, border, 1);
+                if (threadIdx.x == 0) run.any[0] = 1;
+            }
+        }
+        return;
+    } else {
+        const int per_xcd = (run.total_tiles + 7) / 8;
+        const int tile = (int)(blockIdx.x % 8) * per_xcd + (int)(blockIdx.x / 8);
+        if (tile >= run.total_tiles) return;
+        const int p = find_pair(run.npairs, tile, [&](int i) { return pairs[i].tile_base; });
+        const PairDev& P = pairs[p];
+        const int lt = tile - P.tile_base;
+        const int tx = lt % P.tiles_x, ty = lt / P.tiles_x;
+        if (threadIdx.x == 0) run.dirty[0][tile] = 0u;           // reused by pass 2
+        const int border = visit_tile<TW, TH, MX, MY, CONN, NT, BOUND>(P, tx, ty, S, P.counters + C_GEOERR,
+                                                                       kFirstRounds);
+        if (threadIdx.x == 0) atomicAdd(&P.counters[C_TILE_VISITS], 1);
+        if (threadIdx.x == 0 && run.pass_visits) atomicAdd(&run.pass_visits[0], 1);
+        if (border) {
+            mark_neighbours<CONN, LISTED>(P, run, tx, ty, border, 1);
+            if (threadIdx.x == 0) run.any[0] = 1;
+        }
     }
 }
 
@@ -567,8 +609,8 @@ hipError_t launch_l(const PairDev* d_pairs, const RunDev& run, int passes, hipSt
     const int grid = 8 * ((run.total_tiles + 7) / 8);
     const int pgrid = LISTED ? std::min(run.total_tiles, kPassGrid) : grid;
     constexpr int NT0 = first_threads(TH), M0 = first_margin(TH);
-    hipLaunchKernelGGL((k_geo_first<TW, TH, M0, M0, CONN, NT0, LISTED, BOUND>), dim3(grid), dim3(NT0), 0, s,
-                       d_pairs, run);
+    hipLaunchKernelGGL((k_geo_first<TW, TH, M0, M0, CONN, NT0, LISTED, BOUND>), dim3(BOUND ? run.npairs : grid),
+                       dim3(NT0), 0, s, d_pairs, run);
     for (int p = 1; p < passes; ++p) {
         hipLaunchKernelGGL((k_geo_pass<TW, TH, CONN, NT, LISTED, BOUND>), dim3(pgrid), dim3(NT), 0, s, d_pairs, run,
                            p);

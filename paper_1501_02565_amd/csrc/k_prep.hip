@@ -32,9 +32,21 @@ __global__ __launch_bounds__(256) void k_clear(PairDev* __restrict__ pairs, RunD
     const long long i0 = (long long)lb * blockDim.x + threadIdx.x;
     const long long HW = (long long)P.H * P.W;
     const bool f64 = run.precision == 1;
-    for (long long i = i0; i < HW; i += stride) {
-        P.keys[i] = f64 ? DOUBLE_INF_BITS : KEY_INF;
-        if (f64) P.labels[i] = NO_LABEL;
+    if (P.clear_box) {
+        // a bounded single-source run: only the box the previous user of
+        // this workspace reached holds other values than infinity
+        const int4 b = *P.clear_box;
+        if (b.x <= b.z) {
+            const int bw = b.z - b.x + 1;
+            const long long nb = (long long)bw * (b.w - b.y + 1);
+            for (long long i = i0; i < nb; i += stride)
+                P.keys[(long long)(b.y + (int)(i / bw)) * P.W + b.x + (int)(i % bw)] = KEY_INF;
+        }
+    } else {
+        for (long long i = i0; i < HW; i += stride) {
+            P.keys[i] = f64 ? DOUBLE_INF_BITS : KEY_INF;
+            if (f64) P.labels[i] = NO_LABEL;
+        }
     }
     for (long long i = i0; i < P.hash_cap; i += stride) {
         P.hkey[i] = HASH_EMPTY;
