@@ -741,7 +741,8 @@ int epic_interp_exact(epic_ctx* ctx, const float* cost, int H, int W, const floa
         rc = run_pairs(ctx, reqs.data(), n, st, &transform_only, nullptr, tail);
         if (rc != EPIC_OK) return rc;
         // 3. fold the chunk into every pixel's K nearest
-        if (launch_exact_select(ctx->last_desc, n, s0, s0 == 0, A, st) != hipSuccess) return EPIC_ERR_HIP;
+        if (launch_exact_select(ctx->last_desc, n, s0, s0 == 0, s0 + n == N, A, st) != hipSuccess)
+            return EPIC_ERR_HIP;
         if (s0 == 0 && chunk < N && ctx->h_passes_used) {
             // the later chunks launch the passes the first one needed, and a
             // few more (their sources are alike; the finisher completes any

@@ -339,7 +339,7 @@ struct ExactArgs {
     double deg_tau;
 };
 hipError_t launch_exact_owner(const PairDev* full, const ExactArgs& A, hipStream_t s);
-hipError_t launch_exact_select(const PairDev* chunk, int nsrc, int src0, int first, const ExactArgs& A,
+hipError_t launch_exact_select(const PairDev* chunk, int nsrc, int src0, int first, int last, const ExactArgs& A,
                                hipStream_t s);
 hipError_t launch_exact_fit(const ExactArgs& A, hipStream_t s);
 hipError_t launch_exact_bound(const PairDev* full, const ExactArgs& A, hipStream_t s);

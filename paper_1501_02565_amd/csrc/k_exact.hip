@@ -71,25 +71,28 @@ __global__ __launch_bounds__(256) void k_exact_boxes(const PairDev* __restrict__
     A.boxes[j] = b;
 }
 
-// One wavefront per 64 consecutive pixels (a pixel per lane); each lane's
-// sorted list of at most K (<= 128) keys lives in LDS, entry k of lane l at
-// [k * 64 + l] (consecutive lanes, consecutive words; 64 KiB at K = 128).
-// The wavefront first lists the chunk's sources whose box meets its pixels
-// (in index order), then reads only their distances; sources come in
-// increasing index order, so equal distances keep the lower index first.
+// One wavefront per 64 consecutive pixels (a pixel per lane); each lane
+// keeps its K smallest (distance bits << 32 | match) keys as a max-heap in
+// LDS, entry k of lane l at [k * 64 + l] (consecutive lanes, consecutive
+// words; 64 KiB at K = 128), held in the workspace between chunks in heap
+// order and sorted ascending by the last chunk (keys are distinct, so the
+// K smallest and their order are the (distance, index) order whatever the
+// heap's shape).  The wavefront first lists the chunk's sources whose box
+// meets its pixels, then reads only their distances.
 __global__ __launch_bounds__(64) void k_exact_select(const PairDev* __restrict__ chunk, int nsrc, int src0,
-                                                     int first, ExactArgs A) {
+                                                     int first, int last, ExactArgs A) {
     extern __shared__ u64 L[];
     unsigned short* hits = reinterpret_cast<unsigned short*>(L + (size_t)A.K * 64);   // up to kExactChunk
     const int lane = threadIdx.x;
     const long long p0 = (long long)blockIdx.x * 64, p = p0 + lane;
     const bool valid = p < A.HW;
     const int K = A.K;
+    auto H = [&](int k) -> u64& { return L[k * 64 + lane]; };
     int cnt = 0;
     for (int k = 0; k < K; ++k) {
         const u64 v = (!first && valid) ? gmem(A.lists)[(long long)k * A.HW + p] : ~0ull;
-        L[k * 64 + lane] = v;
-        cnt += v != ~0ull ? 1 : 0;
+        H(k) = v;
+        cnt += v != ~0ull ? 1 : 0;          // the heap fills [0, cnt)
     }
     // the wavefront's pixels: rows ya..yb, columns xa..xb (all of them when
     // the run wraps a row)
@@ -123,18 +126,67 @@ __global__ __launch_bounds__(64) void k_exact_select(const PairDev* __restrict__
         for (int u = 0; u < G; ++u) {
             if (!(d[u] < __int_as_float(0x7f800000))) continue;
             const u64 key = ((u64)__float_as_uint(d[u]) << 32) | (u32)(src0 + jj[u]);
-            if (cnt == K && !(key < L[(K - 1) * 64 + lane])) continue;
-            int i = cnt < K ? cnt : K - 1;
-            while (i > 0 && L[(i - 1) * 64 + lane] > key) {
-                L[i * 64 + lane] = L[(i - 1) * 64 + lane];
-                --i;
+            if (cnt < K) {
+                // append and sift up
+                int i = cnt++;
+                while (i > 0) {
+                    const int up = (i - 1) >> 1;
+                    const u64 pv = H(up);
+                    if (!(pv < key)) break;
+                    H(i) = pv;
+                    i = up;
+                }
+                H(i) = key;
+            } else if (key < H(0)) {
+                // replace the largest and sift down
+                int i = 0;
+                for (;;) {
+                    const int l = 2 * i + 1;
+                    if (l >= K) break;
+                    int c = l;
+                    u64 cv = H(l);
+                    if (l + 1 < K) {
+                        const u64 rv = H(l + 1);
+                        if (rv > cv) {
+                            c = l + 1;
+                            cv = rv;
+                        }
+                    }
+                    if (!(cv > key)) break;
+                    H(i) = cv;
+                    i = c;
+                }
+                H(i) = key;
             }
-            L[i * 64 + lane] = key;
-            if (cnt < K) ++cnt;
+        }
+    }
+    if (last) {
+        // heapsort into ascending order
+        for (int end = cnt - 1; end > 0; --end) {
+            const u64 top = H(0), key = H(end);
+            H(end) = top;
+            int i = 0;
+            for (;;) {
+                const int l = 2 * i + 1;
+                if (l >= end) break;
+                int c = l;
+                u64 cv = H(l);
+                if (l + 1 < end) {
+                    const u64 rv = H(l + 1);
+                    if (rv > cv) {
+                        c = l + 1;
+                        cv = rv;
+                    }
+                }
+                if (!(cv > key)) break;
+                H(i) = cv;
+                i = c;
+            }
+            H(i) = key;
         }
     }
     if (valid)
-        for (int k = 0; k < K; ++k) gmem(A.lists)[(long long)k * A.HW + p] = L[k * 64 + lane];
+        for (int k = 0; k < K; ++k) gmem(A.lists)[(long long)k * A.HW + p] = H(k);
 }
 
 // One wavefront per pixel: its list, two entries per lane at most, the
@@ -181,13 +233,13 @@ hipError_t launch_exact_owner(const PairDev* full, const ExactArgs& A, hipStream
     return hipGetLastError();
 }
 
-hipError_t launch_exact_select(const PairDev* chunk, int nsrc, int src0, int first, const ExactArgs& A,
+hipError_t launch_exact_select(const PairDev* chunk, int nsrc, int src0, int first, int last, const ExactArgs& A,
                                hipStream_t s) {
     if (nsrc > kExactChunk) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_exact_boxes, dim3((unsigned)((nsrc + 255) / 256)), dim3(256), 0, s, chunk, nsrc, src0, A);
     const size_t lds = (size_t)A.K * 64 * sizeof(u64) + (size_t)kExactChunk * sizeof(unsigned short);
     hipLaunchKernelGGL(k_exact_select, dim3((unsigned)((A.HW + 63) / 64)), dim3(64), lds, s, chunk, nsrc, src0,
-                       first, A);
+                       first, last, A);
     return hipGetLastError();
 }
 
