@@ -305,8 +305,9 @@ int epic_interp_image(epic_ctx* ctx, const float* image, int H, int W, int chann
  * is the same as with full-image transforms.
  * Arguments as in epic_interp, with K <= 128 and a context created with
  * precision 0 (EPIC_ERR_ARG otherwise).  The workspace must hold
- * 8*K*H*W + 4*H*W + N + 8*N*K bytes (plus 2 KB of alignment) at its end
- * for the pixels' lists, the bounds and the approximated lists, besides
+ * 8*K*H*W + 4*H*W + N + 8*N*K bytes plus 34 KB at its end for the
+ * pixels' lists, the bounds, the approximated lists, the boxes of tiles a
+ * chunk's transforms reached and alignment, besides
  * epic_workspace_bytes(H, W, N, K, mode, 0) for the approximated pass and,
  * per match of a chunk, epic_workspace_bytes(H, W, 1, 1, mode, 0)
  * (EPIC_ERR_WORKSPACE when not even one fits); a chunk of 1024 at

@@ -63,11 +63,11 @@ def test_exact_in_chunks_equals_one_chunk():
     sc = random_case(50, 64, 90, seed=85, K=12)
     cost, m = torch.from_numpy(sc.cost).cuda(), torch.from_numpy(sc.matches).cuda()
     HW = sc.H * sc.W
-    # the lists, bounds and approximated lists at the workspace's end, the
+    # the lists, bounds, approximated lists and boxes at the workspace's end, the
     # approximated pass, then room for about 20 single-source transforms at
     # a time (a pair's bytes: a one-match workspace less the fixed head,
     # which is what a 1 x 1 workspace nearly is)
-    tail = 8 * sc.K * HW + 4 * HW + sc.N + 8 * sc.N * sc.K + 8192
+    tail = 8 * sc.K * HW + 4 * HW + sc.N + 8 * sc.N * sc.K + (36 << 10)
     per = epic.workspace_bytes(sc.H, sc.W, 1, 1) - epic.workspace_bytes(1, 1, 1, 1) + 4096
     small = max(epic.workspace_bytes(sc.H, sc.W, sc.N, sc.K), epic.workspace_bytes(1, 1, 1, 1) + 20 * per) + tail
     assert 20 * per < sc.N * per                       # several chunks
