@@ -64,9 +64,12 @@ struct KnnLds {
     static constexpr int TW = 64;                 // edges per relaxation window (one per lane)
     using DT = typename std::conditional<F64, u64, u32>::type;     // distance bits
     using RT = typename std::conditional<F64, double, float>::type;
-    alignas(16) DT dm[2 * VCAP];  // entry e: tentative distance (2e), lightest edge (2e + 1)
-    uint2 rd[VCAP];               // entry e: CSR start, degree
-    int node[VCAP];
+    // entry e: tentative distance (2e) and lightest incident edge (2e + 1);
+    // FP32 packs the edge's high 16 float bits over the degree (low 16 bits),
+    // the CSR record's own word
+    alignas(16) DT dm[2 * VCAP];
+    // entry e: CSR start (FP64: and degree); after the search, the entry's node
+    u32 rd[F64 ? 2 * VCAP : VCAP];
     u64 buf[VCAP];                // node table (HCAP ints) during the search, sort keys after
     int snode[F64 ? VCAP : 1];    // FP64: node of each sort key
     unsigned short hidx[HCAP];    // node table slot -> entry
@@ -170,19 +173,28 @@ __device__ __forceinline__ bool knn_fit_one(const PairDev& P, const RunDev& run,
     EPIC_GLOBAL float* prm = gmem(P.params) + 6LL * s;
     // the match's own row, fetched now so that its latency hides behind the search
     const float4 me = gload(reinterpret_cast<const float4*>(P.matches) + s);
+    // read once: the LDS ordering points below would make the compiler
+    // reload it from the descriptor at every window
+    const uint4* const adj = P.adj;
 
     // ------------------------------------------------------------ Dijkstra
     for (int i = lane; i < HCAP; i += 64) htab[i] = -1;
     for (int i = lane; i < TW; i += 64) S.head[i] = 0u;
     for (int i = lane; i < 2 * VCAP; i += 64) S.dm[i] = to_bits<F64>(RINF);
-    for (int i = lane; i < VCAP; i += 64) S.rd[i] = make_uint2(0u, 0u);
+    for (int i = lane; i < (F64 ? 2 * VCAP : VCAP); i += 64) S.rd[i] = 0u;
     __syncthreads();
     if (lane == 0) {
         const u32 a = gmem(P.row_ptr)[s], b = gmem(P.row_ptr)[s + 1];
         S.dm[0] = 0;
-        if constexpr (F64) S.dm[1] = gmem(P.minin64)[s]; else S.dm[1] = gmem(P.minin)[s];
-        S.rd[0] = make_uint2(a, b - a);
-        S.node[0] = s;
+        if constexpr (F64) {
+            S.dm[1] = gmem(P.minin64)[s];
+            S.rd[0] = a;
+            S.rd[1] = b - a;
+        } else {
+            // (a degree above 16 bits stops the pair before this kernel)
+            S.dm[1] = (gmem(P.minin)[s] & 0xffff0000u) | (b - a);
+            S.rd[0] = a;
+        }
         const u32 h = node_slot(s, HBITS);
         htab[h] = s;
         S.hidx[h] = 0;
@@ -202,12 +214,12 @@ __device__ __forceinline__ bool knn_fit_one(const PairDev& P, const RunDev& run,
     // entry lane + 64 r, kept across steps as loaded
     using DT2 = typename std::conditional<F64, ulonglong2, uint2>::type;
     DT2 dmr[R];
-    uint2 rdv[R];
+    u32 deg[R];
     RT d[R], mi[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         dmr[r].x = dmr[r].y = to_bits<F64>(RINF);
-        rdv[r] = make_uint2(0u, 0u);
+        deg[r] = 0u;
     }
     RT dstop = RINF;
     for (;;) {
@@ -226,10 +238,15 @@ __device__ __forceinline__ bool knn_fit_one(const PairDev& P, const RunDev& run,
             if (r < ru) {
                 const int e = lane + 64 * r;
                 dmr[r] = *reinterpret_cast<const DT2*>(&S.dm[2 * e]);
-                rdv[r] = S.rd[e];
+                if constexpr (F64) deg[r] = S.rd[2 * e + 1];
             }
             d[r] = from_bits<F64>(dmr[r].x);
-            mi[r] = from_bits<F64>(dmr[r].y);
+            if constexpr (F64) {
+                mi[r] = from_bits<F64>(dmr[r].y);
+            } else {
+                mi[r] = __uint_as_float(dmr[r].y & 0xffff0000u);
+                deg[r] = dmr[r].y & 0xffffu;
+            }
         }
         // frontier minimum (entries not in use are infinite)
         RT fmin = RINF;
@@ -265,7 +282,7 @@ __device__ __forceinline__ bool knn_fit_one(const PairDev& P, const RunDev& run,
             newly[r] = wave::ballot(d[r] <= dmin + mi[r]) & valid & ~smask[r];
             nsettled += __popcll(newly[r]);
             smask[r] |= newly[r];
-            if (__builtin_amdgcn_inverse_ballot_w64(newly[r])) my_edges += (int)rdv[r].y;
+            if (__builtin_amdgcn_inverse_ballot_w64(newly[r])) my_edges += (int)deg[r];
         }
         const int incl = wave::incl_scan(my_edges);
         const int T = __builtin_amdgcn_readlane(incl, 63);
@@ -275,7 +292,7 @@ __device__ __forceinline__ bool knn_fit_one(const PairDev& P, const RunDev& run,
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 off[r] = o;
-                if (r < ru && __builtin_amdgcn_inverse_ballot_w64(newly[r])) o += (int)rdv[r].y;
+                if (r < ru && __builtin_amdgcn_inverse_ballot_w64(newly[r])) o += (int)deg[r];
             }
         }
         int carry_start = 0, carry_e = 0;
@@ -291,7 +308,7 @@ __device__ __forceinline__ bool knn_fit_one(const PairDev& P, const RunDev& run,
             const u32 stamp_hi = (u32)stamp << 12;
 #pragma unroll
             for (int r = 0; r < R; ++r)
-                if (r < ru && __builtin_amdgcn_inverse_ballot_w64(newly[r]) && rdv[r].y > 0u && off[r] >= wb &&
+                if (r < ru && __builtin_amdgcn_inverse_ballot_w64(newly[r]) && deg[r] > 0u && off[r] >= wb &&
                     off[r] < wb + TW)
                     S.head[off[r] - wb] = stamp_hi | (u32)(lane + 64 * r + 1);
             lds_order();
@@ -328,14 +345,14 @@ __device__ __forceinline__ bool knn_fit_one(const PairDev& P, const RunDev& run,
             for (int q = 0; q < Q; ++q) {
                 RT unused;
                 read_dm<VCAP, F64>(S, qe[q], du[q], unused);
-                const uint2 rr = S.rd[qe[q]];
-                ei[q] = act[q] ? rr.x + (u32)(wb + 64 * q + lane - qst[q]) : 0u;
+                const u32 st = S.rd[F64 ? 2 * qe[q] : qe[q]];
+                ei[q] = act[q] ? st + (u32)(wb + 64 * q + lane - qst[q]) : 0u;
             }
             uint4 rec[Q];
             RT cand[Q], nbm[Q];
 #pragma unroll
             for (int q = 0; q < Q; ++q) {
-                rec[q] = gload(P.adj + ei[q]);
+                rec[q] = gload(adj + ei[q]);
                 if constexpr (F64) {
                     cand[q] = du[q] + gmem(P.adjw64)[ei[q]];
                     nbm[q] = dbits(gmem(P.nbmin64)[ei[q]]);
@@ -345,7 +362,6 @@ __device__ __forceinline__ bool knn_fit_one(const PairDev& P, const RunDev& run,
                     // test needs
                     cand[q] = du[q] + __uint_as_float(rec[q].y);
                     nbm[q] = __uint_as_float(rec[q].w & 0xffff0000u);
-                    rec[q].w &= 0xffffu;
                 }
             }
             // find or claim each neighbour's table slot with one
@@ -394,9 +410,14 @@ __device__ __forceinline__ bool knn_fit_one(const PairDev& P, const RunDev& run,
                     const u32 hs = (res[q] & (RES_WON - 1u)) - 1u;
                     if (e < VCAP) {
                         S.dm[2 * e] = to_bits<F64>(cand[q]);
-                        S.dm[2 * e + 1] = to_bits<F64>(nbm[q]);
-                        S.rd[e] = make_uint2(rec[q].z, rec[q].w);
-                        S.node[e] = (int)rec[q].x;
+                        if constexpr (F64) {
+                            S.dm[2 * e + 1] = to_bits<F64>(nbm[q]);
+                            S.rd[2 * e] = rec[q].z;
+                            S.rd[2 * e + 1] = rec[q].w;
+                        } else {
+                            S.dm[2 * e + 1] = rec[q].w;        // lightest edge bits over the degree
+                            S.rd[e] = rec[q].z;
+                        }
                         S.hidx[hs] = (unsigned short)e;
                     } else {
                         S.hidx[hs] = 0xffff;
@@ -423,6 +444,15 @@ __device__ __forceinline__ bool knn_fit_one(const PairDev& P, const RunDev& run,
     // Candidates: settled entries strictly below dstop, sorted in LDS: FP32
     // as packed (distance bits, index) words, FP64 as (distance bits, index)
     // pairs held in two arrays.
+    // each entry's node, from the node table (slot -> node, slot -> entry),
+    // into the CSR array, which the search no longer needs
+    int* const node_of = reinterpret_cast<int*>(S.rd);
+    __syncthreads();
+    for (int h = lane; h < HCAP; h += 64) {
+        const int v = htab[h];
+        const int e = S.hidx[h];
+        if (v >= 0 && e < VCAP) node_of[e] = v;
+    }
     __syncthreads();                 // the node table (aliasing buf) is dead from here
     int nc = 0;
 #pragma unroll
@@ -435,9 +465,9 @@ __device__ __forceinline__ bool knn_fit_one(const PairDev& P, const RunDev& run,
             const int e = lane + 64 * r;
             if constexpr (F64) {
                 S.buf[pos] = bitsd(d[r]);
-                S.snode[pos] = S.node[e];
+                S.snode[pos] = node_of[e];
             } else {
-                S.buf[pos] = ((u64)__float_as_uint(d[r]) << 32) | (u32)S.node[e];
+                S.buf[pos] = ((u64)__float_as_uint(d[r]) << 32) | (u32)node_of[e];
             }
         }
     }
