@@ -336,7 +336,7 @@ int run_pairs(epic_ctx* c, const epic_request* reqs, int n, hipStream_t stream, 
     c->last_used = need;
     int tile_base = 0, pix_blocks = 0, seed_blocks = 0, src_blocks = 0, slot_blocks = 0, init_blocks = 0;
     int emit_blocks = 0;
-    int kmax = 1;
+    int kmax = 1, nmax = 1;
     for (int i = 0; i < n; ++i) c->last_counters[i] = nullptr;
     for (int i = 0; i < n; ++i) {
         const epic_request& r = reqs[i];
@@ -352,6 +352,7 @@ int run_pairs(epic_ctx* c, const epic_request* reqs, int n, hipStream_t stream, 
         P.a = r.a;
         P.mode = r.mode;
         kmax = std::max(kmax, r.K);
+        nmax = std::max(nmax, r.N);
         P.tiles_x = (r.W + tl.tw - 1) / tl.tw;
         P.tiles_y = (r.H + tl.th - 1) / tl.th;
         P.tile_base = tile_base;
@@ -541,7 +542,7 @@ int run_pairs(epic_ctx* c, const epic_request* reqs, int n, hipStream_t stream, 
         if (e == hipSuccess) e = launch_csr_scatter(dd, run, slot_blocks, stream);
         if (e == hipSuccess && c->opt.debug_validate) e = launch_check_graph(dd, run, slot_blocks, stream);
         if (last) mark(5);
-        if (e == hipSuccess) e = launch_knn_fit(dd, run, src_blocks, kmax, stream);
+        if (e == hipSuccess) e = launch_knn_fit(dd, run, src_blocks, kmax, nmax, stream);
         if (last) mark(6);
         if (first) {
             if (e == hipSuccess) e = launch_prune(dd, run, stream);

@@ -295,7 +295,7 @@ hipError_t launch_geodesic64(const PairDev* d_pairs, const RunDev& run, int pass
 hipError_t launch_graph_emit(const PairDev* d_pairs, const RunDev& run, int total_blocks, hipStream_t s);
 hipError_t launch_csr_scan(const PairDev* d_pairs, const RunDev& run, hipStream_t s);
 hipError_t launch_csr_scatter(const PairDev* d_pairs, const RunDev& run, int total_blocks, hipStream_t s);
-hipError_t launch_knn_fit(const PairDev* d_pairs, const RunDev& run, int total_blocks, int kmax,
+hipError_t launch_knn_fit(const PairDev* d_pairs, const RunDev& run, int total_blocks, int kmax, int nmax,
                           hipStream_t s);
 hipError_t launch_assign(const PairDev* d_pairs, const RunDev& run, int total_blocks, hipStream_t s);
 hipError_t launch_prune(PairDev* d_pairs, const RunDev& run, hipStream_t s);

@@ -51,28 +51,46 @@ namespace epic {
 
 namespace {
 
-__device__ __forceinline__ u32 node_slot(int v, int hbits) {
-    return ((u32)v * 2654435761u) >> (32 - hbits);
+// Home slot of node v in a table of hcap slots (multiplicative hash, then
+// the product range reduction, so hcap need not be a power of two).
+__device__ __forceinline__ u32 node_slot(int v, u32 hcap) {
+    return (u32)(((u64)((u32)v * 2654435761u) * hcap) >> 32);
 }
 
 // Compiler-only ordering of the wavefront's LDS accesses (see above).
 __device__ __forceinline__ void lds_order() { __asm__ __volatile__("" ::: "memory"); }
 
+// Node table slot: the node in the high bits over its entry (EB bits; the
+// all-ones entry marks a node that got no entry), all ones when empty.
+// 256-entry tables pack both into 32 bits (nodes below 2^23 - 1), larger
+// ones into 64.
+template <int VCAP>
+struct NodeSlot {
+    using T = typename std::conditional<(VCAP <= 256), u32, u64>::type;
+    static constexpr int EB = VCAP <= 256 ? 9 : 32;
+    static constexpr T EMPTY = ~(T)0;
+    static constexpr u32 NO_ENTRY = VCAP <= 256 ? 0x1ffu : 0xffffffffu;
+    static_assert(VCAP <= 256 ? VCAP < 0x1ff : true, "entry field");
+    __device__ static T pack(int v, u32 e) { return ((T)(u32)v << EB) | (T)e; }
+    __device__ static int node(T w) { return (int)(w >> EB); }
+    __device__ static u32 entry(T w) { return (u32)(w & (T)NO_ENTRY); }
+};
+
 template <int VCAP, bool F64>
 struct KnnLds {
-    static constexpr int HCAP = 2 * VCAP;
+    static constexpr int HCAP = VCAP + VCAP / 2;   // node table slots (load at most 2/3)
     static constexpr int TW = 64;                 // edges per relaxation window (one per lane)
     using DT = typename std::conditional<F64, u64, u32>::type;     // distance bits
     using RT = typename std::conditional<F64, double, float>::type;
+    using ST = typename NodeSlot<VCAP>::T;
     // entry e: tentative distance (2e) and lightest incident edge (2e + 1);
     // FP32 packs the edge's high 16 float bits over the degree (low 16 bits),
-    // the CSR record's own word
+    // the CSR record's own word.  After the search: the sort keys.
     alignas(16) DT dm[2 * VCAP];
     // entry e: CSR start (FP64: and degree); after the search, the entry's node
     u32 rd[F64 ? 2 * VCAP : VCAP];
-    u64 buf[VCAP];                // node table (HCAP ints) during the search, sort keys after
+    ST htab[HCAP];                // node table
     int snode[F64 ? VCAP : 1];    // FP64: node of each sort key
-    unsigned short hidx[HCAP];    // node table slot -> entry
     u32 head[TW];                 // (window stamp << 12) | (1 + entry) of the edge segment
                                   // starting at a window position
 };
@@ -162,14 +180,15 @@ __device__ __forceinline__ bool knn_fit_one(const PairDev& P, const RunDev& run,
     constexpr int TW = LdsT::TW;
     constexpr int Q = TW / 64;          // edges per lane per window
     constexpr int R = VCAP / 64;        // entries per lane
-    constexpr int HBITS = (HCAP == 512) ? 9 : (HCAP == 1024) ? 10 : (HCAP == 2048) ? 11 : 12;
-    static_assert((1 << HBITS) == HCAP, "hash size");
+    using NS = NodeSlot<VCAP>;
+    using ST = typename NS::T;
     static_assert(VCAP < 4096 && TW <= 128, "head mark layout");
     constexpr int RK = KMAX / 64;
     const int lane = threadIdx.x;
     const int K = P.K;
     const int keff = __builtin_amdgcn_readfirstlane(P.counters[C_KEFF]);
-    int* htab = reinterpret_cast<int*>(S.buf);
+    ST* const htab = S.htab;
+    u64* const keys = reinterpret_cast<u64*>(S.dm);       // sort keys, after the search
     EPIC_GLOBAL float* prm = gmem(P.params) + 6LL * s;
     // the match's own row, fetched now so that its latency hides behind the search
     const float4 me = gload(reinterpret_cast<const float4*>(P.matches) + s);
@@ -178,7 +197,7 @@ __device__ __forceinline__ bool knn_fit_one(const PairDev& P, const RunDev& run,
     const uint4* const adj = P.adj;
 
     // ------------------------------------------------------------ Dijkstra
-    for (int i = lane; i < HCAP; i += 64) htab[i] = -1;
+    for (int i = lane; i < HCAP; i += 64) htab[i] = NS::EMPTY;
     for (int i = lane; i < TW; i += 64) S.head[i] = 0u;
     for (int i = lane; i < 2 * VCAP; i += 64) S.dm[i] = to_bits<F64>(RINF);
     for (int i = lane; i < (F64 ? 2 * VCAP : VCAP); i += 64) S.rd[i] = 0u;
@@ -195,9 +214,7 @@ __device__ __forceinline__ bool knn_fit_one(const PairDev& P, const RunDev& run,
             S.dm[1] = (gmem(P.minin)[s] & 0xffff0000u) | (b - a);
             S.rd[0] = a;
         }
-        const u32 h = node_slot(s, HBITS);
-        htab[h] = s;
-        S.hidx[h] = 0;
+        htab[node_slot(s, HCAP)] = NS::pack(s, 0u);
     }
     __syncthreads();
 
@@ -365,8 +382,9 @@ __device__ __forceinline__ bool knn_fit_one(const PairDev& P, const RunDev& run,
                 }
             }
             // find or claim each neighbour's table slot with one
-            // compare-and-swap per probe: it returns -1 (this lane claimed
-            // the slot), v (already there) or another node (next slot).
+            // compare-and-swap per probe: it returns an empty slot (this
+            // lane claimed it, for now without an entry), a slot of v
+            // (already there) or of another node (next slot).
             // res: 0 while probing, else 1 + slot, bit 30 set when this lane
             // claimed it; RES_IDLE for lanes without an edge.
             constexpr u32 RES_WON = 1u << 30, RES_IDLE = ~0u;
@@ -374,22 +392,24 @@ __device__ __forceinline__ bool knn_fit_one(const PairDev& P, const RunDev& run,
 #pragma unroll
             for (int q = 0; q < Q; ++q) {
                 res[q] = act[q] ? 0u : RES_IDLE;
-                hh[q] = node_slot((int)rec[q].x, HBITS);
+                hh[q] = node_slot((int)rec[q].x, HCAP);
             }
             for (int probe = 0; probe < HCAP; ++probe) {
                 bool any = false;
 #pragma unroll
                 for (int q = 0; q < Q; ++q) any = any || res[q] == 0u;
                 if (wave::ballot(any) == 0ull) break;
-                int prev[Q];            // all chunks' compare-and-swaps in flight together
+                ST prev[Q];             // all chunks' compare-and-swaps in flight together
 #pragma unroll
                 for (int q = 0; q < Q; ++q)
-                    prev[q] = res[q] == 0u ? atomicCAS(&htab[hh[q]], -1, (int)rec[q].x) : 0;
+                    prev[q] = res[q] == 0u ? atomicCAS(&htab[hh[q]], NS::EMPTY, NS::pack((int)rec[q].x, NS::NO_ENTRY))
+                                           : (ST)0;
 #pragma unroll
                 for (int q = 0; q < Q; ++q) {
                     if (res[q] == 0u) {
-                        res[q] = prev[q] == -1 ? (hh[q] + 1u) | RES_WON : prev[q] == (int)rec[q].x ? hh[q] + 1u : 0u;
-                        hh[q] = (hh[q] + 1u) & (u32)(HCAP - 1);
+                        res[q] = prev[q] == NS::EMPTY ? (hh[q] + 1u) | RES_WON
+                               : NS::node(prev[q]) == (int)rec[q].x ? hh[q] + 1u : 0u;
+                        hh[q] = hh[q] + 1u == (u32)HCAP ? 0u : hh[q] + 1u;
                     }
                 }
             }
@@ -418,9 +438,7 @@ __device__ __forceinline__ bool knn_fit_one(const PairDev& P, const RunDev& run,
                             S.dm[2 * e + 1] = rec[q].w;        // lightest edge bits over the degree
                             S.rd[e] = rec[q].z;
                         }
-                        S.hidx[hs] = (unsigned short)e;
-                    } else {
-                        S.hidx[hs] = 0xffff;
+                        htab[hs] = NS::pack((int)rec[q].x, (u32)e);
                     }
                 }
             }
@@ -430,8 +448,8 @@ __device__ __forceinline__ bool knn_fit_one(const PairDev& P, const RunDev& run,
 #pragma unroll
             for (int q = 0; q < Q; ++q) {
                 if (res[q] != RES_IDLE && res[q] != 0u && (res[q] & RES_WON) == 0u) {
-                    const int e = S.hidx[res[q] - 1u];
-                    if (e != 0xffff) atomicMin(&S.dm[2 * e], to_bits<F64>(cand[q]));
+                    const u32 e = NS::entry(htab[res[q] - 1u]);
+                    if (e != NS::NO_ENTRY) atomicMin(&S.dm[2 * e], to_bits<F64>(cand[q]));
                 }
             }
             lds_order();
@@ -449,11 +467,11 @@ __device__ __forceinline__ bool knn_fit_one(const PairDev& P, const RunDev& run,
     int* const node_of = reinterpret_cast<int*>(S.rd);
     __syncthreads();
     for (int h = lane; h < HCAP; h += 64) {
-        const int v = htab[h];
-        const int e = S.hidx[h];
-        if (v >= 0 && e < VCAP) node_of[e] = v;
+        const ST w = htab[h];
+        const u32 e = NS::entry(w);
+        if (w != NS::EMPTY && e < (u32)VCAP) node_of[e] = NS::node(w);
     }
-    __syncthreads();                 // the node table (aliasing buf) is dead from here
+    __syncthreads();                 // the distances (the keys' space) are in registers from here
     int nc = 0;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -464,10 +482,10 @@ __device__ __forceinline__ bool knn_fit_one(const PairDev& P, const RunDev& run,
         if (c) {
             const int e = lane + 64 * r;
             if constexpr (F64) {
-                S.buf[pos] = bitsd(d[r]);
+                keys[pos] = bitsd(d[r]);
                 S.snode[pos] = node_of[e];
             } else {
-                S.buf[pos] = ((u64)__float_as_uint(d[r]) << 32) | (u32)node_of[e];
+                keys[pos] = ((u64)__float_as_uint(d[r]) << 32) | (u32)node_of[e];
             }
         }
     }
@@ -482,8 +500,8 @@ __device__ __forceinline__ bool knn_fit_one(const PairDev& P, const RunDev& run,
         if (p2 <= 128) {
             __syncthreads();
             u64 v[2];
-            v[0] = lane < nc ? S.buf[lane] : ~0ull;
-            v[1] = lane + 64 < nc ? S.buf[lane + 64] : ~0ull;
+            v[0] = lane < nc ? keys[lane] : ~0ull;
+            v[1] = lane + 64 < nc ? keys[lane + 64] : ~0ull;
             if (p2 == 64) bitonic_regs<1>(v, lane); else bitonic_regs<2>(v, lane);
 #pragma unroll
             for (int r = 0; r < RK; ++r) {
@@ -495,7 +513,7 @@ __device__ __forceinline__ bool knn_fit_one(const PairDev& P, const RunDev& run,
     }
     if (!sorted) {
         for (int i = nc + lane; i < p2; i += 64) {
-            S.buf[i] = ~0ull;
+            keys[i] = ~0ull;
             if constexpr (F64) S.snode[i] = 0x7fffffff;
         }
         __syncthreads();
@@ -507,23 +525,23 @@ __device__ __forceinline__ bool knn_fit_one(const PairDev& P, const RunDev& run,
                     const int i = ((t & ~(j - 1)) << 1) | (t & (j - 1));
                     const int ixj = i | j;
                     {
-                        const u64 a = S.buf[i], b = S.buf[ixj];
+                        const u64 a = keys[i], b = keys[ixj];
                         const bool up = (i & k) == 0;
                         if constexpr (F64) {
                             const int na = S.snode[i], nb = S.snode[ixj];
                             const bool gt = a > b || (a == b && na > nb);
                             const bool lt = a < b || (a == b && na < nb);
                             if (up ? gt : lt) {
-                                S.buf[i] = b;
-                                S.buf[ixj] = a;
+                                keys[i] = b;
+                                keys[ixj] = a;
                                 S.snode[i] = nb;
                                 S.snode[ixj] = na;
                             }
                         } else {
                             // keys are distinct except the padding, whose swap is harmless
                             if ((a > b) == up) {
-                                S.buf[i] = b;
-                                S.buf[ixj] = a;
+                                keys[i] = b;
+                                keys[ixj] = a;
                             }
                         }
                     }
@@ -534,7 +552,7 @@ __device__ __forceinline__ bool knn_fit_one(const PairDev& P, const RunDev& run,
 #pragma unroll
         for (int r = 0; r < RK; ++r) {
             const int jj = lane + 64 * r;
-            const u64 kb = jj < p2 ? S.buf[jj] : ~0ull;
+            const u64 kb = jj < p2 ? keys[jj] : ~0ull;
             if constexpr (F64) {
                 knode[r] = jj < p2 ? S.snode[jj] : 0x7fffffff;
                 kdist[r] = dbits(kb);
@@ -660,12 +678,15 @@ __global__ __launch_bounds__(64) void k_knn_fit_retry(const PairDev* __restrict_
 
 namespace {
 template <bool F64>
-void launch_knn_t(const PairDev* d_pairs, const RunDev& run, int total_blocks, int kmax, hipStream_t s) {
+void launch_knn_t(const PairDev* d_pairs, const RunDev& run, int total_blocks, int kmax, int nmax, hipStream_t s) {
     const int retry_grid = 512;
-    if (kmax <= 64) {
+    // 256-entry tables keep node and entry in one 32-bit slot (nodes below
+    // 2^23 - 1); a call with larger pairs takes the 512-entry kernels
+    const bool small_ids = nmax < (1 << 23) - 1;
+    if (kmax <= 64 && small_ids) {
         hipLaunchKernelGGL((k_knn_fit<256, 64, F64>), dim3(total_blocks), dim3(64), 0, s, d_pairs, run);
         hipLaunchKernelGGL((k_knn_fit_retry<1024, 64, F64>), dim3(retry_grid), dim3(64), 0, s, d_pairs, run);
-    } else if (kmax <= 128) {
+    } else if (kmax <= 128 && small_ids) {
         hipLaunchKernelGGL((k_knn_fit<256, 128, F64>), dim3(total_blocks), dim3(64), 0, s, d_pairs, run);
         hipLaunchKernelGGL((k_knn_fit_retry<2048, 128, F64>), dim3(retry_grid), dim3(64), 0, s, d_pairs, run);
     } else {
@@ -675,10 +696,10 @@ void launch_knn_t(const PairDev* d_pairs, const RunDev& run, int total_blocks, i
 }
 }  // namespace
 
-hipError_t launch_knn_fit(const PairDev* d_pairs, const RunDev& run, int total_blocks, int kmax,
+hipError_t launch_knn_fit(const PairDev* d_pairs, const RunDev& run, int total_blocks, int kmax, int nmax,
                           hipStream_t s) {
-    if (run.precision == 1) launch_knn_t<true>(d_pairs, run, total_blocks, kmax, s);
-    else launch_knn_t<false>(d_pairs, run, total_blocks, kmax, s);
+    if (run.precision == 1) launch_knn_t<true>(d_pairs, run, total_blocks, kmax, nmax, s);
+    else launch_knn_t<false>(d_pairs, run, total_blocks, kmax, nmax, s);
     return hipGetLastError();
 }
 
