@@ -238,6 +238,12 @@ hipError_t launch_exact_select(const PairDev* chunk, int nsrc, int src0, int fir
     if (nsrc > kExactChunk) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_exact_boxes, dim3((unsigned)((nsrc + 255) / 256)), dim3(256), 0, s, chunk, nsrc, src0, A);
     const size_t lds = (size_t)A.K * 64 * sizeof(u64) + (size_t)kExactChunk * sizeof(unsigned short);
+    if (lds > 65536) {
+        // above the default dynamic LDS limit of a launch (K > 124)
+        const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_exact_select),
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
     hipLaunchKernelGGL(k_exact_select, dim3((unsigned)((A.HW + 63) / 64)), dim3(64), lds, s, chunk, nsrc, src0,
                        first, last, A);
     return hipGetLastError();

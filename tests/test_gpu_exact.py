@@ -11,7 +11,7 @@ from scenes import config_scene, random_case
 
 pytestmark = pytest.mark.gpu
 
-@pytest.mark.parametrize("case", ["config1", "random_la", "random_nw", "k1"])
+@pytest.mark.parametrize("case", ["config1", "random_la", "random_nw", "k1", "k128"])
 def test_exact_matches_oracle(case):
     """Mean EPE within the tolerance; every pixel within MAX_EPE except
     where the oracle's K-th and (K+1)-th distances are a near-tie (FP32
@@ -21,7 +21,9 @@ def test_exact_matches_oracle(case):
     sc = {"config1": lambda: config_scene(1),
           "random_la": lambda: random_case(45, 70, 60, seed=81, K=9, outside=3, duplicates=4),
           "random_nw": lambda: random_case(33, 90, 80, seed=82, K=16, mode=0),
-          "k1": lambda: random_case(40, 50, 30, seed=83, K=1)}[case]()
+          "k1": lambda: random_case(40, 50, 30, seed=83, K=1),
+          # the largest K: the selection's LDS lists exceed 64 KB
+          "k128": lambda: random_case(30, 40, 200, seed=86, K=128)}[case]()
     print(f"[case] exact {sc.name} K={sc.K} mode={sc.mode}", flush=True)
     with epic.Context(0, 256 << 20) as c:
         f = c.interp_exact(torch.from_numpy(sc.cost).cuda(), torch.from_numpy(sc.matches).cuda(),
