@@ -3,9 +3,10 @@
 //
 // One wavefront per match s:
 //  1. Dijkstra from s on the match graph.  The visited set lives in LDS:
-//     entries e (tentative distance, lightest incident edge, CSR range,
-//     node) owned by lane e % 64, and an open-addressing node -> entry
-//     table.  Several frontier nodes are settled per step: a frontier node v
+//     entries e (tentative distance, lightest incident edge, CSR range)
+//     owned by lane e % 64, and an open-addressing node table whose slots
+//     hold a node and its entry in one word.  Several frontier nodes are
+//     settled per step: a frontier node v
 //     with tentative d(v) is final once d(v) <= dmin + lightest_edge(v),
 //     where dmin is the smallest tentative distance on the frontier (no
 //     unsettled node can still lower it).  The edges of all nodes settled in
