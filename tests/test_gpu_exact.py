@@ -78,3 +78,32 @@ def test_exact_in_chunks_equals_one_chunk():
         with epic.Context(0, ws) as c:
             outs.append(c.interp_exact(cost, m, sc.K, sc.a, sc.mode).cpu().numpy())
     assert np.array_equal(outs[0], outs[1])
+
+
+def test_exact_full_size_sampled():
+    """The 1024 x 436 scene (8000 matches, K = 100) in the configuration the
+    benchmark times (chunks of 1024 single-source transforms): sampled
+    pixels -- a spread over the image, its corners and random ones --
+    against the oracle's per-pixel definition, to the bar of the other
+    cases (near-ties of the K-th neighbour excused)."""
+    import torch
+    import paper_1501_02565_amd as epic
+    sc = config_scene(2)
+    HW = sc.H * sc.W
+    rng = np.random.default_rng(87)
+    pix = np.unique(np.concatenate([np.linspace(0, HW - 1, 40).astype(np.int64),
+                                    [0, sc.W - 1, HW - sc.W, HW - 1], rng.integers(0, HW, 20)]))
+    print(f"[case] exact full size {sc.name}, {len(pix)} sampled pixels", flush=True)
+    ws = 8 * sc.K * HW + 4 * HW + sc.N + 8 * sc.N * sc.K + 1024 * epic.workspace_bytes(sc.H, sc.W, 1, 1) \
+        + (64 << 20)
+    with epic.Context(0, ws) as c:
+        f = c.interp_exact(torch.from_numpy(sc.cost).cuda(), torch.from_numpy(sc.matches).cuda(),
+                           sc.K, sc.a, sc.mode).cpu().numpy().reshape(-1, 2).astype(np.float64)
+    rf = epic_ref.exact(sc.cost, sc.matches, sc.K, sc.a, sc.mode, pixels=pix)[0]
+    d2 = epic_ref.exact(sc.cost, sc.matches, sc.K + 1, sc.a, sc.mode, pixels=pix)[2]
+    tie = np.abs(d2[:, sc.K] - d2[:, sc.K - 1]) <= 1e-4 * d2[:, sc.K - 1]
+    epe = np.linalg.norm(f[pix] - rf, axis=1)
+    print(f"mean EPE {epe.mean():.2e}, max {epe.max():.2e}, {int(tie.sum())} tie pixels", flush=True)
+    assert np.isfinite(f).all()
+    assert epe.mean() <= parity.EPE_MEAN
+    assert epe[~tie].max() <= parity.MAX_EPE
