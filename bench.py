@@ -117,7 +117,11 @@ def cpu_baseline(sc, seconds):
             "single_core": {"value": round(reps1 * px / el1 / 1e6, 4), "unit": "Mpix/s", "cores": 1,
                             "ms_per_call": round(el1 / reps1 * 1e3, 1),
                             "sample": f"{reps1} full interpolations in {el1:.1f} s on 1 thread"},
-            "cpu_model": cpu_model(), "nproc": os.cpu_count()}
+            "cpu_model": cpu_model(), "nproc": os.cpu_count(),
+            # context only: the paper's one timing of this path (another
+            # machine, about 5000 matches of a real pair, precision not stated)
+            "paper_context": {"interp_s": 0.25, "mpix_s": round(px / 0.25 / 1e6, 3), "cores": 1,
+                              "clock_ghz": 3.6, "workload": "1024x436 Sintel pair, ~5000 matches, LA"}}
 
 
 def copy_bandwidth(torch, nbytes=256 << 20, reps=20):
