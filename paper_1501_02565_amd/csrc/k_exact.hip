@@ -7,13 +7,17 @@
 //
 // The distances come from single-source transforms: each match is a pair of
 // its own in a batch (the same cost map, that one match) run through the
-// tiled transform of k_geodesic.hip, which gives D_m(p) at every pixel in
-// FP32.  Sources are processed in chunks that fit the workspace; after each
-// chunk, k_exact_select folds the chunk's distances into every pixel's
-// running list of the K smallest (distance, index) keys.  k_exact_owner
-// first marks the matches that hold their pixel (placed, lowest index), so
-// dropped and duplicate matches never enter a list.  k_exact_fit then fits
-// each pixel (fit.h) with the pixel as the anchor.
+// tiled transform of k_geodesic.hip in FP32.  The approximated interpolation
+// runs first and bounds, at every pixel, the distance of its K-th nearest
+// match (k_exact_bound); the transforms keep only distances within those
+// bounds, which is exact: a pixel on a shortest path from one of p's K
+// nearest matches to p has that match among its own K nearest, so the path
+// is never cut.  Sources are processed in chunks that fit the workspace;
+// after each chunk, k_exact_select folds the chunk's distances into every
+// pixel's K smallest (distance, index) keys.  k_exact_owner first marks the
+// matches that hold their pixel (placed, lowest index), so dropped and
+// duplicate matches never enter a list.  k_exact_fit then fits each pixel
+// (fit.h) with the pixel as the anchor.
 #include "epic_dev.h"
 #include "fit.h"
 #include "wave.h"
