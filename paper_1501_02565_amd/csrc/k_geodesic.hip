@@ -134,12 +134,13 @@ constexpr int nb_index(int dx, int dy) {
 // shape its distances, which saves most of the passes that would otherwise
 // carry them in one tile at a time.
 //
-// BOUND: a key whose distance exceeds the pixel's bound (P.ubound) is not
-// taken, so a transform only spreads where its distances can still matter.
-// A value above the bound at some pixel is above it at every pixel the path
-// continues to (the bound is an upper bound of the distance to the K-th
-// nearest match, which grows by at most a step per step), so pruning never
-// hides a distance below a bound.
+// BOUND: a key whose distance exceeds the pixel's bound (P.ubound, at least
+// the distance of the pixel's K-th nearest match) is not taken, so a
+// single-source transform only spreads where its distances can matter.  If
+// the source is one of p's K nearest, every pixel q on a shortest path from
+// it to p has it among its own K nearest (a match closer to q would be
+// closer to p), so its distance at q is within q's bound and the path to p
+// is never cut.
 template <int TW, int TH, int MX, int MY, int CONN, int NT, bool BOUND = false>
 __device__ __forceinline__ int visit_tile(const PairDev& P, int tx, int ty,
                                           TileLdsT<TW + 2 * MX, TH + 2 * MY, BOUND>& S, int* error,
