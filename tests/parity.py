@@ -22,8 +22,15 @@ Tolerances (stated once, used by every parity test):
     the last term the weight change exp(-a d) implied by the FP32 graph
     distances (each within 1e-5 relative, checked above);
   * dense flow: mean endpoint difference to the oracle flow <= 1e-3 px, and
-    at most MAX_EPE = 1e-2 px at every pixel whose label agrees and whose
-    cell's list and model were not excused above.
+    at every pixel p whose label agrees and whose cell's list and model were
+    not excused above at most
+        MAX_EPE + (FIT_REL * max(1, kappa_m) + 2 a max_n |d_gpu - d_ref|) |B_m (p - p_m)|
+    with B_m the oracle's LA matrix of the pixel's cell: the model bound's
+    relative error carried to the pixel.  MAX_EPE = 1e-2 px governs
+    ordinary cells; the second term matters only where a near-degenerate
+    neighbourhood (K = 3 fitted exactly through a thin triangle) gives
+    affine terms of thousands of px, whose FP32 solve then differs from the
+    FP64 one by about 1e-5 of that term.
 Nothing else is excused: no fraction of lists, edges or pixels may differ
 for an unexplained reason.
 """
@@ -138,7 +145,42 @@ def _cov_kappa(pos, w):
     return float(ev[1] / ev[0]) if ev[0] > 0 else np.inf
 
 
-def check_params(sc, g, r, K, a, mode, wpow, skip):
+def model_kappas(sc, r, K, a, mode, wpow):
+    """kappa_m of every match's oracle model (1 for NW and for LA fits that
+    fell back to NW), capped at 1e3 as in the model bound."""
+    pos = sc.matches[:, :2].astype(np.float64)
+    ri, rd = r["knn_idx"][:, :K], r["knn_d"][:, :K]
+    kap = np.ones(ri.shape[0])
+    if mode != 1:
+        return kap
+    for s in range(ri.shape[0]):
+        if ri[s, 0] < 0 or r["status"][s] != 0:
+            continue
+        nb = ri[s][ri[s] >= 0]
+        k = np.exp(-a * rd[s][: len(nb)])
+        kap[s] = min(_cov_kappa(pos[nb], k if wpow == 1 else k * k), 1e3)
+    return kap
+
+
+def flow_extra_tol(sc, g, r, kap, K, a):
+    """Per pixel (FIT_REL * max(1, kappa_m) + 2 a dd_m) * |B_m (p - p_m)| for
+    the oracle's label m of the pixel (0 where the pixel has none), dd_m the
+    largest K-NN distance difference of m's list."""
+    with np.errstate(invalid="ignore"):          # inf - inf past a short list
+        dd = np.abs(g["knn_d"][:, :K].astype(np.float64) - r["knn_d"][:, :K])
+    dd = np.where(np.isfinite(dd), dd, 0.0).max(axis=1)
+    L = r["L"]
+    H, W = L.shape
+    ok = L >= 0
+    m = np.where(ok, L, 0)
+    B = r["params"][:, :4].reshape(-1, 2, 2)[m]
+    yy, xx = np.mgrid[0:H, 0:W]
+    d = np.stack([xx, yy], -1).astype(np.float64) - sc.matches[m][..., :2].astype(np.float64)
+    aff = np.linalg.norm(np.einsum("hwij,hwj->hwi", B, d), axis=-1)
+    return np.where(ok, (FIT_REL * np.maximum(1.0, kap[m]) + 2.0 * a * dd[m]) * aff, 0.0)
+
+
+def check_params(sc, g, r, K, a, mode, wpow, skip, kap=None):
     """Per-match models against the oracle's for every source whose list
     matched (see the module docstring for the bound).  Returns the largest
     ratio of error to bound seen."""
@@ -146,6 +188,8 @@ def check_params(sc, g, r, K, a, mode, wpow, skip):
     pos, disp = m[:, :2], m[:, 2:] - m[:, :2]
     Pg, Pr = g["params"].astype(np.float64), r["params"]
     ri, rd, gd = r["knn_idx"][:, :K], r["knn_d"][:, :K], g["knn_d"][:, :K].astype(np.float64)
+    if kap is None:
+        kap = model_kappas(sc, r, K, a, mode, wpow)
     worst, bad = 0.0, []
     for s in range(ri.shape[0]):
         if ri[s, 0] < 0 or s in skip:
@@ -155,10 +199,7 @@ def check_params(sc, g, r, K, a, mode, wpow, skip):
         dB = (Pg[s, :4] - Pr[s, :4]).reshape(2, 2)
         err = np.abs(dp @ dB.T + (Pg[s, 4:] - Pr[s, 4:])).max()
         S = np.abs(disp[s]).max() + np.abs(disp[nb] - disp[s]).max()
-        kappa = 1.0
-        if mode == 1 and r["status"][s] == 0:
-            k = np.exp(-a * rd[s][: len(nb)])
-            kappa = min(_cov_kappa(pos[nb], k if wpow == 1 else k * k), 1e3)
+        kappa = kap[s]
         dd = np.abs(gd[s][: len(nb)] - rd[s][: len(nb)]).max()
         tol = S * (FIT_REL * max(1.0, kappa) + 2.0 * a * dd) + 1e-6
         worst = max(worst, err / tol)
@@ -168,7 +209,7 @@ def check_params(sc, g, r, K, a, mode, wpow, skip):
     return worst
 
 
-def check_flow(g, r, epe_mean=EPE_MEAN, excused_pixels=None):
+def check_flow(g, r, epe_mean=EPE_MEAN, excused_pixels=None, extra_tol=None):
     fg = g["flow"].astype(np.float64)
     fr = r["flow"]
     if np.isnan(fr).all():
@@ -178,8 +219,11 @@ def check_flow(g, r, epe_mean=EPE_MEAN, excused_pixels=None):
     assert np.isfinite(epe).all()
     assert epe.mean() <= epe_mean, f"mean EPE {epe.mean():.3e}"
     keep = np.ones(epe.shape, bool) if excused_pixels is None else ~excused_pixels
+    tol = MAX_EPE + (0.0 if extra_tol is None else extra_tol)
+    over = (epe > tol) & keep
     mx = float(epe[keep].max()) if keep.any() else 0.0
-    assert mx <= MAX_EPE, f"max EPE {mx:.3e} at a pixel with no excused label or list"
+    assert not over.any(), (f"EPE {float(epe[over].max()):.3e} above its bound at {int(over.sum())} pixels "
+                            "with no excused label or list")
     return float(epe.mean()), mx
 
 
@@ -202,9 +246,10 @@ def full_check(ctx, sc, K=None, a=None, mode=None, conn=8, wpow=2):
     enodes = check_graph(g, r, diff)
     Keff = r["K"]
     kex = check_knn(g, r, Keff, enodes)
-    fit_ratio = check_params(sc, g, r, Keff, a, mode, wpow, kex)
+    kap = model_kappas(sc, r, Keff, a, mode, wpow)
+    fit_ratio = check_params(sc, g, r, Keff, a, mode, wpow, kex, kap)
     excused_px = diff | np.isin(g["L"], list(kex))
-    epe, epe_max = check_flow(g, r, excused_pixels=excused_px)
+    epe, epe_max = check_flow(g, r, excused_pixels=excused_px, extra_tol=flow_extra_tol(sc, g, r, kap, Keff, a))
     return dict(label_diff=int(diff.sum()), excused_edges_nodes=len(enodes), excused_lists=len(kex),
                 fit_err_over_bound=round(fit_ratio, 4), epe=epe, epe_max=epe_max, stats=st)
 
@@ -255,7 +300,9 @@ def full_check_pruned(ctx_pruned, sc, prune_px, K=None, a=None, mode=None, conn=
     diff = check_labels(sk, g, r, conn)
     enodes = check_graph(g, r, diff)
     kex = check_knn(g, r, r["K"], enodes)
-    fit_ratio = check_params(sk, g, r, r["K"], a, mode, wpow, kex)
-    epe, epe_max = check_flow(g, r, excused_pixels=diff | np.isin(g["L"], list(kex)))
+    kap = model_kappas(sk, r, r["K"], a, mode, wpow)
+    fit_ratio = check_params(sk, g, r, r["K"], a, mode, wpow, kex, kap)
+    epe, epe_max = check_flow(g, r, excused_pixels=diff | np.isin(g["L"], list(kex)),
+                              extra_tol=flow_extra_tol(sk, g, r, kap, r["K"], a))
     return dict(kept=n, pruned=st["n_pruned"], label_diff=int(diff.sum()), excused_lists=len(kex),
                 fit_err_over_bound=round(fit_ratio, 4), epe=epe, epe_max=epe_max)
