@@ -2,9 +2,12 @@
 
 Tolerances (stated once, used by every parity test):
   * geodesic distance D: relative 1e-5 wherever the labels agree;
-  * labels L: at most 0.1% of pixels may differ, and every differing pixel
-    must be a near-tie -- the oracle's distance from the GPU's match to the
-    pixel is within 1e-5 (relative) of the oracle's minimum;
+  * labels L: every differing pixel must be a near-tie -- the oracle's
+    distance from the GPU's match to the pixel is within 1e-5 (relative) of
+    the oracle's minimum -- and at most 0.1% of pixels may differ, not
+    counting ties closer than 1e-7 (two matches at the same distance to
+    within FP32 resolution, which no FP32 sum can order as the FP64 oracle
+    does; a sparse scene with flat cost can hold more of them than 0.1%);
   * graph: the same edge set with weights within 1e-5 relative, except edges
     with an endpoint whose cell holds a label near-tie (their weight is a
     minimum over that cell's boundary, which the tie may move);
@@ -21,9 +24,10 @@ Tolerances (stated once, used by every parity test):
     position covariance (the FP32 path solves only kappa <= 1e3 itself) and
     the last term the weight change exp(-a d) implied by the FP32 graph
     distances (each within 1e-5 relative, checked above);
-  * dense flow: mean endpoint difference to the oracle flow <= 1e-3 px, and
-    at every pixel p whose label agrees and whose cell's list and model were
-    not excused above at most
+  * dense flow: over the pixels whose label agrees and whose cell's list
+    and model were not excused above (an excused pixel holds a proven tie,
+    where either match's model is a right answer), mean endpoint difference
+    to the oracle flow <= 1e-3 px, and at every such pixel p at most
         MAX_EPE + (FIT_REL * max(1, kappa_m) + 2 a max_n |d_gpu - d_ref|) |B_m (p - p_m)|
     with B_m the oracle's LA matrix of the pixel's cell: the model bound's
     relative error carried to the pixel.  MAX_EPE = 1e-2 px governs
@@ -42,6 +46,7 @@ from oracle import epic_ref
 
 REL = 1e-5
 LABEL_FRAC = 1e-3
+EXACT_TIE = 1e-7
 EPE_MEAN = 1e-3
 MAX_EPE = 1e-2
 KNN_TIE_REL = 1e-4
@@ -74,7 +79,7 @@ def check_labels(sc, g, r, conn=8, frac=LABEL_FRAC):
     same = Lg == Lr
     np.testing.assert_allclose(Dg[same], Dr[same], rtol=REL, atol=1e-30)
     diff = ~same
-    assert diff.sum() <= frac * Lg.size, f"{int(diff.sum())} label differences"
+    exact_ties = 0
     if diff.any():
         for lab in np.unique(Lg[diff]):
             src = int(r["seed_pix"][lab])
@@ -83,6 +88,9 @@ def check_labels(sc, g, r, conn=8, frac=LABEL_FRAC):
             pts = (Lg == lab) & diff
             np.testing.assert_allclose(Ds[pts], Dr[pts], rtol=REL)
             np.testing.assert_allclose(Dg[pts], Dr[pts], rtol=REL)
+            exact_ties += int((np.abs(Ds[pts] - Dr[pts]) <= EXACT_TIE * Dr[pts]).sum())
+    assert diff.sum() - exact_ties <= frac * Lg.size, \
+        f"{int(diff.sum())} label differences ({exact_ties} exact ties)"
     return diff
 
 
@@ -217,14 +225,17 @@ def check_flow(g, r, epe_mean=EPE_MEAN, excused_pixels=None, extra_tol=None):
         return 0.0, 0.0
     epe = np.linalg.norm(fg - fr, axis=2)
     assert np.isfinite(epe).all()
-    assert epe.mean() <= epe_mean, f"mean EPE {epe.mean():.3e}"
     keep = np.ones(epe.shape, bool) if excused_pixels is None else ~excused_pixels
+    # the mean over the pixels that are not excused: an excused pixel holds
+    # a proven tie, where either match's model is a right answer
+    mean = float(epe[keep].mean()) if keep.any() else 0.0
+    assert mean <= epe_mean, f"mean EPE {mean:.3e}"
     tol = MAX_EPE + (0.0 if extra_tol is None else extra_tol)
     over = (epe > tol) & keep
     mx = float(epe[keep].max()) if keep.any() else 0.0
     assert not over.any(), (f"EPE {float(epe[over].max()):.3e} above its bound at {int(over.sum())} pixels "
                             "with no excused label or list")
-    return float(epe.mean()), mx
+    return mean, mx
 
 
 def full_check(ctx, sc, K=None, a=None, mode=None, conn=8, wpow=2):
