@@ -337,8 +337,13 @@ __device__ __forceinline__ int visit_tile(const PairDev& P, int tx, int ty,
             if (lx >= 0 && ly >= 0 && lx < twe && ly < the && key_dist(k) < __int_as_float(0x7f800000))
                 bm |= B_REACHED;
         }
-        if (lx >= 0 && ly >= 0 && lx < twe && ly < the && k != orig[j]) {
-            dev_st(P.keys + (long long)(y0 + ly) * W + x0 + lx, k);
+        // the first pass of a bounded transform visits only the seed's tile,
+        // so every reached pixel on its border must mark the tile behind it,
+        // the seed itself included (the seeding wrote it, so it never
+        // changes here)
+        const bool spread = BOUND && (MX != 0 || MY != 0) && key_dist(k) < __int_as_float(0x7f800000);
+        if (lx >= 0 && ly >= 0 && lx < twe && ly < the && (k != orig[j] || spread)) {
+            if (k != orig[j]) dev_st(P.keys + (long long)(y0 + ly) * W + x0 + lx, k);
             const bool l = lx == 0, r = lx == twe - 1, t = ly == 0, b = ly == the - 1;
             if (MX != 0 || MY != 0) {
                 // first pass: the neighbours' values are not known yet

@@ -11,7 +11,8 @@ from scenes import config_scene, random_case
 
 pytestmark = pytest.mark.gpu
 
-@pytest.mark.parametrize("case", ["config1", "random_la", "random_nw", "k1", "k128"])
+@pytest.mark.parametrize("case", ["config1", "random_la", "random_nw", "k1", "k128", "seed_on_border_a",
+                                  "seed_on_border_b", "dense_k2"])
 def test_exact_matches_oracle(case):
     """Mean EPE within the tolerance; every pixel within MAX_EPE except
     where the oracle's K-th and (K+1)-th distances are a near-tie (FP32
@@ -23,7 +24,12 @@ def test_exact_matches_oracle(case):
           "random_nw": lambda: random_case(33, 90, 80, seed=82, K=16, mode=0),
           "k1": lambda: random_case(40, 50, 30, seed=83, K=1),
           # the largest K: the selection's LDS lists exceed 64 KB
-          "k128": lambda: random_case(30, 40, 200, seed=86, K=128)}[case]()
+          "k128": lambda: random_case(30, 40, 200, seed=86, K=128),
+          # dense matches and small K (tight bounds): sources seeded on a
+          # tile's border must still reach the tile behind it
+          "seed_on_border_a": lambda: random_case(60, 46, 249, seed=993076779, K=1, mode=0),
+          "seed_on_border_b": lambda: random_case(8, 66, 154, seed=512832132, K=1, mode=0, outside=2),
+          "dense_k2": lambda: random_case(19, 51, 270, seed=177738499, K=2, mode=0)}[case]()
     print(f"[case] exact {sc.name} K={sc.K} mode={sc.mode}", flush=True)
     with epic.Context(0, 256 << 20) as c:
         f = c.interp_exact(torch.from_numpy(sc.cost).cuda(), torch.from_numpy(sc.matches).cuda(),
