@@ -14,23 +14,25 @@ namespace epic {
 __global__ __launch_bounds__(PIX_BLOCK) void k_assign(const PairDev* __restrict__ pairs, RunDev run) {
     const int p = find_pair(run.npairs, (int)blockIdx.x, [&](int i) { return pairs[i].pix_block_base; });
     const PairDev& P = pairs[p];
-    const long long i = (long long)((int)blockIdx.x - P.pix_block_base) * PIX_BLOCK + threadIdx.x;
-    const int W = P.W;
-    if (i >= (long long)W * P.H) return;
+    // H * W < 2^31 (checked on the host): 32-bit index arithmetic
+    const u32 i = (u32)((int)blockIdx.x - P.pix_block_base) * PIX_BLOCK + threadIdx.x;
+    const u32 W = (u32)P.W;
+    if (i >= W * (u32)P.H) return;
+    const int px = (int)(i % W), py = (int)(i / W);
     const u32 m = P.labels ? gmem(P.labels)[i] : key_label(gmem(P.keys)[i]);
     float2 f;
     if (m == NO_LABEL) {
         f.x = f.y = __int_as_float(0x7fc00000);
     } else if (P.params64) {
         const EPIC_GLOBAL double* B = gmem(P.params64) + 6LL * m;
-        const double dx = (double)(int)(i % W) - (double)gmem(P.matches)[4LL * m];
-        const double dy = (double)(int)(i / W) - (double)gmem(P.matches)[4LL * m + 1];
+        const double dx = (double)px - (double)gmem(P.matches)[4LL * m];
+        const double dy = (double)py - (double)gmem(P.matches)[4LL * m + 1];
         f.x = (float)(B[0] * dx + B[1] * dy + B[4]);
         f.y = (float)(B[2] * dx + B[3] * dy + B[5]);
     } else {
         const EPIC_GLOBAL float* B = gmem(P.params) + 6LL * m;
         const float2 pm = gload(reinterpret_cast<const float2*>(P.matches + 4LL * m));
-        const float dx = (float)(int)(i % W) - pm.x, dy = (float)(int)(i / W) - pm.y;
+        const float dx = (float)px - pm.x, dy = (float)py - pm.y;
         f.x = B[0] * dx + B[1] * dy + B[4];
         f.y = B[2] * dx + B[3] * dy + B[5];
     }
