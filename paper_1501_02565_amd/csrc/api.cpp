@@ -87,6 +87,7 @@ size_t tiles_of(int H, int W, Tiling t) {
 }
 
 constexpr size_t kFixed = 4096 + (size_t)kRing * kMaxPairs * sizeof(PairDev);
+static_assert(kFixed % 256 == 0, "the carved arrays start 256-byte aligned (16-byte vector accesses rely on it)");
 // per-tile arrays of a call: two dirty-flag arrays and three dirty-tile lists
 constexpr size_t kTileArrays = 5;
 
@@ -334,6 +335,7 @@ int run_pairs(epic_ctx* c, const epic_request* reqs, int n, hipStream_t stream, 
     for (int i = 0; i < n; ++i) total_n += reqs[i].N;
     int* ovf_list = reinterpret_cast<int*>(take(4 * (size_t)total_n));
     c->last_used = need;
+    long long total_px = 0;
     int tile_base = 0, pix_blocks = 0, seed_blocks = 0, src_blocks = 0, slot_blocks = 0, init_blocks = 0;
     int emit_blocks = 0;
     int kmax = 1, nmax = 1;
@@ -358,8 +360,12 @@ int run_pairs(epic_ctx* c, const epic_request* reqs, int n, hipStream_t stream, 
         P.tile_base = tile_base;
         tile_base += P.tiles_x * P.tiles_y;
         const long long HW = (long long)r.H * r.W;
+        // each pair's pixel blocks come in groups of ASSIGN_PPT, one block of
+        // the assignment's grid per group (the other pixel kernels check
+        // their pixel index against H * W)
+        total_px += HW;
         P.pix_block_base = pix_blocks;
-        pix_blocks += (int)((HW + PIX_BLOCK - 1) / PIX_BLOCK);
+        pix_blocks += (int)((HW + PIX_BLOCK * ASSIGN_PPT - 1) / (PIX_BLOCK * ASSIGN_PPT)) * ASSIGN_PPT;
         P.emit_block_base = emit_blocks;
         emit_blocks += ((r.W + EMIT_TW - 1) / EMIT_TW) * ((r.H + EMIT_TH - 1) / EMIT_TH);
         P.seed_block_base = seed_blocks;
@@ -549,7 +555,7 @@ int run_pairs(epic_ctx* c, const epic_request* reqs, int n, hipStream_t stream, 
             if (dbg && dbg->prune_only) break;
             continue;
         }
-        if (e == hipSuccess && any_flow) e = launch_assign(dd, run, pix_blocks, stream);
+        if (e == hipSuccess && any_flow) e = launch_assign(dd, run, pix_blocks, total_px, stream);
         mark(7);
     }
     c->last_pruned = two_pass && !(dbg && dbg->prune_only);

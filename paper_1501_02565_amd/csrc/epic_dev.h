@@ -74,7 +74,9 @@ struct PairDev {
     // work decomposition (global index bases across the batch)
     int tiles_x, tiles_y;
     int tile_base;          // first global tile id of this pair
-    int pix_block_base;     // first block of pixel-parallel grids
+    int pix_block_base;     // first block of pixel-parallel grids (a multiple of
+                            //   ASSIGN_PPT: the assignment's grid, ASSIGN_PPT times
+                            //   coarser, starts the pair at pix_block_base / ASSIGN_PPT)
     int emit_block_base;    // first block of the graph-emit grid (EMIT_TW x EMIT_TH tiles)
     int src_block_base;     // first block of the per-match grid (one match per block)
     int seed_block_base;    // first block of the seeding grid (PIX_BLOCK matches per block)
@@ -280,6 +282,7 @@ __device__ __forceinline__ int find_pair(int npairs, int idx, F base_of) {
 // host-side launchers (one per stage; defined next to their kernels)
 // ---------------------------------------------------------------------------
 constexpr int PIX_BLOCK = 256;      // pixels per block of pixel-parallel kernels
+constexpr int ASSIGN_PPT = 4;      // pixels per thread of the assignment on calls with many pixels
 constexpr int EMIT_TW = 32, EMIT_TH = 16;  // pixel tile of one graph-emit block
 constexpr int EMIT_NT = EMIT_TW * EMIT_TH; // one thread per pixel
 constexpr int EMIT_LCAP = 4 * EMIT_NT;     // block-local edge slots
@@ -297,7 +300,8 @@ hipError_t launch_csr_scan(const PairDev* d_pairs, const RunDev& run, hipStream_
 hipError_t launch_csr_scatter(const PairDev* d_pairs, const RunDev& run, int total_blocks, hipStream_t s);
 hipError_t launch_knn_fit(const PairDev* d_pairs, const RunDev& run, int total_blocks, int kmax, int nmax,
                           hipStream_t s);
-hipError_t launch_assign(const PairDev* d_pairs, const RunDev& run, int total_blocks, hipStream_t s);
+hipError_t launch_assign(const PairDev* d_pairs, const RunDev& run, int pix_blocks, long long total_px,
+                         hipStream_t s);
 hipError_t launch_prune(PairDev* d_pairs, const RunDev& run, hipStream_t s);
 
 // Cost map from the image gradient: up to kImagesPerLaunch images per launch,

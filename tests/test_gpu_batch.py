@@ -110,7 +110,9 @@ def test_graph_sees_new_inputs(ctx):
 
 def test_full_size_batch_sampled_parity():
     """The 64-pair mixed-size batch at full size (the batched benchmark's
-    launch configuration); every 8th pair is checked against the oracle."""
+    launch configuration); every 8th pair is checked against the oracle and
+    against its own single call, bitwise (the batch assigns four pixels per
+    thread, a call of one such pair one)."""
     import torch
     import paper_1501_02565_amd as epic
     scs = batch_scenes(64)
@@ -128,3 +130,7 @@ def test_full_size_batch_sampled_parity():
             e = _epe(flows[i].cpu().numpy(), ref).mean()
             print(f"pair {i} {scs[i].name}: mean EPE {e:.2e}", flush=True)
             assert e <= parity.EPE_MEAN
+        # (after the batch's stats: a single call becomes the context's last call)
+        for i in range(0, 64, 8):
+            alone = c.interp(*probs[i]).cpu().numpy()
+            assert np.array_equal(alone, flows[i].cpu().numpy()), i

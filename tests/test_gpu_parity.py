@@ -57,6 +57,27 @@ def test_largest_served_size(ctx, K):
     print(res, flush=True)
 
 
+def test_large_call_output_alignment(ctx):
+    """A 2048 x 1080 call has more pixels than the chip holds single-pixel
+    wavefronts, so its assignment takes four pixels per thread and stores
+    16-byte pairs; into an output that is only 8-byte aligned it stores pixel
+    by pixel.  Both outputs hold the same bits."""
+    import torch
+    sc = serve_scene(dict(H=1080, W=2048, N=20000, K=50, seed=7201))
+    _announce(sc.name + " 8-byte aligned output")
+    cost = torch.from_numpy(sc.cost).cuda()
+    matches = torch.from_numpy(sc.matches).cuda()
+    aligned = ctx.interp(cost, matches, sc.K, sc.a, sc.mode)
+    buf = torch.full((sc.H * sc.W * 2 + 2,), 7.0, dtype=torch.float32, device="cuda")
+    out = buf[2:].view(sc.H, sc.W, 2)
+    assert out.data_ptr() % 16 == 8
+    ctx.interp(cost, matches, sc.K, sc.a, sc.mode, out=out)
+    torch.cuda.synchronize()
+    assert ctx.stats()["status"] == 0
+    np.testing.assert_array_equal(out.cpu().numpy(), aligned.cpu().numpy())
+    assert buf[:2].cpu().tolist() == [7.0, 7.0]      # nothing written before the output
+
+
 @pytest.mark.parametrize("K", [1, 2, 3, 7, 128, 256])
 def test_k_values(ctx, K):
     sc = random_case(60, 80, 300, seed=11, K=K)
