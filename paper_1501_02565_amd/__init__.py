@@ -132,7 +132,7 @@ class Context:
         L = _lib.load()
         self.device = int(device)
         if workspace is None:
-            workspace = workspace_bytes(1080, 2048, 40000, 256)
+            workspace = workspace_bytes(1080, 2048, 40000, 256, precision=precision)
         self.workspace = int(workspace)
         self.options = _lib.Options(connectivity, la_weight_power, precision,
                                     fp64_route, degenerate_tau, tile[0], tile[1],

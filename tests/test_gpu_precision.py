@@ -9,7 +9,7 @@ import pytest
 
 import parity
 from oracle import epic_ref
-from scenes import config_scene, random_case
+from scenes import config_scene, random_case, serve_scene
 
 pytestmark = pytest.mark.gpu
 
@@ -30,10 +30,13 @@ def ctx32():
     c.close()
 
 
-@pytest.mark.parametrize("case", ["random", "config1", "config2"])
+@pytest.mark.parametrize("case", ["random", "config1", "config2", "largest"])
 def test_fp64_everywhere_reproduces_the_oracle(ctx64, case):
+    """(largest: a 2048 x 1080 request, whose assignment takes four pixels
+    per thread, in a context of the default workspace)"""
     sc = {"random": lambda: random_case(130, 150, 200, seed=31, K=16, outside=2, duplicates=3),
-          "config1": lambda: config_scene(1), "config2": lambda: config_scene(2)}[case]()
+          "config1": lambda: config_scene(1), "config2": lambda: config_scene(2),
+          "largest": lambda: serve_scene(dict(H=1080, W=2048, N=40000, K=50, seed=7301))}[case]()
     print(f"[case] {sc.name}", flush=True)
     g = parity.gpu_stages(ctx64, sc)
     r = parity.ref_stages(sc)
