@@ -108,6 +108,43 @@ def test_graph_sees_new_inputs(ctx):
         g.close()
 
 
+def _shape_case(H, W, seed):
+    """A pair of any shape (down to one row or column) with three matches."""
+    rng = np.random.default_rng(seed)
+    sc = random_case(max(H, 3), max(W, 3), 3, seed=seed, K=3)
+    sc.cost = rng.uniform(0.01, 1, (H, W)).astype(np.float32)
+    N = min(3, H * W)
+    m = np.zeros((N, 4), np.float32)
+    pix = rng.choice(H * W, N, replace=False)
+    m[:, 0], m[:, 1] = pix % W, pix // W
+    m[:, 2:] = m[:, :2] + rng.normal(0, 2, (N, 2))
+    sc.matches = m
+    return sc
+
+
+def test_large_batch_with_odd_shapes_equals_single():
+    """A batch above 2.1 Mpx assigns four pixels per thread, whose runs wrap
+    rows (every pixel of a one-column image) and end short (pixel counts not
+    a multiple of four); each pair equals its single call, bitwise."""
+    import torch
+    import paper_1501_02565_amd as epic
+    from scenes import serve_scene
+    scs = [serve_scene(dict(H=1080, W=2048, N=5000, K=16, seed=7401))]
+    scs += [_shape_case(H, W, 7402 + i) for i, (H, W) in enumerate([(1, 77), (90, 1), (3, 5), (1, 1), (7, 3)])]
+    print(f"[case] batch of {len(scs)}, {sum(s.H * s.W for s in scs)} px", flush=True)
+    need = sum(epic.workspace_bytes(s.H, s.W, s.N, s.K) for s in scs)
+    with epic.Context(0, need) as c:
+        probs = [_dev(sc) for sc in scs]
+        flows = [f.cpu().numpy() for f in c.interp_batch(probs)]
+        st = [c.stats(i) for i in range(len(scs))]
+        for i, sc in enumerate(scs):
+            assert st[i]["status"] == 0, (i, st[i])
+            alone = c.interp(*probs[i]).cpu().numpy()
+            assert np.array_equal(alone, flows[i]), (i, sc.H, sc.W)
+        ref = epic_ref.interp(scs[1].cost, scs[1].matches, scs[1].K, scs[1].a, scs[1].mode)[0]
+        assert _epe(flows[1], ref).mean() <= parity.EPE_MEAN
+
+
 def test_full_size_batch_sampled_parity():
     """The 64-pair mixed-size batch at full size (the batched benchmark's
     launch configuration); every 8th pair is checked against the oracle and
