@@ -643,8 +643,14 @@ __device__ __forceinline__ bool knn_active(const PairDev& P, int s) {
 }  // namespace
 
 // First launch: one block (one wavefront) per match of every pair.
+// At most 80 scalar registers: with the 82 the compiler otherwise takes,
+// the hardware's allocation granule leaves room for 7 wavefronts per SIMD,
+// not 8 (the dispatcher's SGPR-full stall counter says so, with LDS, VGPRs
+// and wave slots all free), and the last 832 of 8000 matches start only as
+// the first ones end; at 78 all of them start at once.
 template <int VCAP, int KMAX, bool F64>
-__global__ __launch_bounds__(64) void k_knn_fit(const PairDev* __restrict__ pairs, RunDev run) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_num_sgpr(80))) void k_knn_fit(
+    const PairDev* __restrict__ pairs, RunDev run) {
     __shared__ KnnLds<VCAP, F64> S;
     const int p = find_pair(run.npairs, (int)blockIdx.x, [&](int i) { return pairs[i].src_block_base; });
     const PairDev& P = pairs[p];
