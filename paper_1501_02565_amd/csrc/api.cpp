@@ -541,7 +541,7 @@ int run_pairs(epic_ctx* c, const epic_request* reqs, int n, hipStream_t stream, 
         if (dbg && dbg->stop_after == 2) break;
         if (e == hipSuccess && c->opt.debug_validate)
             e = launch_check_transform(dd, run, pix_blocks, c->opt.debug_validate == 2, stream);
-        if (e == hipSuccess) e = launch_graph_emit(dd, run, emit_blocks, stream);
+        if (e == hipSuccess) e = launch_graph_emit(dd, run, emit_blocks, total_px, stream);
         if (last) mark(3);
         if (e == hipSuccess) e = launch_csr_scan(dd, run, stream);
         if (last) mark(4);

@@ -295,7 +295,8 @@ hipError_t launch_check_cost(const PairDev* d_pairs, const RunDev& run, int tota
 hipError_t launch_geodesic(const PairDev* d_pairs, const RunDev& run, int tile_w, int tile_h, int threads,
                            int passes, hipStream_t s);
 hipError_t launch_geodesic64(const PairDev* d_pairs, const RunDev& run, int passes0, int passes1, hipStream_t s);
-hipError_t launch_graph_emit(const PairDev* d_pairs, const RunDev& run, int total_blocks, hipStream_t s);
+hipError_t launch_graph_emit(const PairDev* d_pairs, const RunDev& run, int total_blocks, long long total_px,
+                             hipStream_t s);
 hipError_t launch_csr_scan(const PairDev* d_pairs, const RunDev& run, hipStream_t s);
 hipError_t launch_csr_scatter(const PairDev* d_pairs, const RunDev& run, int total_blocks, hipStream_t s);
 hipError_t launch_knn_fit(const PairDev* d_pairs, const RunDev& run, int total_blocks, int kmax, int nmax,

@@ -87,9 +87,13 @@ __device__ __forceinline__ void global_insert(const PairDev& P, u64 hk, u64 wb) 
 // the same size, so few edges reach the global hash per block.  The occupied
 // local slots are listed first, so the block's inserts run on distinct
 // threads at once instead of in sequence on the threads that own several.
-template <int CONN, bool F64>
-__global__ __launch_bounds__(EMIT_NT) void k_graph_emit(const PairDev* __restrict__ pairs, RunDev run) {
-    constexpr int LCAP = EMIT_LCAP;                   // block-local edge slots (overflow goes global)
+// PPT pixels per thread (rows y and y + EMIT_TH / PPT of the tile) with a
+// local table PPT times smaller: more blocks fit a CU at once, which pays
+// when the call has many tiles to keep the chip busy.
+template <int CONN, bool F64, int PPT>
+__global__ __launch_bounds__(EMIT_NT / PPT) void k_graph_emit(const PairDev* __restrict__ pairs, RunDev run) {
+    constexpr int NT = EMIT_NT / PPT;                 // threads of the block
+    constexpr int LCAP = EMIT_LCAP / PPT;             // block-local edge slots (overflow goes global)
     constexpr int LBITS = __builtin_ctz(LCAP);
     static_assert((1 << LBITS) == LCAP && LCAP <= 65536, "local hash: a power of two, 16-bit slot list");
     using V = typename std::conditional<F64, u64, u32>::type;
@@ -99,7 +103,7 @@ __global__ __launch_bounds__(EMIT_NT) void k_graph_emit(const PairDev* __restric
     __shared__ int s_cnt;
     const int p = find_pair(run.npairs, (int)blockIdx.x, [&](int i) { return pairs[i].emit_block_base; });
     const PairDev& P = pairs[p];
-    for (int i = threadIdx.x; i < LCAP; i += EMIT_NT) {
+    for (int i = threadIdx.x; i < LCAP; i += NT) {
         lkey[i] = HASH_EMPTY;
         lval[i] = F64 ? (V)DOUBLE_INF_BITS : (V)FLOAT_INF_BITS;
     }
@@ -107,73 +111,77 @@ __global__ __launch_bounds__(EMIT_NT) void k_graph_emit(const PairDev* __restric
     __syncthreads();
     const int W = P.W, H = P.H;
     const int tb = (int)blockIdx.x - P.emit_block_base, etx = (W + EMIT_TW - 1) / EMIT_TW;
-    const int x = (tb % etx) * EMIT_TW + (int)threadIdx.x % EMIT_TW;
-    const int y = (tb / etx) * EMIT_TH + (int)threadIdx.x / EMIT_TW;
-    const long long i = (long long)y * W + x;
-    if (x < W && y < H) {
-        // forward half-neighbourhood: (1,0), (0,1), (1,1), (-1,1); all loads
-        // are issued before any is used (outside neighbours read the pixel
-        // itself and are skipped)
-        constexpr int HX[4] = {1, 0, 1, -1};
-        constexpr int HY[4] = {0, 1, 1, 1};
-        constexpr int NK = CONN == 8 ? 4 : 2;
-        const u64 kp = gmem(P.keys)[i];
-        const float cp = gmem(P.cost)[i];
-        const u32 lp = F64 ? gmem(P.labels)[i] : key_label(kp);
-        u64 kqa[NK];
-        float cqa[NK];
-        u32 lqa[NK];
-        bool in[NK];
 #pragma unroll
-        for (int k = 0; k < NK; ++k) {
-            const int qx = x + HX[k], qy = y + HY[k];
-            in[k] = qx >= 0 && qx < W && qy < H;
-            const long long qi = in[k] ? (long long)qy * W + qx : i;
-            kqa[k] = gmem(P.keys)[qi];
-            cqa[k] = gmem(P.cost)[qi];
-            if (F64) lqa[k] = gmem(P.labels)[qi];
-        }
-        if (lp != NO_LABEL) {
+    for (int pp = 0; pp < PPT; ++pp) {
+        const int t = (int)threadIdx.x + pp * NT;         // pixel of the tile
+        const int x = (tb % etx) * EMIT_TW + t % EMIT_TW;
+        const int y = (tb / etx) * EMIT_TH + t / EMIT_TW;
+        const long long i = (long long)y * W + x;
+        if (x < W && y < H) {
+            // forward half-neighbourhood: (1,0), (0,1), (1,1), (-1,1); all loads
+            // are issued before any is used (outside neighbours read the pixel
+            // itself and are skipped)
+            constexpr int HX[4] = {1, 0, 1, -1};
+            constexpr int HY[4] = {0, 1, 1, 1};
+            constexpr int NK = CONN == 8 ? 4 : 2;
+            const u64 kp = gmem(P.keys)[i];
+            const float cp = gmem(P.cost)[i];
+            const u32 lp = F64 ? gmem(P.labels)[i] : key_label(kp);
+            u64 kqa[NK];
+            float cqa[NK];
+            u32 lqa[NK];
+            bool in[NK];
 #pragma unroll
             for (int k = 0; k < NK; ++k) {
-                if (!in[k]) continue;
-                const u64 kq = kqa[k];
-                const u32 lq = F64 ? lqa[k] : key_label(kq);
-                if (lq == lp || lq == NO_LABEL) continue;
-                V wb;
-                // (D(p) + step) + D(q), each operation rounded on its own (the
-                // helpers are never fused into multiply-adds)
-                if (F64) {
-                    const double step = step_f64(cp, cqa[k], k < 2 ? 0 : 4);
-                    wb = (V)bitsd(relax_f64(relax_f64(dbits(kp), step), dbits(kq)));
-                } else {
-                    const float len = (k < 2) ? 1.0f : 1.41421356237309515f;
-                    const float w = step_f32(len, cp, cqa[k]);
-                    wb = (V)__float_as_uint(relax_f32(relax_f32(key_dist(kp), w), key_dist(kq)));
-                }
-                const u32 m = min(lp, lq), n = max(lp, lq);
-                const u64 hk = ((u64)m << 32) | n;
-                u32 h = (u32)(((hk ^ (hk >> 29)) * 0x9e3779b97f4a7c15ull) >> (64 - LBITS));
-                bool done = false;
-                for (int probe = 0; probe < LCAP; ++probe) {
-                    const u64 prev = atomicCAS(&lkey[h], HASH_EMPTY, hk);
-                    if (prev == HASH_EMPTY || prev == hk) {
-                        atomicMin(&lval[h], wb);
-                        done = true;
-                        break;
+                const int qx = x + HX[k], qy = y + HY[k];
+                in[k] = qx >= 0 && qx < W && qy < H;
+                const long long qi = in[k] ? (long long)qy * W + qx : i;
+                kqa[k] = gmem(P.keys)[qi];
+                cqa[k] = gmem(P.cost)[qi];
+                if (F64) lqa[k] = gmem(P.labels)[qi];
+            }
+            if (lp != NO_LABEL) {
+#pragma unroll
+                for (int k = 0; k < NK; ++k) {
+                    if (!in[k]) continue;
+                    const u64 kq = kqa[k];
+                    const u32 lq = F64 ? lqa[k] : key_label(kq);
+                    if (lq == lp || lq == NO_LABEL) continue;
+                    V wb;
+                    // (D(p) + step) + D(q), each operation rounded on its own (the
+                    // helpers are never fused into multiply-adds)
+                    if (F64) {
+                        const double step = step_f64(cp, cqa[k], k < 2 ? 0 : 4);
+                        wb = (V)bitsd(relax_f64(relax_f64(dbits(kp), step), dbits(kq)));
+                    } else {
+                        const float len = (k < 2) ? 1.0f : 1.41421356237309515f;
+                        const float w = step_f32(len, cp, cqa[k]);
+                        wb = (V)__float_as_uint(relax_f32(relax_f32(key_dist(kp), w), key_dist(kq)));
                     }
-                    h = (h + 1u) & (LCAP - 1);
+                    const u32 m = min(lp, lq), n = max(lp, lq);
+                    const u64 hk = ((u64)m << 32) | n;
+                    u32 h = (u32)(((hk ^ (hk >> 29)) * 0x9e3779b97f4a7c15ull) >> (64 - LBITS));
+                    bool done = false;
+                    for (int probe = 0; probe < LCAP; ++probe) {
+                        const u64 prev = atomicCAS(&lkey[h], HASH_EMPTY, hk);
+                        if (prev == HASH_EMPTY || prev == hk) {
+                            atomicMin(&lval[h], wb);
+                            done = true;
+                            break;
+                        }
+                        h = (h + 1u) & (LCAP - 1);
+                    }
+                    if (!done) global_insert<F64>(P, hk, wb);
                 }
-                if (!done) global_insert<F64>(P, hk, wb);
             }
         }
     }
     __syncthreads();
-    for (int j = threadIdx.x; j < LCAP; j += EMIT_NT)
+    for (int j = threadIdx.x; j < LCAP; j += NT)
         if (lkey[j] != HASH_EMPTY) s_list[atomicAdd(&s_cnt, 1)] = (unsigned short)j;
     __syncthreads();
     const int cnt = s_cnt;
-    for (int k = threadIdx.x; k < cnt; k += EMIT_NT) {
+    for (int k = threadIdx.x; k < cnt; k += NT) {
         const int j = s_list[k];
         global_insert<F64>(P, lkey[j], lval[j]);
     }
@@ -299,14 +307,29 @@ __global__ __launch_bounds__(SLOT_BLOCK) void k_csr_scatter(const PairDev* __res
     }
 }
 
-hipError_t launch_graph_emit(const PairDev* d_pairs, const RunDev& run, int total_blocks, hipStream_t s) {
+hipError_t launch_graph_emit(const PairDev* d_pairs, const RunDev& run, int total_blocks, long long total_px,
+                             hipStream_t s) {
     const bool f64 = run.precision == 1;
+    // two pixels per thread once the call has at least 2.1 Mpx (the tiles of
+    // four full chips of one-pixel threads)
+    const bool two = total_px >= 4LL * 256 * 32 * 64;
+    const dim3 b1(EMIT_NT), b2(EMIT_NT / 2);
     if (run.conn == 4) {
-        if (f64) hipLaunchKernelGGL((k_graph_emit<4, true>), dim3(total_blocks), dim3(EMIT_NT), 0, s, d_pairs, run);
-        else hipLaunchKernelGGL((k_graph_emit<4, false>), dim3(total_blocks), dim3(EMIT_NT), 0, s, d_pairs, run);
+        if (f64) {
+            if (two) hipLaunchKernelGGL((k_graph_emit<4, true, 2>), dim3(total_blocks), b2, 0, s, d_pairs, run);
+            else hipLaunchKernelGGL((k_graph_emit<4, true, 1>), dim3(total_blocks), b1, 0, s, d_pairs, run);
+        } else {
+            if (two) hipLaunchKernelGGL((k_graph_emit<4, false, 2>), dim3(total_blocks), b2, 0, s, d_pairs, run);
+            else hipLaunchKernelGGL((k_graph_emit<4, false, 1>), dim3(total_blocks), b1, 0, s, d_pairs, run);
+        }
     } else {
-        if (f64) hipLaunchKernelGGL((k_graph_emit<8, true>), dim3(total_blocks), dim3(EMIT_NT), 0, s, d_pairs, run);
-        else hipLaunchKernelGGL((k_graph_emit<8, false>), dim3(total_blocks), dim3(EMIT_NT), 0, s, d_pairs, run);
+        if (f64) {
+            if (two) hipLaunchKernelGGL((k_graph_emit<8, true, 2>), dim3(total_blocks), b2, 0, s, d_pairs, run);
+            else hipLaunchKernelGGL((k_graph_emit<8, true, 1>), dim3(total_blocks), b1, 0, s, d_pairs, run);
+        } else {
+            if (two) hipLaunchKernelGGL((k_graph_emit<8, false, 2>), dim3(total_blocks), b2, 0, s, d_pairs, run);
+            else hipLaunchKernelGGL((k_graph_emit<8, false, 1>), dim3(total_blocks), b1, 0, s, d_pairs, run);
+        }
     }
     return hipGetLastError();
 }
