@@ -145,6 +145,39 @@ def test_large_batch_with_odd_shapes_equals_single():
         assert _epe(flows[1], ref).mean() <= parity.EPE_MEAN
 
 
+@pytest.mark.parametrize("seed", [11, 12])
+def test_random_large_batch(seed):
+    """A random pair above 2.1 Mpx beside five small random pairs: the
+    large-call forms (two-pixel emit, four-pixel assignment) give each pair
+    its single call's flow, bitwise, and the large pair matches the oracle
+    at every stage."""
+    import torch
+    import paper_1501_02565_amd as epic
+    rng = np.random.default_rng(seed)
+    H, W = int(rng.integers(1450, 1500)), int(rng.integers(1500, 2048))
+    big = random_case(H, W, int(rng.integers(3000, 18000)), seed=int(rng.integers(1 << 30)),
+                      K=int(rng.choice([16, 50, 100])), mode=int(rng.integers(0, 2)))
+    smalls = []
+    for _ in range(5):
+        h, w = int(rng.integers(3, 200)), int(rng.integers(3, 200))
+        smalls.append(random_case(h, w, int(rng.integers(2, max(3, h * w // 4))), seed=int(rng.integers(1 << 30)),
+                                  K=int(rng.choice([3, 8, 32, 100])), mode=int(rng.integers(0, 2)),
+                                  outside=int(rng.integers(0, 3))))
+    scs = [big] + smalls
+    assert sum(s.H * s.W for s in scs) >= 4 * 256 * 32 * 64
+    print(f"[case] seed {seed}: {big.name} with 5 small pairs", flush=True)
+    need = sum(epic.workspace_bytes(s.H, s.W, s.N, s.K) for s in scs)
+    with epic.Context(0, need) as c:
+        probs = [_dev(sc) for sc in scs]
+        flows = [f.cpu().numpy() for f in c.interp_batch(probs)]
+        st = [c.stats(i) for i in range(len(scs))]
+        assert all(x["status"] == 0 for x in st), st
+        for i in range(len(scs)):
+            alone = c.interp(*probs[i]).cpu().numpy()
+            assert np.array_equal(alone, flows[i]), i
+        parity.full_check(c, big)
+
+
 def test_full_size_batch_sampled_parity():
     """The 64-pair mixed-size batch at full size (the batched benchmark's
     launch configuration); every 8th pair is checked against the oracle and
