@@ -451,7 +451,13 @@ constexpr int kPassRounds = 5;
 template <int TW, int TH, int CONN, int NT, bool LISTED, bool BOUND = false>
 __global__ __launch_bounds__(NT) void k_geo_pass(const PairDev* __restrict__ pairs, RunDev run, int pass) {
     __shared__ TileLdsT<TW, TH, BOUND> S;
-    if (pass > 0 && run.any[pass - 1] == 0) return;          // converged
+    // A listed pass reads its list only while the transform still changes.
+    // A block-per-tile pass needs no such gate in front of its own flag (one
+    // memory round trip less on every visit): every mark sets its pass's
+    // change flag, and the seeding's marks are cleared by the first pass,
+    // which visits every tile they name, so after a pass without changes no
+    // tile of the next one is marked.
+    if (LISTED && pass > 0 && run.any[pass - 1] == 0) return;
     u32* dirty = run.dirty[pass & 1];
     auto visit = [&](int tile) {
         const int p = find_pair(run.npairs, tile, [&](int k) { return pairs[k].tile_base; });
@@ -475,8 +481,15 @@ __global__ __launch_bounds__(NT) void k_geo_pass(const PairDev* __restrict__ pai
         const u32* list = run.wl[pass % 3];
         for (int i = (int)blockIdx.x; i < cnt; i += (int)gridDim.x) visit((int)list[i]);
     } else {
+        // the flag is read before the bound is tested (its argument loads
+        // then go out together): the grid is the tile count rounded up to a
+        // multiple of 8 and each flag array is carved to a multiple of 64
+        // entries, so the read stays within the array
         const int tile = (int)blockIdx.x;
-        if (tile >= run.total_tiles || dirty[tile] == 0u) return;
+        u32* const d0 = run.dirty[0];
+        u32* const d1 = run.dirty[1];
+        const u32 dflag = ((pass & 1) ? d1 : d0)[tile];
+        if (tile >= run.total_tiles || dflag == 0u) return;
         visit(tile);
     }
 }
